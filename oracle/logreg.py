@@ -1,0 +1,167 @@
+"""l1-logistic regression oracle (test infrastructure).
+
+Problem (Sec. 4.2, in the machine-learning form of Sec. 3.3):
+    minimize sum_i l(w_i) + lam ||x||_1,   l(w) = log(1 + e^w),   w_i = -y_i a_i^T x,
+with labels y_i in {-1, +1}.  Reading: the data are generated with
+P(y = +1 | a) = sigmoid(a^T x0), so the per-sample margin is w_i = -y_i a_i^T x
+(the paper's form with x replaced by -x); y is folded into the vectors.
+
+With rows a~_i = -y_i a_i (the paper's a_i = b_i a_i), f(x) = sum l(a~_i^T x),
+    grad f(x)   = A^T (-y o l'(w)),          l'(w)  = sigmoid(w)
+    Hess f(x)   = A^T diag(l''(w)) A,        l''(w) = sigmoid(w)(1 - sigmoid(w))
+(Sec. 3.3, gradient and Hessian of the ML objective).
+
+What is here
+------------
+* ``admm``: GeNIOS's ADMM for ML problems (Sec. 3.3): the x-system
+  (A^T D_k A + (rho + sigma) I) x = (A^T D_k A + sigma I) x^k - grad f(x^k) + rho (z^k - u^k)
+  (eq. x-update-lin-sys; reading: the sign of the rho-term follows the general
+  form, the ML display has a sign typo), solved exactly (Cholesky / Woodbury);
+  or, with ``xstep='exact'``, the classic ADMM x-step minimised by damped
+  Newton.  z- and u-updates, over-relaxation and residuals as for the Lasso.
+* ``duality_gap``: App. A with f*(v) = v log v + (1 - v) log(1 - v) on [0, 1]
+  and the dual point nu = sigmoid(w) min(1, lam / ||A^T (y o sigmoid(w))||_inf).
+* ``solve``: classic exact-x-step ADMM certified by the duality gap.
+
+Pins (tests/test_oracle_logreg.py): lam >= ||A^T y||_inf / 2 gives x* = 0
+(App. A with f'(0) = 1/2); KKT with f' = sigmoid; gap >= 0 and -> 0;
+agreement with scipy's L-BFGS-B on the split (x+, x-) >= 0 reformulation.
+"""
+import numpy as np
+from scipy.special import expit, xlogy
+
+from .lasso import ShiftedGramSolve
+from .prox import soft_threshold
+from .residuals import r_kkt
+
+
+def _f64(a):
+    return np.asarray(a, dtype=np.float64)
+
+
+def margins(A, y, x):
+    return -_f64(y) * (_f64(A) @ _f64(x))
+
+
+def objective(A, y, lam, x):
+    w = margins(A, y, x)
+    return float(np.sum(np.logaddexp(0.0, w))) + lam * float(np.sum(np.abs(x)))
+
+
+def grad_f(A, y, x):
+    w = margins(A, y, x)
+    return _f64(A).T @ (-_f64(y) * expit(w))
+
+
+def hess_diag(A, y, x):
+    s = expit(margins(A, y, x))
+    return s * (1.0 - s)
+
+
+def _newton_prox(A, y, rho, v, x0, tol=1e-12, max_newton=100):
+    """argmin_x f(x) + (rho/2)||x - v||^2 by damped Newton with Armijo backtracking."""
+    A = _f64(A)
+    x = _f64(x0).copy()
+
+    def phi(xx):
+        w = margins(A, y, xx)
+        return float(np.sum(np.logaddexp(0.0, w))) + 0.5 * rho * float((xx - v) @ (xx - v))
+
+    for _ in range(max_newton):
+        g = grad_f(A, y, x) + rho * (x - v)
+        if np.linalg.norm(g) <= tol * max(1.0, np.linalg.norm(x)):
+            break
+        d = hess_diag(A, y, x)
+        step = -ShiftedGramSolve(A, rho, d).solve(g)
+        t, f0, slope = 1.0, phi(x), float(g @ step)
+        while phi(x + t * step) > f0 + 1e-4 * t * slope and t > 1e-12:
+            t *= 0.5
+        x = x + t * step
+    return x
+
+
+def admm(A, y, lam, rho=1.0, alpha=1.0, sigma=0.0, max_iter=500, eps=None,
+         xstep="approx", rho_update_every=0, rho_update_until=500, tau=2.0, mu=10.0):
+    """ADMM of Sec. 2 / Sec. 3.3 for l1-logistic; returns (x, z, u, rho, hist)."""
+    A = _f64(A)
+    y = _f64(y)
+    m, n = A.shape
+    x = np.zeros(n)
+    z = np.zeros(n)
+    u = np.zeros(n)
+    hist = []
+    for k in range(1, max_iter + 1):
+        if xstep == "approx":
+            d = hess_diag(A, y, x)
+            g = grad_f(A, y, x)
+            Hx = A.T @ (d * (A @ x))
+            rhs = Hx + sigma * x - g + rho * (z - u)
+            x = ShiftedGramSolve(A, rho + sigma, d).solve(rhs)
+        else:
+            x = _newton_prox(A, y, rho, z - u, x)
+        xh = alpha * x + (1.0 - alpha) * z
+        z = soft_threshold(xh + u, lam / rho)
+        u = u + xh - z
+        rk, rp, rd = r_kkt(x, z, u, rho, grad_f(A, y, x))
+        rho_used = rho
+        if rho_update_every > 0 and k % rho_update_every == 0 and k <= rho_update_until:
+            new = rho
+            if rp > mu * rd:
+                new = tau * rho
+            elif rd > mu * rp:
+                new = rho / tau
+            if new != rho:
+                u = u * (rho / new)
+                rho = new
+        hist.append((k, rp, rd, rk, rho_used, rho))
+        if eps is not None and rk <= eps:
+            break
+    return x, z, u, rho, np.array(hist)
+
+
+def duality_gap(A, y, lam, x):
+    """(gap, primal, dual): App. A with the logistic conjugate and lam2 = 0."""
+    A = _f64(A)
+    y = _f64(y)
+    w = margins(A, y, x)
+    s = expit(w)
+    g = A.T @ (y * s)
+    ginf = float(np.max(np.abs(g)))
+    scale = 1.0 if ginf <= lam else lam / ginf
+    nu = scale * s
+    dual = -float(np.sum(xlogy(nu, nu) + xlogy(1.0 - nu, 1.0 - nu)))
+    primal = objective(A, y, lam, x)
+    return primal - dual, primal, dual
+
+
+def kkt_violation(A, y, lam, x):
+    x = _f64(x)
+    g = grad_f(A, y, x)
+    on = x != 0
+    v = np.where(on, np.abs(g + lam * np.sign(x)), np.maximum(np.abs(g) - lam, 0.0))
+    return float(np.max(v)) / lam
+
+
+def solve(A, y, lam, rho=1.0, max_iter=5000, gap_rel=1e-12, check_every=5):
+    """Certified optimum by classic ADMM (exact Newton x-step, fixed rho)."""
+    A = _f64(A)
+    y = _f64(y)
+    n = A.shape[1]
+    x = np.zeros(n)
+    z = np.zeros(n)
+    u = np.zeros(n)
+    out = None
+    for k in range(1, max_iter + 1):
+        x = _newton_prox(A, y, rho, z - u, x)
+        z = soft_threshold(x + u, lam / rho)
+        u = u + x - z
+        if k % check_every == 0:
+            gap, F, _ = duality_gap(A, y, lam, z)
+            if gap <= gap_rel * F:
+                out = (z, F, gap, k)
+                break
+    if out is None:
+        gap, F, _ = duality_gap(A, y, lam, z)
+        out = (z, F, gap, max_iter)
+    z, F, gap, k = out
+    return dict(x=z, F=F, gap=gap, iters=k)
