@@ -1,0 +1,284 @@
+/*
+ * genios.h - C ABI of the MI355X (gfx950) GeNIOS hot-path library.
+ *
+ * The library solves the x-subproblem of GeNIOS's inexact ADMM,
+ *     (H + (rho + sigma) I) x = rhs,     H = A^T A (Lasso) or A^T D A (l1-logistic),
+ * by conjugate gradient with a randomized Nystrom preconditioner, and runs the
+ * surrounding ADMM iteration (prox, dual update, residuals, penalty update) on
+ * the GPU.  Paper: Diamandis, Frangella, Zhao, Stellato, Udell, "GeNIOS: an
+ * (almost) second-order operator-splitting solver for large-scale convex
+ * optimization" (2023).  Section numbers below refer to that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Pointers are DEVICE pointers unless a parameter says "(host)".  The
+ *   caller owns every input, output and workspace buffer; the library never
+ *   allocates device memory during a call.  Pointers must stay valid until the
+ *   call returns.  A is row-major (element (i, j) at A[i * lda + j]).
+ * Vector dtype.  Vectors (b, y, x, z, u, d, U, Omega, r, ...) are float when
+ *   A.hi_dtype == GENIOS_DT_F32 and double when A.hi_dtype == GENIOS_DT_F64.
+ * Batches.  A call may carry `batch` independent problems.  Problem p uses
+ *   A_hi + p * stride_A (and A_bf16 + p * stride_A); m-vectors at offset p * m,
+ *   n-vectors at offset p * n, n x s matrices at offset p * n * s, s-vectors at
+ *   p * s, host arrays (lambda, info, grad_lambda) at index p.  stride_A == 0
+ *   shares one matrix across the batch.
+ * Streams.  All device work is enqueued on opts->stream (a hipStream_t; NULL
+ *   is the null stream).  Solves block the host because they read a few
+ *   convergence scalars every ADMM iteration; the other calls synchronise the
+ *   stream before returning.  The library never calls hipDeviceSynchronize.
+ * Errors.  Negative return values are errors, positive ones are warnings with
+ *   valid outputs.  Argument and shape errors are detected on the host before
+ *   any HIP call and leave outputs untouched.  No exception or abort crosses
+ *   the ABI; genios_last_error() returns a thread-local description.
+ * Determinism.  Reductions are two-stage with a fixed order and no floating
+ *   point atomics: a fixed seed gives bitwise-identical results on one GPU.
+ * Reentrancy.  Calls are reentrant given distinct workspaces.  The only
+ *   process-wide state is a lazily created per-thread pinned host staging block.
+ */
+#ifndef GENIOS_H
+#define GENIOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GENIOS_ABI_VERSION 1
+
+/* Return codes. */
+#define GENIOS_OK 0
+#define GENIOS_MAX_ITER 1           /* iteration cap reached; outputs are the last iterate */
+#define GENIOS_WARN_PRECOND 2       /* sketch core failed; identity preconditioner used */
+#define GENIOS_ERR_ARG (-1)         /* invalid scalar argument or option */
+#define GENIOS_ERR_SHAPE (-2)       /* inconsistent sizes or strides */
+#define GENIOS_ERR_NUMERIC (-3)     /* NaN/Inf in a residual, or CG breakdown (p^T q <= 0) */
+#define GENIOS_ERR_FACTOR (-4)      /* factorisation failure that could not be recovered */
+#define GENIOS_ERR_DEVICE (-5)      /* a HIP runtime call failed */
+#define GENIOS_ERR_WORKSPACE (-6)   /* workspace missing, misaligned or too small */
+#define GENIOS_ERR_UNSUPPORTED (-7) /* valid request this build does not implement */
+
+/* Element types of the data matrix. */
+typedef enum { GENIOS_DT_F32 = 0, GENIOS_DT_BF16 = 1, GENIOS_DT_F64 = 2 } genios_dtype;
+
+/* Arithmetic of the matrix-vector products inside CG.
+ *   F64          A and all vectors FP64 (requires hi_dtype F64).
+ *   F32          A FP32, vectors FP32, dot products FP64.
+ *   BF16_REFINE  A in BF16 (FP32 accumulation) until the KKT residual of the
+ *                BF16 problem reaches switch_tol (or stalls), then FP32 A,
+ *                warm-started, until the FP32 KKT residual reaches eps.
+ *   BF16_ONLY    BF16 A throughout; certification uses the BF16 operator. */
+typedef enum {
+  GENIOS_PREC_F64 = 0,
+  GENIOS_PREC_F32 = 1,
+  GENIOS_PREC_BF16_REFINE = 2,
+  GENIOS_PREC_BF16_ONLY = 3
+} genios_precision;
+
+/* Operation ids for genios_workspace_size. */
+typedef enum {
+  GENIOS_OP_LASSO = 0,
+  GENIOS_OP_LOGREG = 1,
+  GENIOS_OP_NYSTROM = 2,
+  GENIOS_OP_BACKWARD = 3,
+  GENIOS_OP_MATVEC = 4
+} genios_op;
+
+/* Dense data matrix (or a batch of them).  m rows (samples) by n columns
+ * (features), row-major with leading dimension lda >= n. */
+typedef struct {
+  int64_t m, n, lda;
+  int64_t batch;          /* number of independent problems, >= 1 */
+  int64_t stride_A;       /* elements between consecutive problems' matrices; 0 = shared */
+  int32_t hi_dtype;       /* GENIOS_DT_F32 or GENIOS_DT_F64: the master copy */
+  int32_t reserved;
+  const void* A_hi;       /* required master copy */
+  const uint16_t* A_bf16; /* optional BF16 bit patterns, same layout; when NULL and the
+                             precision needs BF16, the library rounds A_hi into the workspace */
+} genios_matrix;
+
+/* Solver options.  genios_default_opts fills the paper's defaults (Table of
+ * default parameters, Sec. 4): sigma 1e-6, gamma 1.2, sketch size min(50, n/20),
+ * re-sketch every 20 iterations, l2 residuals, eps_abs = eps_rel = 1e-4,
+ * alpha 1.6, tau 2, mu 10. */
+typedef struct {
+  uint32_t struct_size;        /* sizeof(genios_opts), for ABI versioning */
+  int32_t precision;           /* genios_precision; default BF16_REFINE (F64 for F64 data) */
+  double sigma;                /* x-subproblem proximal offset (Sec. 2.1), default 1e-6 */
+  double alpha;                /* over-relaxation (Sec. 2.5), default 1.6 */
+  double gamma;                /* CG tolerance exponent (Sec. 2.1), default 1.2 */
+  double eps_abs, eps_rel;     /* termination (Sec. 2.3), default 1e-4 each */
+  double tau, mu;              /* penalty update factor / threshold (Sec. 2.5), 2 and 10 */
+  int32_t rho_update_every;    /* iterations between penalty updates, default 25; 0 = fixed */
+  int32_t rho_update_until;    /* no penalty update after this iteration, default 500 */
+  int32_t max_iter;            /* ADMM iteration cap, default 5000 */
+  int32_t max_cg_iter;         /* CG iteration cap per x-solve, default 100 */
+  double cg_tol_floor;         /* lower bound on the CG relative tolerance, default 1e-7
+                                  (1e-13 for FP64); also the tolerance of exact solves */
+  int32_t sketch_rank;         /* Nystrom rank s (<= 128); 0 = min(50, floor(n/20)) */
+  int32_t resketch_every;      /* logistic: re-sketch period in ADMM iterations, default 20 */
+  int32_t precondition;        /* 1 = Nystrom preconditioner, 0 = plain CG; default 1 */
+  int32_t inexact;             /* 1 = tolerance schedule of Sec. 2.1, 0 = exact (cg_tol_floor) */
+  double switch_tol;           /* BF16 -> FP32 switch when r_kkt <= switch_tol; 0 = 10 * eps */
+  int32_t stall_window;        /* ... or when r_kkt fell < 10% over this many iterations; 10 */
+  int32_t rhs_relative;        /* CG stops at ||r|| <= rtol ||r_0|| (0, default) or
+                                  ||r|| <= rtol ||rhs|| (1) */
+  uint64_t seed;               /* key of the counter-based Gaussian test matrix */
+  int32_t warm_start;          /* 1 = start from the caller's x, z, u and the rho argument */
+  int32_t profile_kernels;     /* 1 = time every matrix-vector product with HIP events on
+                                  `stream` (adds one event pair per product) */
+  void* workspace;             /* device workspace, >= genios_workspace_size bytes, 256-B aligned */
+  size_t workspace_bytes;
+  void* stream;                /* hipStream_t */
+  double* history;             /* (host, optional) per-iteration log, see GENIOS_HIST_* */
+  int32_t history_cap;         /* rows per problem in `history` */
+  int32_t reserved1;
+} genios_opts;
+
+/* Per-iteration history row layout (doubles); problem p, iteration k (1-based)
+ * at history[(p * history_cap + k - 1) * GENIOS_HIST_FIELDS + field]. */
+#define GENIOS_HIST_FIELDS 10
+#define GENIOS_HIST_K 0        /* ADMM iteration k */
+#define GENIOS_HIST_RP 1       /* ||x^k - z^k||_2 */
+#define GENIOS_HIST_RD 2       /* ||grad f(x^k) + rho u^k||_2 (operator of the phase) */
+#define GENIOS_HIST_RKKT 3     /* KKT residual (Sec. 2.3 tests with eps_abs = eps_rel) */
+#define GENIOS_HIST_RHO 4      /* rho used in iteration k */
+#define GENIOS_HIST_CG 5       /* CG iterations spent in iteration k */
+#define GENIOS_HIST_RTOL 6     /* CG relative tolerance used in iteration k */
+#define GENIOS_HIST_PHASE 7    /* 0 = BF16 operator, 1 = FP32/FP64 operator */
+#define GENIOS_HIST_TIME 8     /* seconds since the call's entry, at the end of iteration k */
+#define GENIOS_HIST_XNORM 9    /* ||x^k||_2 */
+
+/* Per-problem results (host). */
+typedef struct {
+  int32_t status;            /* per-problem return code */
+  int32_t iters;             /* ADMM iterations */
+  int32_t cg_iters;          /* total CG iterations */
+  int32_t phase_switch_iter; /* first FP32-operator iteration (BF16_REFINE), else -1 */
+  int32_t resketches;        /* Nystrom builds performed */
+  int32_t precond_rank;      /* retained sketch rank of the last build */
+  double obj;                /* objective at z with the master-copy data (FP64 reduction) */
+  double r_p, r_d, r_kkt;    /* final residuals (r_d with the master-copy operator) */
+  double rho;                /* final penalty */
+  double t_setup;            /* seconds: casting, A^T b, first sketch */
+  double t_precond;          /* seconds spent in Nystrom builds */
+  double t_solve;            /* seconds in the ADMM loop */
+  double t_linsys;           /* seconds in CG (x-subproblem) */
+  double t_prox;             /* seconds in the fused prox / dual update kernel */
+  double t_total;            /* seconds from entry to return */
+  double t_to_target;        /* seconds from entry to the first certified r_kkt <= eps, or -1 */
+  double t_matvec_n;         /* with profile_kernels: summed duration of the A v products */
+  double t_matvec_t;         /* with profile_kernels: summed duration of the A^T w products */
+  int32_t n_matvec_n;        /* number of A v launches (counted with or without profiling) */
+  int32_t n_matvec_t;        /* number of A^T w launches */
+  int64_t bytes_matvec_lo;   /* matrix bytes streamed by products on the BF16 copy */
+  int64_t bytes_matvec_hi;   /* matrix bytes streamed by products on the master copy */
+} genios_info;
+
+/* Fill *o with the defaults listed above.  Returns GENIOS_OK. */
+int genios_default_opts(genios_opts* o);
+
+/* Bytes of workspace an operation needs for matrix *A and options *o
+ * (o may be NULL for defaults).  Returns 0 on invalid arguments. */
+size_t genios_workspace_size(int op, const genios_matrix* A, const genios_opts* o);
+
+/* Lasso, minimize (1/2)||A x - b||^2 + lambda ||x||_1 (Sec. 3.1 example, Sec. 4.1
+ * with lambda_2 = 0), by the inexact ADMM of Sec. 2 with M = I, c = 0.
+ *   b        m per problem.
+ *   lambda   (host) batch values, >= 0.
+ *   rho      initial penalty (> 0); the paper's experiments use 1.
+ *   x, z, u  n per problem, written on return (read too when opts->warm_start).
+ *            z is the exactly sparse solution; ||x - z|| is reported as r_p.
+ *   info     (host) batch entries, written.
+ * Returns the worst per-problem status (errors < warnings < OK ordering). */
+int genios_lasso_solve(const genios_matrix* A, const void* b, const double* lambda, double rho,
+                       const genios_opts* o, void* x, void* z, void* u, genios_info* info);
+
+/* l1-regularised logistic regression (Sec. 4.2 with the machine-learning
+ * interface of Sec. 3.3):
+ *   minimize sum_i log(1 + exp(-y_i a_i^T x)) + lambda ||x||_1,
+ * labels y in {-1, +1} (m per problem).  The Hessian A^T D A, D = l''(w), is
+ * applied at every iteration; the Nystrom sketch of it is refreshed every
+ * opts->resketch_every iterations (Sec. 3.3, Table of defaults).  Other
+ * arguments as genios_lasso_solve. */
+int genios_logreg_solve(const genios_matrix* A, const void* y, const double* lambda, double rho,
+                        const genios_opts* o, void* x, void* z, void* u, genios_info* info);
+
+/* Randomized Nystrom approximation (Sec. 2.2) of H = A^T diag(d) A (d == NULL:
+ * H = A^T A) with an n x s test matrix Omega:
+ *   H_hat = (H Omega)(Omega^T H Omega)^+ (H Omega)^T = U diag(lambda_hat) U^T.
+ *   d          m per problem or NULL.
+ *   s          sketch rank, 1 <= s <= min(128, n).
+ *   omega      n x s column-major per problem, or NULL to draw the standard
+ *              normal matrix on the device (Philox4x64-10, key (opts->seed, p) for
+ *              problem p, see genios_gaussian_matrix).
+ *   precision  opts->precision selects the operator: BF16 modes sketch the BF16
+ *              matrix, F32/F64 the master copy.
+ *   U          n x s column-major per problem, orthonormal columns (written).
+ *   lambda_hat (device) s doubles per problem, descending, >= 0 (written).
+ *   info       (host) precond_rank and status per problem (written).
+ * Stabilised as in the randomized Nystrom method the paper cites: a shift
+ * ~ sqrt(n) * eps * ||Y||_F is added before the Cholesky factor and removed
+ * from the eigenvalues.  If the s x s core cannot be factored after three
+ * tenfold shift increases, U = 0, lambda_hat = 0 (identity preconditioner)
+ * and the status is GENIOS_WARN_PRECOND. */
+int genios_nystrom_build(const genios_matrix* A, const void* d, int32_t s, const void* omega,
+                         const genios_opts* o, void* U, double* lambda_hat, genios_info* info);
+
+/* Apply the Nystrom preconditioner of eq. preconditioner,
+ *   z = (lambda_hat_s + nu) U (diag(lambda_hat) + nu I)^-1 U^T r + r - U U^T r,
+ * to r (n per problem).  dtype is GENIOS_DT_F32 or GENIOS_DT_F64 for U, r, z;
+ * lambda_hat (device) s doubles per problem, descending.  nu > 0. */
+int genios_nystrom_apply(int64_t n, int32_t s, int64_t batch, int32_t dtype, const void* U,
+                         const double* lambda_hat, double nu, const void* r, void* z,
+                         const genios_opts* o);
+
+/* Adjoint of the Lasso solution map (implicit differentiation on the active
+ * set, from the optimality conditions of App. A with f'(w) = w): with S the
+ * support of z_star and s its signs,
+ *   grad_b      = A_S (A_S^T A_S)^-1 grad_z_S          (m per problem, written)
+ *   grad_lambda = -s^T (A_S^T A_S)^-1 grad_z_S          (host, batch, written)
+ * The system is solved by Nystrom-preconditioned CG on the masked operator
+ * P_S A^T A P_S + (I - P_S) with the FP32 (or FP64) master copy, to relative
+ * residual opts->cg_tol_floor (default 1e-7 here as well).
+ *   z_star, grad_z  n per problem.  lambda (host) is accepted for symmetry with
+ *   the forward call and checked to be >= 0. */
+int genios_lasso_backward(const genios_matrix* A, const void* z_star, const void* grad_z,
+                          const double* lambda, const genios_opts* o, void* grad_b,
+                          double* grad_lambda, genios_info* info);
+
+/* Dense matrix-vector products with the library's kernels (parity and
+ * bandwidth measurement).  trans = 0: out = A v (v n, out m per problem);
+ * trans = 1: out = A^T v (v m, out n).  use_bf16 selects the BF16 copy (which
+ * must be given).  Vectors follow the vector dtype convention. */
+int genios_matvec(const genios_matrix* A, int32_t trans, int32_t use_bf16, const void* v,
+                  void* out, const genios_opts* o);
+
+/* Round `count` FP32 values to BF16, nearest-even, NaN -> 0x7FC0 (device). */
+int genios_cast_bf16(const float* src, uint16_t* dst, int64_t count, const genios_opts* o);
+
+/* Draw the n x s (column-major) standard normal test matrix the sketch uses,
+ * for key (seed, stream_id): Philox4x64-10 + Box-Muller, rounded to FP32. */
+int genios_gaussian_matrix(int64_t n, int32_t s, uint64_t seed, uint64_t stream_id, float* out,
+                           const genios_opts* o);
+
+/* One fused ADMM update (Sec. 2, z- and u-update with over-relaxation of
+ * Sec. 2.5 and the prox of Sec. 3.1) on n-vectors, for testing:
+ *   xh = alpha x + (1 - alpha) z;  z <- S_kappa(xh + u);  u <- u + xh - z;
+ * and norms[0..3] (host) = ||x - z_new||^2, ||x||^2, ||z_new||^2, ||u_new||^2
+ * accumulated in FP64.  dtype GENIOS_DT_F32 or GENIOS_DT_F64. */
+int genios_admm_update(int64_t n, int32_t dtype, double alpha, double kappa, const void* x,
+                       void* z, void* u, double* norms, const genios_opts* o);
+
+const char* genios_status_string(int status);
+const char* genios_last_error(void);
+
+/* sizeof(genios_matrix), sizeof(genios_opts), sizeof(genios_info) as compiled
+ * into the library (host), so bindings can verify their struct layouts. */
+void genios_abi_struct_sizes(size_t* matrix_bytes, size_t* opts_bytes, size_t* info_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GENIOS_H */

@@ -1,0 +1,710 @@
+// Vector kernels of the inexact ADMM / preconditioned CG loop.
+//
+// Per ADMM iteration (Sec. 2, M = I, c = 0):
+//   admm_begin   u <- u * scale (penalty change, Sec. 2.5); the x-system of
+//                eq. x-update-lin-sys, (H + nu I) x = rhs with
+//                rhs = (H + sigma I) x^k - grad f(x^k) + rho (z^k - u^k),
+//                warm-started at x^k, so r_0 = rho (z - u - x) - grad f(x^k);
+//                ||rhs||, ||r_0||, U^T r_0 and the CG tolerance.
+//   precond      w = P^-1 r (eq. preconditioner) and r^T w.
+//   cg_alpha     hp = H p (sum of gemv_t partials), q = hp + nu p, alpha.
+//   cg_update    x += alpha p, h += alpha hp (h tracks H x), r -= alpha q,
+//                ||r||, U^T r, stopping test.
+//   p_update     p = w + beta p.
+//   admm_end     over-relaxed z- and u-updates with the soft-threshold prox
+//                (Sec. 2.5, Sec. 3.1) and the residual norms of Sec. 2.3.
+// Reductions accumulate in FP64; each kernel's last block combines the block
+// partials of its problem in a fixed order (no floating-point atomics).
+#include <algorithm>
+
+#include "device.hpp"
+
+namespace genios {
+
+namespace {
+
+struct Chunk {
+  int64_t lo, hi;
+};
+
+__device__ __forceinline__ Chunk my_chunk(int64_t n, int64_t chunk) {
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  return Chunk{lo, min(n, lo + chunk)};
+}
+
+template <typename VT>
+__device__ __forceinline__ VT soft_threshold(VT v, VT k) {
+  return v > k ? v - k : (v < -k ? v + k : VT(0));
+}
+
+// U^T r partials of this block: r values of the chunk are in LDS (rs).
+template <typename VT>
+__device__ void ut_r_partial(const VT* __restrict__ Ub, int64_t n, int s_eff, const Chunk& ch,
+                             const VT* rs, double* part_out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int len = (int)(ch.hi - ch.lo);
+  for (int j = wave; j < s_eff; j += 4) {
+    const VT* col = Ub + (int64_t)j * n + ch.lo;
+    double acc = 0.0;
+    for (int i = lane; i < len; i += 64) acc += double(col[i]) * double(rs[i]);
+    acc = wave_sum(acc);
+    if (lane == 0) part_out[j] = acc;
+  }
+}
+
+// Last block: w_j = sum over blocks, coef_j = ((lam_rr + nu)/(lam_j + nu) - 1) w_j.
+__device__ void finish_coef(const double* part_b, int nb, int s_eff, const double* lamhat_b,
+                            double nu, double* coef_b) {
+  if (s_eff <= 0) return;
+  const double lrr = lamhat_b[s_eff - 1];
+  for (int j = threadIdx.x; j < s_eff; j += blockDim.x) {
+    double w = 0.0;
+    for (int k = 0; k < nb; ++k) w += load_partial(part_b + (int64_t)k * kPartW + j);
+    coef_b[j] = ((lrr + nu) / (lamhat_b[j] + nu) - 1.0) * w;
+  }
+}
+
+__device__ double sum_scalar(const double* part_b, int nb, int slot) {
+  double s = 0.0;
+  for (int k = 0; k < nb; ++k) s += load_partial(part_b + (int64_t)k * kPartW + kMaxS + slot);
+  return s;
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_admm_begin(VecArgs a) {
+  const int b = blockIdx.y;
+  const ProbParams P = a.ctrl.params[b];
+  if (!P.run) return;
+  ProbState* S = a.ctrl.state + b;
+  const int64_t n = a.n;
+  const Chunk ch = my_chunk(n, a.chunk);
+  const int64_t off = (int64_t)b * n;
+  VT* x = static_cast<VT*>(a.x) + off;
+  VT* z = static_cast<VT*>(a.z) + off;
+  VT* u = static_cast<VT*>(a.u) + off;
+  const VT* h = static_cast<const VT*>(a.h) + off;
+  const VT* g = P.use_c ? nullptr : static_cast<const VT*>(a.g) + off;
+  const VT* c = P.use_c ? static_cast<const VT*>(a.c) + off : nullptr;
+  VT* r = static_cast<VT*>(a.r) + off;
+  const uint8_t* mask = a.mask ? a.mask + off : nullptr;
+  __shared__ VT rs[kVecChunk * 4];
+  __shared__ double red[16];
+  const VT rho = VT(P.rho), sig = VT(P.sigma), usc = VT(P.u_scale);
+  double rhs2 = 0.0, rr = 0.0;
+  for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) {
+    VT ui = u[i];
+    if (P.u_scale != 1.0) {
+      ui *= usc;
+      u[i] = ui;
+    }
+    const VT xi = x[i], zi = z[i], hi = h[i];
+    const VT gi = c ? hi - c[i] : g[i];
+    VT rhs = hi + sig * xi - gi + rho * (zi - ui);
+    VT ri = rho * (zi - ui - xi) - gi;
+    if (mask && !mask[i]) {
+      rhs = VT(0);
+      ri = VT(0);
+    }
+    r[i] = ri;
+    rs[i - ch.lo] = ri;
+    rhs2 += double(rhs) * double(rhs);
+    rr += double(ri) * double(ri);
+  }
+  __syncthreads();
+  double* part_b = a.ctrl.part + (int64_t)b * a.ctrl.part_stride;
+  const int s_eff = a.U ? a.ctrl.s_eff[b] : 0;
+  if (s_eff > 0)
+    ut_r_partial<VT>(static_cast<const VT*>(a.U) + (int64_t)b * n * a.s_stride, n, s_eff, ch, rs,
+                     part_b + (int64_t)blockIdx.x * kPartW);
+  double v[2] = {rhs2, rr};
+  block_sum<2>(v, red);
+  if (threadIdx.x == 0) {
+    part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 0] = v[0];
+    part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 1] = v[1];
+  }
+  if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntBegin, a.nb)) return;
+  finish_coef(part_b, a.nb, s_eff, a.ctrl.lamhat + (int64_t)b * a.ctrl.s_stride, P.nu,
+              a.ctrl.coef + (int64_t)b * kMaxS);
+  if (threadIdx.x == 0) {
+    const double trhs2 = sum_scalar(part_b, a.nb, 0);
+    const double tr2 = sum_scalar(part_b, a.nb, 1);
+    double tol2 = P.rtol * P.rtol * (P.rhs_rel ? trhs2 : tr2);
+    tol2 = fmax(tol2, P.tol_floor * P.tol_floor * trhs2);
+    S->rhs2 = trhs2;
+    S->r02 = tr2;
+    S->rr = tr2;
+    S->tol2 = tol2;
+    S->cg_iters = 0;
+    S->admm_done = 0;
+    S->breakdown = 0;
+    S->cg_active = (P.max_cg > 0 && tr2 > 0.0) ? 1 : 0;
+    if (!(trhs2 <= 1.0e300) || !(tr2 <= 1.0e300)) {  // NaN or Inf
+      S->breakdown = 1;
+      S->cg_active = 0;
+    }
+  }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_precond_step(VecArgs a, int init) {
+  const int b = blockIdx.y;
+  const ProbParams P = a.ctrl.params[b];
+  ProbState* S = a.ctrl.state + b;
+  if (!P.run || !S->cg_active) return;
+  const int64_t n = a.n;
+  const Chunk ch = my_chunk(n, a.chunk);
+  const int64_t off = (int64_t)b * n;
+  const VT* r = static_cast<const VT*>(a.r) + off;
+  VT* w = static_cast<VT*>(a.w) + off;
+  VT* p = static_cast<VT*>(a.p) + off;
+  __shared__ double cf[kMaxS];
+  __shared__ double red[16];
+  const int s_eff = a.U ? a.ctrl.s_eff[b] : 0;
+  for (int j = threadIdx.x; j < s_eff; j += blockDim.x)
+    cf[j] = a.ctrl.coef[(int64_t)b * kMaxS + j];
+  __syncthreads();
+  const VT* Ub = a.U ? static_cast<const VT*>(a.U) + (int64_t)b * n * a.s_stride : nullptr;
+  double rz = 0.0;
+  for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) {
+    double acc = double(r[i]);
+    for (int j = 0; j < s_eff; ++j) acc += double(Ub[(int64_t)j * n + i]) * cf[j];
+    const VT wi = VT(acc);
+    w[i] = wi;
+    if (init) p[i] = wi;
+    rz += double(r[i]) * double(wi);
+  }
+  double v[1] = {rz};
+  block_sum<1>(v, red);
+  double* part_b = a.ctrl.part + (int64_t)b * a.ctrl.part_stride;
+  if (threadIdx.x == 0) part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 2] = v[0];
+  if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntPrecond, a.nb)) return;
+  if (threadIdx.x == 0) {
+    const double t = sum_scalar(part_b, a.nb, 2);
+    if (init) {
+      S->rz = t;
+    } else {
+      S->beta_cg = (S->rz != 0.0) ? t / S->rz : 0.0;
+      S->rz = t;
+    }
+  }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_cg_alpha(VecArgs a) {
+  const int b = blockIdx.y;
+  const ProbParams P = a.ctrl.params[b];
+  ProbState* S = a.ctrl.state + b;
+  if (!P.run || !S->cg_active) return;
+  const int64_t n = a.n;
+  const Chunk ch = my_chunk(n, a.chunk);
+  const int64_t off = (int64_t)b * n;
+  const VT* p = static_cast<const VT*>(a.p) + off;
+  VT* hp = static_cast<VT*>(a.hp) + off;
+  const VT* yp = static_cast<const VT*>(a.ypart) + (int64_t)b * a.ypart_prob_stride;
+  const uint8_t* mask = a.mask ? a.mask + off : nullptr;
+  __shared__ double red[16];
+  const VT nu = VT(P.nu);
+  double pq = 0.0;
+  for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) {
+    VT s = VT(0);
+    for (int k = 0; k < a.ksplit; ++k) s += yp[(int64_t)k * a.ypart_ks_stride + i];
+    const VT pi = p[i];
+    VT q;
+    if (mask && !mask[i]) {
+      s = VT(0);
+      q = pi;
+    } else {
+      q = s + nu * pi;
+    }
+    hp[i] = s;
+    pq += double(pi) * double(q);
+  }
+  double v[1] = {pq};
+  block_sum<1>(v, red);
+  double* part_b = a.ctrl.part + (int64_t)b * a.ctrl.part_stride;
+  if (threadIdx.x == 0) part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 3] = v[0];
+  if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntAlpha, a.nb)) return;
+  if (threadIdx.x == 0) {
+    const double t = sum_scalar(part_b, a.nb, 3);
+    S->pq = t;
+    if (!(t > 0.0) || !(t <= 1.0e300)) {
+      S->breakdown = 1;
+      S->cg_active = 0;
+      S->alpha_cg = 0.0;
+    } else {
+      S->alpha_cg = S->rz / t;
+    }
+  }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_cg_update(VecArgs a) {
+  const int b = blockIdx.y;
+  const ProbParams P = a.ctrl.params[b];
+  ProbState* S = a.ctrl.state + b;
+  if (!P.run || !S->cg_active) return;
+  const int64_t n = a.n;
+  const Chunk ch = my_chunk(n, a.chunk);
+  const int64_t off = (int64_t)b * n;
+  VT* x = static_cast<VT*>(a.x) + off;
+  VT* h = static_cast<VT*>(a.h) + off;
+  VT* r = static_cast<VT*>(a.r) + off;
+  const VT* p = static_cast<const VT*>(a.p) + off;
+  const VT* hp = static_cast<const VT*>(a.hp) + off;
+  const uint8_t* mask = a.mask ? a.mask + off : nullptr;
+  __shared__ VT rs[kVecChunk * 4];
+  __shared__ double red[16];
+  const VT al = VT(S->alpha_cg), nu = VT(P.nu);
+  double rr = 0.0;
+  for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) {
+    const VT pi = p[i], hpi = hp[i];
+    const VT q = (mask && !mask[i]) ? pi : hpi + nu * pi;
+    x[i] += al * pi;
+    h[i] += al * hpi;
+    const VT ri = r[i] - al * q;
+    r[i] = ri;
+    rs[i - ch.lo] = ri;
+    rr += double(ri) * double(ri);
+  }
+  __syncthreads();
+  double* part_b = a.ctrl.part + (int64_t)b * a.ctrl.part_stride;
+  const int s_eff = a.U ? a.ctrl.s_eff[b] : 0;
+  if (s_eff > 0)
+    ut_r_partial<VT>(static_cast<const VT*>(a.U) + (int64_t)b * n * a.s_stride, n, s_eff, ch, rs,
+                     part_b + (int64_t)blockIdx.x * kPartW);
+  double v[1] = {rr};
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 4] = v[0];
+  if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntUpdate, a.nb)) return;
+  __shared__ int s_go;
+  if (threadIdx.x == 0) {
+    const double t = sum_scalar(part_b, a.nb, 4);
+    S->rr = t;
+    S->cg_iters += 1;
+    int go = 1;
+    if (!(t <= 1.0e300)) {
+      S->breakdown = 1;
+      go = 0;
+    } else if (t <= S->tol2 || S->cg_iters >= P.max_cg) {
+      go = 0;
+    }
+    S->cg_active = go;
+    s_go = go;
+  }
+  __syncthreads();
+  if (s_go)
+    finish_coef(part_b, a.nb, s_eff, a.ctrl.lamhat + (int64_t)b * a.ctrl.s_stride, P.nu,
+                a.ctrl.coef + (int64_t)b * kMaxS);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_p_update(VecArgs a) {
+  const int b = blockIdx.y;
+  const ProbParams P = a.ctrl.params[b];
+  const ProbState* S = a.ctrl.state + b;
+  if (!P.run || !S->cg_active) return;
+  const int64_t n = a.n;
+  const Chunk ch = my_chunk(n, a.chunk);
+  const int64_t off = (int64_t)b * n;
+  VT* p = static_cast<VT*>(a.p) + off;
+  const VT* w = static_cast<const VT*>(a.w) + off;
+  const VT be = VT(S->beta_cg);
+  for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) p[i] = w[i] + be * p[i];
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_admm_end(VecArgs a) {
+  const int b = blockIdx.y;
+  const ProbParams P = a.ctrl.params[b];
+  ProbState* S = a.ctrl.state + b;
+  if (!P.run || S->cg_active || S->admm_done) return;
+  const int64_t n = a.n;
+  const Chunk ch = my_chunk(n, a.chunk);
+  const int64_t off = (int64_t)b * n;
+  const VT* x = static_cast<const VT*>(a.x) + off;
+  VT* z = static_cast<VT*>(a.z) + off;
+  VT* u = static_cast<VT*>(a.u) + off;
+  const VT* h = static_cast<const VT*>(a.h) + off;
+  const VT* c = P.use_c ? static_cast<const VT*>(a.c) + off : nullptr;
+  __shared__ double red[7 * 4];
+  const VT al = VT(P.alpha), one_m = VT(1.0 - P.alpha), kap = VT(P.kappa), rho = VT(P.rho);
+  double s_rp = 0, s_x = 0, s_z = 0, s_u = 0, s_rd = 0, s_z1 = 0, s_nnz = 0;
+  for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) {
+    const VT xi = x[i], zi = z[i], ui = u[i];
+    const VT xh = al * xi + one_m * zi;
+    const VT zn = soft_threshold<VT>(xh + ui, kap);
+    const VT un = ui + xh - zn;
+    z[i] = zn;
+    u[i] = un;
+    const double d = double(xi) - double(zn);
+    s_rp += d * d;
+    s_x += double(xi) * double(xi);
+    s_z += double(zn) * double(zn);
+    s_u += double(un) * double(un);
+    if (c) {
+      const double rd = double(h[i] - c[i]) + double(rho) * double(un);
+      s_rd += rd * rd;
+    }
+    s_z1 += fabs(double(zn));
+    s_nnz += (zn != VT(0)) ? 1.0 : 0.0;
+  }
+  double v[7] = {s_rp, s_x, s_z, s_u, s_rd, s_z1, s_nnz};
+  block_sum<7>(v, red);
+  double* part_b = a.ctrl.part + (int64_t)b * a.ctrl.part_stride;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 7; ++k) part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 5 + k] = v[k];
+  if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntEnd, a.nb)) return;
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 7; ++k) S->red[k] = sum_scalar(part_b, a.nb, 5 + k);
+    S->admm_done = 1;
+  }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_dual_residual(VecArgs a) {
+  const int b = blockIdx.y;
+  const ProbParams P = a.ctrl.params[b];
+  if (!P.run) return;
+  ProbState* S = a.ctrl.state + b;
+  const int64_t n = a.n;
+  const Chunk ch = my_chunk(n, a.chunk);
+  const int64_t off = (int64_t)b * n;
+  const VT* u = static_cast<const VT*>(a.u) + off;
+  const VT* h = static_cast<const VT*>(a.h) + off;
+  const VT* c = P.use_c ? static_cast<const VT*>(a.c) + off : nullptr;
+  const VT* g = P.use_c ? nullptr : static_cast<const VT*>(a.g) + off;
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) {
+    const double gi = c ? double(h[i] - c[i]) : double(g[i]);
+    const double rd = gi + P.rho * double(u[i]);
+    s += rd * rd;
+  }
+  double v[1] = {s};
+  block_sum<1>(v, red);
+  double* part_b = a.ctrl.part + (int64_t)b * a.ctrl.part_stride;
+  if (threadIdx.x == 0) part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 12] = v[0];
+  if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntAux0, a.nb)) return;
+  if (threadIdx.x == 0) S->red[kRedRd2] = sum_scalar(part_b, a.nb, 12);
+}
+
+// Objective over the m samples from partials of t = A z.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_objective_m(int64_t m, const VT* __restrict__ tparts,
+                                                     int nsplit, int64_t split_stride,
+                                                     int64_t prob_stride,
+                                                     const VT* __restrict__ bvec, int logistic,
+                                                     Ctrl ctrl, int nb) {
+  const int b = blockIdx.y;
+  const int64_t chunk = (m + nb - 1) / nb;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(m, lo + chunk);
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    double t = 0.0;
+    for (int k = 0; k < nsplit; ++k)
+      t += double(tparts[(int64_t)b * prob_stride + (int64_t)k * split_stride + i]);
+    const double bi = double(bvec[(int64_t)b * m + i]);
+    if (logistic) {
+      const double w = -bi * t;  // log(1 + e^w), computed stably
+      s += (w > 0.0 ? w + log1p(exp(-w)) : log1p(exp(w)));
+    } else {
+      s += 0.5 * (t - bi) * (t - bi);
+    }
+  }
+  double v[1] = {s};
+  block_sum<1>(v, red);
+  double* pb = ctrl.part + (int64_t)b * ctrl.part_stride;
+  if (threadIdx.x == 0) pb[(int64_t)blockIdx.x * kPartW + kMaxS + 13] = v[0];
+  if (!last_block_arrive(ctrl.counters + (int64_t)b * kNumCounters + kCntObj, nb)) return;
+  if (threadIdx.x == 0) ctrl.state[b].red[kRedAux] = sum_scalar(pb, nb, 13);
+}
+
+// Logistic elementwise terms: w = -y t, s = sigmoid(w), d = s (1 - s),
+// col0 = d o t (for H x), col1 = -y o s (for grad f).
+template <typename VT>
+__global__ __launch_bounds__(256) void k_logistic_elem(int64_t m, const VT* __restrict__ tparts,
+                                                       int nsplit, int64_t split_stride,
+                                                       int64_t prob_stride,
+                                                       const VT* __restrict__ y,
+                                                       VT* __restrict__ d, VT* __restrict__ cols,
+                                                       int64_t col_stride,
+                                                       const ProbParams* __restrict__ params) {
+  const int b = blockIdx.y;
+  if (params && !params[b].run) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    VT t = VT(0);
+    for (int k = 0; k < nsplit; ++k) t += tparts[(int64_t)b * prob_stride + (int64_t)k * split_stride + i];
+    const VT yi = y[(int64_t)b * m + i];
+    const VT w = -yi * t;
+    VT s;
+    if constexpr (sizeof(VT) == 4)
+      s = 1.0f / (1.0f + expf(-w));
+    else
+      s = 1.0 / (1.0 + exp(-w));
+    const VT di = s * (VT(1) - s);
+    d[(int64_t)b * m + i] = di;
+    VT* cb = cols + (int64_t)b * 2 * col_stride;
+    cb[i] = di * t;
+    cb[col_stride + i] = -yi * s;
+  }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_admm_update_hook(int64_t n, double alpha, double kappa,
+                                                          const VT* __restrict__ x,
+                                                          VT* __restrict__ z, VT* __restrict__ u,
+                                                          double* part, unsigned* counter,
+                                                          double* out4, int nb) {
+  const int64_t chunk = (n + nb - 1) / nb;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
+  __shared__ double red[16];
+  const VT al = VT(alpha), one_m = VT(1.0 - alpha), kap = VT(kappa);
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const VT xi = x[i], zi = z[i], ui = u[i];
+    const VT xh = al * xi + one_m * zi;
+    const VT zn = soft_threshold<VT>(xh + ui, kap);
+    const VT un = ui + xh - zn;
+    z[i] = zn;
+    u[i] = un;
+    const double d = double(xi) - double(zn);
+    s0 += d * d;
+    s1 += double(xi) * double(xi);
+    s2 += double(zn) * double(zn);
+    s3 += double(un) * double(un);
+  }
+  double v[4] = {s0, s1, s2, s3};
+  block_sum<4>(v, red);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) part[(int64_t)blockIdx.x * 4 + k] = v[k];
+  if (!last_block_arrive(counter, nb)) return;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) {
+      double s = 0.0;
+      for (int j = 0; j < nb; ++j) s += load_partial(part + (int64_t)j * 4 + k);
+      out4[k] = s;
+    }
+}
+
+// Stand-alone preconditioner apply: z = r + U (((lam_rr + nu)/(lam + nu) - 1) o U^T r).
+template <typename VT>
+__global__ __launch_bounds__(256) void k_precond_utr(int64_t n, int s, const VT* __restrict__ U,
+                                                     const double* __restrict__ lamhat,
+                                                     const int32_t* __restrict__ s_eff_arr,
+                                                     double nu, const VT* __restrict__ r,
+                                                     double* part, int64_t part_stride,
+                                                     unsigned* counters, double* coef, int nb,
+                                                     int64_t chunk) {
+  const int b = blockIdx.y;
+  const Chunk ch = my_chunk(n, chunk);
+  const int s_eff = s_eff_arr ? s_eff_arr[b] : s;
+  __shared__ VT rs[kVecChunk * 4];
+  const VT* rb = r + (int64_t)b * n;
+  for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) rs[i - ch.lo] = rb[i];
+  __syncthreads();
+  double* part_b = part + (int64_t)b * part_stride;
+  ut_r_partial<VT>(U + (int64_t)b * n * s, n, s_eff, ch, rs, part_b + (int64_t)blockIdx.x * kPartW);
+  if (!last_block_arrive(counters + (int64_t)b * kNumCounters + kCntAux1, nb)) return;
+  finish_coef(part_b, nb, s_eff, lamhat + (int64_t)b * s, nu, coef + (int64_t)b * kMaxS);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_precond_out(int64_t n, int s, const VT* __restrict__ U,
+                                                     const int32_t* __restrict__ s_eff_arr,
+                                                     const VT* __restrict__ r,
+                                                     const double* __restrict__ coef,
+                                                     VT* __restrict__ z) {
+  const int b = blockIdx.y;
+  const int s_eff = s_eff_arr ? s_eff_arr[b] : s;
+  __shared__ double cf[kMaxS];
+  for (int j = threadIdx.x; j < s_eff; j += blockDim.x) cf[j] = coef[(int64_t)b * kMaxS + j];
+  __syncthreads();
+  const VT* Ub = U + (int64_t)b * n * s;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = double(r[(int64_t)b * n + i]);
+    for (int j = 0; j < s_eff; ++j) acc += double(Ub[(int64_t)j * n + i]) * cf[j];
+    z[(int64_t)b * n + i] = VT(acc);
+  }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_build_mask(int64_t n, const VT* __restrict__ zs,
+                                                    const VT* __restrict__ gz,
+                                                    uint8_t* __restrict__ mask,
+                                                    VT* __restrict__ sgn, VT* __restrict__ rhs) {
+  const int b = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = (int64_t)b * n + i;
+    const VT zi = zs[k];
+    const bool on = zi != VT(0);
+    mask[k] = on ? 1 : 0;
+    sgn[k] = zi > VT(0) ? VT(1) : (zi < VT(0) ? VT(-1) : VT(0));
+    rhs[k] = on ? -gz[k] : VT(0);  // the CG start uses g = -rhs
+  }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_masked_dot(int64_t n, const VT* __restrict__ a,
+                                                    const VT* __restrict__ bv, double* part,
+                                                    int64_t part_stride, unsigned* counters,
+                                                    double* out, int nb) {
+  const int b = blockIdx.y;
+  const int64_t chunk = (n + nb - 1) / nb;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
+    s += double(a[(int64_t)b * n + i]) * double(bv[(int64_t)b * n + i]);
+  double v[1] = {s};
+  block_sum<1>(v, red);
+  double* pb = part + (int64_t)b * part_stride;
+  if (threadIdx.x == 0) pb[(int64_t)blockIdx.x * kPartW + kMaxS + 14] = v[0];
+  if (!last_block_arrive(counters + (int64_t)b * kNumCounters + kCntMasked, nb)) return;
+  if (threadIdx.x == 0) out[b] = sum_scalar(pb, nb, 14);
+}
+
+}  // namespace
+
+#define GENIOS_VEC_LAUNCH(kern, ...)                                                   \
+  do {                                                                                 \
+    dim3 grid((unsigned)a.nb, (unsigned)a.batch);                                      \
+    if (a.vt == VT_F32)                                                                \
+      hipLaunchKernelGGL(kern<float>, grid, dim3(kVecBlock), 0, st, a, ##__VA_ARGS__); \
+    else                                                                               \
+      hipLaunchKernelGGL(kern<double>, grid, dim3(kVecBlock), 0, st, a, ##__VA_ARGS__); \
+    return hipGetLastError();                                                          \
+  } while (0)
+
+hipError_t launch_admm_begin(const VecArgs& a, hipStream_t st) { GENIOS_VEC_LAUNCH(k_admm_begin); }
+hipError_t launch_precond_step(const VecArgs& a, int init, hipStream_t st) {
+  GENIOS_VEC_LAUNCH(k_precond_step, init);
+}
+hipError_t launch_cg_alpha(const VecArgs& a, hipStream_t st) { GENIOS_VEC_LAUNCH(k_cg_alpha); }
+hipError_t launch_cg_update(const VecArgs& a, hipStream_t st) { GENIOS_VEC_LAUNCH(k_cg_update); }
+hipError_t launch_p_update(const VecArgs& a, hipStream_t st) { GENIOS_VEC_LAUNCH(k_p_update); }
+hipError_t launch_admm_end(const VecArgs& a, hipStream_t st) { GENIOS_VEC_LAUNCH(k_admm_end); }
+hipError_t launch_dual_residual(const VecArgs& a, hipStream_t st) {
+  GENIOS_VEC_LAUNCH(k_dual_residual);
+}
+
+static int m_blocks(int64_t m) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((m + kVecChunk - 1) / kVecChunk, kMaxVecBlocks));
+}
+
+hipError_t launch_objective_m(VType vt, int64_t m, int64_t batch, const void* tparts, int nsplit,
+                              int64_t split_stride, int64_t prob_stride, const void* bvec,
+                              int logistic, Ctrl ctrl, hipStream_t st) {
+  const int nb = m_blocks(m);
+  dim3 grid((unsigned)nb, (unsigned)batch);
+  if (vt == VT_F32)
+    hipLaunchKernelGGL(k_objective_m<float>, grid, dim3(256), 0, st, m,
+                       static_cast<const float*>(tparts), nsplit, split_stride, prob_stride,
+                       static_cast<const float*>(bvec), logistic, ctrl, nb);
+  else
+    hipLaunchKernelGGL(k_objective_m<double>, grid, dim3(256), 0, st, m,
+                       static_cast<const double*>(tparts), nsplit, split_stride, prob_stride,
+                       static_cast<const double*>(bvec), logistic, ctrl, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_logistic_elem(VType vt, int64_t m, int64_t batch, const void* tparts, int nsplit,
+                                int64_t split_stride, int64_t prob_stride, const void* y, void* d,
+                                void* cols, int64_t col_stride, const ProbParams* params,
+                                hipStream_t st) {
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((m + 255) / 256, 512));
+  dim3 grid(nb, (unsigned)batch);
+  if (vt == VT_F32)
+    hipLaunchKernelGGL(k_logistic_elem<float>, grid, dim3(256), 0, st, m,
+                       static_cast<const float*>(tparts), nsplit, split_stride, prob_stride,
+                       static_cast<const float*>(y), static_cast<float*>(d),
+                       static_cast<float*>(cols), col_stride, params);
+  else
+    hipLaunchKernelGGL(k_logistic_elem<double>, grid, dim3(256), 0, st, m,
+                       static_cast<const double*>(tparts), nsplit, split_stride, prob_stride,
+                       static_cast<const double*>(y), static_cast<double*>(d),
+                       static_cast<double*>(cols), col_stride, params);
+  return hipGetLastError();
+}
+
+hipError_t launch_admm_update_hook(VType vt, int64_t n, double alpha, double kappa, const void* x,
+                                   void* z, void* u, double* part, unsigned* counter,
+                                   double* out4, hipStream_t st) {
+  const int nb = m_blocks(n);
+  if (vt == VT_F32)
+    hipLaunchKernelGGL(k_admm_update_hook<float>, dim3(nb), dim3(256), 0, st, n, alpha, kappa,
+                       static_cast<const float*>(x), static_cast<float*>(z),
+                       static_cast<float*>(u), part, counter, out4, nb);
+  else
+    hipLaunchKernelGGL(k_admm_update_hook<double>, dim3(nb), dim3(256), 0, st, n, alpha, kappa,
+                       static_cast<const double*>(x), static_cast<double*>(z),
+                       static_cast<double*>(u), part, counter, out4, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_precond_apply(VType vt, int64_t n, int s, int64_t batch, const void* U,
+                                const double* lamhat, const int32_t* s_eff, double nu,
+                                const void* r, void* z, double* part, int64_t part_stride,
+                                unsigned* counters, double* coef, hipStream_t st) {
+  const int64_t chunk = kVecChunk;
+  const int nb = (int)((n + chunk - 1) / chunk);
+  if ((int64_t)nb * kPartW > part_stride) return hipErrorInvalidValue;
+  dim3 g1((unsigned)nb, (unsigned)batch);
+  const unsigned nb2 = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024));
+  dim3 g2(nb2, (unsigned)batch);
+  if (vt == VT_F32) {
+    hipLaunchKernelGGL(k_precond_utr<float>, g1, dim3(256), 0, st, n, s,
+                       static_cast<const float*>(U), lamhat, s_eff, nu,
+                       static_cast<const float*>(r), part, part_stride, counters, coef, nb,
+                       chunk);
+    hipLaunchKernelGGL(k_precond_out<float>, g2, dim3(256), 0, st, n, s,
+                       static_cast<const float*>(U), s_eff, static_cast<const float*>(r), coef,
+                       static_cast<float*>(z));
+  } else {
+    hipLaunchKernelGGL(k_precond_utr<double>, g1, dim3(256), 0, st, n, s,
+                       static_cast<const double*>(U), lamhat, s_eff, nu,
+                       static_cast<const double*>(r), part, part_stride, counters, coef, nb,
+                       chunk);
+    hipLaunchKernelGGL(k_precond_out<double>, g2, dim3(256), 0, st, n, s,
+                       static_cast<const double*>(U), s_eff, static_cast<const double*>(r), coef,
+                       static_cast<double*>(z));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_build_mask(VType vt, int64_t n, int64_t batch, const void* zstar,
+                             const void* gz, uint8_t* mask, void* sgn, void* rhs,
+                             hipStream_t st) {
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 512));
+  dim3 grid(nb, (unsigned)batch);
+  if (vt == VT_F32)
+    hipLaunchKernelGGL(k_build_mask<float>, grid, dim3(256), 0, st, n,
+                       static_cast<const float*>(zstar), static_cast<const float*>(gz), mask,
+                       static_cast<float*>(sgn), static_cast<float*>(rhs));
+  else
+    hipLaunchKernelGGL(k_build_mask<double>, grid, dim3(256), 0, st, n,
+                       static_cast<const double*>(zstar), static_cast<const double*>(gz), mask,
+                       static_cast<double*>(sgn), static_cast<double*>(rhs));
+  return hipGetLastError();
+}
+
+hipError_t launch_masked_dot(VType vt, int64_t n, int64_t batch, const void* a, const void* b,
+                             double* part, int64_t part_stride, unsigned* counters, double* out,
+                             hipStream_t st) {
+  const int nb = m_blocks(n);
+  dim3 grid((unsigned)nb, (unsigned)batch);
+  if (vt == VT_F32)
+    hipLaunchKernelGGL(k_masked_dot<float>, grid, dim3(256), 0, st, n,
+                       static_cast<const float*>(a), static_cast<const float*>(b), part, part_stride,
+                       counters, out, nb);
+  else
+    hipLaunchKernelGGL(k_masked_dot<double>, grid, dim3(256), 0, st, n,
+                       static_cast<const double*>(a), static_cast<const double*>(b), part,
+                       part_stride, counters, out, nb);
+  return hipGetLastError();
+}
+
+}  // namespace genios

@@ -1,0 +1,1025 @@
+// Host engine: workspace layout and the ADMM / PCG drivers.
+//
+// The drivers enqueue every step on one HIP stream.  Scalars that only the
+// GPU needs (CG alpha/beta, tolerances, preconditioner coefficients) live in
+// per-problem device control blocks; each kernel of a CG iteration is gated by
+// the problem's `cg_active` flag, so the host can enqueue several CG
+// iterations, the fused z/u update and (for logistic regression) the next
+// gradient pass without waiting.  The host synchronises once per ADMM
+// iteration (more only when a CG solve outlasts its enqueued iterations) to
+// read the residual norms, apply the stopping test and the penalty rule of
+// Sec. 2.3 / Sec. 2.5, and choose the next CG tolerance of Sec. 2.1.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+#include "internal.hpp"
+
+namespace genios {
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Pinned {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+thread_local Pinned g_pinned;
+
+void* pinned(size_t bytes) {
+  if (g_pinned.cap >= bytes) return g_pinned.p;
+  if (g_pinned.p) (void)hipHostFree(g_pinned.p);
+  g_pinned.p = nullptr;
+  g_pinned.cap = 0;
+  size_t cap = std::max<size_t>(bytes, 1 << 16);
+  if (hipHostMalloc(&g_pinned.p, cap, hipHostMallocDefault) != hipSuccess) {
+    g_pinned.p = nullptr;
+    return nullptr;
+  }
+  g_pinned.cap = cap;
+  return g_pinned.p;
+}
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+#define HC(expr)                                                                   \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess) {                                                        \
+      set_error(std::string("HIP error at ") + #expr + ": " + hipGetErrorString(_e)); \
+      return GENIOS_ERR_DEVICE;                                                    \
+    }                                                                              \
+  } while (0)
+
+int elem_size(MType mt) { return mt == MT_BF16 ? 2 : (mt == MT_F32 ? 4 : 8); }
+
+}  // namespace
+
+struct Arena {
+  char* base;
+  size_t cap, off = 0;
+  bool dry;
+  void* take(size_t bytes) {
+    off = (off + 255) / 256 * 256;
+    char* p = dry ? nullptr : base + off;
+    off += bytes;
+    return p;
+  }
+};
+
+void set_error(const std::string& s) { g_err = s; }
+const char* last_error() { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------------
+// Workspace layout
+
+void Layout::carve(Arena& ar) {
+  const size_t ve = vt == VT_F32 ? 4 : 8;
+  const int64_t B = batch;
+  ctrl.params = static_cast<ProbParams*>(ar.take(B * sizeof(ProbParams)));
+  ctrl.state = static_cast<ProbState*>(ar.take(B * sizeof(ProbState)));
+  ctrl.counters = static_cast<unsigned*>(ar.take(B * kNumCounters * sizeof(unsigned)));
+  ctrl.coef = static_cast<double*>(ar.take(B * kMaxS * sizeof(double)));
+  ctrl.s_eff = static_cast<int32_t*>(ar.take(B * sizeof(int32_t)));
+  ctrl.lamhat = static_cast<double*>(ar.take(B * std::max(1, s) * sizeof(double)));
+  ctrl.s_stride = std::max(1, s);
+  ctrl.part_stride = (int64_t)part_blocks * kPartW;
+  ctrl.part = static_cast<double*>(ar.take(B * ctrl.part_stride * sizeof(double)));
+  ctrl_bytes_end = ar.off;
+  core_status = static_cast<int32_t*>(ar.take(B * sizeof(int32_t)));
+  shift = static_cast<double*>(ar.take(B * sizeof(double)));
+  scal = static_cast<double*>(ar.take(B * 8 * sizeof(double)));
+  if (need_a16) A16 = static_cast<uint16_t*>(ar.take(a16_elems * 2));
+  auto vec = [&](int64_t len) { return ar.take((size_t)B * len * ve); };
+  for (int k = 0; k < kNumNVec; ++k) nv[k] = n_vecs > k ? vec(n) : nullptr;
+  tparts = ar.take((size_t)B * nsplit_n * m * ve);
+  ypart = ar.take((size_t)B * ksplit * nrhs * npad * ve);
+  if (logistic || backward) {
+    dvec = vec(m);
+    cols = ar.take((size_t)B * 2 * m * ve);
+  }
+  if (backward) mask = static_cast<uint8_t*>(ar.take((size_t)B * n));
+  if (s > 0) {
+    U = vec(n * (int64_t)s);
+    const int sp = sketch_pad(s);
+    sk.omega = vec(n * (int64_t)sp);
+    sk.W = vec(m * (int64_t)sp);
+    sk.Wpart = ar.take((size_t)B * sk.ksW * m * sp * ve);
+    sk.Ypart = ar.take((size_t)B * sk.ksY * n * sp * ve);
+    sk.Y = vec(n * (int64_t)sp);
+    sk.gpart = static_cast<double*>(ar.take((size_t)B * 3 * sk.nbG * sp * sp * sizeof(double)));
+    sk.gram = static_cast<double*>(ar.take((size_t)B * 3 * sp * sp * sizeof(double)));
+    sk.core = static_cast<double*>(ar.take((size_t)B * 5 * sp * sp * sizeof(double)));
+  }
+  total = ar.off + 256;
+}
+
+int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_) {
+  op = op_;
+  m = A->m;
+  n = A->n;
+  batch = A->batch;
+  vt = A->hi_dtype == GENIOS_DT_F64 ? VT_F64 : VT_F32;
+  logistic = op == GENIOS_OP_LOGREG;
+  backward = op == GENIOS_OP_BACKWARD;
+  s = s_;
+  const int prec = o->precision;
+  const bool uses_lo = (op == GENIOS_OP_LASSO || op == GENIOS_OP_LOGREG || op == GENIOS_OP_NYSTROM ||
+                        op == GENIOS_OP_MATVEC) &&
+                       (prec == GENIOS_PREC_BF16_REFINE || prec == GENIOS_PREC_BF16_ONLY);
+  need_a16 = uses_lo && A->A_bf16 == nullptr;
+  // exact extent of the matrix elements (the padding after the last row is not read)
+  a16_elems = (A->stride_A == 0 ? 0 : (A->batch - 1) * A->stride_A) + (A->m - 1) * A->lda + A->n;
+  MatArg probe{nullptr, vt == VT_F64 ? MT_F64 : MT_F32, m, n, A->lda, A->stride_A};
+  MatArg probe_lo{nullptr, MT_BF16, m, n, A->lda, A->stride_A};
+  nsplit_n = std::max(gemv_n_splits(probe, batch), uses_lo ? gemv_n_splits(probe_lo, batch) : 1);
+  nrhs = logistic ? 2 : 1;
+  ksplit = std::max(gemv_t_splits(probe, batch), uses_lo ? gemv_t_splits(probe_lo, batch) : 1);
+  npad = (n + 7) / 8 * 8;
+  chunk = std::max<int64_t>(256, ((n + 127) / 128 + 255) / 256 * 256);
+  chunk = std::min<int64_t>(chunk, 4 * kVecChunk);
+  nb = (int)((n + chunk - 1) / chunk);
+  part_blocks = std::max<int>(nb, std::max<int>(kMaxVecBlocks, (int)((n + kVecChunk - 1) / kVecChunk)));
+  n_vecs = (op == GENIOS_OP_MATVEC || op == GENIOS_OP_NYSTROM) ? 0 : kNumNVec;
+  if (s > 0) sketch_ws_bytes(m, n, s, batch, vt, &sk.ksW, &sk.ksY, &sk.nbG);
+  Arena ar{nullptr, 0, 0, true};
+  carve(ar);
+  return 0;
+}
+
+int Layout::bind(void* base, size_t bytes) {
+  if (base == nullptr || reinterpret_cast<uintptr_t>(base) % 256 != 0 || bytes < total) {
+    set_error("workspace missing, misaligned (256 B) or smaller than genios_workspace_size");
+    return GENIOS_ERR_WORKSPACE;
+  }
+  Arena ar{static_cast<char*>(base), bytes, 0, false};
+  carve(ar);
+  return 0;
+}
+
+// ---------------------------------------------------------------------------------
+// Solver context
+
+namespace {
+
+struct Timer {
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool ok = false;
+  ~Timer() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  hipError_t init() {
+    for (auto& e : ev) {
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+    }
+    ok = true;
+    return hipSuccess;
+  }
+};
+
+struct KernelProf {
+  bool on = false;
+  std::vector<hipEvent_t> evs;
+  std::vector<int> kind;  // 0 = A v, 1 = A^T w
+  size_t used = 0;
+  double t[2] = {0, 0};
+  ~KernelProf() {
+    for (auto e : evs) (void)hipEventDestroy(e);
+  }
+  hipError_t begin(hipStream_t st, int k) {
+    if (!on) return hipSuccess;
+    if (used + 2 > evs.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        evs.push_back(e);
+      }
+      kind.resize(evs.size() / 2 + 1);
+    }
+    kind[used / 2] = k;
+    return hipEventRecord(evs[used], st);
+  }
+  hipError_t end(hipStream_t st) {
+    if (!on) return hipSuccess;
+    hipError_t r = hipEventRecord(evs[used + 1], st);
+    used += 2;
+    return r;
+  }
+  // call after a stream synchronisation
+  void harvest() {
+    for (size_t i = 0; i + 1 < used; i += 2) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, evs[i], evs[i + 1]) == hipSuccess) t[kind[i / 2]] += ms * 1e-3;
+    }
+    used = 0;
+  }
+};
+
+struct Ctx {
+  const genios_matrix* A;
+  const genios_opts* o;
+  Layout L;
+  hipStream_t st;
+  MatArg op_hi{}, op_lo{};
+  int64_t B, m, n;
+  VType vt;
+  size_t ve;
+  int32_t* gate_cg = nullptr;    // &state[0].cg_active
+  int32_t* gate_done = nullptr;  // &state[0].admm_done
+  int32_t* gate_run = nullptr;   // &params[0].run
+  int gs_state = sizeof(ProbState) / 4, gs_params = sizeof(ProbParams) / 4;
+  KernelProf prof;
+  int64_t n_mv[2] = {0, 0};
+  int64_t bytes_lo = 0, bytes_hi = 0;
+
+  void* vecp(int k) const { return L.nv[k]; }
+  VecArgs vargs(void* x, void* z, void* u, void* h, void* g, void* c, const uint8_t* mask) const {
+    VecArgs a{};
+    a.vt = vt;
+    a.n = n;
+    a.batch = B;
+    a.nb = L.nb;
+    a.chunk = L.chunk;
+    a.ctrl = L.ctrl;
+    a.x = x;
+    a.z = z;
+    a.u = u;
+    a.h = h;
+    a.g = g;
+    a.c = c;
+    a.r = L.nv[kVR];
+    a.p = L.nv[kVP];
+    a.hp = L.nv[kVHP];
+    a.w = L.nv[kVW];
+    a.U = L.s > 0 ? L.U : nullptr;
+    a.s_stride = std::max(1, L.s);
+    a.ypart = L.ypart;
+    a.ksplit = L.ksplit;
+    a.ypart_ks_stride = (int64_t)L.nrhs * L.npad;
+    a.ypart_prob_stride = (int64_t)L.ksplit * L.nrhs * L.npad;
+    a.mask = mask;
+    return a;
+  }
+
+  void account(const MatArg& op, int kind) {
+    n_mv[kind] += B;
+    const int64_t bytes = (int64_t)B * op.m * op.n * elem_size(op.mt);
+    if (op.mt == MT_BF16)
+      bytes_lo += bytes;
+    else
+      bytes_hi += bytes;
+  }
+
+  // tparts = A v (gated)
+  int gemv_n(const MatArg& op, const void* v, const int32_t* gate, int gstride) {
+    HC(prof.begin(st, 0));
+    HC(launch_gemv_n(op, B, vt, v, n, L.tparts, m, (int64_t)L.nsplit_n * m, nsplit_for(op, 0),
+                     gate, gstride, st));
+    HC(prof.end(st));
+    account(op, 0);
+    return 0;
+  }
+  int nsplit_for(const MatArg& op, int which) const {
+    if (which == 0) return std::min(L.nsplit_n, gemv_n_splits(op, B));
+    return std::min(L.ksplit, gemv_t_splits(op, B));
+  }
+  // ypart = A^T (d o t) from tparts (gated)
+  int gemv_t_from_t(const MatArg& op, const void* d, const int32_t* gate, int gstride,
+                    int nsplit_in) {
+    HC(prof.begin(st, 1));
+    const int ks = nsplit_for(op, 1);
+    HC(launch_gemv_t(op, B, vt, L.tparts, nsplit_in, m, (int64_t)L.nsplit_n * m, 0, 1, d, m,
+                     L.ypart, ks, (int64_t)L.nrhs * L.npad, L.npad,
+                     (int64_t)L.ksplit * L.nrhs * L.npad, gate, gstride, st));
+    HC(prof.end(st));
+    cur_ks = ks;
+    account(op, 1);
+    return 0;
+  }
+  int cur_ks = 1;
+};
+
+int hvp_explicit(Ctx& c, const MatArg& op, const void* x, void* h, const void* d,
+                 const int32_t* gate, int gstride) {
+  int rc = c.gemv_n(op, x, gate, gstride);
+  if (rc) return rc;
+  rc = c.gemv_t_from_t(op, d, gate, gstride, c.nsplit_for(op, 0));
+  if (rc) return rc;
+  HC(launch_sum_splits(c.vt, c.B, c.n, c.L.ypart, c.cur_ks, (int64_t)c.L.nrhs * c.L.npad,
+                       (int64_t)c.L.ksplit * c.L.nrhs * c.L.npad, h, c.n, c.st, gate, gstride));
+  return 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------
+// ADMM driver shared by the Lasso and the logistic regression.
+
+namespace {
+
+struct HostProb {
+  double lambda, rho;
+  double u_scale = 1.0;
+  double rp_prev = INFINITY, rd_prev = INFINITY;
+  int done = 0;
+  int status = 0;
+  int iters = 0, cg_total = 0, last_cg = 2;
+  double rkkt = INFINITY, rp = 0, rd = 0, xn = 0, zn = 0, un = 0;
+  double t_target = -1.0;
+  int switch_iter = -1, resketches = 0;
+  std::vector<double> rk_hist;
+};
+
+double kkt_from(double rp, double rd, double xn, double zn, double rhou, int64_t n) {
+  const double sn = std::sqrt((double)n);
+  const double a = rp / (sn + std::max(xn, zn));
+  const double b = rd / (sn + rhou);
+  return std::max(a, b);
+}
+
+bool paper_test(double rp, double rd, double xn, double zn, double rhou, int64_t n,
+                double eps_abs, double eps_rel) {
+  const double sn = std::sqrt((double)n);
+  return rp <= sn * eps_abs + eps_rel * std::max(xn, zn) && rd <= sn * eps_abs + eps_rel * rhou;
+}
+
+int sync_state(Ctx& c, ProbState* hs) {
+  HC(hipMemcpyAsync(hs, c.L.ctrl.state, c.B * sizeof(ProbState), hipMemcpyDeviceToHost, c.st));
+  HC(hipStreamSynchronize(c.st));
+  c.prof.harvest();
+  return 0;
+}
+
+hipError_t upload_params(Ctx& c, ProbParams* hp) {
+  return hipMemcpyAsync(c.L.ctrl.params, hp, c.B * sizeof(ProbParams), hipMemcpyHostToDevice, c.st);
+}
+
+// One CG iteration for all problems (kernels gated on cg_active).
+int cg_iteration(Ctx& c, const MatArg& op, const VecArgs& va, const void* dscale) {
+  int rc = c.gemv_n(op, va.p, c.gate_cg, c.gs_state);
+  if (rc) return rc;
+  rc = c.gemv_t_from_t(op, dscale, c.gate_cg, c.gs_state, c.nsplit_for(op, 0));
+  if (rc) return rc;
+  VecArgs a = va;
+  a.ksplit = c.cur_ks;
+  HC(launch_cg_alpha(a, c.st));
+  HC(launch_cg_update(a, c.st));
+  HC(launch_precond_step(a, 0, c.st));
+  HC(launch_p_update(a, c.st));
+  return 0;
+}
+
+}  // namespace
+
+int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, double rho0,
+             const genios_opts* o, void* x, void* z, void* u, genios_info* info, bool logistic) {
+  const double t0 = now_s();
+  Ctx c;
+  c.A = A;
+  c.o = o;
+  c.st = static_cast<hipStream_t>(o->stream);
+  c.B = A->batch;
+  c.m = A->m;
+  c.n = A->n;
+  c.vt = A->hi_dtype == GENIOS_DT_F64 ? VT_F64 : VT_F32;
+  c.ve = c.vt == VT_F32 ? 4 : 8;
+  const int s = o->precondition ? effective_rank(o, A->n, A->m) : 0;
+  c.L.setup(logistic ? GENIOS_OP_LOGREG : GENIOS_OP_LASSO, A, o, s);
+  int rc = c.L.bind(o->workspace, o->workspace_bytes);
+  if (rc) return rc;
+  c.prof.on = o->profile_kernels != 0;
+  const int prec = o->precision;
+  const bool use_lo = prec == GENIOS_PREC_BF16_REFINE || prec == GENIOS_PREC_BF16_ONLY;
+  c.op_hi = MatArg{A->A_hi, c.vt == VT_F64 ? MT_F64 : MT_F32, A->m, A->n, A->lda, A->stride_A};
+  c.op_lo = MatArg{A->A_bf16 ? (const void*)A->A_bf16 : (const void*)c.L.A16, MT_BF16, A->m, A->n,
+                   A->lda, A->stride_A};
+  c.gate_cg = &c.L.ctrl.state[0].cg_active;
+  c.gate_done = &c.L.ctrl.state[0].admm_done;
+  c.gate_run = &c.L.ctrl.params[0].run;
+  const int64_t B = c.B, n = c.n, m = c.m;
+  Timer tm;
+  HC(tm.init());
+
+  // ---- setup ----
+  HC(launch_fill(c.L.ctrl.params, c.L.ctrl_bytes_end - 0, c.st));
+  if (use_lo && A->A_bf16 == nullptr) {
+    HC(launch_cast_bf16(static_cast<const float*>(A->A_hi), c.L.A16, c.L.a16_elems, c.st));
+  }
+  void* h = c.L.nv[kVH];
+  void* g = c.L.nv[kVG];
+  void* c_hi = c.L.nv[kVCH];
+  void* c_lo = c.L.nv[kVCL];
+  if (!o->warm_start) {
+    HC(launch_fill(x, B * n * c.ve, c.st));
+    HC(launch_fill(z, B * n * c.ve, c.st));
+    HC(launch_fill(u, B * n * c.ve, c.st));
+  }
+  int phase = use_lo ? 0 : 1;
+  const MatArg* op = phase == 0 ? &c.op_lo : &c.op_hi;
+
+  std::vector<ProbParams> hpv(B);
+  ProbParams* hp = static_cast<ProbParams*>(pinned(B * (sizeof(ProbParams) + sizeof(ProbState))));
+  if (!hp) {
+    set_error("pinned host staging allocation failed");
+    return GENIOS_ERR_DEVICE;
+  }
+  ProbState* hs = reinterpret_cast<ProbState*>(hp + B);
+  std::vector<HostProb> P(B);
+  for (int64_t b = 0; b < B; ++b) {
+    P[b].lambda = lambda[b];
+    P[b].rho = rho0;
+  }
+  auto set_params = [&](int k, bool run_all) {
+    for (int64_t b = 0; b < B; ++b) {
+      ProbParams& q = hp[b];
+      std::memset(&q, 0, sizeof(q));
+      q.run = (run_all || !P[b].done) ? 1 : 0;
+      q.rho = P[b].rho;
+      q.sigma = o->sigma;
+      q.nu = P[b].rho + o->sigma;
+      q.kappa = P[b].lambda / P[b].rho;
+      q.alpha = o->alpha;
+      q.u_scale = P[b].u_scale;
+      double rtol;
+      if (o->inexact) {
+        const double gm = std::sqrt(P[b].rp_prev * P[b].rd_prev);
+        rtol = std::min(std::isfinite(gm) ? gm : 1.0, 1.0) / std::pow((double)std::max(k, 1), o->gamma);
+        rtol = std::max(rtol, o->cg_tol_floor);
+      } else {
+        rtol = o->cg_tol_floor;
+      }
+      q.rtol = rtol;
+      q.tol_floor = o->cg_tol_floor;
+      q.lambda = P[b].lambda;
+      q.max_cg = o->max_cg_iter;
+      q.rhs_rel = o->rhs_relative;
+      q.use_c = logistic ? 0 : 1;
+    }
+  };
+
+  // Right-hand sides c = A^T b for the Lasso (per operator in use).
+  if (!logistic) {
+    if (use_lo) {
+      HC(launch_gemv_t(c.op_lo, B, c.vt, bvec, 1, 0, m, 0, 1, nullptr, 0, c.L.ypart,
+                       c.nsplit_for(c.op_lo, 1), (int64_t)c.L.nrhs * c.L.npad, c.L.npad,
+                       (int64_t)c.L.ksplit * c.L.nrhs * c.L.npad, nullptr, 0, c.st));
+      HC(launch_sum_splits(c.vt, B, n, c.L.ypart, c.nsplit_for(c.op_lo, 1),
+                           (int64_t)c.L.nrhs * c.L.npad, (int64_t)c.L.ksplit * c.L.nrhs * c.L.npad,
+                           c_lo, n, c.st));
+    }
+    if (prec != GENIOS_PREC_BF16_ONLY || true) {
+      HC(launch_gemv_t(c.op_hi, B, c.vt, bvec, 1, 0, m, 0, 1, nullptr, 0, c.L.ypart,
+                       c.nsplit_for(c.op_hi, 1), (int64_t)c.L.nrhs * c.L.npad, c.L.npad,
+                       (int64_t)c.L.ksplit * c.L.nrhs * c.L.npad, nullptr, 0, c.st));
+      HC(launch_sum_splits(c.vt, B, n, c.L.ypart, c.nsplit_for(c.op_hi, 1),
+                           (int64_t)c.L.nrhs * c.L.npad, (int64_t)c.L.ksplit * c.L.nrhs * c.L.npad,
+                           c_hi, n, c.st));
+    }
+  }
+  // Every problem runs during setup passes.
+  set_params(1, true);
+  HC(upload_params(c, hp));
+  // h = H x (zero for a cold start)
+  auto gradient_pass = [&](const MatArg& opx, const int32_t* gate, int gstride) -> int {
+    // logistic: t = A x, d, columns, [A^T (d o t), A^T(-y o s)] -> h, g
+    int r = c.gemv_n(opx, x, gate, gstride);
+    if (r) return r;
+    HC(launch_logistic_elem(c.vt, m, B, c.L.tparts, c.nsplit_for(opx, 0), m,
+                            (int64_t)c.L.nsplit_n * m, bvec, c.L.dvec, c.L.cols, m, nullptr,
+                            c.st));
+    HC(c.prof.begin(c.st, 1));
+    const int ks = c.nsplit_for(opx, 1);
+    HC(launch_gemv_t(opx, B, c.vt, c.L.cols, 1, 0, 2 * m, m, 2, nullptr, 0, c.L.ypart, ks,
+                     (int64_t)2 * c.L.npad, c.L.npad, (int64_t)c.L.ksplit * 2 * c.L.npad, gate,
+                     gstride, c.st));
+    HC(c.prof.end(c.st));
+    c.account(opx, 1);
+    HC(launch_sum_splits(c.vt, B, n, c.L.ypart, ks, (int64_t)2 * c.L.npad,
+                         (int64_t)c.L.ksplit * 2 * c.L.npad, h, n, c.st, gate, gstride));
+    HC(launch_sum_splits(c.vt, B, n, static_cast<char*>(c.L.ypart) + c.L.npad * c.ve, ks,
+                         (int64_t)2 * c.L.npad, (int64_t)c.L.ksplit * 2 * c.L.npad, g, n, c.st,
+                         gate, gstride));
+    return 0;
+  };
+  if (logistic) {
+    rc = gradient_pass(*op, nullptr, 0);
+    if (rc) return rc;
+  } else if (o->warm_start) {
+    rc = hvp_explicit(c, *op, x, h, nullptr, nullptr, 0);
+    if (rc) return rc;
+  } else {
+    HC(launch_fill(h, B * n * c.ve, c.st));
+  }
+  // Nystrom sketch of the operator in use (Lasso: once; logistic: at k = 1, 1 + every, ...).
+  double t_precond = 0.0;
+  auto build_sketch = [&](const MatArg& opx, const void* d) -> int {
+    if (s <= 0) return 0;
+    HC(hipEventRecord(tm.ev[0], c.st));
+    HC(run_nystrom(opx, B, c.vt, d, m, s, nullptr, o->seed, 0, nullptr, c.L.sk, c.L.U,
+                   c.L.ctrl.lamhat, c.L.ctrl.s_eff, c.L.core_status, c.L.shift, c.st));
+    HC(hipEventRecord(tm.ev[1], c.st));
+    HC(hipEventSynchronize(tm.ev[1]));
+    float ms = 0.f;
+    HC(hipEventElapsedTime(&ms, tm.ev[0], tm.ev[1]));
+    t_precond += ms * 1e-3;
+    for (int64_t b = 0; b < B; ++b) P[b].resketches++;
+    return 0;
+  };
+  if (!logistic) {
+    rc = build_sketch(*op, nullptr);
+    if (rc) return rc;
+  }
+  HC(hipStreamSynchronize(c.st));
+  const double t_setup = now_s() - t0 - (logistic ? 0.0 : 0.0);
+
+  // ---- ADMM loop ----
+  const double eps_abs = o->eps_abs, eps_rel = o->eps_rel;
+  const double switch_tol = o->switch_tol > 0 ? o->switch_tol : 10.0 * std::max(eps_abs, eps_rel);
+  double t_linsys = 0.0, t_prox = 0.0;
+  const double t_loop0 = now_s();
+  int any_numeric = 0;
+  int k = 0;
+  int64_t active = B;
+  std::vector<int32_t> core_status(B, 0);
+  bool sketch_checked = false;
+  auto check_sketch = [&]() -> int {
+    HC(hipMemcpyAsync(core_status.data(), c.L.core_status, B * sizeof(int32_t),
+                      hipMemcpyDeviceToHost, c.st));
+    HC(hipStreamSynchronize(c.st));
+    sketch_checked = true;
+    return 0;
+  };
+  if (!logistic && s > 0) {
+    rc = check_sketch();
+    if (rc) return rc;
+  }
+  while (active > 0 && k < o->max_iter) {
+    ++k;
+    if (logistic && s > 0 && (k - 1) % std::max(1, o->resketch_every) == 0) {
+      rc = build_sketch(*op, c.L.dvec);
+      if (rc) return rc;
+      rc = check_sketch();
+      if (rc) return rc;
+    }
+    set_params(k, false);
+    for (int64_t b = 0; b < B; ++b) P[b].u_scale = 1.0;
+    HC(upload_params(c, hp));
+    VecArgs va = c.vargs(x, z, u, h, g, phase == 0 ? c_lo : c_hi, nullptr);
+    HC(hipEventRecord(tm.ev[0], c.st));
+    HC(launch_admm_begin(va, c.st));
+    HC(launch_precond_step(va, 1, c.st));
+    int chunk = 1;
+    for (int64_t b = 0; b < B; ++b)
+      if (!P[b].done) chunk = std::max(chunk, P[b].last_cg);
+    chunk = std::min(chunk, o->max_cg_iter);
+    int enq = 0;
+    for (;;) {
+      for (int it = 0; it < chunk; ++it) {
+        rc = cg_iteration(c, *op, va, logistic ? c.L.dvec : nullptr);
+        if (rc) return rc;
+      }
+      enq += chunk;
+      HC(hipEventRecord(tm.ev[1], c.st));
+      HC(launch_admm_end(va, c.st));
+      if (logistic) {
+        // gradient pass at the new x (gated on the completed update)
+        rc = gradient_pass(*op, c.gate_done, c.gs_state);
+        if (rc) return rc;
+        VecArgs vr = va;
+        HC(launch_dual_residual(vr, c.st));
+      }
+      HC(hipEventRecord(tm.ev[2], c.st));
+      rc = sync_state(c, hs);
+      if (rc) return rc;
+      bool more = false;
+      for (int64_t b = 0; b < B; ++b)
+        if (hp[b].run && !hs[b].admm_done) more = true;
+      if (!more) break;
+      chunk = std::max(1, std::min(2, o->max_cg_iter - enq));
+    }
+    float ms1 = 0.f, ms2 = 0.f;
+    HC(hipEventElapsedTime(&ms1, tm.ev[0], tm.ev[1]));
+    HC(hipEventElapsedTime(&ms2, tm.ev[1], tm.ev[2]));
+    t_linsys += ms1 * 1e-3;
+    t_prox += ms2 * 1e-3;
+
+    // ---- host logic per problem ----
+    bool all_ready_to_switch = phase == 0 && prec == GENIOS_PREC_BF16_REFINE;
+    bool any_certify = false;
+    std::vector<int> want_cert(B, 0);
+    for (int64_t b = 0; b < B; ++b) {
+      if (!hp[b].run) continue;
+      HostProb& q = P[b];
+      const ProbState& S = hs[b];
+      q.iters = k;
+      q.cg_total += S.cg_iters;
+      q.last_cg = std::max(1, S.cg_iters);
+      q.rp = std::sqrt(S.red[kRedRp2]);
+      q.xn = std::sqrt(S.red[kRedX2]);
+      q.zn = std::sqrt(S.red[kRedZ2]);
+      q.un = std::sqrt(S.red[kRedU2]);
+      q.rd = std::sqrt(S.red[kRedRd2]);
+      const double rhou = q.rho * q.un;
+      q.rkkt = kkt_from(q.rp, q.rd, q.xn, q.zn, rhou, n);
+      if (!std::isfinite(q.rkkt) || (S.breakdown && !std::isfinite(S.pq))) {
+        q.status = GENIOS_ERR_NUMERIC;
+        q.done = 1;
+        any_numeric = 1;
+        continue;
+      }
+      q.rk_hist.push_back(q.rkkt);
+      if (o->history && k <= o->history_cap) {
+        double* row = o->history + ((int64_t)b * o->history_cap + (k - 1)) * GENIOS_HIST_FIELDS;
+        row[GENIOS_HIST_K] = k;
+        row[GENIOS_HIST_RP] = q.rp;
+        row[GENIOS_HIST_RD] = q.rd;
+        row[GENIOS_HIST_RKKT] = q.rkkt;
+        row[GENIOS_HIST_RHO] = q.rho;
+        row[GENIOS_HIST_CG] = S.cg_iters;
+        row[GENIOS_HIST_RTOL] = hp[b].rtol;
+        row[GENIOS_HIST_PHASE] = phase;
+        row[GENIOS_HIST_TIME] = now_s() - t0;
+        row[GENIOS_HIST_XNORM] = q.xn;
+      }
+      const bool conv = paper_test(q.rp, q.rd, q.xn, q.zn, rhou, n, eps_abs, eps_rel);
+      if (phase == 0 && prec == GENIOS_PREC_BF16_REFINE) {
+        bool ready = q.rkkt <= switch_tol;
+        const int W = std::max(1, o->stall_window);
+        const size_t L = q.rk_hist.size();
+        if (!ready && (int)L > W) {
+          const double old = q.rk_hist[L - 1 - W];
+          if (q.rkkt > 0.9 * old) ready = true;  // < 10% decrease over the window
+        }
+        if (!ready) all_ready_to_switch = false;
+      } else if (conv) {
+        want_cert[b] = 1;
+        any_certify = true;
+      }
+      // penalty update (Sec. 2.5)
+      if (o->rho_update_every > 0 && k % o->rho_update_every == 0 && k <= o->rho_update_until) {
+        double nr = q.rho;
+        if (q.rp > o->mu * q.rd)
+          nr = o->tau * q.rho;
+        else if (q.rd > o->mu * q.rp)
+          nr = q.rho / o->tau;
+        if (nr != q.rho) {
+          q.u_scale = q.rho / nr;
+          q.rho = nr;
+        }
+      }
+      q.rp_prev = q.rp;
+      q.rd_prev = q.rd;
+    }
+    // BF16 -> FP32 switch (whole batch at once)
+    if (all_ready_to_switch) {
+      phase = 1;
+      op = &c.op_hi;
+      for (int64_t b = 0; b < B; ++b)
+        if (!P[b].done) {
+          P[b].switch_iter = k + 1;
+          P[b].rk_hist.clear();
+        }
+      // refresh H x (and the logistic gradient) with the FP32 operator
+      set_params(k, false);
+      HC(upload_params(c, hp));
+      if (logistic) {
+        rc = gradient_pass(*op, c.gate_run, c.gs_params);
+      } else {
+        rc = hvp_explicit(c, *op, x, h, nullptr, c.gate_run, c.gs_params);
+      }
+      if (rc) return rc;
+      continue;
+    }
+    // Certification with the operator of the phase (explicit products, no recursion).
+    if (any_certify) {
+      for (int64_t b = 0; b < B; ++b) hp[b].run = want_cert[b];
+      HC(upload_params(c, hp));
+      if (!logistic) {
+        rc = hvp_explicit(c, *op, x, h, nullptr, c.gate_run, c.gs_params);
+        if (rc) return rc;
+        VecArgs vr = c.vargs(x, z, u, h, g, phase == 0 ? c_lo : c_hi, nullptr);
+        HC(launch_dual_residual(vr, c.st));
+        rc = sync_state(c, hs);
+        if (rc) return rc;
+      }
+      for (int64_t b = 0; b < B; ++b) {
+        if (!want_cert[b]) continue;
+        HostProb& q = P[b];
+        if (!logistic) q.rd = std::sqrt(hs[b].red[kRedRd2]);
+        // the certifying residuals use the rho of the finished iteration
+        const double rho_it = hp[b].rho;
+        const double rhou = rho_it * q.un;
+        q.rkkt = kkt_from(q.rp, q.rd, q.xn, q.zn, rhou, n);
+        if (paper_test(q.rp, q.rd, q.xn, q.zn, rhou, n, eps_abs, eps_rel)) {
+          q.done = 1;
+          q.t_target = now_s() - t0;
+          q.status = GENIOS_OK;
+          // undo a penalty change decided in this iteration (u was not rescaled yet)
+          q.rho = rho_it;
+          q.u_scale = 1.0;
+          --active;
+        }
+      }
+    }
+    active = 0;
+    for (int64_t b = 0; b < B; ++b)
+      if (!P[b].done) ++active;
+  }
+  const double t_solve = now_s() - t_loop0;
+  for (int64_t b = 0; b < B; ++b)
+    if (!P[b].done) P[b].status = GENIOS_MAX_ITER;
+  // pending u rescale (penalty changed in the last iteration without a following one)
+  {
+    bool pend = false;
+    for (int64_t b = 0; b < B; ++b)
+      if (P[b].u_scale != 1.0) pend = true;
+    if (pend) {
+      for (int64_t b = 0; b < B; ++b) {
+        // apply by running nothing but the scale: re-use admm_begin would also overwrite r;
+        // instead report the state consistently with rho before the change.
+        P[b].rho = P[b].rho * P[b].u_scale;
+        P[b].u_scale = 1.0;
+      }
+    }
+  }
+
+  // ---- final report with the master-copy operator ----
+  set_params(k, true);
+  HC(upload_params(c, hp));
+  if (logistic) {
+    rc = gradient_pass(c.op_hi, nullptr, 0);
+    if (rc) return rc;
+  } else {
+    rc = hvp_explicit(c, c.op_hi, x, h, nullptr, nullptr, 0);
+    if (rc) return rc;
+  }
+  {
+    VecArgs vr = c.vargs(x, z, u, h, g, c_hi, nullptr);
+    HC(launch_dual_residual(vr, c.st));
+  }
+  // objective at z
+  rc = c.gemv_n(c.op_hi, z, nullptr, 0);
+  if (rc) return rc;
+  HC(launch_objective_m(c.vt, m, B, c.L.tparts, c.nsplit_for(c.op_hi, 0), m,
+                        (int64_t)c.L.nsplit_n * m, bvec, logistic ? 1 : 0, c.L.ctrl, c.st));
+  rc = sync_state(c, hs);
+  if (rc) return rc;
+  const double t_total = now_s() - t0;
+  int worst = GENIOS_OK;
+  for (int64_t b = 0; b < B; ++b) {
+    HostProb& q = P[b];
+    genios_info& I = info[b];
+    std::memset(&I, 0, sizeof(I));
+    int st = q.status;
+    if (st == GENIOS_OK && s > 0 && core_status[b] == GENIOS_WARN_PRECOND) st = GENIOS_WARN_PRECOND;
+    I.status = st;
+    I.iters = q.iters;
+    I.cg_iters = q.cg_total;
+    I.phase_switch_iter = q.switch_iter;
+    I.resketches = q.resketches;
+    I.precond_rank = 0;
+    I.rho = q.rho;
+    I.r_p = q.rp;
+    I.r_d = std::sqrt(hs[b].red[kRedRd2]);
+    I.r_kkt = kkt_from(I.r_p, I.r_d, q.xn, q.zn, q.rho * q.un, n);
+    I.obj = hs[b].red[kRedAux] + q.lambda * hs[b].red[kRedZ1];
+    I.t_setup = t_setup;
+    I.t_precond = t_precond;
+    I.t_solve = t_solve;
+    I.t_linsys = t_linsys;
+    I.t_prox = t_prox;
+    I.t_total = t_total;
+    I.t_to_target = q.t_target;
+    I.t_matvec_n = c.prof.t[0];
+    I.t_matvec_t = c.prof.t[1];
+    I.n_matvec_n = (int32_t)c.n_mv[0];
+    I.n_matvec_t = (int32_t)c.n_mv[1];
+    I.bytes_matvec_lo = c.bytes_lo;
+    I.bytes_matvec_hi = c.bytes_hi;
+    if (st < 0 && (worst >= 0 || st < worst)) worst = st;
+    if (worst >= 0 && st > worst) worst = st;
+  }
+  if (s > 0) {
+    std::vector<int32_t> se(B);
+    HC(hipMemcpyAsync(se.data(), c.L.ctrl.s_eff, B * sizeof(int32_t), hipMemcpyDeviceToHost,
+                      c.st));
+    HC(hipStreamSynchronize(c.st));
+    for (int64_t b = 0; b < B; ++b) info[b].precond_rank = se[b];
+  }
+  (void)any_numeric;
+  (void)sketch_checked;
+  return worst;
+}
+
+int effective_rank(const genios_opts* o, int64_t n, int64_t m) {
+  int s = o->sketch_rank;
+  if (s <= 0) s = (int)std::min<int64_t>(50, n / 20);
+  s = (int)std::min<int64_t>(s, std::min<int64_t>(n, kMaxS));
+  (void)m;
+  return std::max(0, s);
+}
+
+// ---------------------------------------------------------------------------------
+
+int run_nystrom_build(const genios_matrix* A, const void* d, int s, const void* omega,
+                      const genios_opts* o, void* U, double* lamhat, genios_info* info) {
+  Ctx c;
+  c.st = static_cast<hipStream_t>(o->stream);
+  c.B = A->batch;
+  c.m = A->m;
+  c.n = A->n;
+  c.vt = A->hi_dtype == GENIOS_DT_F64 ? VT_F64 : VT_F32;
+  c.L.setup(GENIOS_OP_NYSTROM, A, o, s);
+  int rc = c.L.bind(o->workspace, o->workspace_bytes);
+  if (rc) return rc;
+  const bool use_lo = o->precision == GENIOS_PREC_BF16_REFINE || o->precision == GENIOS_PREC_BF16_ONLY;
+  MatArg op{A->A_hi, c.vt == VT_F64 ? MT_F64 : MT_F32, A->m, A->n, A->lda, A->stride_A};
+  if (use_lo) {
+    if (A->A_bf16 == nullptr)
+      HC(launch_cast_bf16(static_cast<const float*>(A->A_hi), c.L.A16, c.L.a16_elems, c.st));
+    op = MatArg{A->A_bf16 ? (const void*)A->A_bf16 : (const void*)c.L.A16, MT_BF16, A->m, A->n,
+                A->lda, A->stride_A};
+  }
+  HC(launch_fill(c.L.ctrl.params, c.L.ctrl_bytes_end, c.st));
+  HC(run_nystrom(op, c.B, c.vt, d, A->m, s, omega, o->seed, 0, nullptr, c.L.sk, U, lamhat,
+                 c.L.ctrl.s_eff, c.L.core_status, c.L.shift, c.st));
+  std::vector<int32_t> se(c.B), cs(c.B);
+  HC(hipMemcpyAsync(se.data(), c.L.ctrl.s_eff, c.B * 4, hipMemcpyDeviceToHost, c.st));
+  HC(hipMemcpyAsync(cs.data(), c.L.core_status, c.B * 4, hipMemcpyDeviceToHost, c.st));
+  HC(hipStreamSynchronize(c.st));
+  int worst = 0;
+  for (int64_t b = 0; b < c.B; ++b) {
+    if (info) {
+      std::memset(&info[b], 0, sizeof(genios_info));
+      info[b].status = cs[b];
+      info[b].precond_rank = se[b];
+      info[b].resketches = 1;
+    }
+    worst = std::max(worst, cs[b]);
+  }
+  return worst;
+}
+
+int run_matvec(const genios_matrix* A, int trans, int use_bf16, const void* v, void* out,
+               const genios_opts* o) {
+  Ctx c;
+  c.st = static_cast<hipStream_t>(o->stream);
+  c.B = A->batch;
+  c.m = A->m;
+  c.n = A->n;
+  c.vt = A->hi_dtype == GENIOS_DT_F64 ? VT_F64 : VT_F32;
+  c.ve = c.vt == VT_F32 ? 4 : 8;
+  genios_opts oo = *o;
+  oo.precision = use_bf16 ? GENIOS_PREC_BF16_ONLY : GENIOS_PREC_F32;
+  genios_matrix AA = *A;
+  c.L.setup(GENIOS_OP_MATVEC, &AA, &oo, 0);
+  int rc = c.L.bind(o->workspace, o->workspace_bytes);
+  if (rc) return rc;
+  MatArg op = use_bf16 ? MatArg{A->A_bf16, MT_BF16, A->m, A->n, A->lda, A->stride_A}
+                       : MatArg{A->A_hi, c.vt == VT_F64 ? MT_F64 : MT_F32, A->m, A->n, A->lda,
+                                A->stride_A};
+  if (!trans) {
+    const int ns = std::min(c.L.nsplit_n, gemv_n_splits(op, c.B));
+    HC(launch_gemv_n(op, c.B, c.vt, v, c.n, c.L.tparts, c.m, (int64_t)c.L.nsplit_n * c.m, ns,
+                     nullptr, 0, c.st));
+    HC(launch_sum_splits(c.vt, c.B, c.m, c.L.tparts, ns, c.m, (int64_t)c.L.nsplit_n * c.m, out,
+                         c.m, c.st));
+  } else {
+    const int ks = std::min(c.L.ksplit, gemv_t_splits(op, c.B));
+    HC(launch_gemv_t(op, c.B, c.vt, v, 1, 0, c.m, 0, 1, nullptr, 0, c.L.ypart, ks, c.L.npad,
+                     c.L.npad, (int64_t)c.L.ksplit * c.L.npad, nullptr, 0, c.st));
+    HC(launch_sum_splits(c.vt, c.B, c.n, c.L.ypart, ks, c.L.npad, (int64_t)c.L.ksplit * c.L.npad,
+                         out, c.n, c.st));
+  }
+  HC(hipStreamSynchronize(c.st));
+  return 0;
+}
+
+// ---------------------------------------------------------------------------------
+// Adjoint: solve (P_S A^T A P_S + (I - P_S)) w = P_S g by masked Nystrom PCG.
+
+int run_backward(const genios_matrix* A, const void* zstar, const void* gz, const genios_opts* o,
+                 void* grad_b, double* grad_lambda, genios_info* info) {
+  const double t0 = now_s();
+  Ctx c;
+  c.A = A;
+  c.o = o;
+  c.st = static_cast<hipStream_t>(o->stream);
+  c.B = A->batch;
+  c.m = A->m;
+  c.n = A->n;
+  c.vt = A->hi_dtype == GENIOS_DT_F64 ? VT_F64 : VT_F32;
+  c.ve = c.vt == VT_F32 ? 4 : 8;
+  const int s = o->precondition ? effective_rank(o, A->n, A->m) : 0;
+  c.L.setup(GENIOS_OP_BACKWARD, A, o, s);
+  int rc = c.L.bind(o->workspace, o->workspace_bytes);
+  if (rc) return rc;
+  c.prof.on = o->profile_kernels != 0;
+  c.op_hi = MatArg{A->A_hi, c.vt == VT_F64 ? MT_F64 : MT_F32, A->m, A->n, A->lda, A->stride_A};
+  c.gate_cg = &c.L.ctrl.state[0].cg_active;
+  const int64_t B = c.B, n = c.n, m = c.m;
+  HC(launch_fill(c.L.ctrl.params, c.L.ctrl_bytes_end, c.st));
+  void* w = c.L.nv[kVX];
+  void* zero_z = c.L.nv[kVZ];
+  void* zero_u = c.L.nv[kVU];
+  void* h = c.L.nv[kVH];
+  void* ng = c.L.nv[kVG];
+  void* sgn = c.L.nv[kVCH];
+  HC(launch_fill(w, B * n * c.ve, c.st));
+  HC(launch_fill(zero_z, B * n * c.ve, c.st));
+  HC(launch_fill(zero_u, B * n * c.ve, c.st));
+  HC(launch_fill(h, B * n * c.ve, c.st));
+  HC(launch_build_mask(c.vt, n, B, zstar, gz, c.L.mask, sgn, ng, c.st));
+  if (s > 0) {
+    HC(run_nystrom(c.op_hi, B, c.vt, nullptr, m, s, nullptr, o->seed, 0, c.L.mask, c.L.sk, c.L.U,
+                   c.L.ctrl.lamhat, c.L.ctrl.s_eff, c.L.core_status, c.L.shift, c.st));
+  }
+  ProbParams* hp = static_cast<ProbParams*>(pinned(B * (sizeof(ProbParams) + sizeof(ProbState))));
+  if (!hp) return GENIOS_ERR_DEVICE;
+  ProbState* hs = reinterpret_cast<ProbState*>(hp + B);
+  for (int64_t b = 0; b < B; ++b) {
+    ProbParams& q = hp[b];
+    std::memset(&q, 0, sizeof(q));
+    q.run = 1;
+    q.rho = 1.0;
+    q.sigma = 0.0;
+    q.nu = 0.0;
+    q.kappa = 0.0;
+    q.alpha = 1.0;
+    q.u_scale = 1.0;
+    q.rtol = o->cg_tol_floor;
+    q.tol_floor = o->cg_tol_floor;
+    q.max_cg = std::max(o->max_cg_iter, 1);
+    q.rhs_rel = 1;
+    q.use_c = 0;
+  }
+  HC(upload_params(c, hp));
+  VecArgs va = c.vargs(w, zero_z, zero_u, h, ng, nullptr, c.L.mask);
+  HC(launch_admm_begin(va, c.st));
+  HC(launch_precond_step(va, 1, c.st));
+  int total_cg = 0;
+  int chunk = 8;
+  for (;;) {
+    for (int it = 0; it < chunk; ++it) {
+      rc = cg_iteration(c, c.op_hi, va, nullptr);
+      if (rc) return rc;
+    }
+    rc = sync_state(c, hs);
+    if (rc) return rc;
+    bool more = false;
+    for (int64_t b = 0; b < B; ++b)
+      if (hs[b].cg_active) more = true;
+    if (!more) break;
+  }
+  // grad_b = A (P_S w); grad_lambda = -s^T w
+  rc = c.gemv_n(c.op_hi, w, nullptr, 0);
+  if (rc) return rc;
+  HC(launch_sum_splits(c.vt, B, m, c.L.tparts, c.nsplit_for(c.op_hi, 0), m,
+                       (int64_t)c.L.nsplit_n * m, grad_b, m, c.st));
+  HC(launch_masked_dot(c.vt, n, B, sgn, w, c.L.ctrl.part, c.L.ctrl.part_stride, c.L.ctrl.counters,
+                       c.L.scal, c.st));
+  std::vector<double> gl(B);
+  std::vector<int32_t> se(B, 0);
+  HC(hipMemcpyAsync(gl.data(), c.L.scal, B * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  if (s > 0) HC(hipMemcpyAsync(se.data(), c.L.ctrl.s_eff, B * 4, hipMemcpyDeviceToHost, c.st));
+  HC(hipStreamSynchronize(c.st));
+  int worst = 0;
+  for (int64_t b = 0; b < B; ++b) {
+    grad_lambda[b] = -gl[b];
+    total_cg = hs[b].cg_iters;
+    int st = 0;
+    if (hs[b].breakdown && !(hs[b].rr <= 1e300)) st = GENIOS_ERR_NUMERIC;
+    else if (hs[b].rr > hs[b].tol2) st = GENIOS_MAX_ITER;
+    if (info) {
+      std::memset(&info[b], 0, sizeof(genios_info));
+      info[b].status = st;
+      info[b].cg_iters = total_cg;
+      info[b].precond_rank = se[b];
+      info[b].r_d = std::sqrt(hs[b].rr);
+      info[b].t_total = now_s() - t0;
+      info[b].t_matvec_n = c.prof.t[0];
+      info[b].t_matvec_t = c.prof.t[1];
+      info[b].n_matvec_n = (int32_t)c.n_mv[0];
+      info[b].n_matvec_t = (int32_t)c.n_mv[1];
+      info[b].bytes_matvec_hi = c.bytes_hi;
+    }
+    if (st < 0 && (worst >= 0 || st < worst)) worst = st;
+    if (worst >= 0 && st > worst) worst = st;
+  }
+  return worst;
+}
+
+}  // namespace genios

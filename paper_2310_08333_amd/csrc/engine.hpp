@@ -1,0 +1,72 @@
+// Host engine interface: workspace layout and the drivers behind the C ABI.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "genios.h"
+#include "internal.hpp"
+
+namespace genios {
+
+// Internal n-vector slots of the workspace.
+enum {
+  kVH = 0,   // h = H x (tracked through CG)
+  kVG,       // gradient of the smooth part (logistic) / -rhs (adjoint)
+  kVCH,      // c = A^T b with the master copy (adjoint: signs of z*)
+  kVCL,      // c = A^T b with the BF16 copy
+  kVR,       // CG residual
+  kVP,       // CG direction
+  kVHP,      // H p
+  kVW,       // preconditioned residual
+  kVX,       // adjoint solution
+  kVZ,       // adjoint zero vector
+  kVU,       // adjoint zero vector
+  kNumNVec
+};
+
+struct Arena;
+
+struct Layout {
+  int op = 0;
+  int64_t m = 0, n = 0, batch = 1;
+  VType vt = VT_F32;
+  bool logistic = false, backward = false;
+  int s = 0;
+  bool need_a16 = false;
+  int64_t a16_elems = 0;
+  int nsplit_n = 1, nrhs = 1, ksplit = 1;
+  int64_t npad = 0, chunk = 256;
+  int nb = 1, part_blocks = 1, n_vecs = 0;
+  SketchWs sk{};
+  Ctrl ctrl{};
+  size_t ctrl_bytes_end = 0;
+  int32_t* core_status = nullptr;
+  double* shift = nullptr;
+  double* scal = nullptr;
+  uint16_t* A16 = nullptr;
+  void* nv[kNumNVec] = {};
+  void* tparts = nullptr;
+  void* ypart = nullptr;
+  void* dvec = nullptr;
+  void* cols = nullptr;
+  uint8_t* mask = nullptr;
+  void* U = nullptr;
+  size_t total = 0;
+
+  int setup(int op, const genios_matrix* A, const genios_opts* o, int s);
+  int bind(void* base, size_t bytes);
+  void carve(Arena& ar);
+};
+
+int effective_rank(const genios_opts* o, int64_t n, int64_t m);
+int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, double rho0,
+             const genios_opts* o, void* x, void* z, void* u, genios_info* info, bool logistic);
+int run_nystrom_build(const genios_matrix* A, const void* d, int s, const void* omega,
+                      const genios_opts* o, void* U, double* lamhat, genios_info* info);
+int run_matvec(const genios_matrix* A, int trans, int use_bf16, const void* v, void* out,
+               const genios_opts* o);
+int run_backward(const genios_matrix* A, const void* zstar, const void* gz, const genios_opts* o,
+                 void* grad_b, double* grad_lambda, genios_info* info);
+
+}  // namespace genios

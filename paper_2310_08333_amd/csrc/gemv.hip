@@ -1,0 +1,431 @@
+// Dense matrix-vector products for the Hessian-vector product of the CG loop.
+//
+// The x-subproblem operator is applied as two matrix-vector products,
+// H v = A^T (D (A v)) (Sec. 3.1 HVP example, Sec. 3.3 ML Hessian), both
+// HBM-bandwidth bound: every element of A is read once per product.
+//
+//   gemv_n   t = A v         one wavefront owns ROWS rows of a column split;
+//                            lanes stride the row with 16-byte loads, the
+//                            partial sums are reduced with cross-lane shuffles.
+//   gemv_t   y = A^T (d o t) one thread owns V consecutive columns (16 bytes of
+//                            each row), a block covers 256*V columns and a row
+//                            split; the split's t values (optionally scaled by
+//                            d and summed over gemv_n's column splits) are
+//                            staged in LDS; results are written as per-split
+//                            partials reduced later in a fixed order.
+// No floating-point atomics: results are bitwise reproducible.
+#include <algorithm>
+
+#include "device.hpp"
+
+namespace genios {
+
+namespace {
+
+constexpr int kGemvNRows = 4;  // rows per wavefront in gemv_n
+constexpr int kMaxRowsPerSplit = 1024;
+
+template <typename T, typename VT, int ROWS, bool VEC>
+__global__ __launch_bounds__(256) void k_gemv_n(const T* __restrict__ A, int64_t lda,
+                                                int64_t strideA, int m, int n,
+                                                const VT* __restrict__ v, int64_t v_stride,
+                                                VT* __restrict__ out, int64_t out_split_stride,
+                                                int64_t out_prob_stride, int cols_per_split,
+                                                const int32_t* __restrict__ gate, int gate_stride) {
+  using Acc = typename Elem<T>::Acc;
+  constexpr int V = Elem<T>::V;
+  const int b = blockIdx.z;
+  if (gate != nullptr && gate[(int64_t)b * gate_stride] == 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row0 = (blockIdx.x * 4 + wave) * ROWS;
+  if (row0 >= m) return;
+  const int split = blockIdx.y;
+  const int c0 = split * cols_per_split;
+  const int c1 = min(n, c0 + cols_per_split);
+  const T* Ab = A + (int64_t)b * strideA;
+  const VT* vb = v + (int64_t)b * v_stride;
+  const T* rowp[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) rowp[r] = Ab + (int64_t)min(row0 + r, m - 1) * lda;
+  Acc acc[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) acc[r] = Acc(0);
+  if constexpr (VEC) {
+    int c = c0 + lane * V;
+#pragma unroll 2
+    for (; c + V <= c1; c += 64 * V) {
+      Acc vv[V];
+      load_vec<VT, Acc, V>(vb + c, vv);
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) {
+        Acc av[V];
+        Elem<T>::load(rowp[r] + c, av);
+#pragma unroll
+        for (int j = 0; j < V; ++j) acc[r] += av[j] * vv[j];
+      }
+    }
+    for (int cc = c; cc < c1 && cc < c + V; ++cc) {
+      const Acc vv = Acc(vb[cc]);
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) acc[r] += Elem<T>::cvt(rowp[r][cc]) * vv;
+    }
+  } else {
+    for (int cc = c0 + lane; cc < c1; cc += 64) {
+      const Acc vv = Acc(vb[cc]);
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) acc[r] += Elem<T>::cvt(rowp[r][cc]) * vv;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) acc[r] = wave_sum(acc[r]);
+  if (lane < ROWS && row0 + lane < m) {
+    Acc mine = acc[0];
+#pragma unroll
+    for (int r = 1; r < ROWS; ++r)
+      if (lane == r) mine = acc[r];
+    out[(int64_t)b * out_prob_stride + (int64_t)split * out_split_stride + row0 + lane] = VT(mine);
+  }
+}
+
+template <typename T, typename VT, int NR, bool VEC>
+__global__ __launch_bounds__(256) void k_gemv_t(
+    const T* __restrict__ A, int64_t lda, int64_t strideA, int m, int n,
+    const VT* __restrict__ tin, int nsplit_in, int64_t tin_split_stride, int64_t tin_prob_stride,
+    int64_t tin_col_stride, const VT* __restrict__ dscale, int64_t d_stride,
+    VT* __restrict__ ypart, int64_t ypart_ks_stride, int64_t ypart_col_stride,
+    int64_t ypart_prob_stride, int rows_per_split, const int32_t* __restrict__ gate,
+    int gate_stride) {
+  using Acc = typename Elem<T>::Acc;
+  constexpr int V = VEC ? Elem<T>::V : 1;
+  __shared__ Acc ts[NR][kMaxRowsPerSplit];
+  const int b = blockIdx.z;
+  if (gate != nullptr && gate[(int64_t)b * gate_stride] == 0) return;
+  const int ks = blockIdx.y;
+  const int r0 = ks * rows_per_split;
+  const int r1 = min(m, r0 + rows_per_split);
+  const int nr = r1 - r0;
+  const VT* tb = tin + (int64_t)b * tin_prob_stride;
+  for (int i = threadIdx.x; i < nr; i += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      Acc s = Acc(0);
+      for (int sp = 0; sp < nsplit_in; ++sp)
+        s += Acc(tb[(int64_t)k * tin_col_stride + (int64_t)sp * tin_split_stride + r0 + i]);
+      if (dscale != nullptr) s *= Acc(dscale[(int64_t)b * d_stride + r0 + i]);
+      ts[k][i] = s;
+    }
+  }
+  __syncthreads();
+  const int c = (blockIdx.x * blockDim.x + threadIdx.x) * V;
+  if (c >= n) return;
+  const T* Ab = A + (int64_t)b * strideA + (int64_t)r0 * lda;
+  VT* yb = ypart + (int64_t)b * ypart_prob_stride + (int64_t)ks * ypart_ks_stride;
+  Acc acc[NR][V];
+#pragma unroll
+  for (int k = 0; k < NR; ++k)
+#pragma unroll
+    for (int j = 0; j < V; ++j) acc[k][j] = Acc(0);
+  if (VEC && c + V <= n) {
+    int i = 0;
+    for (; i + 4 <= nr; i += 4) {
+      Acc av[4][V];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if constexpr (VEC) {
+          Elem<T>::load(Ab + (int64_t)(i + u) * lda + c, av[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          const Acc t = ts[k][i + u];
+#pragma unroll
+          for (int j = 0; j < V; ++j) acc[k][j] += av[u][j] * t;
+        }
+    }
+    for (; i < nr; ++i) {
+      Acc av[V];
+      if constexpr (VEC) {
+        Elem<T>::load(Ab + (int64_t)i * lda + c, av);
+      }
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const Acc t = ts[k][i];
+#pragma unroll
+        for (int j = 0; j < V; ++j) acc[k][j] += av[j] * t;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+#pragma unroll
+      for (int j = 0; j < V; ++j) yb[(int64_t)k * ypart_col_stride + c + j] = VT(acc[k][j]);
+  } else {
+    const int ce = min(n, c + V);
+    for (int i = 0; i < nr; ++i) {
+      for (int cc = c; cc < ce; ++cc) {
+        const Acc a = Elem<T>::cvt(Ab[(int64_t)i * lda + cc]);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k][cc - c] += a * ts[k][i];
+      }
+    }
+    for (int cc = c; cc < ce; ++cc)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) yb[(int64_t)k * ypart_col_stride + cc] = VT(acc[k][cc - c]);
+  }
+}
+
+int elem_v(MType mt) { return mt == MT_BF16 ? 8 : (mt == MT_F32 ? 4 : 2); }
+int elem_bytes(MType mt) { return mt == MT_BF16 ? 2 : (mt == MT_F32 ? 4 : 8); }
+
+bool vec_ok(const MatArg& A, VType vt, const void* v) {
+  const int V = elem_v(A.mt);
+  const uintptr_t pa = reinterpret_cast<uintptr_t>(A.ptr);
+  if (pa % 16 != 0) return false;
+  if (A.lda % V != 0) return false;
+  if (A.strideA % V != 0) return false;
+  (void)vt;
+  (void)v;
+  return true;
+}
+
+}  // namespace
+
+int gemv_n_splits(const MatArg& A, int64_t batch) {
+  const int64_t rb = (A.m + 4 * kGemvNRows - 1) / (4 * kGemvNRows);
+  const int V = elem_v(A.mt);
+  const int64_t want = (2048 + rb * batch - 1) / (rb * batch);
+  const int64_t maxs = std::max<int64_t>(1, A.n / (64 * V * 8));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(want, std::min<int64_t>(maxs, 64)));
+}
+
+int gemv_t_splits(const MatArg& A, int64_t batch) {
+  const int V = elem_v(A.mt);
+  const int64_t cb = (A.n + 256 * V - 1) / (256 * V);
+  int64_t ks = (2048 + cb * batch - 1) / (cb * batch);
+  // keep the partial traffic at <= ~2% of the matrix traffic
+  const int64_t cap = std::max<int64_t>(1, (A.m * elem_bytes(A.mt)) / (50 * 4));
+  ks = std::min(ks, cap);
+  ks = std::min<int64_t>(ks, (A.m + 31) / 32);
+  ks = std::max<int64_t>(ks, (A.m + kMaxRowsPerSplit - 1) / kMaxRowsPerSplit);
+  return (int)std::max<int64_t>(1, ks);
+}
+
+int gemv_t_rows_per_split(const MatArg& A, int ksplit) {
+  return (int)((A.m + ksplit - 1) / ksplit);
+}
+
+template <typename T, typename VT>
+static hipError_t gemv_n_t(const MatArg& A, int64_t batch, const VT* v, int64_t v_stride, VT* out,
+                           int64_t oss, int64_t ops, int nsplit, const int32_t* gate, int gs,
+                           hipStream_t st) {
+  constexpr int V = Elem<T>::V;
+  const int64_t rb = (A.m + 4 * kGemvNRows - 1) / (4 * kGemvNRows);
+  int cps = (int)((A.n + nsplit - 1) / nsplit);
+  cps = ((cps + V - 1) / V) * V;
+  dim3 grid((unsigned)rb, (unsigned)nsplit, (unsigned)batch);
+  const bool vec = vec_ok(A, VT_F32, v) && (reinterpret_cast<uintptr_t>(v) % 16 == 0) &&
+                   (v_stride % V == 0);
+  const T* Ap = static_cast<const T*>(A.ptr);
+  if (vec)
+    hipLaunchKernelGGL((k_gemv_n<T, VT, kGemvNRows, true>), grid, dim3(256), 0, st, Ap, A.lda,
+                       A.strideA, (int)A.m, (int)A.n, v, v_stride, out, oss, ops, cps, gate, gs);
+  else
+    hipLaunchKernelGGL((k_gemv_n<T, VT, kGemvNRows, false>), grid, dim3(256), 0, st, Ap, A.lda,
+                       A.strideA, (int)A.m, (int)A.n, v, v_stride, out, oss, ops, cps, gate, gs);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_n(const MatArg& A, int64_t batch, VType vt, const void* v, int64_t v_stride,
+                         void* out, int64_t oss, int64_t ops, int nsplit, const int32_t* gate,
+                         int gs, hipStream_t st) {
+  if (vt == VT_F32) {
+    const float* vv = static_cast<const float*>(v);
+    float* o = static_cast<float*>(out);
+    if (A.mt == MT_BF16)
+      return gemv_n_t<uint16_t, float>(A, batch, vv, v_stride, o, oss, ops, nsplit, gate, gs, st);
+    if (A.mt == MT_F32)
+      return gemv_n_t<float, float>(A, batch, vv, v_stride, o, oss, ops, nsplit, gate, gs, st);
+    return hipErrorInvalidValue;
+  }
+  if (A.mt != MT_F64) return hipErrorInvalidValue;
+  return gemv_n_t<double, double>(A, batch, static_cast<const double*>(v), v_stride,
+                                  static_cast<double*>(out), oss, ops, nsplit, gate, gs, st);
+}
+
+template <typename T, typename VT, int NR>
+static hipError_t gemv_t_t(const MatArg& A, int64_t batch, const VT* tin, int nsplit_in,
+                           int64_t tss, int64_t tps, int64_t tcs, const VT* d, int64_t ds,
+                           VT* yp, int ksplit, int64_t yks, int64_t ycs, int64_t yps,
+                           const int32_t* gate, int gs, hipStream_t st) {
+  constexpr int V = Elem<T>::V;
+  const int rps = gemv_t_rows_per_split(A, ksplit);
+  if (rps > kMaxRowsPerSplit) return hipErrorInvalidValue;
+  const bool vec = vec_ok(A, VT_F32, nullptr) && (reinterpret_cast<uintptr_t>(yp) % 16 == 0) &&
+                   (yks % V == 0) && (ycs % V == 0) && (yps % V == 0);
+  const T* Ap = static_cast<const T*>(A.ptr);
+  if (vec) {
+    dim3 grid((unsigned)((A.n + 256 * V - 1) / (256 * V)), (unsigned)ksplit, (unsigned)batch);
+    hipLaunchKernelGGL((k_gemv_t<T, VT, NR, true>), grid, dim3(256), 0, st, Ap, A.lda, A.strideA,
+                       (int)A.m, (int)A.n, tin, nsplit_in, tss, tps, tcs, d, ds, yp, yks, ycs, yps,
+                       rps, gate, gs);
+  } else {
+    dim3 grid((unsigned)((A.n + 255) / 256), (unsigned)ksplit, (unsigned)batch);
+    hipLaunchKernelGGL((k_gemv_t<T, VT, NR, false>), grid, dim3(256), 0, st, Ap, A.lda,
+                       A.strideA, (int)A.m, (int)A.n, tin, nsplit_in, tss, tps, tcs, d, ds, yp,
+                       yks, ycs, yps, rps, gate, gs);
+  }
+  return hipGetLastError();
+}
+
+template <typename VT>
+static hipError_t gemv_t_vt(const MatArg& A, int64_t batch, const VT* tin, int nsplit_in,
+                            int64_t tss, int64_t tps, int64_t tcs, int nrhs, const VT* d,
+                            int64_t ds, VT* yp, int ksplit, int64_t yks, int64_t ycs, int64_t yps,
+                            const int32_t* gate, int gs, hipStream_t st) {
+  if constexpr (sizeof(VT) == 4) {
+    if (A.mt == MT_BF16) {
+      if (nrhs == 1)
+        return gemv_t_t<uint16_t, VT, 1>(A, batch, tin, nsplit_in, tss, tps, tcs, d, ds, yp,
+                                         ksplit, yks, ycs, yps, gate, gs, st);
+      return gemv_t_t<uint16_t, VT, 2>(A, batch, tin, nsplit_in, tss, tps, tcs, d, ds, yp, ksplit,
+                                       yks, ycs, yps, gate, gs, st);
+    }
+    if (A.mt == MT_F32) {
+      if (nrhs == 1)
+        return gemv_t_t<float, VT, 1>(A, batch, tin, nsplit_in, tss, tps, tcs, d, ds, yp, ksplit,
+                                      yks, ycs, yps, gate, gs, st);
+      return gemv_t_t<float, VT, 2>(A, batch, tin, nsplit_in, tss, tps, tcs, d, ds, yp, ksplit,
+                                    yks, ycs, yps, gate, gs, st);
+    }
+    return hipErrorInvalidValue;
+  } else {
+    if (A.mt != MT_F64) return hipErrorInvalidValue;
+    if (nrhs == 1)
+      return gemv_t_t<double, VT, 1>(A, batch, tin, nsplit_in, tss, tps, tcs, d, ds, yp, ksplit,
+                                     yks, ycs, yps, gate, gs, st);
+    return gemv_t_t<double, VT, 2>(A, batch, tin, nsplit_in, tss, tps, tcs, d, ds, yp, ksplit, yks,
+                                   ycs, yps, gate, gs, st);
+  }
+}
+
+hipError_t launch_gemv_t(const MatArg& A, int64_t batch, VType vt, const void* tin, int nsplit_in,
+                         int64_t tss, int64_t tps, int64_t tcs, int nrhs, const void* d,
+                         int64_t ds, void* yp, int ksplit, int64_t yks, int64_t ycs, int64_t yps,
+                         const int32_t* gate, int gs, hipStream_t st) {
+  if (nrhs < 1 || nrhs > 2) return hipErrorInvalidValue;
+  if (vt == VT_F32)
+    return gemv_t_vt<float>(A, batch, static_cast<const float*>(tin), nsplit_in, tss, tps, tcs,
+                            nrhs, static_cast<const float*>(d), ds, static_cast<float*>(yp),
+                            ksplit, yks, ycs, yps, gate, gs, st);
+  return gemv_t_vt<double>(A, batch, static_cast<const double*>(tin), nsplit_in, tss, tps, tcs,
+                           nrhs, static_cast<const double*>(d), ds, static_cast<double*>(yp),
+                           ksplit, yks, ycs, yps, gate, gs, st);
+}
+
+// ---- small utility kernels ---------------------------------------------------
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_sum_splits(int64_t len, const VT* __restrict__ in,
+                                                    int nsplit, int64_t split_stride,
+                                                    int64_t psi, VT* __restrict__ out,
+                                                    int64_t pso, const int32_t* __restrict__ gate,
+                                                    int gate_stride) {
+  const int b = blockIdx.y;
+  if (gate != nullptr && gate[(int64_t)b * gate_stride] == 0) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    VT s = VT(0);
+    for (int k = 0; k < nsplit; ++k) s += in[(int64_t)b * psi + (int64_t)k * split_stride + i];
+    out[(int64_t)b * pso + i] = s;
+  }
+}
+
+hipError_t launch_sum_splits(VType vt, int64_t batch, int64_t len, const void* in, int nsplit,
+                             int64_t split_stride, int64_t psi, void* out, int64_t pso,
+                             hipStream_t st, const int32_t* gate, int gate_stride) {
+  const unsigned nb = (unsigned)std::min<int64_t>((len + 255) / 256, 1024);
+  dim3 grid(std::max(1u, nb), (unsigned)batch);
+  if (vt == VT_F32)
+    hipLaunchKernelGGL(k_sum_splits<float>, grid, dim3(256), 0, st, len,
+                       static_cast<const float*>(in), nsplit, split_stride, psi,
+                       static_cast<float*>(out), pso, gate, gate_stride);
+  else
+    hipLaunchKernelGGL(k_sum_splits<double>, grid, dim3(256), 0, st, len,
+                       static_cast<const double*>(in), nsplit, split_stride, psi,
+                       static_cast<double*>(out), pso, gate, gate_stride);
+  return hipGetLastError();
+}
+
+// FP32 -> BF16, round to nearest even; NaN -> canonical quiet NaN 0x7FC0.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  const uint32_t x = __float_as_uint(f);
+  if ((x & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;
+  const uint32_t lsb = (x >> 16) & 1u;
+  return static_cast<uint16_t>((x + 0x7fffu + lsb) >> 16);
+}
+
+__global__ __launch_bounds__(256) void k_cast_bf16(const float* __restrict__ src,
+                                                   uint16_t* __restrict__ dst, int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * 8;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8; i < count; i += stride) {
+    if (i + 8 <= count && (reinterpret_cast<uintptr_t>(src + i) % 16 == 0) &&
+        (reinterpret_cast<uintptr_t>(dst + i) % 16 == 0)) {
+      const float4 a = *reinterpret_cast<const float4*>(src + i);
+      const float4 b = *reinterpret_cast<const float4*>(src + i + 4);
+      uint4 o;
+      o.x = f32_to_bf16_rne(a.x) | (uint32_t(f32_to_bf16_rne(a.y)) << 16);
+      o.y = f32_to_bf16_rne(a.z) | (uint32_t(f32_to_bf16_rne(a.w)) << 16);
+      o.z = f32_to_bf16_rne(b.x) | (uint32_t(f32_to_bf16_rne(b.y)) << 16);
+      o.w = f32_to_bf16_rne(b.z) | (uint32_t(f32_to_bf16_rne(b.w)) << 16);
+      *reinterpret_cast<uint4*>(dst + i) = o;
+    } else {
+      for (int64_t k = i; k < count && k < i + 8; ++k) dst[k] = f32_to_bf16_rne(src[k]);
+    }
+  }
+}
+
+hipError_t launch_cast_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int64_t groups = (count + 7) / 8;
+  const unsigned nb = (unsigned)std::min<int64_t>((groups + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_cast_bf16, dim3(nb), dim3(256), 0, st, src, dst, count);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(uint32_t* __restrict__ p, int64_t words) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  if (bytes % 4 != 0 || reinterpret_cast<uintptr_t>(p) % 4 != 0) return hipErrorInvalidValue;
+  const int64_t words = (int64_t)(bytes / 4);
+  const unsigned nb = (unsigned)std::min<int64_t>((words + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_zero, dim3(nb), dim3(256), 0, st, static_cast<uint32_t*>(p), words);
+  return hipGetLastError();
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_copy(const VT* __restrict__ s, VT* __restrict__ d,
+                                              int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+
+hipError_t launch_copy(VType vt, const void* src, void* dst, int64_t count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)std::min<int64_t>((count + 255) / 256, 4096);
+  if (vt == VT_F32)
+    hipLaunchKernelGGL(k_copy<float>, dim3(nb), dim3(256), 0, st, static_cast<const float*>(src),
+                       static_cast<float*>(dst), count);
+  else
+    hipLaunchKernelGGL(k_copy<double>, dim3(nb), dim3(256), 0, st,
+                       static_cast<const double*>(src), static_cast<double*>(dst), count);
+  return hipGetLastError();
+}
+
+}  // namespace genios

@@ -1,0 +1,203 @@
+// Internal declarations shared by the HIP kernels, the host engine and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "genios.h"
+
+namespace genios {
+
+// Vector element type of a call: float when the master copy is FP32, double for FP64.
+enum VType { VT_F32 = 0, VT_F64 = 1 };
+// Element type of the matrix a product reads.
+enum MType { MT_BF16 = 0, MT_F32 = 1, MT_F64 = 2 };
+
+constexpr int kMaxS = 128;            // largest supported sketch rank
+constexpr int kVecBlock = 256;        // threads per block of the vector kernels
+constexpr int kVecChunk = 1024;       // elements per block of the vector kernels
+constexpr int kMaxVecBlocks = 128;    // blocks per problem of the vector kernels
+constexpr int kPartW = kMaxS + 16;    // doubles per block partial (U^T r + scalars)
+constexpr int kNumCounters = 16;      // last-block counters per problem
+
+// Host-written parameters of one problem, uploaded before each ADMM iteration.
+struct alignas(128) ProbParams {
+  double nu;         // CG shift rho + sigma
+  double rho;
+  double sigma;
+  double kappa;      // lambda / rho, the soft-threshold level
+  double alpha;      // over-relaxation
+  double u_scale;    // u <- u * u_scale at the start of the iteration (penalty change)
+  double rtol;       // CG relative tolerance of this iteration
+  double tol_floor;  // CG tolerance floor, relative to ||rhs||
+  double lambda;
+  int32_t run;       // problem takes part in this iteration
+  int32_t max_cg;
+  int32_t rhs_rel;   // 1: tolerance relative to ||rhs||, 0: relative to ||r_0||
+  int32_t use_c;     // 1: gradient is h - c (Lasso); 0: gradient vector given
+};
+
+// Device-written state of one problem (read back by the host after each sync).
+struct alignas(128) ProbState {
+  double rz;         // r^T P^-1 r of the current CG iterate
+  double pq;         // p^T (H + nu I) p
+  double rr;         // ||r||^2
+  double tol2;       // squared absolute CG tolerance
+  double alpha_cg, beta_cg;
+  double rhs2;       // ||rhs||^2
+  double r02;        // ||r_0||^2
+  int32_t cg_active; // CG running for this problem
+  int32_t cg_iters;  // CG iterations in the current x-solve
+  int32_t admm_done; // the fused z/u update ran this iteration
+  int32_t breakdown; // p^T q <= 0 or non-finite
+  double red[8];     // reductions of the fused update (see kRed*)
+};
+
+// Indices into ProbState::red written by the fused ADMM update.
+enum {
+  kRedRp2 = 0,   // ||x - z||^2
+  kRedX2 = 1,    // ||x||^2
+  kRedZ2 = 2,    // ||z||^2
+  kRedU2 = 3,    // ||u||^2 (scaled dual)
+  kRedRd2 = 4,   // ||grad + rho u||^2 (Lasso: grad = h - c)
+  kRedZ1 = 5,    // ||z||_1
+  kRedNnz = 6,   // nonzeros of z
+  kRedAux = 7
+};
+
+// Counter slots for the last-block reductions.
+enum {
+  kCntBegin = 0, kCntPrecond, kCntAlpha, kCntUpdate, kCntEnd, kCntAux0, kCntAux1, kCntAux2,
+  kCntObj, kCntMasked
+};
+
+// Pointers to the per-problem control arrays in the workspace.
+struct Ctrl {
+  ProbParams* params;   // [batch]
+  ProbState* state;     // [batch]
+  double* part;         // [batch][part_stride] block partials (kPartW doubles per block)
+  int64_t part_stride;  // doubles per problem in `part`
+  unsigned* counters;   // [batch][kNumCounters]
+  double* coef;         // [batch][kMaxS] preconditioner coefficients of the current r
+  int32_t* s_eff;       // [batch] retained sketch rank
+  double* lamhat;       // [batch][s] (s = sketch stride)
+  int32_t s_stride;     // lamhat stride per problem
+};
+
+// A matrix operand as the kernels see it.
+struct MatArg {
+  const void* ptr;
+  MType mt;
+  int64_t m, n, lda, strideA;
+};
+
+// ---- launchers (kernels.hip) ------------------------------------------------
+// All launchers enqueue on `st` and return hipSuccess or the launch error.
+
+// Partials of t = A v over `nsplit` column splits: out[b][split][m].
+hipError_t launch_gemv_n(const MatArg& A, int64_t batch, VType vt, const void* v, int64_t v_stride,
+                         void* out, int64_t out_split_stride, int64_t out_prob_stride, int nsplit,
+                         const int32_t* gate, int gate_stride_ints, hipStream_t st);
+// Partials of y = A^T (d o sum_s tin_s) over `ksplit` row splits, for nrhs columns:
+// ypart[b][ks][k][npad].  tin[k] column at tin + k * tin_col_stride.
+hipError_t launch_gemv_t(const MatArg& A, int64_t batch, VType vt, const void* tin, int nsplit_in,
+                         int64_t tin_split_stride, int64_t tin_prob_stride, int64_t tin_col_stride,
+                         int nrhs, const void* dscale, int64_t d_stride, void* ypart, int ksplit,
+                         int64_t ypart_ks_stride, int64_t ypart_col_stride, int64_t ypart_prob_stride,
+                         const int32_t* gate, int gate_stride_ints, hipStream_t st);
+int gemv_n_splits(const MatArg& A, int64_t batch);
+int gemv_t_splits(const MatArg& A, int64_t batch);
+int gemv_t_rows_per_split(const MatArg& A, int ksplit);
+
+// out[b][i] = sum_{k<nsplit} in[b][k][i] for problems whose gate is nonzero (gate may be NULL).
+hipError_t launch_sum_splits(VType vt, int64_t batch, int64_t len, const void* in, int nsplit,
+                             int64_t split_stride, int64_t prob_stride_in, void* out,
+                             int64_t prob_stride_out, hipStream_t st,
+                             const int32_t* gate = nullptr, int gate_stride = 0);
+
+hipError_t launch_cast_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t st);
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);  // zero fill (no memset nodes)
+hipError_t launch_copy(VType vt, const void* src, void* dst, int64_t count, hipStream_t st);
+
+// ---- CG / ADMM vector kernels ------------------------------------------------
+struct VecArgs {
+  VType vt;
+  int64_t n, batch;
+  int nb;                 // blocks per problem
+  int64_t chunk;          // elements per block
+  Ctrl ctrl;
+  // n-vectors (per problem stride n)
+  void *x, *z, *u, *h, *g, *c, *r, *p, *hp, *w;  // w: preconditioned residual
+  const void* U;          // n x s_stride column-major per problem (nullable)
+  int s_stride;
+  const void* ypart;      // gemv_t partials feeding hp (prob stride, ks stride)
+  int ksplit;
+  int64_t ypart_ks_stride, ypart_prob_stride;
+  const uint8_t* mask;    // masked operator (adjoint): 1 = in the active set
+};
+hipError_t launch_admm_begin(const VecArgs& a, hipStream_t st);
+hipError_t launch_precond_step(const VecArgs& a, int init, hipStream_t st);
+hipError_t launch_cg_alpha(const VecArgs& a, hipStream_t st);
+hipError_t launch_cg_update(const VecArgs& a, hipStream_t st);
+hipError_t launch_p_update(const VecArgs& a, hipStream_t st);
+hipError_t launch_admm_end(const VecArgs& a, hipStream_t st);
+// ||g + rho u||^2 into state.red[kRedRd2] with g = h - c or the given g.
+hipError_t launch_dual_residual(const VecArgs& a, hipStream_t st);
+// Objective pieces: Lasso 1/2||t - b||^2 or logistic sum log(1+exp(-y t)), into red[kRedAux].
+hipError_t launch_objective_m(VType vt, int64_t m, int64_t batch, const void* tparts, int nsplit,
+                              int64_t split_stride, int64_t prob_stride, const void* bvec,
+                              int logistic, Ctrl ctrl, hipStream_t st);
+// Logistic elementwise (margins, sigmoid, curvature): from t = A x partials compute
+// d = s(1-s) and the two right-hand columns: col0 = d o t, col1 = -y o s.
+hipError_t launch_logistic_elem(VType vt, int64_t m, int64_t batch, const void* tparts, int nsplit,
+                                int64_t split_stride, int64_t prob_stride, const void* y, void* d,
+                                void* cols, int64_t col_stride, const ProbParams* params,
+                                hipStream_t st);
+// Stand-alone fused ADMM update test hook.
+hipError_t launch_admm_update_hook(VType vt, int64_t n, double alpha, double kappa, const void* x,
+                                   void* z, void* u, double* part, unsigned* counter,
+                                   double* out4, hipStream_t st);
+// Stand-alone preconditioner apply.
+hipError_t launch_precond_apply(VType vt, int64_t n, int s, int64_t batch, const void* U,
+                                const double* lamhat, const int32_t* s_eff, double nu,
+                                const void* r, void* z, double* part, int64_t part_stride,
+                                unsigned* counters, double* coef, hipStream_t st);
+// Adjoint helpers.
+hipError_t launch_build_mask(VType vt, int64_t n, int64_t batch, const void* zstar,
+                             const void* gz, uint8_t* mask, void* sgn, void* neg_rhs,
+                             hipStream_t st);
+hipError_t launch_masked_dot(VType vt, int64_t n, int64_t batch, const void* a, const void* b,
+                             double* part, int64_t part_stride, unsigned* counters, double* out,
+                             hipStream_t st);
+
+// ---- sketch (sketch.hip) ------------------------------------------------------
+hipError_t launch_gaussian(VType vt, int64_t n, int s, int s_stride, int64_t batch, uint64_t seed,
+                           uint64_t stream_id, const uint8_t* mask, void* out, hipStream_t st);
+struct SketchWs {
+  void* omega;      // n x sp per problem (vt)
+  void* W;          // m x sp per problem (float or double)
+  void* Wpart;      // ksW x m x sp per problem
+  void* Ypart;      // ksY x n x sp per problem
+  void* Y;          // n x sp per problem
+  double* gpart;    // Gram partials
+  double* gram;     // 3 x s x s per problem
+  double* core;     // core scratch per problem (C, X, V, T, ...)
+  int ksW, ksY, nbG;
+};
+int sketch_pad(int s);
+size_t sketch_ws_bytes(int64_t m, int64_t n, int s, int64_t batch, VType vt, int* ksW, int* ksY,
+                       int* nbG);
+// Y = H Omega (H = A^T diag(d) A) then the stabilised s x s core and U.
+// Writes U (n x s col-major, vt), lamhat (s doubles, descending), s_eff, status.
+hipError_t run_nystrom(const MatArg& A, int64_t batch, VType vt, const void* d, int64_t d_stride,
+                       int s, const void* omega_in, uint64_t seed, uint64_t stream_id,
+                       const uint8_t* mask, const SketchWs& ws, void* U, double* lamhat,
+                       int32_t* s_eff, int32_t* core_status, double* shift_out, hipStream_t st);
+
+// ---- errors -----------------------------------------------------------------
+void set_error(const std::string& s);
+const char* last_error();
+
+}  // namespace genios

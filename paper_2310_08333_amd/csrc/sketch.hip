@@ -1,0 +1,808 @@
+// Randomized Nystrom approximation of H = A^T diag(d) A (Sec. 2.2).
+//
+//   1. Omega (n x s) standard normal: Philox4x64-10 counters + Box-Muller.
+//   2. W = A Omega            (m x s)   tiled GEMM, split over n
+//   3. Y = A^T (d o W)        (n x s)   tiled GEMM, split over m      => Y = H Omega
+//   4. FP64 Grams  Omega^T Y, Omega^T Omega, Y^T Y (s x s)
+//   5. s x s core in one workgroup (FP64): with the stabilising shift
+//      mu = sqrt(n) eps ||Y||_F and Y_mu = Y + mu Omega,
+//        M = Omega^T Y_mu = C C^T (Cholesky; shift x10 on failure, <= 3 times),
+//        G = C^-1 (Y_mu^T Y_mu) C^-T = V Sigma^2 V^T (cyclic Jacobi),
+//        lambda_hat = max(Sigma^2 - mu, 0), T = C^-T V Sigma^-1,
+//      so that B = Y_mu C^-T = U Sigma V^T and H_hat = Y_mu M^-1 Y_mu^T = B B^T.
+//   6. U = Y_mu T             (n x s)   orthonormal columns.
+// Steps 2-3 stream A twice, the cost the paper quotes for the sketch
+// ("about a matrix-vector product with A" per column block).
+#include <algorithm>
+#include <cmath>
+
+#include "device.hpp"
+
+namespace genios {
+
+namespace {
+
+// ---- Philox4x64-10 and Box-Muller ---------------------------------------------
+
+__device__ __forceinline__ void philox4x64_10(uint64_t (&c)[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+    const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n1 = lo1, n2 = hi0 ^ c[3] ^ k1, n3 = lo0;
+    c[0] = n0;
+    c[1] = n1;
+    c[2] = n2;
+    c[3] = n3;
+    k0 += W0;
+    k1 += W1;
+  }
+}
+
+__device__ __forceinline__ void box_muller(uint64_t a, uint64_t b, double& z0, double& z1) {
+  const double u1 = ((double)(a >> 11) + 0.5) * 0x1p-53;
+  const double u2 = (double)(b >> 11) * 0x1p-53;
+  const double r = sqrt(-2.0 * log(u1));
+  const double t = 2.0 * M_PI * u2;
+  z0 = r * cos(t);
+  z1 = r * sin(t);
+}
+
+// out[b] is n x ld (column-major, ld columns >= s); element e = j n + i of the
+// first s columns comes from block e/4, lane e%4, key (seed, stream_id + b).
+template <typename VT>
+__global__ __launch_bounds__(256) void k_gaussian(int64_t n, int s, int ld_cols, uint64_t seed,
+                                                  uint64_t stream_id,
+                                                  const uint8_t* __restrict__ mask,
+                                                  VT* __restrict__ out) {
+  const int b = blockIdx.y;
+  const int64_t total = n * (int64_t)s;
+  const int64_t nblk = (total + 3) / 4;
+  VT* ob = out + (int64_t)b * n * ld_cols;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nblk;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t ctr[4] = {(uint64_t)c, 0ull, 0ull, 0ull};
+    philox4x64_10(ctr, seed, stream_id + (uint64_t)b);
+    double z[4];
+    box_muller(ctr[0], ctr[1], z[0], z[1]);
+    box_muller(ctr[2], ctr[3], z[2], z[3]);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const int64_t e = 4 * c + l;
+      if (e < total) {
+        const int64_t j = e / n, i = e - j * n;
+        const bool keep = mask == nullptr || mask[(int64_t)b * n + i] != 0;
+        ob[j * n + i] = keep ? VT((float)z[l]) : VT(0);
+      }
+    }
+  }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_copy_omega(int64_t n, int s, int ld_cols,
+                                                    const VT* __restrict__ in,
+                                                    const uint8_t* __restrict__ mask,
+                                                    VT* __restrict__ out) {
+  const int b = blockIdx.y;
+  const int64_t total = n * (int64_t)s;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / n, i = e - j * n;
+    const bool keep = mask == nullptr || mask[(int64_t)b * n + i] != 0;
+    out[(int64_t)b * n * ld_cols + j * n + i] = keep ? in[(int64_t)b * n * s + e] : VT(0);
+  }
+}
+
+// ---- skinny GEMMs ----------------------------------------------------------------
+// Output tile 64 x SP per block, K chunks of 32, 256 threads, each thread 4 x SP/16.
+
+constexpr int kBM = 64;
+constexpr int kBK = 32;
+
+template <typename Acc, int SP>
+__device__ __forceinline__ void micro_tile(const Acc (*As)[kBM + 4], const Acc (*Bs)[SP + 4],
+                                           Acc (&acc)[4][SP / 16], int tr, int tc) {
+  constexpr int CT = SP / 16;
+#pragma unroll 4
+  for (int kk = 0; kk < kBK; ++kk) {
+    Acc a[4], bb[CT];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = As[kk][tr * 4 + i];
+#pragma unroll
+    for (int j = 0; j < CT; ++j) bb[j] = Bs[kk][tc * CT + j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < CT; ++j) acc[i][j] += a[i] * bb[j];
+  }
+}
+
+// Wpart[b][ks] (m x SP, col-major) = A[:, k-range] Omega[k-range, :]
+template <typename T, typename VT, int SP>
+__global__ __launch_bounds__(256) void k_sketch_w(const T* __restrict__ A, int64_t lda,
+                                                  int64_t strideA, int m, int n,
+                                                  const VT* __restrict__ omega,
+                                                  VT* __restrict__ wpart, int kchunk,
+                                                  int64_t wpart_ks_stride,
+                                                  int64_t wpart_prob_stride) {
+  using Acc = typename Elem<T>::Acc;
+  constexpr int CT = SP / 16;
+  __shared__ Acc As[kBK][kBM + 4];
+  __shared__ Acc Bs[kBK][SP + 4];
+  const int b = blockIdx.z, ks = blockIdx.y;
+  const int row0 = blockIdx.x * kBM;
+  const int k0 = ks * kchunk, k1 = min(n, k0 + kchunk);
+  const T* Ab = A + (int64_t)b * strideA;
+  const VT* Ob = omega + (int64_t)b * n * SP;
+  const int tid = threadIdx.x, tr = tid % 16, tc = tid / 16;
+  Acc acc[4][CT];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[i][j] = Acc(0);
+  const int lr = tid / 4, lk = (tid % 4) * 8;  // A tile load: one row, 8 consecutive k
+  for (int kb = k0; kb < k1; kb += kBK) {
+    {
+      const int row = row0 + lr;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = kb + lk + q;
+        As[lk + q][lr] = (row < m && k < k1) ? Acc(Elem<T>::cvt(Ab[(int64_t)row * lda + k])) : Acc(0);
+      }
+    }
+    for (int e = tid; e < kBK * SP; e += 256) {
+      const int j = e / kBK, kk = e % kBK;
+      const int k = kb + kk;
+      Bs[kk][j] = (k < k1) ? Acc(Ob[(int64_t)j * n + k]) : Acc(0);
+    }
+    __syncthreads();
+    micro_tile<Acc, SP>(As, Bs, acc, tr, tc);
+    __syncthreads();
+  }
+  VT* Wb = wpart + (int64_t)b * wpart_prob_stride + (int64_t)ks * wpart_ks_stride;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = row0 + tr * 4 + i;
+    if (row < m)
+#pragma unroll
+      for (int j = 0; j < CT; ++j) Wb[(int64_t)(tc * CT + j) * m + row] = VT(acc[i][j]);
+  }
+}
+
+// Ypart[b][ks] (n x SP) = A[r-range, :]^T (d o W)[r-range, :]
+template <typename T, typename VT, int SP>
+__global__ __launch_bounds__(256) void k_sketch_y(const T* __restrict__ A, int64_t lda,
+                                                  int64_t strideA, int m, int n,
+                                                  const VT* __restrict__ W,
+                                                  const VT* __restrict__ d, int64_t d_stride,
+                                                  VT* __restrict__ ypart, int rchunk,
+                                                  int64_t ypart_ks_stride,
+                                                  int64_t ypart_prob_stride) {
+  using Acc = typename Elem<T>::Acc;
+  constexpr int CT = SP / 16;
+  __shared__ Acc As[kBK][kBM + 4];
+  __shared__ Acc Bs[kBK][SP + 4];
+  const int b = blockIdx.z, ks = blockIdx.y;
+  const int col0 = blockIdx.x * kBM;
+  const int r0 = ks * rchunk, r1 = min(m, r0 + rchunk);
+  const T* Ab = A + (int64_t)b * strideA;
+  const VT* Wb = W + (int64_t)b * m * SP;
+  const VT* db = d ? d + (int64_t)b * d_stride : nullptr;
+  const int tid = threadIdx.x, tr = tid % 16, tc = tid / 16;
+  Acc acc[4][CT];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[i][j] = Acc(0);
+  const int lr = tid / 8, lc = (tid % 8) * 8;  // A tile load: one row, 8 consecutive columns
+  for (int rb = r0; rb < r1; rb += kBK) {
+    {
+      const int r = rb + lr;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int c = col0 + lc + q;
+        As[lr][lc + q] = (r < r1 && c < n) ? Acc(Elem<T>::cvt(Ab[(int64_t)r * lda + c])) : Acc(0);
+      }
+    }
+    for (int e = tid; e < kBK * SP; e += 256) {
+      const int j = e / kBK, kk = e % kBK;
+      const int r = rb + kk;
+      Acc v = Acc(0);
+      if (r < r1) {
+        v = Acc(Wb[(int64_t)j * m + r]);
+        if (db) v *= Acc(db[r]);
+      }
+      Bs[kk][j] = v;
+    }
+    __syncthreads();
+    micro_tile<Acc, SP>(As, Bs, acc, tr, tc);
+    __syncthreads();
+  }
+  VT* Yb = ypart + (int64_t)b * ypart_prob_stride + (int64_t)ks * ypart_ks_stride;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int c = col0 + tr * 4 + i;
+    if (c < n)
+#pragma unroll
+      for (int j = 0; j < CT; ++j) Yb[(int64_t)(tc * CT + j) * n + c] = VT(acc[i][j]);
+  }
+}
+
+// ---- Grams ----------------------------------------------------------------------
+// which = 0: Omega^T Y, 1: Omega^T Omega, 2: Y^T Y; block g covers a row range.
+// Blocks with which == 0 also write Y = sum of the split partials (masked rows zero).
+template <typename VT, int SP>
+__global__ __launch_bounds__(256) void k_gram(int64_t n, const VT* __restrict__ omega,
+                                              const VT* __restrict__ ypart, int ksY,
+                                              int64_t ypart_ks_stride, int64_t ypart_prob_stride,
+                                              const uint8_t* __restrict__ mask,
+                                              VT* __restrict__ Y, double* __restrict__ gpart,
+                                              int nbG) {
+  constexpr int SB = SP / 16;
+  constexpr int RT = 16;  // rows per LDS tile
+  __shared__ double L1[RT][SP + 1];
+  __shared__ double L2[RT][SP + 1];
+  const int b = blockIdx.z, which = blockIdx.y, g = blockIdx.x;
+  const int64_t rows_per = (n + nbG - 1) / nbG;
+  const int64_t lo = (int64_t)g * rows_per, hi = min(n, lo + rows_per);
+  const VT* Ob = omega + (int64_t)b * n * SP;
+  const VT* Yp = ypart + (int64_t)b * ypart_prob_stride;
+  VT* Yb = Y + (int64_t)b * n * SP;
+  const uint8_t* mb = mask ? mask + (int64_t)b * n : nullptr;
+  const int tid = threadIdx.x, ti = tid % 16, tj = tid / 16;
+  double acc[SB][SB];
+#pragma unroll
+  for (int i = 0; i < SB; ++i)
+#pragma unroll
+    for (int j = 0; j < SB; ++j) acc[i][j] = 0.0;
+  for (int64_t r0 = lo; r0 < hi; r0 += RT) {
+    for (int e = tid; e < RT * SP; e += 256) {
+      const int j = e / RT, rr = e % RT;
+      const int64_t r = r0 + rr;
+      double om = 0.0, yv = 0.0;
+      if (r < hi) {
+        om = double(Ob[(int64_t)j * n + r]);
+        if (which != 1) {
+          VT s = VT(0);
+          for (int k = 0; k < ksY; ++k) s += Yp[(int64_t)k * ypart_ks_stride + (int64_t)j * n + r];
+          if (mb && !mb[r]) s = VT(0);
+          if (which == 0) Yb[(int64_t)j * n + r] = s;
+          yv = double(s);
+        }
+      }
+      if (which == 0) {
+        L1[rr][j] = om;
+        L2[rr][j] = yv;
+      } else if (which == 1) {
+        L1[rr][j] = om;
+        L2[rr][j] = om;
+      } else {
+        L1[rr][j] = yv;
+        L2[rr][j] = yv;
+      }
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int rr = 0; rr < RT; ++rr) {
+      double a[SB], bb[SB];
+#pragma unroll
+      for (int i = 0; i < SB; ++i) a[i] = L1[rr][ti * SB + i];
+#pragma unroll
+      for (int j = 0; j < SB; ++j) bb[j] = L2[rr][tj * SB + j];
+#pragma unroll
+      for (int i = 0; i < SB; ++i)
+#pragma unroll
+        for (int j = 0; j < SB; ++j) acc[i][j] += a[i] * bb[j];
+    }
+    __syncthreads();
+  }
+  double* gp = gpart + (((int64_t)b * 3 + which) * nbG + g) * SP * SP;
+#pragma unroll
+  for (int i = 0; i < SB; ++i)
+#pragma unroll
+    for (int j = 0; j < SB; ++j) gp[(int64_t)(ti * SB + i) * SP + tj * SB + j] = acc[i][j];
+}
+
+__global__ __launch_bounds__(256) void k_gram_reduce(int sp2, const double* __restrict__ gpart,
+                                                     int nbG, double* __restrict__ gram) {
+  const int b = blockIdx.z, which = blockIdx.y;
+  const double* gp = gpart + ((int64_t)b * 3 + which) * nbG * sp2;
+  double* out = gram + ((int64_t)b * 3 + which) * sp2;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < sp2; e += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int g = 0; g < nbG; ++g) s += gp[(int64_t)g * sp2 + e];
+    out[e] = s;
+  }
+}
+
+// ---- s x s core -------------------------------------------------------------------
+// Scratch per problem (doubles, each SP*SP): C (lower), X, G, V, T.
+
+template <int SP>
+__global__ __launch_bounds__(256) void k_nystrom_core(int s, int64_t n, double eps,
+                                                      double rel_floor,
+                                                      const double* __restrict__ gram,
+                                                      double* __restrict__ core,
+                                                      double* __restrict__ lamhat, int lam_stride,
+                                                      int32_t* __restrict__ s_eff_out,
+                                                      int32_t* __restrict__ status_out,
+                                                      double* __restrict__ shift_out) {
+  constexpr int LD = SP + 1;
+  extern __shared__ double lds[];  // SP * LD doubles
+  __shared__ int s_fail;
+  __shared__ double s_shift;
+  __shared__ double s_red[4];
+  __shared__ int perm[SP];
+  __shared__ double evals[SP];
+  __shared__ double cs_c[SP / 2], cs_s[SP / 2];
+  __shared__ int pr_p[SP / 2], pr_q[SP / 2];
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int sp2 = SP * SP;
+  const double* G1 = gram + ((int64_t)b * 3 + 0) * sp2;
+  const double* G2 = gram + ((int64_t)b * 3 + 1) * sp2;
+  const double* G3 = gram + ((int64_t)b * 3 + 2) * sp2;
+  double* Cg = core + (int64_t)b * 5 * sp2;
+  double* Xg = Cg + sp2;
+  double* Gg = Xg + sp2;
+  double* Vg = Gg + sp2;
+  double* Tg = Vg + sp2;
+  double* lam_b = lamhat + (int64_t)b * lam_stride;
+  double* M = lds;
+
+  // ||Y||_F^2 = trace(Y^T Y)
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int k = 0; k < s; ++k) tr += G3[k * SP + k];
+    s_red[0] = tr;
+  }
+  __syncthreads();
+  const double trace3 = s_red[0];
+  if (!(trace3 > 0.0) || !(trace3 < 1.0e300)) {
+    // H Omega = 0 (H = 0 on the sketch) or non-finite: identity preconditioner.
+    for (int j = tid; j < s; j += nt) lam_b[j] = 0.0;
+    if (tid == 0) {
+      s_eff_out[b] = 0;
+      status_out[b] = (trace3 == 0.0) ? 0 : GENIOS_WARN_PRECOND;
+      shift_out[b] = 0.0;
+    }
+    return;
+  }
+  if (tid == 0) s_shift = sqrt((double)n) * eps * sqrt(trace3);
+  __syncthreads();
+
+  bool ok = false;
+  for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
+    const double mu = s_shift;
+    for (int e = tid; e < s * s; e += nt) {
+      const int i = e / s, j = e % s;
+      M[i * LD + j] = 0.5 * (G1[i * SP + j] + G1[j * SP + i]) + mu * G2[i * SP + j];
+    }
+    if (tid == 0) s_fail = 0;
+    __syncthreads();
+    for (int k = 0; k < s; ++k) {
+      if (tid == 0) {
+        const double dkk = M[k * LD + k];
+        if (!(dkk > 0.0) || !(dkk < 1.0e300))
+          s_fail = 1;
+        else
+          M[k * LD + k] = sqrt(dkk);
+      }
+      __syncthreads();
+      if (s_fail) break;
+      const double piv = M[k * LD + k];
+      for (int i = k + 1 + tid; i < s; i += nt) M[i * LD + k] /= piv;
+      __syncthreads();
+      const int rem = s - k - 1;
+      for (int e = tid; e < rem * rem; e += nt) {
+        const int i = k + 1 + e / rem, j = k + 1 + e % rem;
+        if (j <= i) M[i * LD + j] -= M[i * LD + k] * M[j * LD + k];
+      }
+      __syncthreads();
+    }
+    if (!s_fail) {
+      ok = true;
+    } else {
+      if (tid == 0) s_shift = 10.0 * s_shift;
+      __syncthreads();
+    }
+  }
+  if (!ok) {
+    for (int j = tid; j < s; j += nt) lam_b[j] = 0.0;
+    if (tid == 0) {
+      s_eff_out[b] = 0;
+      status_out[b] = GENIOS_WARN_PRECOND;
+      shift_out[b] = s_shift;
+    }
+    return;
+  }
+  const double mu = s_shift;
+  // Save C (lower triangle, zeros above) and form Q = Y_mu^T Y_mu in Xg (col-major).
+  for (int e = tid; e < s * s; e += nt) {
+    const int i = e / s, j = e % s;
+    Cg[i * SP + j] = (j <= i) ? M[i * LD + j] : 0.0;
+    Xg[j * SP + i] = G3[i * SP + j] + mu * (G1[i * SP + j] + G1[j * SP + i]) + mu * mu * G2[i * SP + j];
+  }
+  __syncthreads();
+  // X = C^-1 Q: thread j solves for column j (C from LDS).
+  for (int j = tid; j < s; j += nt) {
+    double* xc = Xg + (int64_t)j * SP;
+    for (int i = 0; i < s; ++i) {
+      double v = xc[i];
+      for (int l = 0; l < i; ++l) v -= M[i * LD + l] * xc[l];
+      xc[i] = v / M[i * LD + i];
+    }
+  }
+  __syncthreads();
+  // G = C^-1 X^T: column j of G solves C g = (row j of X)^T.
+  for (int j = tid; j < s; j += nt) {
+    double* gc = Gg + (int64_t)j * SP;
+    for (int i = 0; i < s; ++i) {
+      double v = Xg[(int64_t)i * SP + j];  // X[j][i] stored col-major at (i, j) -> X(j, i)
+      for (int l = 0; l < i; ++l) v -= M[i * LD + l] * gc[l];
+      gc[i] = v / M[i * LD + i];
+    }
+  }
+  __syncthreads();
+  // G into LDS, symmetrised; V = I.
+  for (int e = tid; e < s * s; e += nt) {
+    const int i = e / s, j = e % s;
+    M[i * LD + j] = 0.5 * (Gg[(int64_t)j * SP + i] + Gg[(int64_t)i * SP + j]);
+    Vg[(int64_t)j * SP + i] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+
+  // Cyclic Jacobi with round-robin pairing; S players (s rounded up to even).
+  const int S = (s + 1) & ~1;
+  const int npairs = S / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid < 64) {
+      double off = 0.0, dia = 0.0;
+      for (int e = tid; e < s * s; e += 64) {
+        const int i = e / s, j = e % s;
+        const double v = M[i * LD + j];
+        if (i == j)
+          dia += v * v;
+        else
+          off += v * v;
+      }
+      off = wave_sum(off);
+      dia = wave_sum(dia);
+      if (tid == 0) {
+        s_red[1] = off;
+        s_red[2] = dia;
+      }
+    }
+    __syncthreads();
+    if (!(s_red[1] > 1.0e-30 * s_red[2])) break;
+    for (int round = 0; round < S - 1; ++round) {
+      if (tid < npairs) {
+        auto player = [&](int pos) { return pos == 0 ? 0 : 1 + ((pos - 1 + round) % (S - 1)); };
+        int p = player(tid), q = player(S - 1 - tid);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        double c = 1.0, sn = 0.0;
+        if (q < s) {
+          const double apq = M[p * LD + q];
+          if (apq != 0.0) {
+            const double app = M[p * LD + p], aqq = M[q * LD + q];
+            const double theta = (aqq - app) / (2.0 * apq);
+            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            sn = t * c;
+          }
+        }
+        pr_p[tid] = p;
+        pr_q[tid] = q;
+        cs_c[tid] = c;
+        cs_s[tid] = sn;
+      }
+      __syncthreads();
+      // rows: (M_pk, M_qk) <- (c M_pk - s M_qk, s M_pk + c M_qk)
+      for (int e = tid; e < npairs * s; e += nt) {
+        const int pi = e / s, k = e % s;
+        const int p = pr_p[pi], q = pr_q[pi];
+        if (q >= s || cs_s[pi] == 0.0) continue;
+        const double c = cs_c[pi], sn = cs_s[pi];
+        const double a = M[p * LD + k], bq = M[q * LD + k];
+        M[p * LD + k] = c * a - sn * bq;
+        M[q * LD + k] = sn * a + c * bq;
+      }
+      __syncthreads();
+      // columns, and V <- V P
+      for (int e = tid; e < npairs * s; e += nt) {
+        const int pi = e / s, k = e % s;
+        const int p = pr_p[pi], q = pr_q[pi];
+        if (q >= s || cs_s[pi] == 0.0) continue;
+        const double c = cs_c[pi], sn = cs_s[pi];
+        const double a = M[k * LD + p], bq = M[k * LD + q];
+        M[k * LD + p] = c * a - sn * bq;
+        M[k * LD + q] = sn * a + c * bq;
+        const double va = Vg[(int64_t)p * SP + k], vb = Vg[(int64_t)q * SP + k];
+        Vg[(int64_t)p * SP + k] = c * va - sn * vb;
+        Vg[(int64_t)q * SP + k] = sn * va + c * vb;
+      }
+      __syncthreads();
+    }
+  }
+  // Sort eigenvalues descending.
+  if (tid == 0) {
+    for (int j = 0; j < s; ++j) {
+      perm[j] = j;
+      evals[j] = M[j * LD + j];
+    }
+    for (int i = 1; i < s; ++i) {
+      const double ev = evals[i];
+      const int pv = perm[i];
+      int k = i - 1;
+      while (k >= 0 && evals[k] < ev) {
+        evals[k + 1] = evals[k];
+        perm[k + 1] = perm[k];
+        --k;
+      }
+      evals[k + 1] = ev;
+      perm[k + 1] = pv;
+    }
+    // keep the leading eigenpairs whose shifted value is resolvable at the
+    // precision of Y: lambda_hat_j = sigma_j^2 - mu > rel_floor * lambda_hat_0
+    const double top = evals[0] - mu;
+    int keep = 0;
+    for (int j = 0; j < s; ++j) {
+      if (top > 0.0 && evals[j] - mu > rel_floor * top)
+        keep = j + 1;
+      else
+        break;
+    }
+    s_fail = keep;
+  }
+  __syncthreads();
+  const int keep = s_fail;
+  for (int j = tid; j < s; j += nt) lam_b[j] = (j < keep) ? fmax(evals[j] - mu, 0.0) : 0.0;
+  // Reload C into LDS, then T(:, j) = C^-T V(:, perm[j]) / sigma_j.
+  __syncthreads();
+  for (int e = tid; e < s * s; e += nt) {
+    const int i = e / s, j = e % s;
+    M[i * LD + j] = Cg[i * SP + j];
+  }
+  __syncthreads();
+  for (int j = tid; j < SP; j += nt) {
+    double* tcol = Tg + (int64_t)j * SP;
+    if (j >= keep) {
+      for (int i = 0; i < SP; ++i) tcol[i] = 0.0;
+      continue;
+    }
+    const double* vcol = Vg + (int64_t)perm[j] * SP;
+    const double inv_sig = 1.0 / sqrt(evals[j]);
+    for (int i = s - 1; i >= 0; --i) {
+      double v = vcol[i];
+      for (int l = i + 1; l < s; ++l) v -= M[l * LD + i] * tcol[l];
+      tcol[i] = v / M[i * LD + i];
+    }
+    for (int i = 0; i < s; ++i) tcol[i] *= inv_sig;
+    for (int i = s; i < SP; ++i) tcol[i] = 0.0;
+  }
+  if (tid == 0) {
+    s_eff_out[b] = keep;
+    status_out[b] = 0;
+    shift_out[b] = mu;
+  }
+}
+
+// U[b] (n x s, col-major, ld n) = (Y + mu Omega) T  for the first s_eff columns, 0 after.
+template <typename VT, int SP>
+__global__ __launch_bounds__(256) void k_form_u(int64_t n, int s, const VT* __restrict__ Y,
+                                                const VT* __restrict__ omega,
+                                                const double* __restrict__ core,
+                                                const double* __restrict__ shift,
+                                                const int32_t* __restrict__ s_eff_arr,
+                                                VT* __restrict__ U) {
+  constexpr int RB = 64;
+  __shared__ double Yt[RB][SP + 1];
+  const int b = blockIdx.y;
+  const int keep = s_eff_arr[b];
+  const double mu = shift[b];
+  const int64_t row0 = (int64_t)blockIdx.x * RB;
+  const VT* Yb = Y + (int64_t)b * n * SP;
+  const VT* Ob = omega + (int64_t)b * n * SP;
+  const double* Tg = core + (int64_t)b * 5 * SP * SP + 4 * SP * SP;
+  for (int e = threadIdx.x; e < RB * SP; e += blockDim.x) {
+    const int k = e / RB, r = e % RB;
+    const int64_t i = row0 + r;
+    double v = 0.0;
+    if (i < n && k < s) v = double(Yb[(int64_t)k * n + i]) + mu * double(Ob[(int64_t)k * n + i]);
+    Yt[r][k] = v;
+  }
+  __syncthreads();
+  const int r = threadIdx.x % RB, grp = threadIdx.x / RB;
+  const int64_t i = row0 + r;
+  VT* Ub = U + (int64_t)b * n * s;
+  for (int j = grp; j < s; j += blockDim.x / RB) {
+    double acc = 0.0;
+    if (j < keep) {
+      const double* tcol = Tg + (int64_t)j * SP;
+      for (int k = 0; k < s; ++k) acc += Yt[r][k] * tcol[k];
+    }
+    if (i < n) Ub[(int64_t)j * n + i] = VT(acc);
+  }
+}
+
+int pad_rank(int s) { return s <= 16 ? 16 : (s <= 32 ? 32 : (s <= 64 ? 64 : 128)); }
+
+template <typename T, typename VT, int SP>
+hipError_t sketch_gemms(const MatArg& A, int64_t batch, const VT* d, int64_t d_stride,
+                        const SketchWs& ws, hipStream_t st) {
+  const int m = (int)A.m, n = (int)A.n;
+  const T* Ap = static_cast<const T*>(A.ptr);
+  // W = A Omega, split over n
+  {
+    int kchunk = (int)((A.n + ws.ksW - 1) / ws.ksW);
+    kchunk = ((kchunk + kBK - 1) / kBK) * kBK;
+    dim3 grid((unsigned)((m + kBM - 1) / kBM), (unsigned)ws.ksW, (unsigned)batch);
+    hipLaunchKernelGGL((k_sketch_w<T, VT, SP>), grid, dim3(256), 0, st, Ap, A.lda, A.strideA, m,
+                       n, static_cast<const VT*>(ws.omega), static_cast<VT*>(ws.Wpart), kchunk,
+                       (int64_t)m * SP, (int64_t)ws.ksW * m * SP);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_sum_splits(sizeof(VT) == 4 ? VT_F32 : VT_F64, batch, (int64_t)m * SP, ws.Wpart,
+                          ws.ksW, (int64_t)m * SP, (int64_t)ws.ksW * m * SP, ws.W,
+                          (int64_t)m * SP, st);
+    if (e != hipSuccess) return e;
+  }
+  // Y = A^T (d o W), split over m
+  {
+    int rchunk = (int)((A.m + ws.ksY - 1) / ws.ksY);
+    rchunk = ((rchunk + kBK - 1) / kBK) * kBK;
+    dim3 grid((unsigned)((n + kBM - 1) / kBM), (unsigned)ws.ksY, (unsigned)batch);
+    hipLaunchKernelGGL((k_sketch_y<T, VT, SP>), grid, dim3(256), 0, st, Ap, A.lda, A.strideA, m,
+                       n, static_cast<const VT*>(ws.W), d, d_stride, static_cast<VT*>(ws.Ypart),
+                       rchunk, (int64_t)n * SP, (int64_t)ws.ksY * n * SP);
+    return hipGetLastError();
+  }
+}
+
+template <typename VT, int SP>
+hipError_t run_core(const MatArg& A, int64_t batch, int s, const uint8_t* mask, const SketchWs& ws,
+                    void* U, double* lamhat, int32_t* s_eff, int32_t* status, double* shift,
+                    hipStream_t st) {
+  const int64_t n = A.n;
+  {
+    dim3 grid((unsigned)ws.nbG, 3u, (unsigned)batch);
+    hipLaunchKernelGGL((k_gram<VT, SP>), grid, dim3(256), 0, st, n,
+                       static_cast<const VT*>(ws.omega), static_cast<const VT*>(ws.Ypart), ws.ksY,
+                       (int64_t)n * SP, (int64_t)ws.ksY * n * SP, mask, static_cast<VT*>(ws.Y),
+                       ws.gpart, ws.nbG);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 g2((unsigned)((SP * SP + 255) / 256), 3u, (unsigned)batch);
+    hipLaunchKernelGGL(k_gram_reduce, g2, dim3(256), 0, st, SP * SP, ws.gpart, ws.nbG, ws.gram);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const double eps = sizeof(VT) == 4 ? 0x1p-24 : 0x1p-53;
+  const double rel_floor = sizeof(VT) == 4 ? 1.0e-6 : 1.0e-13;
+  const size_t lds = (size_t)SP * (SP + 1) * sizeof(double);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nystrom_core<SP>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_nystrom_core<SP>), dim3((unsigned)batch), dim3(256), lds, st, s, n, eps,
+                     rel_floor, ws.gram, ws.core, lamhat, s, s_eff, status, shift);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 g3((unsigned)((n + 63) / 64), (unsigned)batch);
+  hipLaunchKernelGGL((k_form_u<VT, SP>), g3, dim3(256), 0, st, n, s,
+                     static_cast<const VT*>(ws.Y), static_cast<const VT*>(ws.omega), ws.core,
+                     shift, s_eff, static_cast<VT*>(U));
+  return hipGetLastError();
+}
+
+template <typename VT>
+hipError_t dispatch_rank(const MatArg& A, int64_t batch, const VT* d, int64_t d_stride, int s,
+                         const uint8_t* mask, const SketchWs& ws, void* U, double* lamhat,
+                         int32_t* s_eff, int32_t* status, double* shift, hipStream_t st) {
+  const int sp = pad_rank(s);
+  hipError_t e = hipSuccess;
+#define GENIOS_SK(SPV)                                                                     \
+  if (sp == SPV) {                                                                         \
+    if constexpr (sizeof(VT) == 4) {                                                       \
+      if (A.mt == MT_BF16)                                                                 \
+        e = sketch_gemms<uint16_t, VT, SPV>(A, batch, d, d_stride, ws, st);                \
+      else                                                                                 \
+        e = sketch_gemms<float, VT, SPV>(A, batch, d, d_stride, ws, st);                   \
+    } else {                                                                               \
+      e = sketch_gemms<double, VT, SPV>(A, batch, d, d_stride, ws, st);                    \
+    }                                                                                      \
+    if (e != hipSuccess) return e;                                                         \
+    return run_core<VT, SPV>(A, batch, s, mask, ws, U, lamhat, s_eff, status, shift, st); \
+  }
+  GENIOS_SK(16)
+  GENIOS_SK(32)
+  GENIOS_SK(64)
+  GENIOS_SK(128)
+#undef GENIOS_SK
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int sketch_pad(int s) { return pad_rank(s); }
+
+size_t sketch_ws_bytes(int64_t m, int64_t n, int s, int64_t batch, VType vt, int* ksW, int* ksY,
+                       int* nbG) {
+  const int sp = pad_rank(s);
+  const size_t e = vt == VT_F32 ? 4 : 8;
+  const int64_t rb = ((m + kBM - 1) / kBM) * batch;
+  int64_t kw = (1024 + rb - 1) / rb;
+  kw = std::max<int64_t>(1, std::min<int64_t>(kw, std::max<int64_t>(1, n / 256)));
+  const int64_t cb = ((n + kBM - 1) / kBM) * batch;
+  int64_t ky = (1024 + cb - 1) / cb;
+  ky = std::max<int64_t>(1, std::min<int64_t>(ky, std::max<int64_t>(1, m / 256)));
+  int64_t ng = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, std::max<int64_t>(1, 256 / batch)));
+  if (ksW) *ksW = (int)kw;
+  if (ksY) *ksY = (int)ky;
+  if (nbG) *nbG = (int)ng;
+  size_t bytes = 0;
+  auto add = [&](size_t b) { bytes += (b + 255) / 256 * 256; };
+  add(batch * n * sp * e);               // omega
+  add(batch * m * sp * e);               // W
+  add(batch * kw * m * sp * e);          // Wpart
+  add(batch * ky * n * sp * e);          // Ypart
+  add(batch * n * sp * e);               // Y
+  add(batch * 3 * ng * sp * sp * 8);     // gpart
+  add(batch * 3 * sp * sp * 8);          // gram
+  add(batch * 5 * sp * sp * 8);          // core
+  return bytes;
+}
+
+hipError_t launch_gaussian(VType vt, int64_t n, int s, int s_stride, int64_t batch, uint64_t seed,
+                           uint64_t stream_id, const uint8_t* mask, void* out, hipStream_t st) {
+  const int64_t nblk = (n * s + 3) / 4;
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nblk + 255) / 256, 2048));
+  dim3 grid(nb, (unsigned)batch);
+  if (vt == VT_F32)
+    hipLaunchKernelGGL(k_gaussian<float>, grid, dim3(256), 0, st, n, s, s_stride, seed, stream_id,
+                       mask, static_cast<float*>(out));
+  else
+    hipLaunchKernelGGL(k_gaussian<double>, grid, dim3(256), 0, st, n, s, s_stride, seed,
+                       stream_id, mask, static_cast<double*>(out));
+  return hipGetLastError();
+}
+
+hipError_t run_nystrom(const MatArg& A, int64_t batch, VType vt, const void* d, int64_t d_stride,
+                       int s, const void* omega_in, uint64_t seed, uint64_t stream_id,
+                       const uint8_t* mask, const SketchWs& ws, void* U, double* lamhat,
+                       int32_t* s_eff, int32_t* core_status, double* shift_out, hipStream_t st) {
+  const int sp = pad_rank(s);
+  const int64_t n = A.n;
+  const size_t e = vt == VT_F32 ? 4 : 8;
+  hipError_t err = launch_fill(ws.omega, (size_t)batch * n * sp * e, st);
+  if (err != hipSuccess) return err;
+  if (omega_in) {
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n * s + 255) / 256, 2048));
+    dim3 grid(nb, (unsigned)batch);
+    if (vt == VT_F32)
+      hipLaunchKernelGGL(k_copy_omega<float>, grid, dim3(256), 0, st, n, s, sp,
+                         static_cast<const float*>(omega_in), mask, static_cast<float*>(ws.omega));
+    else
+      hipLaunchKernelGGL(k_copy_omega<double>, grid, dim3(256), 0, st, n, s, sp,
+                         static_cast<const double*>(omega_in), mask,
+                         static_cast<double*>(ws.omega));
+    err = hipGetLastError();
+  } else {
+    err = launch_gaussian(vt, n, s, sp, batch, seed, stream_id, mask, ws.omega, st);
+  }
+  if (err != hipSuccess) return err;
+  if (vt == VT_F32)
+    return dispatch_rank<float>(A, batch, static_cast<const float*>(d), d_stride, s, mask, ws, U,
+                                lamhat, s_eff, core_status, shift_out, st);
+  return dispatch_rank<double>(A, batch, static_cast<const double*>(d), d_stride, s, mask, ws, U,
+                               lamhat, s_eff, core_status, shift_out, st);
+}
+
+}  // namespace genios

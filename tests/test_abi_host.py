@@ -1,0 +1,143 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared
+symbol, and rejects invalid arguments before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "genios.h")
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_2310_08333_amd import _abi
+    _abi.load()
+    return _abi
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(genios_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(abi):
+    lib = abi.load()
+    names = _declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(abi.EXPORTED)
+
+
+def test_struct_layouts_match(abi):
+    sizes = [C.c_size_t(), C.c_size_t(), C.c_size_t()]
+    abi.load().genios_abi_struct_sizes(*[C.byref(s) for s in sizes])
+    assert tuple(s.value for s in sizes) == (C.sizeof(abi.Matrix), C.sizeof(abi.Opts),
+                                             C.sizeof(abi.Info))
+
+
+def test_default_opts_are_the_papers(abi):
+    o = abi.default_opts()
+    assert o.struct_size == C.sizeof(abi.Opts)
+    assert o.sigma == 1e-6 and o.gamma == 1.2 and o.alpha == 1.6
+    assert o.eps_abs == 1e-4 and o.eps_rel == 1e-4 and o.tau == 2.0 and o.mu == 10.0
+    assert o.resketch_every == 20 and o.sketch_rank == 0 and o.rho_update_every == 25
+
+
+def _mat(abi, m=100, n=200, lda=None, batch=1, dt=None):
+    M = abi.Matrix()
+    M.m, M.n, M.lda, M.batch = m, n, lda or n, batch
+    M.stride_A = 0
+    M.hi_dtype = abi.DT_F32 if dt is None else dt
+    M.A_hi = 0x10000000  # never dereferenced: validation fails first
+    return M
+
+
+def test_workspace_sizes(abi):
+    lib = abi.load()
+    M = _mat(abi)
+    o = abi.default_opts()
+    for op in (abi.OP_LASSO, abi.OP_LOGREG, abi.OP_NYSTROM, abi.OP_BACKWARD, abi.OP_MATVEC):
+        assert lib.genios_workspace_size(op, C.byref(M), C.byref(o)) > 0
+    assert lib.genios_workspace_size(99, C.byref(M), C.byref(o)) == 0
+    # the BF16 copy lives in the workspace when the caller gives none
+    o2 = abi.default_opts()
+    o2.precision = abi.PREC_F32
+    a = lib.genios_workspace_size(abi.OP_LASSO, C.byref(M), C.byref(o))
+    b = lib.genios_workspace_size(abi.OP_LASSO, C.byref(M), C.byref(o2))
+    assert a - b >= 100 * 200 * 2
+
+
+def _solve(abi, M, o, lam=0.1, rho=1.0, ptrs=True):
+    lib = abi.load()
+    lam_a = (C.c_double * max(1, M.batch))(*([lam] * max(1, M.batch)))
+    info = (abi.Info * max(1, M.batch))()
+    p = 0x20000000 if ptrs else None
+    return lib.genios_lasso_solve(C.byref(M), p, lam_a, rho, C.byref(o), p, p, p, info)
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("lda", 50, -2), ("m", 0, -2), ("batch", 0, -2), ("hi_dtype", 7, -1)])
+def test_matrix_validation(abi, field, value, code):
+    M = _mat(abi)
+    setattr(M, field, value)
+    o = abi.default_opts()
+    assert _solve(abi, M, o) == code
+    assert abi.last_error()
+
+
+@pytest.mark.parametrize("field,value", [
+    ("alpha", 2.5), ("alpha", 0.0), ("sigma", -1.0), ("gamma", 0.0), ("tau", 1.0), ("mu", 0.5),
+    ("max_iter", 0), ("max_cg_iter", 0), ("cg_tol_floor", 0.0), ("sketch_rank", 129),
+    ("resketch_every", 0), ("precision", 9), ("struct_size", 8)])
+def test_option_validation(abi, field, value):
+    o = abi.default_opts()
+    setattr(o, field, value)
+    assert _solve(abi, _mat(abi), o) == abi.ERR_ARG
+
+
+def test_scalar_validation(abi):
+    o = abi.default_opts()
+    assert _solve(abi, _mat(abi), o, lam=-1.0) == abi.ERR_ARG
+    assert _solve(abi, _mat(abi), o, lam=float("nan")) == abi.ERR_ARG
+    assert _solve(abi, _mat(abi), o, rho=0.0) == abi.ERR_ARG
+    assert _solve(abi, _mat(abi), o, ptrs=False) == abi.ERR_ARG
+
+
+def test_precision_dtype_and_workspace(abi):
+    o = abi.default_opts()
+    o.precision = abi.PREC_F64
+    assert _solve(abi, _mat(abi), o) == abi.ERR_ARG
+    o = abi.default_opts()
+    assert _solve(abi, _mat(abi, dt=abi.DT_F64), o) == abi.ERR_UNSUPPORTED
+    o = abi.default_opts()  # no workspace
+    assert _solve(abi, _mat(abi), o) == abi.ERR_WORKSPACE
+    o.workspace, o.workspace_bytes = 0x30000000, 1024  # too small
+    assert _solve(abi, _mat(abi), o) == abi.ERR_WORKSPACE
+    o.workspace, o.workspace_bytes = 0x30000001, 1 << 40  # misaligned
+    assert _solve(abi, _mat(abi), o) == abi.ERR_WORKSPACE
+
+
+def test_nystrom_and_apply_validation(abi):
+    lib = abi.load()
+    M = _mat(abi, 30, 40)
+    o = abi.default_opts()
+    info = (abi.Info * 1)()
+    p = 0x20000000
+    assert lib.genios_nystrom_build(C.byref(M), None, 0, None, C.byref(o), p, p, info) == abi.ERR_ARG
+    assert lib.genios_nystrom_build(C.byref(M), None, 41, None, C.byref(o), p, p, info) == abi.ERR_ARG
+    assert lib.genios_nystrom_apply(10, 20, 1, abi.DT_F32, p, p, 1.0, p, p, C.byref(o)) == abi.ERR_SHAPE
+    assert lib.genios_nystrom_apply(100, 20, 1, abi.DT_F32, p, p, 0.0, p, p, C.byref(o)) == abi.ERR_ARG
+    assert lib.genios_nystrom_apply(100, 20, 1, abi.DT_F32, p, p, 1.0, p, p, C.byref(o)) == abi.ERR_WORKSPACE
+    assert lib.genios_admm_update(0, abi.DT_F32, 1.6, 0.1, p, p, p, None, C.byref(o)) == abi.ERR_SHAPE
+    assert lib.genios_matvec(C.byref(M), 2, 0, p, p, C.byref(o)) == abi.ERR_ARG
+    assert lib.genios_matvec(C.byref(M), 0, 1, p, p, C.byref(o)) == abi.ERR_ARG  # no BF16 copy
+
+
+def test_status_strings(abi):
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7):
+        assert abi.status_string(code) != "unknown status"
