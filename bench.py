@@ -1,0 +1,176 @@
+"""Benchmark of the GeNIOS hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one pass of the whole hot path over the workload: a cold-start Lasso
+solve in BF16-A + FP32-refinement precision (BF16 rounding of A, A^T b, the
+Nystrom sketch, the ADMM loop with Nystrom-preconditioned CG, the FP32 phase
+and its certification) followed by the adjoint (masked Nystrom PCG) of the loss
+||z* - x0||^2.  The data are synthetic and resident in HBM before timing.
+
+Prints one JSON line: value = ADMM iterations per second over the timed steps,
+plus time-to-1e-4 for BF16-A + refine and for plain FP32 A, the matrix-vector
+kernels' bandwidth against the HBM roofline (HIP events on the solver's
+stream), and the CPU FP64 oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "time-to-1e-4 KKT resid & ADMM iters/s: FP32 vs BF16-A; matvec HBM GB/s"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(P, rows=5000, cols=10000, budget_iters=60):
+    """The oracle's GeNIOS ADMM (exact Cholesky x-steps) on the leading rows x cols
+    block of the workload's matrix: ADMM iterations per second on the host."""
+    import threadpoolctl
+
+    from oracle import lasso as olasso
+    A = P["A"][:rows, :cols].astype(np.float64)
+    x0 = P["x0"][:cols]
+    rng = np.random.default_rng(12345)
+    b = A @ x0 + 0.1 * rng.standard_normal(rows)
+    lam = 0.05 * float(np.max(np.abs(A.T @ b)))
+    info = threadpoolctl.threadpool_info()
+    cores = max([d.get("num_threads", 1) for d in info] or [os.cpu_count() or 1])
+    t0 = time.perf_counter()
+    x, z, u, rho, hist = olasso.admm(A, b, lam, rho=1.0, alpha=1.6, sigma=1e-6,
+                                     max_iter=budget_iters, eps=1e-4, rho_update_every=25)
+    dt = time.perf_counter() - t0
+    return {"value": round(len(hist) / dt, 3), "unit": "ADMM iters/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"oracle Lasso ADMM (exact Cholesky x-step, Woodbury), leading "
+                      f"{rows}x{cols} block of the workload's A, {len(hist)} iterations "
+                      f"incl. factorisation, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="lasso_20000x40000")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import genios_data
+    import paper_2310_08333_amd as g
+
+    t0 = time.time()
+    P = genios_data.config(args.workload)
+    log(f"generated {P['name']} in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(P["A"]).to(dev)
+    b = torch.from_numpy(P["b"]).to(dev)
+    x0 = torch.from_numpy(P["x0"]).to(dev, torch.float32)
+    lam, s = P["lam"], P["s"]
+    m, n = P["A"].shape
+    torch.cuda.synchronize()
+    opts = dict(eps=1e-4, sketch_rank=s)
+
+    def step(profile):
+        out = g.lasso_solve(A, b, lam, precision="bf16_refine", profile_kernels=profile, **opts)
+        bw = None
+        if not args.no_backward:
+            gz = (2.0 * (out["z"] - x0)).contiguous()
+            bw = g.lasso_backward(A, out["z"], gz, lam, sketch_rank=s, profile_kernels=profile)
+        return out, bw
+
+    for i in range(args.warmup):
+        out, _ = step(0)
+        log(f"warmup {i}: status {out['status']} iters {out['info'][0]['iters']}")
+    torch.cuda.synchronize()
+    iters, ttt, infos, binfos = [], [], [], []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        out, bw = step(1)
+        inf = out["info"][0]
+        infos.append(inf)
+        if bw is not None:
+            binfos.append(bw[2][0])
+        iters.append(inf["iters"])
+        ttt.append(inf["t_to_target"])
+        log(f"step {i}: status {out['status']} iters {inf['iters']} cg {inf['cg_iters']} "
+            f"switch {inf['phase_switch_iter']} t_to_1e-4 {inf['t_to_target']:.4f}s "
+            f"r_kkt {inf['r_kkt']:.2e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    # matrix-vector kernels measured with HIP events on the solver's stream
+    tn = sum(i["t_matvec_n"] for i in infos) + sum(i["t_matvec_n"] for i in binfos)
+    tt = sum(i["t_matvec_t"] for i in infos) + sum(i["t_matvec_t"] for i in binfos)
+    bn = sum(i["bytes_matvec_n"] for i in infos) + sum(i["bytes_matvec_n"] for i in binfos)
+    bt = sum(i["bytes_matvec_t"] for i in infos) + sum(i["bytes_matvec_t"] for i in binfos)
+    nn = sum(i["n_matvec_n"] for i in infos) + sum(i["n_matvec_n"] for i in binfos)
+    nt = sum(i["n_matvec_t"] for i in infos) + sum(i["n_matvec_t"] for i in binfos)
+    gbs_n = bn / tn / 1e9 if tn > 0 else None
+    gbs_t = bt / tt / 1e9 if tt > 0 else None
+    dom = "gemv_t (A^T w)" if tt >= tn else "gemv_n (A v)"
+    ach = gbs_t if tt >= tn else gbs_n
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1) if ach else None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4) if ach else None, "traffic": None,
+                "gemv_n_GBps": round(gbs_n, 1) if gbs_n else None,
+                "gemv_t_GBps": round(gbs_t, 1) if gbs_t else None,
+                "launches": {"gemv_n": nn, "gemv_t": nt},
+                "avg_us": {"gemv_n": round(1e6 * tn / max(nn, 1), 2),
+                           "gemv_t": round(1e6 * tt / max(nt, 1), 2)}}
+
+    fp32 = None
+    if not args.no_fp32:
+        o32 = g.lasso_solve(A, b, lam, precision="f32", **opts)["info"][0]
+        o32 = g.lasso_solve(A, b, lam, precision="f32", **opts)["info"][0]
+        fp32 = {"time_to_1e-4_s": round(o32["t_to_target"], 4), "iters": o32["iters"],
+                "cg_iters": o32["cg_iters"], "iters_per_s": round(o32["iters"] / o32["t_total"], 2)}
+        log(f"fp32: {fp32}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(P)
+        log(f"cpu baseline: {cpu}")
+
+    value = sum(iters) / elapsed
+    rec = {
+        "metric": METRIC, "value": round(value, 3), "unit": "ADMM iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": P["name"], "m": m, "n": n, "sketch_rank": s,
+                   "precision": "bf16_refine", "step": "lasso solve + adjoint" if not args.no_backward else "lasso solve",
+                   "eps": 1e-4},
+        "time_to_1e-4_s": {"bf16_refine": round(statistics.median(ttt), 4),
+                           "fp32": fp32["time_to_1e-4_s"] if fp32 else None},
+        "admm_iters": statistics.median(iters),
+        "fp32": fp32,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -120,10 +120,11 @@ typedef struct {
   int32_t resketch_every;      /* logistic: re-sketch period in ADMM iterations, default 20 */
   int32_t precondition;        /* 1 = Nystrom preconditioner, 0 = plain CG; default 1 */
   int32_t inexact;             /* 1 = tolerance schedule of Sec. 2.1, 0 = exact (cg_tol_floor) */
-  double switch_tol;           /* BF16 -> FP32 switch when r_kkt <= switch_tol; 0 = 10 * eps */
+  double switch_tol;           /* BF16 -> FP32 switch when the BF16 problem's r_kkt <= switch_tol;
+                                  0 = max(eps_abs, eps_rel) */
   int32_t stall_window;        /* ... or when r_kkt fell < 10% over this many iterations; 10 */
-  int32_t rhs_relative;        /* CG stops at ||r|| <= rtol ||r_0|| (0, default) or
-                                  ||r|| <= rtol ||rhs|| (1) */
+  int32_t rhs_relative;        /* CG stops at ||r|| <= rtol ||rhs|| of the x-system (1, default)
+                                  or at ||r|| <= rtol ||r_0|| of the warm-started solve (0) */
   uint64_t seed;               /* key of the counter-based Gaussian test matrix */
   int32_t warm_start;          /* 1 = start from the caller's x, z, u and the rho argument */
   int32_t profile_kernels;     /* 1 = time every matrix-vector product with HIP events on
@@ -172,8 +173,8 @@ typedef struct {
   double t_matvec_t;         /* with profile_kernels: summed duration of the A^T w products */
   int32_t n_matvec_n;        /* number of A v launches (counted with or without profiling) */
   int32_t n_matvec_t;        /* number of A^T w launches */
-  int64_t bytes_matvec_lo;   /* matrix bytes streamed by products on the BF16 copy */
-  int64_t bytes_matvec_hi;   /* matrix bytes streamed by products on the master copy */
+  int64_t bytes_matvec_n;    /* matrix bytes streamed by the A v products (BF16 or master copy) */
+  int64_t bytes_matvec_t;    /* matrix bytes streamed by the A^T w products */
 } genios_info;
 
 /* Fill *o with the defaults listed above.  Returns GENIOS_OK. */
@@ -219,7 +220,9 @@ int genios_logreg_solve(const genios_matrix* A, const void* y, const double* lam
  *   lambda_hat (device) s doubles per problem, descending, >= 0 (written).
  *   info       (host) precond_rank and status per problem (written).
  * Stabilised as in the randomized Nystrom method the paper cites: a shift
- * ~ sqrt(n) * eps * ||Y||_F is added before the Cholesky factor and removed
+ * mu = eps * ||Y||_F (eps = unit roundoff of Y; equal to the published
+ * sqrt(n) eps ||Y|| for an orthonormal test matrix of the same range) is added
+ * as Y + mu Omega before the Cholesky factor and removed
  * from the eigenvalues.  If the s x s core cannot be factored after three
  * tenfold shift increases, U = 0, lambda_hat = 0 (identity preconditioner)
  * and the status is GENIOS_WARN_PRECOND. */

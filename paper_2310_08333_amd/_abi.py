@@ -69,8 +69,8 @@ class Info(C.Structure):
                 ("t_linsys", C.c_double), ("t_prox", C.c_double), ("t_total", C.c_double),
                 ("t_to_target", C.c_double), ("t_matvec_n", C.c_double),
                 ("t_matvec_t", C.c_double), ("n_matvec_n", C.c_int32),
-                ("n_matvec_t", C.c_int32), ("bytes_matvec_lo", C.c_int64),
-                ("bytes_matvec_hi", C.c_int64)]
+                ("n_matvec_t", C.c_int32), ("bytes_matvec_n", C.c_int64),
+                ("bytes_matvec_t", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -129,7 +129,7 @@ int genios_default_opts(genios_opts* o) {
   o->inexact = 1;
   o->switch_tol = 0.0;
   o->stall_window = 10;
-  o->rhs_relative = 0;
+  o->rhs_relative = 1;
   o->seed = 0x5eed2310ull;
   return GENIOS_OK;
 }

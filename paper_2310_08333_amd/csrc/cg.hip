@@ -429,9 +429,10 @@ __global__ __launch_bounds__(256) void k_logistic_elem(int64_t m, const VT* __re
                                                        const VT* __restrict__ y,
                                                        VT* __restrict__ d, VT* __restrict__ cols,
                                                        int64_t col_stride,
-                                                       const ProbParams* __restrict__ params) {
+                                                       const int32_t* __restrict__ gate,
+                                                       int gate_stride) {
   const int b = blockIdx.y;
-  if (params && !params[b].run) return;
+  if (gate != nullptr && gate[(int64_t)b * gate_stride] == 0) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
        i += (int64_t)gridDim.x * blockDim.x) {
     VT t = VT(0);
@@ -613,20 +614,20 @@ hipError_t launch_objective_m(VType vt, int64_t m, int64_t batch, const void* tp
 
 hipError_t launch_logistic_elem(VType vt, int64_t m, int64_t batch, const void* tparts, int nsplit,
                                 int64_t split_stride, int64_t prob_stride, const void* y, void* d,
-                                void* cols, int64_t col_stride, const ProbParams* params,
-                                hipStream_t st) {
+                                void* cols, int64_t col_stride, const int32_t* gate,
+                                int gate_stride, hipStream_t st) {
   const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((m + 255) / 256, 512));
   dim3 grid(nb, (unsigned)batch);
   if (vt == VT_F32)
     hipLaunchKernelGGL(k_logistic_elem<float>, grid, dim3(256), 0, st, m,
                        static_cast<const float*>(tparts), nsplit, split_stride, prob_stride,
                        static_cast<const float*>(y), static_cast<float*>(d),
-                       static_cast<float*>(cols), col_stride, params);
+                       static_cast<float*>(cols), col_stride, gate, gate_stride);
   else
     hipLaunchKernelGGL(k_logistic_elem<double>, grid, dim3(256), 0, st, m,
                        static_cast<const double*>(tparts), nsplit, split_stride, prob_stride,
                        static_cast<const double*>(y), static_cast<double*>(d),
-                       static_cast<double*>(cols), col_stride, params);
+                       static_cast<double*>(cols), col_stride, gate, gate_stride);
   return hipGetLastError();
 }
 

@@ -243,7 +243,7 @@ struct Ctx {
   int gs_state = sizeof(ProbState) / 4, gs_params = sizeof(ProbParams) / 4;
   KernelProf prof;
   int64_t n_mv[2] = {0, 0};
-  int64_t bytes_lo = 0, bytes_hi = 0;
+  int64_t bytes_kind[2] = {0, 0};  // matrix bytes of A v / A^T w products
 
   void* vecp(int k) const { return L.nv[k]; }
   VecArgs vargs(void* x, void* z, void* u, void* h, void* g, void* c, const uint8_t* mask) const {
@@ -276,11 +276,7 @@ struct Ctx {
 
   void account(const MatArg& op, int kind) {
     n_mv[kind] += B;
-    const int64_t bytes = (int64_t)B * op.m * op.n * elem_size(op.mt);
-    if (op.mt == MT_BF16)
-      bytes_lo += bytes;
-    else
-      bytes_hi += bytes;
+    bytes_kind[kind] += (int64_t)B * op.m * op.n * elem_size(op.mt);
   }
 
   // tparts = A v (gated)
@@ -498,8 +494,8 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     int r = c.gemv_n(opx, x, gate, gstride);
     if (r) return r;
     HC(launch_logistic_elem(c.vt, m, B, c.L.tparts, c.nsplit_for(opx, 0), m,
-                            (int64_t)c.L.nsplit_n * m, bvec, c.L.dvec, c.L.cols, m, nullptr,
-                            c.st));
+                            (int64_t)c.L.nsplit_n * m, bvec, c.L.dvec, c.L.cols, m, gate,
+                            gstride, c.st));
     HC(c.prof.begin(c.st, 1));
     const int ks = c.nsplit_for(opx, 1);
     HC(launch_gemv_t(opx, B, c.vt, c.L.cols, 1, 0, 2 * m, m, 2, nullptr, 0, c.L.ypart, ks,
@@ -547,7 +543,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
 
   // ---- ADMM loop ----
   const double eps_abs = o->eps_abs, eps_rel = o->eps_rel;
-  const double switch_tol = o->switch_tol > 0 ? o->switch_tol : 10.0 * std::max(eps_abs, eps_rel);
+  const double switch_tol = o->switch_tol > 0 ? o->switch_tol : std::max(eps_abs, eps_rel);
   double t_linsys = 0.0, t_prox = 0.0;
   const double t_loop0 = now_s();
   int any_numeric = 0;
@@ -634,7 +630,10 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
       q.rd = std::sqrt(S.red[kRedRd2]);
       const double rhou = q.rho * q.un;
       q.rkkt = kkt_from(q.rp, q.rd, q.xn, q.zn, rhou, n);
-      if (!std::isfinite(q.rkkt) || (S.breakdown && !std::isfinite(S.pq))) {
+      const bool finite = std::isfinite(q.rp) && std::isfinite(q.rd) && std::isfinite(q.xn) &&
+                          std::isfinite(q.zn) && std::isfinite(q.un) && std::isfinite(S.rr) &&
+                          std::isfinite(S.rhs2);
+      if (!finite || !std::isfinite(q.rkkt) || (S.breakdown && !std::isfinite(S.pq))) {
         q.status = GENIOS_ERR_NUMERIC;
         q.done = 1;
         any_numeric = 1;
@@ -807,8 +806,8 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     I.t_matvec_t = c.prof.t[1];
     I.n_matvec_n = (int32_t)c.n_mv[0];
     I.n_matvec_t = (int32_t)c.n_mv[1];
-    I.bytes_matvec_lo = c.bytes_lo;
-    I.bytes_matvec_hi = c.bytes_hi;
+    I.bytes_matvec_n = c.bytes_kind[0];
+    I.bytes_matvec_t = c.bytes_kind[1];
     if (st < 0 && (worst >= 0 || st < worst)) worst = st;
     if (worst >= 0 && st > worst) worst = st;
   }
@@ -1014,7 +1013,8 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
       info[b].t_matvec_t = c.prof.t[1];
       info[b].n_matvec_n = (int32_t)c.n_mv[0];
       info[b].n_matvec_t = (int32_t)c.n_mv[1];
-      info[b].bytes_matvec_hi = c.bytes_hi;
+      info[b].bytes_matvec_n = c.bytes_kind[0];
+      info[b].bytes_matvec_t = c.bytes_kind[1];
     }
     if (st < 0 && (worst >= 0 || st < worst)) worst = st;
     if (worst >= 0 && st > worst) worst = st;

@@ -153,8 +153,8 @@ hipError_t launch_objective_m(VType vt, int64_t m, int64_t batch, const void* tp
 // d = s(1-s) and the two right-hand columns: col0 = d o t, col1 = -y o s.
 hipError_t launch_logistic_elem(VType vt, int64_t m, int64_t batch, const void* tparts, int nsplit,
                                 int64_t split_stride, int64_t prob_stride, const void* y, void* d,
-                                void* cols, int64_t col_stride, const ProbParams* params,
-                                hipStream_t st);
+                                void* cols, int64_t col_stride, const int32_t* gate,
+                                int gate_stride, hipStream_t st);
 // Stand-alone fused ADMM update test hook.
 hipError_t launch_admm_update_hook(VType vt, int64_t n, double alpha, double kappa, const void* x,
                                    void* z, void* u, double* part, unsigned* counter,

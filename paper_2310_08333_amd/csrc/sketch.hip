@@ -5,7 +5,10 @@
 //   3. Y = A^T (d o W)        (n x s)   tiled GEMM, split over m      => Y = H Omega
 //   4. FP64 Grams  Omega^T Y, Omega^T Omega, Y^T Y (s x s)
 //   5. s x s core in one workgroup (FP64): with the stabilising shift
-//      mu = sqrt(n) eps ||Y||_F and Y_mu = Y + mu Omega,
+//      mu = eps ||Y||_F and Y_mu = Y + mu Omega (the published shift
+//      sqrt(n) eps ||Y|| of the stabilised Nystrom method assumes an
+//      orthonormal test matrix; a Gaussian Omega with the same range has
+//      columns of norm ~sqrt(n), and the equivalent shift is eps ||Y||_F),
 //        M = Omega^T Y_mu = C C^T (Cholesky; shift x10 on failure, <= 3 times),
 //        G = C^-1 (Y_mu^T Y_mu) C^-T = V Sigma^2 V^T (cyclic Jacobi),
 //        lambda_hat = max(Sigma^2 - mu, 0), T = C^-T V Sigma^-1,
@@ -370,7 +373,8 @@ __global__ __launch_bounds__(256) void k_nystrom_core(int s, int64_t n, double e
     }
     return;
   }
-  if (tid == 0) s_shift = sqrt((double)n) * eps * sqrt(trace3);
+  if (tid == 0) s_shift = eps * sqrt(trace3);
+  (void)n;
   __syncthreads();
 
   bool ok = false;
