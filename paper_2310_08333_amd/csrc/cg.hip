@@ -41,14 +41,30 @@ __device__ __forceinline__ VT soft_threshold(VT v, VT k) {
 template <typename VT>
 __device__ void ut_r_partial(const VT* __restrict__ Ub, int64_t n, int s_eff, const Chunk& ch,
                              const VT* rs, double* part_out) {
+  // wave w owns columns w, w+4, ...; each lane keeps one accumulator per column so
+  // the column loads of a row are independent and pipeline
+  constexpr int JMAX = kMaxS / 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int len = (int)(ch.hi - ch.lo);
-  for (int j = wave; j < s_eff; j += 4) {
-    const VT* col = Ub + (int64_t)j * n + ch.lo;
-    double acc = 0.0;
-    for (int i = lane; i < len; i += 64) acc += double(col[i]) * double(rs[i]);
-    acc = wave_sum(acc);
-    if (lane == 0) part_out[j] = acc;
+  const VT* base = Ub + ch.lo;
+  double acc[JMAX];
+#pragma unroll
+  for (int jj = 0; jj < JMAX; ++jj) acc[jj] = 0.0;
+  for (int i = lane; i < len; i += 64) {
+    const double r = double(rs[i]);
+#pragma unroll
+    for (int jj = 0; jj < JMAX; ++jj) {
+      const int j = wave + 4 * jj;
+      if (j < s_eff) acc[jj] += double(base[(int64_t)j * n + i]) * r;
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < JMAX; ++jj) {
+    const int j = wave + 4 * jj;
+    if (j < s_eff) {
+      const double v = wave_sum(acc[jj]);
+      if (lane == 0) part_out[j] = v;
+    }
   }
 }
 
@@ -64,10 +80,18 @@ __device__ void finish_coef(const double* part_b, int nb, int s_eff, const doubl
   }
 }
 
-__device__ double sum_scalar(const double* part_b, int nb, int slot) {
-  double s = 0.0;
-  for (int k = 0; k < nb; ++k) s += load_partial(part_b + (int64_t)k * kPartW + kMaxS + slot);
-  return s;
+// Fixed-order parallel sum of NV scalar slots over the nb block partials of one
+// problem.  Called by every thread of the last block; the result is valid in
+// thread 0.
+template <int NV>
+__device__ void sum_slots(const double* part_b, int nb, int slot0, double (&v)[NV],
+                          double* smem) {
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = 0.0;
+  for (int k = threadIdx.x; k < nb; k += blockDim.x)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] += load_partial(part_b + (int64_t)k * kPartW + kMaxS + slot0 + q);
+  block_sum<NV>(v, smem);
 }
 
 template <typename VT>
@@ -125,9 +149,11 @@ __global__ __launch_bounds__(256) void k_admm_begin(VecArgs a) {
   if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntBegin, a.nb)) return;
   finish_coef(part_b, a.nb, s_eff, a.ctrl.lamhat + (int64_t)b * a.ctrl.s_stride, P.nu,
               a.ctrl.coef + (int64_t)b * kMaxS);
+  double tv[2];
+  sum_slots<2>(part_b, a.nb, 0, tv, red);
   if (threadIdx.x == 0) {
-    const double trhs2 = sum_scalar(part_b, a.nb, 0);
-    const double tr2 = sum_scalar(part_b, a.nb, 1);
+    const double trhs2 = tv[0];
+    const double tr2 = tv[1];
     double tol2 = P.rtol * P.rtol * (P.rhs_rel ? trhs2 : tr2);
     tol2 = fmax(tol2, P.tol_floor * P.tol_floor * trhs2);
     S->rhs2 = trhs2;
@@ -178,8 +204,10 @@ __global__ __launch_bounds__(256) void k_precond_step(VecArgs a, int init) {
   double* part_b = a.ctrl.part + (int64_t)b * a.ctrl.part_stride;
   if (threadIdx.x == 0) part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 2] = v[0];
   if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntPrecond, a.nb)) return;
+  double tv[1];
+  sum_slots<1>(part_b, a.nb, 2, tv, red);
   if (threadIdx.x == 0) {
-    const double t = sum_scalar(part_b, a.nb, 2);
+    const double t = tv[0];
     if (init) {
       S->rz = t;
     } else {
@@ -224,8 +252,10 @@ __global__ __launch_bounds__(256) void k_cg_alpha(VecArgs a) {
   double* part_b = a.ctrl.part + (int64_t)b * a.ctrl.part_stride;
   if (threadIdx.x == 0) part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 3] = v[0];
   if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntAlpha, a.nb)) return;
+  double tv[1];
+  sum_slots<1>(part_b, a.nb, 3, tv, red);
   if (threadIdx.x == 0) {
-    const double t = sum_scalar(part_b, a.nb, 3);
+    const double t = tv[0];
     S->pq = t;
     if (!(t > 0.0) || !(t <= 1.0e300)) {
       S->breakdown = 1;
@@ -277,8 +307,10 @@ __global__ __launch_bounds__(256) void k_cg_update(VecArgs a) {
   if (threadIdx.x == 0) part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 4] = v[0];
   if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntUpdate, a.nb)) return;
   __shared__ int s_go;
+  double tv[1];
+  sum_slots<1>(part_b, a.nb, 4, tv, red);
   if (threadIdx.x == 0) {
-    const double t = sum_scalar(part_b, a.nb, 4);
+    const double t = tv[0];
     S->rr = t;
     S->cg_iters += 1;
     int go = 1;
@@ -354,8 +386,10 @@ __global__ __launch_bounds__(256) void k_admm_end(VecArgs a) {
   if (threadIdx.x == 0)
     for (int k = 0; k < 7; ++k) part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 5 + k] = v[k];
   if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntEnd, a.nb)) return;
+  double tv[7];
+  sum_slots<7>(part_b, a.nb, 5, tv, red);
   if (threadIdx.x == 0) {
-    for (int k = 0; k < 7; ++k) S->red[k] = sum_scalar(part_b, a.nb, 5 + k);
+    for (int k = 0; k < 7; ++k) S->red[k] = tv[k];
     S->admm_done = 1;
   }
 }
@@ -385,7 +419,9 @@ __global__ __launch_bounds__(256) void k_dual_residual(VecArgs a) {
   double* part_b = a.ctrl.part + (int64_t)b * a.ctrl.part_stride;
   if (threadIdx.x == 0) part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 12] = v[0];
   if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntAux0, a.nb)) return;
-  if (threadIdx.x == 0) S->red[kRedRd2] = sum_scalar(part_b, a.nb, 12);
+  double tv[1];
+  sum_slots<1>(part_b, a.nb, 12, tv, red);
+  if (threadIdx.x == 0) S->red[kRedRd2] = tv[0];
 }
 
 // Objective over the m samples from partials of t = A z.
@@ -417,7 +453,9 @@ __global__ __launch_bounds__(256) void k_objective_m(int64_t m, const VT* __rest
   double* pb = ctrl.part + (int64_t)b * ctrl.part_stride;
   if (threadIdx.x == 0) pb[(int64_t)blockIdx.x * kPartW + kMaxS + 13] = v[0];
   if (!last_block_arrive(ctrl.counters + (int64_t)b * kNumCounters + kCntObj, nb)) return;
-  if (threadIdx.x == 0) ctrl.state[b].red[kRedAux] = sum_scalar(pb, nb, 13);
+  double tv[1];
+  sum_slots<1>(pb, nb, 13, tv, red);
+  if (threadIdx.x == 0) ctrl.state[b].red[kRedAux] = tv[0];
 }
 
 // Logistic elementwise terms: w = -y t, s = sigmoid(w), d = s (1 - s),
@@ -565,7 +603,9 @@ __global__ __launch_bounds__(256) void k_masked_dot(int64_t n, const VT* __restr
   double* pb = part + (int64_t)b * part_stride;
   if (threadIdx.x == 0) pb[(int64_t)blockIdx.x * kPartW + kMaxS + 14] = v[0];
   if (!last_block_arrive(counters + (int64_t)b * kNumCounters + kCntMasked, nb)) return;
-  if (threadIdx.x == 0) out[b] = sum_scalar(pb, nb, 14);
+  double tv[1];
+  sum_slots<1>(pb, nb, 14, tv, red);
+  if (threadIdx.x == 0) out[b] = tv[0];
 }
 
 }  // namespace
@@ -705,6 +745,123 @@ hipError_t launch_masked_dot(VType vt, int64_t n, int64_t batch, const void* a, 
     hipLaunchKernelGGL(k_masked_dot<double>, grid, dim3(256), 0, st, n,
                        static_cast<const double*>(a), static_cast<const double*>(b), part,
                        part_stride, counters, out, nb);
+  return hipGetLastError();
+}
+
+}  // namespace genios
+
+// ---- active-set compaction for the adjoint ---------------------------------------
+namespace genios {
+
+namespace {
+
+// idx[b][0..cnt) = positions of the nonzero mask entries of problem b, in order.
+// One 1024-thread block per problem: per-thread counts, a block scan in LDS,
+// then ordered writes (deterministic).
+__global__ __launch_bounds__(1024) void k_compact_index(int64_t n, const uint8_t* __restrict__ mask,
+                                                        int32_t* __restrict__ idx,
+                                                        int32_t* __restrict__ cnt) {
+  __shared__ int32_t sc[1024];
+  const int b = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
+  const int64_t per = (n + nt - 1) / nt;
+  const int64_t lo = min(n, (int64_t)t * per), hi = min(n, lo + per);
+  const uint8_t* mb = mask + (int64_t)b * n;
+  int32_t c = 0;
+  for (int64_t i = lo; i < hi; ++i) c += mb[i] ? 1 : 0;
+  sc[t] = c;
+  __syncthreads();
+  for (int off = 1; off < nt; off <<= 1) {  // inclusive Hillis-Steele scan
+    const int32_t v = t >= off ? sc[t - off] : 0;
+    __syncthreads();
+    sc[t] += v;
+    __syncthreads();
+  }
+  int32_t pos = sc[t] - c;
+  int32_t* ib = idx + (int64_t)b * n;
+  for (int64_t i = lo; i < hi; ++i)
+    if (mb[i]) ib[pos++] = (int32_t)i;
+  if (t == nt - 1) cnt[b] = sc[t];
+}
+
+// out[b] (m x ldS, row-major) = columns idx[b][0..cnt) of A[b], zero padding.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_cols(const T* __restrict__ A, int64_t lda,
+                                                     int64_t strideA, int64_t m, int64_t n,
+                                                     const int32_t* __restrict__ idx,
+                                                     const int32_t* __restrict__ cnt, int ldS,
+                                                     T* __restrict__ out) {
+  const int b = blockIdx.y;
+  const int c = cnt[b];
+  const T* Ab = A + (int64_t)b * strideA;
+  const int32_t* ib = idx + (int64_t)b * n;
+  T* ob = out + (int64_t)b * m * ldS;
+  const int64_t total = m * (int64_t)ldS;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / ldS;
+    const int k = (int)(e - r * ldS);
+    ob[e] = k < c ? Ab[r * lda + ib[k]] : T(0);
+  }
+}
+
+// out[b][k] = in[b][idx[b][k]] for k < cnt[b], 0 after (length ldS); mask_out[b][k] = k < cnt[b].
+template <typename VT>
+__global__ __launch_bounds__(256) void k_gather_vec(int64_t n, const int32_t* __restrict__ idx,
+                                                    const int32_t* __restrict__ cnt, int ldS,
+                                                    const VT* __restrict__ in0, VT* __restrict__ out0,
+                                                    const VT* __restrict__ in1, VT* __restrict__ out1,
+                                                    uint8_t* __restrict__ mask_out) {
+  const int b = blockIdx.y;
+  const int c = cnt[b];
+  const int32_t* ib = idx + (int64_t)b * n;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ldS; k += gridDim.x * blockDim.x) {
+    const bool on = k < c;
+    const int64_t src = on ? ib[k] : 0;
+    out0[(int64_t)b * ldS + k] = on ? in0[(int64_t)b * n + src] : VT(0);
+    out1[(int64_t)b * ldS + k] = on ? in1[(int64_t)b * n + src] : VT(0);
+    mask_out[(int64_t)b * ldS + k] = on ? 1 : 0;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_compact_index(int64_t n, int64_t batch, const uint8_t* mask, int32_t* idx,
+                                int32_t* cnt, hipStream_t st) {
+  hipLaunchKernelGGL(k_compact_index, dim3((unsigned)batch), dim3(1024), 0, st, n, mask, idx, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_cols(MType mt, const void* A, int64_t lda, int64_t strideA, int64_t m,
+                              int64_t n, int64_t batch, const int32_t* idx, const int32_t* cnt,
+                              int ldS, void* out, hipStream_t st) {
+  const int64_t total = m * (int64_t)ldS;
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 8192));
+  dim3 grid(nb, (unsigned)batch);
+  if (mt == MT_F32)
+    hipLaunchKernelGGL(k_gather_cols<float>, grid, dim3(256), 0, st, static_cast<const float*>(A),
+                       lda, strideA, m, n, idx, cnt, ldS, static_cast<float*>(out));
+  else if (mt == MT_F64)
+    hipLaunchKernelGGL(k_gather_cols<double>, grid, dim3(256), 0, st,
+                       static_cast<const double*>(A), lda, strideA, m, n, idx, cnt, ldS,
+                       static_cast<double*>(out));
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_vec(VType vt, int64_t n, int64_t batch, const int32_t* idx,
+                             const int32_t* cnt, int ldS, const void* in0, void* out0,
+                             const void* in1, void* out1, uint8_t* mask_out, hipStream_t st) {
+  const unsigned nb = (unsigned)std::max(1, std::min((ldS + 255) / 256, 1024));
+  dim3 grid(nb, (unsigned)batch);
+  if (vt == VT_F32)
+    hipLaunchKernelGGL(k_gather_vec<float>, grid, dim3(256), 0, st, n, idx, cnt, ldS,
+                       static_cast<const float*>(in0), static_cast<float*>(out0),
+                       static_cast<const float*>(in1), static_cast<float*>(out1), mask_out);
+  else
+    hipLaunchKernelGGL(k_gather_vec<double>, grid, dim3(256), 0, st, n, idx, cnt, ldS,
+                       static_cast<const double*>(in0), static_cast<double*>(out0),
+                       static_cast<const double*>(in1), static_cast<double*>(out1), mask_out);
   return hipGetLastError();
 }
 

@@ -117,6 +117,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* smem /* >= 4*
 // Returns true in every thread of the last block, which also resets the counter.
 __device__ __forceinline__ bool last_block_arrive(unsigned* counter, unsigned nblocks) {
   __shared__ int s_last;
+  // every wave may have written partials: release them at agent scope first
+  __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
@@ -132,9 +134,9 @@ __device__ __forceinline__ bool last_block_arrive(unsigned* counter, unsigned nb
   return last;
 }
 
-// Coherent load of a partial written by another block in the same kernel.
-__device__ __forceinline__ double load_partial(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// Load of a partial written by another block of the same kernel.  Only used by
+// the last block after last_block_arrive(), whose agent-scope acquire fence
+// invalidates this CU's vector L1, so a plain (pipelined) load is coherent.
+__device__ __forceinline__ double load_partial(const double* p) { return *p; }
 
 }  // namespace genios

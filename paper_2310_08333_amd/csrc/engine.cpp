@@ -108,7 +108,13 @@ void Layout::carve(Arena& ar) {
     dvec = vec(m);
     cols = ar.take((size_t)B * 2 * m * ve);
   }
-  if (backward) mask = static_cast<uint8_t*>(ar.take((size_t)B * n));
+  if (backward) {
+    mask = static_cast<uint8_t*>(ar.take((size_t)B * n));
+    idx = static_cast<int32_t*>(ar.take((size_t)B * n * sizeof(int32_t)));
+    cnt = static_cast<int32_t*>(ar.take((size_t)B * sizeof(int32_t)));
+    AS = ar.take((size_t)B * m * ldS_max * ve);
+    maskS = static_cast<uint8_t*>(ar.take((size_t)B * ldS_max));
+  }
   if (s > 0) {
     U = vec(n * (int64_t)s);
     const int sp = sketch_pad(s);
@@ -151,6 +157,7 @@ int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_)
   nb = (int)((n + chunk - 1) / chunk);
   part_blocks = std::max<int>(nb, std::max<int>(kMaxVecBlocks, (int)((n + kVecChunk - 1) / kVecChunk)));
   n_vecs = (op == GENIOS_OP_MATVEC || op == GENIOS_OP_NYSTROM) ? 0 : kNumNVec;
+  ldS_max = backward ? (int)((std::min(m, n) + 7) / 8 * 8) : 0;
   if (s > 0) sketch_ws_bytes(m, n, s, batch, vt, &sk.ksW, &sk.ksY, &sk.nbG);
   Arena ar{nullptr, 0, 0, true};
   carve(ar);
@@ -908,7 +915,12 @@ int run_matvec(const genios_matrix* A, int trans, int use_bf16, const void* v, v
 }
 
 // ---------------------------------------------------------------------------------
-// Adjoint: solve (P_S A^T A P_S + (I - P_S)) w = P_S g by masked Nystrom PCG.
+// Adjoint.  With S the support of z*, s its signs and g = dL/dz*, the solution
+// map's derivatives are dL/db = A_S G^-1 g_S and dL/dlam = -s^T G^-1 g_S with
+// G = A_S^T A_S.  The active set is compacted on the device (ordered indices,
+// columns of the master copy gathered into an m x ldS block, zero padding); the
+// system (G on S, identity on the padding) is solved by Nystrom-preconditioned
+// CG with the masked kernels, so every CG product streams only m x |S| values.
 
 int run_backward(const genios_matrix* A, const void* zstar, const void* gz, const genios_opts* o,
                  void* grad_b, double* grad_lambda, genios_info* info) {
@@ -922,33 +934,76 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
   c.n = A->n;
   c.vt = A->hi_dtype == GENIOS_DT_F64 ? VT_F64 : VT_F32;
   c.ve = c.vt == VT_F32 ? 4 : 8;
-  const int s = o->precondition ? effective_rank(o, A->n, A->m) : 0;
-  c.L.setup(GENIOS_OP_BACKWARD, A, o, s);
+  const int s_req = o->precondition ? effective_rank(o, A->n, A->m) : 0;
+  c.L.setup(GENIOS_OP_BACKWARD, A, o, s_req);
   int rc = c.L.bind(o->workspace, o->workspace_bytes);
   if (rc) return rc;
   c.prof.on = o->profile_kernels != 0;
-  c.op_hi = MatArg{A->A_hi, c.vt == VT_F64 ? MT_F64 : MT_F32, A->m, A->n, A->lda, A->stride_A};
+  const MType mt = c.vt == VT_F64 ? MT_F64 : MT_F32;
+  c.op_hi = MatArg{A->A_hi, mt, A->m, A->n, A->lda, A->stride_A};
   c.gate_cg = &c.L.ctrl.state[0].cg_active;
   const int64_t B = c.B, n = c.n, m = c.m;
   HC(launch_fill(c.L.ctrl.params, c.L.ctrl_bytes_end, c.st));
+  void* sgn_full = c.L.nv[kVR];
+  void* neg_full = c.L.nv[kVW];
+  HC(launch_build_mask(c.vt, n, B, zstar, gz, c.L.mask, sgn_full, neg_full, c.st));
+  HC(launch_compact_index(n, B, c.L.mask, c.L.idx, c.L.cnt, c.st));
+  std::vector<int32_t> cnt(B);
+  HC(hipMemcpyAsync(cnt.data(), c.L.cnt, B * sizeof(int32_t), hipMemcpyDeviceToHost, c.st));
+  HC(hipStreamSynchronize(c.st));
+  int cmax = 0;
+  for (int64_t b = 0; b < B; ++b) cmax = std::max(cmax, cnt[b]);
+  if (cmax > std::min<int64_t>(m, n)) {
+    set_error("active set larger than the number of rows: A_S^T A_S is singular");
+    return GENIOS_ERR_NUMERIC;
+  }
+  std::vector<double> gl(B, 0.0);
+  std::vector<int32_t> se(B, 0);
+  std::vector<ProbState> hsv(B);
+  ProbState* hs = hsv.data();
+  if (cmax == 0) {  // z* = 0 for every problem: the solution map is locally constant
+    HC(launch_fill(grad_b, B * m * c.ve, c.st));
+    HC(hipStreamSynchronize(c.st));
+    for (int64_t b = 0; b < B; ++b) {
+      grad_lambda[b] = 0.0;
+      if (info) std::memset(&info[b], 0, sizeof(genios_info));
+    }
+    return 0;
+  }
+  // padded to a multiple of 8 (vector loads) but never beyond n, the capacity of
+  // the n-vector workspace slots reused for the compact vectors
+  const int ldS = (int)std::min<int64_t>((cmax + 7) / 8 * 8, n);
+  // compact problem: A_S (m x ldS), g_S, signs, padding mask
+  void* sgnS = c.L.nv[kVCH];
+  void* negS = c.L.nv[kVG];
+  HC(launch_gather_vec(c.vt, n, B, c.L.idx, c.L.cnt, ldS, neg_full, negS, sgn_full, sgnS,
+                       c.L.maskS, c.st));
+  HC(launch_gather_cols(mt, A->A_hi, A->lda, A->stride_A, m, n, B, c.L.idx, c.L.cnt, ldS, c.L.AS,
+                        c.st));
+  const MatArg opS{c.L.AS, mt, m, ldS, ldS, m * (int64_t)ldS};
   void* w = c.L.nv[kVX];
   void* zero_z = c.L.nv[kVZ];
   void* zero_u = c.L.nv[kVU];
   void* h = c.L.nv[kVH];
-  void* ng = c.L.nv[kVG];
-  void* sgn = c.L.nv[kVCH];
-  HC(launch_fill(w, B * n * c.ve, c.st));
-  HC(launch_fill(zero_z, B * n * c.ve, c.st));
-  HC(launch_fill(zero_u, B * n * c.ve, c.st));
-  HC(launch_fill(h, B * n * c.ve, c.st));
-  HC(launch_build_mask(c.vt, n, B, zstar, gz, c.L.mask, sgn, ng, c.st));
+  HC(launch_fill(w, B * ldS * c.ve, c.st));
+  HC(launch_fill(zero_z, B * ldS * c.ve, c.st));
+  HC(launch_fill(zero_u, B * ldS * c.ve, c.st));
+  HC(launch_fill(h, B * ldS * c.ve, c.st));
+  // sketch of the compact operator (padding rows of Omega and Y masked)
+  const int s = std::min(s_req, ldS);
   if (s > 0) {
-    HC(run_nystrom(c.op_hi, B, c.vt, nullptr, m, s, nullptr, o->seed, 0, c.L.mask, c.L.sk, c.L.U,
+    SketchWs skc = c.L.sk;
+    int kw = 1, ky = 1, ng = 1;
+    sketch_ws_bytes(m, ldS, s, B, c.vt, &kw, &ky, &ng);
+    skc.ksW = std::max(1, std::min(kw, c.L.sk.ksW));
+    skc.ksY = std::max(1, std::min<int>(ky, (int)((int64_t)c.L.sk.ksY * n / ldS)));
+    skc.nbG = std::max(1, std::min(ng, c.L.sk.nbG));
+    if (sketch_pad(s) > sketch_pad(c.L.s)) return GENIOS_ERR_DEVICE;  // cannot happen: s <= s_req
+    HC(run_nystrom(opS, B, c.vt, nullptr, m, s, nullptr, o->seed, 0, c.L.maskS, skc, c.L.U,
                    c.L.ctrl.lamhat, c.L.ctrl.s_eff, c.L.core_status, c.L.shift, c.st));
   }
-  ProbParams* hp = static_cast<ProbParams*>(pinned(B * (sizeof(ProbParams) + sizeof(ProbState))));
+  ProbParams* hp = static_cast<ProbParams*>(pinned(B * sizeof(ProbParams)));
   if (!hp) return GENIOS_ERR_DEVICE;
-  ProbState* hs = reinterpret_cast<ProbState*>(hp + B);
   for (int64_t b = 0; b < B; ++b) {
     ProbParams& q = hp[b];
     std::memset(&q, 0, sizeof(q));
@@ -966,14 +1021,43 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
     q.use_c = 0;
   }
   HC(upload_params(c, hp));
-  VecArgs va = c.vargs(w, zero_z, zero_u, h, ng, nullptr, c.L.mask);
+  // vector-kernel geometry of the compact problem
+  VecArgs va = c.vargs(w, zero_z, zero_u, h, negS, nullptr, c.L.maskS);
+  va.n = ldS;
+  va.chunk = std::min<int64_t>(4 * kVecChunk, std::max<int64_t>(256, ((ldS + 127) / 128 + 255) / 256 * 256));
+  va.nb = (int)((ldS + va.chunk - 1) / va.chunk);
+  va.U = s > 0 ? c.L.U : nullptr;
+  va.s_stride = std::max(1, s);
+  const int nsS = std::min(gemv_n_splits(opS, B), c.L.nsplit_n);
+  const int ksS = std::max(
+      1, std::min<int>(gemv_t_splits(opS, B), (int)((int64_t)c.L.ksplit * c.L.nrhs * c.L.npad / ldS)));
+  va.ksplit = ksS;
+  va.ypart_ks_stride = ldS;
+  va.ypart_prob_stride = (int64_t)ksS * ldS;
+  // the lamhat stride used by the kernels must match the compact sketch rank
+  va.ctrl.s_stride = std::max(1, s);
   HC(launch_admm_begin(va, c.st));
   HC(launch_precond_step(va, 1, c.st));
-  int total_cg = 0;
-  int chunk = 8;
+  auto hvp_cg = [&]() -> int {
+    HC(c.prof.begin(c.st, 0));
+    HC(launch_gemv_n(opS, B, c.vt, va.p, ldS, c.L.tparts, m, (int64_t)c.L.nsplit_n * m, nsS,
+                     c.gate_cg, c.gs_state, c.st));
+    HC(c.prof.end(c.st));
+    c.account(opS, 0);
+    HC(c.prof.begin(c.st, 1));
+    HC(launch_gemv_t(opS, B, c.vt, c.L.tparts, nsS, m, (int64_t)c.L.nsplit_n * m, 0, 1, nullptr, 0,
+                     c.L.ypart, ksS, ldS, ldS, (int64_t)ksS * ldS, c.gate_cg, c.gs_state, c.st));
+    HC(c.prof.end(c.st));
+    c.account(opS, 1);
+    HC(launch_cg_alpha(va, c.st));
+    HC(launch_cg_update(va, c.st));
+    HC(launch_precond_step(va, 0, c.st));
+    HC(launch_p_update(va, c.st));
+    return 0;
+  };
   for (;;) {
-    for (int it = 0; it < chunk; ++it) {
-      rc = cg_iteration(c, c.op_hi, va, nullptr);
+    for (int it = 0; it < 8; ++it) {
+      rc = hvp_cg();
       if (rc) return rc;
     }
     rc = sync_state(c, hs);
@@ -983,30 +1067,31 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
       if (hs[b].cg_active) more = true;
     if (!more) break;
   }
-  // grad_b = A (P_S w); grad_lambda = -s^T w
-  rc = c.gemv_n(c.op_hi, w, nullptr, 0);
-  if (rc) return rc;
-  HC(launch_sum_splits(c.vt, B, m, c.L.tparts, c.nsplit_for(c.op_hi, 0), m,
-                       (int64_t)c.L.nsplit_n * m, grad_b, m, c.st));
-  HC(launch_masked_dot(c.vt, n, B, sgn, w, c.L.ctrl.part, c.L.ctrl.part_stride, c.L.ctrl.counters,
-                       c.L.scal, c.st));
-  std::vector<double> gl(B);
-  std::vector<int32_t> se(B, 0);
+  // grad_b = A_S w_S; grad_lambda = -s_S^T w_S
+  rc = 0;
+  HC(launch_gemv_n(opS, B, c.vt, w, ldS, c.L.tparts, m, (int64_t)c.L.nsplit_n * m, nsS, nullptr, 0,
+                   c.st));
+  c.account(opS, 0);
+  HC(launch_sum_splits(c.vt, B, m, c.L.tparts, nsS, m, (int64_t)c.L.nsplit_n * m, grad_b, m, c.st));
+  HC(launch_masked_dot(c.vt, ldS, B, sgnS, w, c.L.ctrl.part, c.L.ctrl.part_stride,
+                       c.L.ctrl.counters, c.L.scal, c.st));
   HC(hipMemcpyAsync(gl.data(), c.L.scal, B * sizeof(double), hipMemcpyDeviceToHost, c.st));
   if (s > 0) HC(hipMemcpyAsync(se.data(), c.L.ctrl.s_eff, B * 4, hipMemcpyDeviceToHost, c.st));
   HC(hipStreamSynchronize(c.st));
   int worst = 0;
   for (int64_t b = 0; b < B; ++b) {
     grad_lambda[b] = -gl[b];
-    total_cg = hs[b].cg_iters;
     int st = 0;
-    if (hs[b].breakdown && !(hs[b].rr <= 1e300)) st = GENIOS_ERR_NUMERIC;
-    else if (hs[b].rr > hs[b].tol2) st = GENIOS_MAX_ITER;
+    if (hs[b].breakdown && !(hs[b].rr <= 1e300))
+      st = GENIOS_ERR_NUMERIC;
+    else if (hs[b].rr > hs[b].tol2)
+      st = GENIOS_MAX_ITER;
     if (info) {
       std::memset(&info[b], 0, sizeof(genios_info));
       info[b].status = st;
-      info[b].cg_iters = total_cg;
+      info[b].cg_iters = hs[b].cg_iters;
       info[b].precond_rank = se[b];
+      info[b].iters = cnt[b];  // active-set size
       info[b].r_d = std::sqrt(hs[b].rr);
       info[b].t_total = now_s() - t0;
       info[b].t_matvec_n = c.prof.t[0];

@@ -52,6 +52,12 @@ struct Layout {
   void* cols = nullptr;
   uint8_t* mask = nullptr;
   void* U = nullptr;
+  // adjoint: active-set compaction
+  int ldS_max = 0;          // columns reserved for the compacted A_S (multiple of 8)
+  int32_t* idx = nullptr;   // [batch][n] ordered active indices
+  int32_t* cnt = nullptr;   // [batch] active-set sizes
+  void* AS = nullptr;       // [batch][m][ldS] gathered columns of the master copy
+  uint8_t* maskS = nullptr; // [batch][ldS] 1 for real columns, 0 for padding
   size_t total = 0;
 
   int setup(int op, const genios_matrix* A, const genios_opts* o, int s);

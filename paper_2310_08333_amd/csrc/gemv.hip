@@ -7,12 +7,13 @@
 //   gemv_n   t = A v         one wavefront owns ROWS rows of a column split;
 //                            lanes stride the row with 16-byte loads, the
 //                            partial sums are reduced with cross-lane shuffles.
-//   gemv_t   y = A^T (d o t) one thread owns V consecutive columns (16 bytes of
-//                            each row), a block covers 256*V columns and a row
-//                            split; the split's t values (optionally scaled by
-//                            d and summed over gemv_n's column splits) are
-//                            staged in LDS; results are written as per-split
-//                            partials reduced later in a fixed order.
+//   gemv_t   y = A^T (d o t) a lane owns V consecutive columns (16 bytes of
+//                            each row); a block's four wavefronts cover the
+//                            same 64*V columns over interleaved rows of a row
+//                            split and combine in LDS; the split's t values
+//                            (optionally scaled by d and summed over gemv_n's
+//                            column splits) are staged in LDS; results are
+//                            per-split partials reduced later in a fixed order.
 // No floating-point atomics: results are bitwise reproducible.
 #include <algorithm>
 
@@ -22,8 +23,14 @@ namespace genios {
 
 namespace {
 
-constexpr int kGemvNRows = 4;  // rows per wavefront in gemv_n
-constexpr int kMaxRowsPerSplit = 1024;
+constexpr int kMaxRowsPerSplit = 2048;
+
+// Rows per wavefront in gemv_n: 8 for BF16 (the FP32 vector chunk is then read
+// once per 8 rows of 16-byte matrix loads), 4 otherwise.
+template <typename T>
+constexpr int gemv_n_rows() {
+  return sizeof(T) == 2 ? 8 : 4;
+}
 
 template <typename T, typename VT, int ROWS, bool VEC>
 __global__ __launch_bounds__(256) void k_gemv_n(const T* __restrict__ A, int64_t lda,
@@ -54,15 +61,15 @@ __global__ __launch_bounds__(256) void k_gemv_n(const T* __restrict__ A, int64_t
     int c = c0 + lane * V;
 #pragma unroll 2
     for (; c + V <= c1; c += 64 * V) {
+      Acc av[ROWS][V];
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) Elem<T>::load(rowp[r] + c, av[r]);
       Acc vv[V];
       load_vec<VT, Acc, V>(vb + c, vv);
 #pragma unroll
-      for (int r = 0; r < ROWS; ++r) {
-        Acc av[V];
-        Elem<T>::load(rowp[r] + c, av);
+      for (int r = 0; r < ROWS; ++r)
 #pragma unroll
-        for (int j = 0; j < V; ++j) acc[r] += av[j] * vv[j];
-      }
+        for (int j = 0; j < V; ++j) acc[r] += av[r][j] * vv[j];
     }
     for (int cc = c; cc < c1 && cc < c + V; ++cc) {
       const Acc vv = Acc(vb[cc]);
@@ -87,6 +94,8 @@ __global__ __launch_bounds__(256) void k_gemv_n(const T* __restrict__ A, int64_t
   }
 }
 
+// Block = 4 wavefronts sharing one 64*V-column tile of a row split: wave w takes
+// rows w, w+4, ...; the four partial sums are combined in LDS in a fixed order.
 template <typename T, typename VT, int NR, bool VEC>
 __global__ __launch_bounds__(256) void k_gemv_t(
     const T* __restrict__ A, int64_t lda, int64_t strideA, int m, int n,
@@ -98,6 +107,7 @@ __global__ __launch_bounds__(256) void k_gemv_t(
   using Acc = typename Elem<T>::Acc;
   constexpr int V = VEC ? Elem<T>::V : 1;
   __shared__ Acc ts[NR][kMaxRowsPerSplit];
+  __shared__ Acc red[3][NR][64 * V];
   const int b = blockIdx.z;
   if (gate != nullptr && gate[(int64_t)b * gate_stride] == 0) return;
   const int ks = blockIdx.y;
@@ -116,83 +126,92 @@ __global__ __launch_bounds__(256) void k_gemv_t(
     }
   }
   __syncthreads();
-  const int c = (blockIdx.x * blockDim.x + threadIdx.x) * V;
-  if (c >= n) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = (blockIdx.x * 64 + lane) * V;
   const T* Ab = A + (int64_t)b * strideA + (int64_t)r0 * lda;
-  VT* yb = ypart + (int64_t)b * ypart_prob_stride + (int64_t)ks * ypart_ks_stride;
   Acc acc[NR][V];
 #pragma unroll
   for (int k = 0; k < NR; ++k)
 #pragma unroll
     for (int j = 0; j < V; ++j) acc[k][j] = Acc(0);
-  if (VEC && c + V <= n) {
-    int i = 0;
-    for (; i + 4 <= nr; i += 4) {
-      Acc av[4][V];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if constexpr (VEC) {
-          Elem<T>::load(Ab + (int64_t)(i + u) * lda + c, av[u]);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-          const Acc t = ts[k][i + u];
-#pragma unroll
-          for (int j = 0; j < V; ++j) acc[k][j] += av[u][j] * t;
-        }
-    }
-    for (; i < nr; ++i) {
-      Acc av[V];
+  if (c < n) {
+    if (VEC && c + V <= n) {
       if constexpr (VEC) {
-        Elem<T>::load(Ab + (int64_t)i * lda + c, av);
+        constexpr int U = 8;
+        int i = wave;
+        for (; i + 4 * (U - 1) < nr; i += 4 * U) {
+          Acc av[U][V];
+#pragma unroll
+          for (int u = 0; u < U; ++u) Elem<T>::load(Ab + (int64_t)(i + 4 * u) * lda + c, av[u]);
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+              const Acc t = ts[k][i + 4 * u];
+#pragma unroll
+              for (int j = 0; j < V; ++j) acc[k][j] += av[u][j] * t;
+            }
+        }
+        for (; i < nr; i += 4) {
+          Acc av[V];
+          Elem<T>::load(Ab + (int64_t)i * lda + c, av);
+#pragma unroll
+          for (int k = 0; k < NR; ++k) {
+            const Acc t = ts[k][i];
+#pragma unroll
+            for (int j = 0; j < V; ++j) acc[k][j] += av[j] * t;
+          }
+        }
       }
+    } else {
+      const int ce = min(n, c + V);
+      for (int i = wave; i < nr; i += 4) {
+        for (int cc = c; cc < ce; ++cc) {
+          const Acc a = Elem<T>::cvt(Ab[(int64_t)i * lda + cc]);
 #pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        const Acc t = ts[k][i];
-#pragma unroll
-        for (int j = 0; j < V; ++j) acc[k][j] += av[j] * t;
+          for (int k = 0; k < NR; ++k) acc[k][cc - c] += a * ts[k][i];
+        }
       }
     }
+  }
+  if (wave > 0) {
 #pragma unroll
     for (int k = 0; k < NR; ++k)
 #pragma unroll
-      for (int j = 0; j < V; ++j) yb[(int64_t)k * ypart_col_stride + c + j] = VT(acc[k][j]);
-  } else {
-    const int ce = min(n, c + V);
-    for (int i = 0; i < nr; ++i) {
-      for (int cc = c; cc < ce; ++cc) {
-        const Acc a = Elem<T>::cvt(Ab[(int64_t)i * lda + cc]);
-#pragma unroll
-        for (int k = 0; k < NR; ++k) acc[k][cc - c] += a * ts[k][i];
-      }
-    }
-    for (int cc = c; cc < ce; ++cc)
-#pragma unroll
-      for (int k = 0; k < NR; ++k) yb[(int64_t)k * ypart_col_stride + cc] = VT(acc[k][cc - c]);
+      for (int j = 0; j < V; ++j) red[wave - 1][k][lane * V + j] = acc[k][j];
   }
+  __syncthreads();
+  if (wave != 0 || c >= n) return;
+#pragma unroll
+  for (int w = 0; w < 3; ++w)
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+#pragma unroll
+      for (int j = 0; j < V; ++j) acc[k][j] += red[w][k][lane * V + j];
+  VT* yb = ypart + (int64_t)b * ypart_prob_stride + (int64_t)ks * ypart_ks_stride;
+  const int ce = min(n, c + V);
+#pragma unroll
+  for (int k = 0; k < NR; ++k)
+#pragma unroll
+    for (int j = 0; j < V; ++j)
+      if (c + j < ce) yb[(int64_t)k * ypart_col_stride + c + j] = VT(acc[k][j]);
 }
 
 int elem_v(MType mt) { return mt == MT_BF16 ? 8 : (mt == MT_F32 ? 4 : 2); }
 int elem_bytes(MType mt) { return mt == MT_BF16 ? 2 : (mt == MT_F32 ? 4 : 8); }
+int rows_n(MType mt) { return mt == MT_BF16 ? 8 : 4; }
 
-bool vec_ok(const MatArg& A, VType vt, const void* v) {
+bool vec_ok(const MatArg& A) {
   const int V = elem_v(A.mt);
   const uintptr_t pa = reinterpret_cast<uintptr_t>(A.ptr);
-  if (pa % 16 != 0) return false;
-  if (A.lda % V != 0) return false;
-  if (A.strideA % V != 0) return false;
-  (void)vt;
-  (void)v;
-  return true;
+  return pa % 16 == 0 && A.lda % V == 0 && A.strideA % V == 0;
 }
 
 }  // namespace
 
 int gemv_n_splits(const MatArg& A, int64_t batch) {
-  const int64_t rb = (A.m + 4 * kGemvNRows - 1) / (4 * kGemvNRows);
+  const int R = rows_n(A.mt);
+  const int64_t rb = (A.m + 4 * R - 1) / (4 * R);
   const int V = elem_v(A.mt);
   const int64_t want = (2048 + rb * batch - 1) / (rb * batch);
   const int64_t maxs = std::max<int64_t>(1, A.n / (64 * V * 8));
@@ -201,7 +220,7 @@ int gemv_n_splits(const MatArg& A, int64_t batch) {
 
 int gemv_t_splits(const MatArg& A, int64_t batch) {
   const int V = elem_v(A.mt);
-  const int64_t cb = (A.n + 256 * V - 1) / (256 * V);
+  const int64_t cb = (A.n + 64 * V - 1) / (64 * V);
   int64_t ks = (2048 + cb * batch - 1) / (cb * batch);
   // keep the partial traffic at <= ~2% of the matrix traffic
   const int64_t cap = std::max<int64_t>(1, (A.m * elem_bytes(A.mt)) / (50 * 4));
@@ -220,19 +239,19 @@ static hipError_t gemv_n_t(const MatArg& A, int64_t batch, const VT* v, int64_t 
                            int64_t oss, int64_t ops, int nsplit, const int32_t* gate, int gs,
                            hipStream_t st) {
   constexpr int V = Elem<T>::V;
-  const int64_t rb = (A.m + 4 * kGemvNRows - 1) / (4 * kGemvNRows);
+  constexpr int R = gemv_n_rows<T>();
+  const int64_t rb = (A.m + 4 * R - 1) / (4 * R);
   int cps = (int)((A.n + nsplit - 1) / nsplit);
   cps = ((cps + V - 1) / V) * V;
   dim3 grid((unsigned)rb, (unsigned)nsplit, (unsigned)batch);
-  const bool vec = vec_ok(A, VT_F32, v) && (reinterpret_cast<uintptr_t>(v) % 16 == 0) &&
-                   (v_stride % V == 0);
+  const bool vec = vec_ok(A) && (reinterpret_cast<uintptr_t>(v) % 16 == 0) && (v_stride % V == 0);
   const T* Ap = static_cast<const T*>(A.ptr);
   if (vec)
-    hipLaunchKernelGGL((k_gemv_n<T, VT, kGemvNRows, true>), grid, dim3(256), 0, st, Ap, A.lda,
-                       A.strideA, (int)A.m, (int)A.n, v, v_stride, out, oss, ops, cps, gate, gs);
+    hipLaunchKernelGGL((k_gemv_n<T, VT, R, true>), grid, dim3(256), 0, st, Ap, A.lda, A.strideA,
+                       (int)A.m, (int)A.n, v, v_stride, out, oss, ops, cps, gate, gs);
   else
-    hipLaunchKernelGGL((k_gemv_n<T, VT, kGemvNRows, false>), grid, dim3(256), 0, st, Ap, A.lda,
-                       A.strideA, (int)A.m, (int)A.n, v, v_stride, out, oss, ops, cps, gate, gs);
+    hipLaunchKernelGGL((k_gemv_n<T, VT, R, false>), grid, dim3(256), 0, st, Ap, A.lda, A.strideA,
+                       (int)A.m, (int)A.n, v, v_stride, out, oss, ops, cps, gate, gs);
   return hipGetLastError();
 }
 
@@ -261,16 +280,15 @@ static hipError_t gemv_t_t(const MatArg& A, int64_t batch, const VT* tin, int ns
   constexpr int V = Elem<T>::V;
   const int rps = gemv_t_rows_per_split(A, ksplit);
   if (rps > kMaxRowsPerSplit) return hipErrorInvalidValue;
-  const bool vec = vec_ok(A, VT_F32, nullptr) && (reinterpret_cast<uintptr_t>(yp) % 16 == 0) &&
-                   (yks % V == 0) && (ycs % V == 0) && (yps % V == 0);
+  const bool vec = vec_ok(A);
   const T* Ap = static_cast<const T*>(A.ptr);
   if (vec) {
-    dim3 grid((unsigned)((A.n + 256 * V - 1) / (256 * V)), (unsigned)ksplit, (unsigned)batch);
+    dim3 grid((unsigned)((A.n + 64 * V - 1) / (64 * V)), (unsigned)ksplit, (unsigned)batch);
     hipLaunchKernelGGL((k_gemv_t<T, VT, NR, true>), grid, dim3(256), 0, st, Ap, A.lda, A.strideA,
                        (int)A.m, (int)A.n, tin, nsplit_in, tss, tps, tcs, d, ds, yp, yks, ycs, yps,
                        rps, gate, gs);
   } else {
-    dim3 grid((unsigned)((A.n + 255) / 256), (unsigned)ksplit, (unsigned)batch);
+    dim3 grid((unsigned)((A.n + 63) / 64), (unsigned)ksplit, (unsigned)batch);
     hipLaunchKernelGGL((k_gemv_t<T, VT, NR, false>), grid, dim3(256), 0, st, Ap, A.lda,
                        A.strideA, (int)A.m, (int)A.n, tin, nsplit_in, tss, tps, tcs, d, ds, yp,
                        yks, ycs, yps, rps, gate, gs);

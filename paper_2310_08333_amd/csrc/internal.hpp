@@ -201,3 +201,16 @@ void set_error(const std::string& s);
 const char* last_error();
 
 }  // namespace genios
+
+namespace genios {
+// Active-set compaction (adjoint): ordered indices of the mask, column gather of
+// A (zero padding up to ldS), gather of two n-vectors plus the padding mask.
+hipError_t launch_compact_index(int64_t n, int64_t batch, const uint8_t* mask, int32_t* idx,
+                                int32_t* cnt, hipStream_t st);
+hipError_t launch_gather_cols(MType mt, const void* A, int64_t lda, int64_t strideA, int64_t m,
+                              int64_t n, int64_t batch, const int32_t* idx, const int32_t* cnt,
+                              int ldS, void* out, hipStream_t st);
+hipError_t launch_gather_vec(VType vt, int64_t n, int64_t batch, const int32_t* idx,
+                             const int32_t* cnt, int ldS, const void* in0, void* out0,
+                             const void* in1, void* out1, uint8_t* mask_out, hipStream_t st);
+}  // namespace genios

@@ -597,6 +597,290 @@ __global__ __launch_bounds__(256) void k_nystrom_core(int s, int64_t n, double e
   }
 }
 
+// The same s x s core with every matrix in LDS (s <= kCoreLdsMaxS): two
+// regions, R1 (s*s) and R2 (s*(s+1)), hold in turn
+//   R2: M -> C (Cholesky)          R1: Q -> X = C^-1 Q -> G = X C^-T
+//   R2: G (Jacobi, rows/columns)   R1: V (column-major, rotations)
+//   R2: C (reloaded)               R1: T' = C^-T V (back substitution)
+// and the eigenvalues, permutation and rotation parameters are small arrays.
+// One 1024-thread workgroup per problem; all loops are barrier-separated.
+constexpr int kCoreLdsMaxS = 100;
+constexpr int kCoreThreads = 1024;
+
+__global__ __launch_bounds__(kCoreThreads) void k_nystrom_core_lds(
+    int s, double eps, double rel_floor, const double* __restrict__ gram, int SPg,
+    double* __restrict__ core, double* __restrict__ lamhat, int lam_stride,
+    int32_t* __restrict__ s_eff_out, int32_t* __restrict__ status_out,
+    double* __restrict__ shift_out) {
+  extern __shared__ double lds[];
+  __shared__ double cs_c[kCoreLdsMaxS / 2 + 1], cs_s[kCoreLdsMaxS / 2 + 1];
+  __shared__ int16_t pr_p[kCoreLdsMaxS / 2 + 1], pr_q[kCoreLdsMaxS / 2 + 1];
+  __shared__ int16_t perm[kCoreLdsMaxS];
+  __shared__ double evals[kCoreLdsMaxS];
+  __shared__ double s_red[4];
+  __shared__ double s_shift;
+  __shared__ int s_flag;
+  const int b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int LG = s + 1;
+  double* R1 = lds;          // s * s
+  double* R2 = lds + s * s;  // s * LG
+  const int sp2 = SPg * SPg;
+  const double* G1 = gram + ((int64_t)b * 3 + 0) * sp2;
+  const double* G2 = gram + ((int64_t)b * 3 + 1) * sp2;
+  const double* G3 = gram + ((int64_t)b * 3 + 2) * sp2;
+  double* Cg = core + (int64_t)b * 5 * sp2;
+  double* Tg = Cg + 4 * sp2;
+  double* lam_b = lamhat + (int64_t)b * lam_stride;
+
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int k = 0; k < s; ++k) tr += G3[k * SPg + k];
+    s_red[0] = tr;
+  }
+  __syncthreads();
+  const double trace3 = s_red[0];
+  if (!(trace3 > 0.0) || !(trace3 < 1.0e300)) {
+    for (int j = tid; j < s; j += nt) lam_b[j] = 0.0;
+    if (tid == 0) {
+      s_eff_out[b] = 0;
+      status_out[b] = (trace3 == 0.0) ? 0 : GENIOS_WARN_PRECOND;
+      shift_out[b] = 0.0;
+    }
+    return;
+  }
+  if (tid == 0) s_shift = eps * sqrt(trace3);
+  __syncthreads();
+
+  // ---- Cholesky of M = sym(Omega^T Y) + mu Omega^T Omega in R2 (retry with 10 mu) ----
+  bool ok = false;
+  for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
+    const double mu = s_shift;
+    for (int e = tid; e < s * s; e += nt) {
+      const int i = e / s, j = e % s;
+      R2[i * LG + j] = 0.5 * (G1[i * SPg + j] + G1[j * SPg + i]) + mu * G2[i * SPg + j];
+    }
+    if (tid == 0) s_flag = 0;
+    __syncthreads();
+    for (int k = 0; k < s; ++k) {
+      if (tid == 0) {
+        const double dkk = R2[k * LG + k];
+        if (!(dkk > 0.0) || !(dkk < 1.0e300))
+          s_flag = 1;
+        else
+          R2[k * LG + k] = sqrt(dkk);
+      }
+      __syncthreads();
+      if (s_flag) break;
+      const double piv = R2[k * LG + k];
+      for (int i = k + 1 + tid; i < s; i += nt) R2[i * LG + k] /= piv;
+      __syncthreads();
+      const int rem = s - k - 1;
+      for (int e = tid; e < rem * rem; e += nt) {
+        const int i = k + 1 + e / rem, j = k + 1 + e % rem;
+        if (j <= i) R2[i * LG + j] -= R2[i * LG + k] * R2[j * LG + k];
+      }
+      __syncthreads();
+    }
+    if (!s_flag) {
+      ok = true;
+    } else {
+      if (tid == 0) s_shift = 10.0 * s_shift;
+      __syncthreads();
+    }
+  }
+  if (!ok) {
+    for (int j = tid; j < s; j += nt) lam_b[j] = 0.0;
+    if (tid == 0) {
+      s_eff_out[b] = 0;
+      status_out[b] = GENIOS_WARN_PRECOND;
+      shift_out[b] = s_shift;
+    }
+    return;
+  }
+  const double mu = s_shift;
+  // save C (lower) to global; Q = Y_mu^T Y_mu into R1 (row-major, ld s)
+  for (int e = tid; e < s * s; e += nt) {
+    const int i = e / s, j = e % s;
+    Cg[i * SPg + j] = (j <= i) ? R2[i * LG + j] : 0.0;
+    R1[i * s + j] =
+        G3[i * SPg + j] + mu * (G1[i * SPg + j] + G1[j * SPg + i]) + mu * mu * G2[i * SPg + j];
+  }
+  __syncthreads();
+  // X = C^-1 Q (right-looking forward substitution, in place in R1)
+  for (int l = 0; l < s; ++l) {
+    const double inv = 1.0 / R2[l * LG + l];
+    for (int j = tid; j < s; j += nt) R1[l * s + j] *= inv;
+    __syncthreads();
+    const int rem = s - l - 1;
+    for (int e = tid; e < rem * s; e += nt) {
+      const int i = l + 1 + e / s, j = e % s;
+      R1[i * s + j] -= R2[i * LG + l] * R1[l * s + j];
+    }
+    __syncthreads();
+  }
+  // G = X C^-T: solve G C^T = X column by column (right-looking), in place in R1
+  for (int l = 0; l < s; ++l) {
+    const double inv = 1.0 / R2[l * LG + l];
+    for (int i = tid; i < s; i += nt) R1[i * s + l] *= inv;
+    __syncthreads();
+    const int rem = s - l - 1;
+    for (int e = tid; e < s * rem; e += nt) {
+      const int i = e / rem, k = l + 1 + e % rem;
+      R1[i * s + k] -= R1[i * s + l] * R2[k * LG + l];
+    }
+    __syncthreads();
+  }
+  // G (symmetrised) into R2 with ld s+1; V = I into R1 (column-major)
+  for (int e = tid; e < s * s; e += nt) {
+    const int i = e / s, j = e % s;
+    R2[i * LG + j] = 0.5 * (R1[i * s + j] + R1[j * s + i]);
+  }
+  __syncthreads();
+  for (int e = tid; e < s * s; e += nt) {
+    const int p = e / s, k = e % s;
+    R1[p * s + k] = (p == k) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+
+  // ---- cyclic Jacobi, round-robin pairs ----
+  const int S = (s + 1) & ~1;
+  const int npairs = S / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid < 64) {
+      double off = 0.0, dia = 0.0;
+      for (int e = tid; e < s * s; e += 64) {
+        const int i = e / s, j = e % s;
+        const double v = R2[i * LG + j];
+        if (i == j)
+          dia += v * v;
+        else
+          off += v * v;
+      }
+      off = wave_sum(off);
+      dia = wave_sum(dia);
+      if (tid == 0) {
+        s_red[1] = off;
+        s_red[2] = dia;
+      }
+    }
+    __syncthreads();
+    if (!(s_red[1] > 1.0e-28 * s_red[2])) break;
+    for (int round = 0; round < S - 1; ++round) {
+      if (tid < npairs) {
+        const int a0 = tid, a1 = S - 1 - tid;
+        int p = a0 == 0 ? 0 : 1 + ((a0 - 1 + round) % (S - 1));
+        int q = a1 == 0 ? 0 : 1 + ((a1 - 1 + round) % (S - 1));
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        double c = 1.0, sn = 0.0;
+        if (q < s) {
+          const double apq = R2[p * LG + q];
+          if (apq != 0.0) {
+            const double app = R2[p * LG + p], aqq = R2[q * LG + q];
+            const double theta = (aqq - app) / (2.0 * apq);
+            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            sn = t * c;
+          }
+        }
+        pr_p[tid] = (int16_t)p;
+        pr_q[tid] = (int16_t)q;
+        cs_c[tid] = c;
+        cs_s[tid] = sn;
+      }
+      __syncthreads();
+      for (int e = tid; e < npairs * s; e += nt) {  // rows of G
+        const int pi = e / s, k = e % s;
+        const int p = pr_p[pi], q = pr_q[pi];
+        const double sn = cs_s[pi];
+        if (q >= s || sn == 0.0) continue;
+        const double c = cs_c[pi];
+        const double a = R2[p * LG + k], bq = R2[q * LG + k];
+        R2[p * LG + k] = c * a - sn * bq;
+        R2[q * LG + k] = sn * a + c * bq;
+      }
+      __syncthreads();
+      for (int e = tid; e < npairs * s; e += nt) {  // columns of G, and V <- V P
+        const int pi = e / s, k = e % s;
+        const int p = pr_p[pi], q = pr_q[pi];
+        const double sn = cs_s[pi];
+        if (q >= s || sn == 0.0) continue;
+        const double c = cs_c[pi];
+        const double a = R2[k * LG + p], bq = R2[k * LG + q];
+        R2[k * LG + p] = c * a - sn * bq;
+        R2[k * LG + q] = sn * a + c * bq;
+        const double va = R1[p * s + k], vb = R1[q * s + k];
+        R1[p * s + k] = c * va - sn * vb;
+        R1[q * s + k] = sn * va + c * vb;
+      }
+      __syncthreads();
+    }
+  }
+  // eigenvalues (diagonal of G) sorted descending
+  if (tid == 0) {
+    for (int j = 0; j < s; ++j) {
+      perm[j] = (int16_t)j;
+      evals[j] = R2[j * LG + j];
+    }
+    for (int i = 1; i < s; ++i) {
+      const double ev = evals[i];
+      const int16_t pv = perm[i];
+      int k = i - 1;
+      while (k >= 0 && evals[k] < ev) {
+        evals[k + 1] = evals[k];
+        perm[k + 1] = perm[k];
+        --k;
+      }
+      evals[k + 1] = ev;
+      perm[k + 1] = pv;
+    }
+    const double top = evals[0] - mu;
+    int keep = 0;
+    for (int j = 0; j < s; ++j) {
+      if (top > 0.0 && evals[j] - mu > rel_floor * top)
+        keep = j + 1;
+      else
+        break;
+    }
+    s_flag = keep;
+  }
+  __syncthreads();
+  const int keep = s_flag;
+  for (int j = tid; j < s; j += nt) lam_b[j] = (j < keep) ? fmax(evals[j] - mu, 0.0) : 0.0;
+  // reload C into R2
+  for (int e = tid; e < s * s; e += nt) {
+    const int i = e / s, j = e % s;
+    R2[i * LG + j] = Cg[i * SPg + j];
+  }
+  __syncthreads();
+  // T' = C^-T V in place in R1 (column p of V stored at R1[p * s + .])
+  for (int i = s - 1; i >= 0; --i) {
+    const double inv = 1.0 / R2[i * LG + i];
+    for (int p = tid; p < s; p += nt) R1[p * s + i] *= inv;
+    __syncthreads();
+    for (int e = tid; e < s * i; e += nt) {
+      const int p = e / i, l = e % i;
+      R1[p * s + l] -= R2[i * LG + l] * R1[p * s + i];
+    }
+    __syncthreads();
+  }
+  // T(:, j) = T'(:, perm[j]) / sigma_j for the kept columns, zero elsewhere
+  for (int e = tid; e < SPg * SPg; e += nt) {
+    const int j = e / SPg, i = e % SPg;
+    double v = 0.0;
+    if (j < keep && i < s) v = R1[(int)perm[j] * s + i] / sqrt(evals[j]);
+    Tg[(int64_t)j * SPg + i] = v;
+  }
+  if (tid == 0) {
+    s_eff_out[b] = keep;
+    status_out[b] = 0;
+    shift_out[b] = mu;
+  }
+}
+
 // U[b] (n x s, col-major, ld n) = (Y + mu Omega) T  for the first s_eff columns, 0 after.
 template <typename VT, int SP>
 __global__ __launch_bounds__(256) void k_form_u(int64_t n, int s, const VT* __restrict__ Y,
@@ -689,15 +973,23 @@ hipError_t run_core(const MatArg& A, int64_t batch, int s, const uint8_t* mask, 
   }
   const double eps = sizeof(VT) == 4 ? 0x1p-24 : 0x1p-53;
   const double rel_floor = sizeof(VT) == 4 ? 1.0e-6 : 1.0e-13;
-  const size_t lds = (size_t)SP * (SP + 1) * sizeof(double);
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nystrom_core<SP>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = hipSuccess;
+  if (s <= kCoreLdsMaxS) {
+    const size_t lds = (size_t)(2 * s * s + s) * sizeof(double);
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nystrom_core_lds),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_nystrom_core_lds, dim3((unsigned)batch), dim3(kCoreThreads), lds, st, s,
+                       eps, rel_floor, ws.gram, SP, ws.core, lamhat, s, s_eff, status, shift);
+  } else {
+    const size_t lds = (size_t)SP * (SP + 1) * sizeof(double);
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nystrom_core<SP>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_nystrom_core<SP>), dim3((unsigned)batch), dim3(256), lds, st, s, n, eps,
+                       rel_floor, ws.gram, ws.core, lamhat, s, s_eff, status, shift);
   }
-  hipLaunchKernelGGL((k_nystrom_core<SP>), dim3((unsigned)batch), dim3(256), lds, st, s, n, eps,
-                     rel_floor, ws.gram, ws.core, lamhat, s, s_eff, status, shift);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   dim3 g3((unsigned)((n + 63) / 64), (unsigned)batch);
   hipLaunchKernelGGL((k_form_u<VT, SP>), g3, dim3(256), 0, st, n, s,
