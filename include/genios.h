@@ -82,7 +82,8 @@ typedef enum {
   GENIOS_OP_LOGREG = 1,
   GENIOS_OP_NYSTROM = 2,
   GENIOS_OP_BACKWARD = 3,
-  GENIOS_OP_MATVEC = 4
+  GENIOS_OP_MATVEC = 4,
+  GENIOS_OP_HVP = 5
 } genios_op;
 
 /* Dense data matrix (or a batch of them).  m rows (samples) by n columns
@@ -123,8 +124,11 @@ typedef struct {
   double switch_tol;           /* BF16 -> FP32 switch when the BF16 problem's r_kkt <= switch_tol;
                                   0 = max(eps_abs, eps_rel) */
   int32_t stall_window;        /* ... or when r_kkt fell < 10% over this many iterations; 10 */
-  int32_t rhs_relative;        /* CG stops at ||r|| <= rtol ||rhs|| of the x-system (1, default)
-                                  or at ||r|| <= rtol ||r_0|| of the warm-started solve (0) */
+  int32_t rhs_relative;        /* CG stops at ||r|| <= rtol ||r_0||, r_0 the residual of the
+                                  solve warm-started at x^k (0, default: the relative tolerance
+                                  of Sec. 2.1 taken against the initial residual), or at
+                                  ||r|| <= rtol ||rhs|| of the x-system (1: looser, still a
+                                  summable error sequence) */
   uint64_t seed;               /* key of the counter-based Gaussian test matrix */
   int32_t warm_start;          /* 1 = start from the caller's x, z, u and the rho argument */
   int32_t profile_kernels;     /* 1 = time every matrix-vector product with HIP events on
@@ -175,6 +179,11 @@ typedef struct {
   int32_t n_matvec_t;        /* number of A^T w launches */
   int64_t bytes_matvec_n;    /* matrix bytes streamed by the A v products (BF16 or master copy) */
   int64_t bytes_matvec_t;    /* matrix bytes streamed by the A^T w products */
+  double t_hvp;              /* with profile_kernels: summed duration of the fused H p products
+                                (A^T D A p in one pass over A) */
+  int32_t n_hvp;             /* number of fused H p launches */
+  int32_t reserved_info;
+  int64_t bytes_hvp;         /* matrix bytes streamed by the fused H p products */
 } genios_info;
 
 /* Fill *o with the defaults listed above.  Returns GENIOS_OK. */
@@ -257,6 +266,15 @@ int genios_lasso_backward(const genios_matrix* A, const void* z_star, const void
  * must be given).  Vectors follow the vector dtype convention. */
 int genios_matvec(const genios_matrix* A, int32_t trans, int32_t use_bf16, const void* v,
                   void* out, const genios_opts* o);
+
+/* The Hessian-vector product of the x-subproblem, out = A^T diag(d) A p
+ * (Sec. 3.1 HVP example; Sec. 3.3 ML Hessian with D = diag(d); d NULL: D = I),
+ * with the kernels the CG loop uses: one pass over A when the matrix qualifies
+ * (FP32 vectors, n % 8 == 0 and lda % 8 == 0 for BF16 or % 4 for FP32, n <= 40704),
+ * else A p then A^T (d o A p).  use_bf16 selects the BF16 copy (which must be
+ * given).  p, out: n per problem; d: m per problem.  Synchronises o->stream. */
+int genios_hvp(const genios_matrix* A, int32_t use_bf16, const void* d, const void* p, void* out,
+               const genios_opts* o);
 
 /* Round `count` FP32 values to BF16, nearest-even, NaN -> 0x7FC0 (device). */
 int genios_cast_bf16(const float* src, uint16_t* dst, int64_t count, const genios_opts* o);

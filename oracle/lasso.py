@@ -57,6 +57,17 @@ def grad_f(A, b, x):
     return A.T @ (A @ _f64(x) - _f64(b))
 
 
+def hessian_vector(A, p, d=None):
+    """H p with H = A^T diag(d) A: the Lasso Hessian A^T A (d = None, Sec. 3.1
+    HVP example) or the logistic one with curvature weights d (Sec. 3.3).
+    Written as two products, A p then A^T (d o A p)."""
+    A = _f64(A)
+    t = A @ _f64(p)
+    if d is not None:
+        t = _f64(d) * t
+    return A.T @ t
+
+
 class ShiftedGramSolve:
     """Exact solves with (A^T diag(d) A + nu I); d = None means d = 1.
 

@@ -25,14 +25,19 @@ import numpy as np
 def nystrom(H, Omega, rel_thresh=1e-12):
     """Return (U, lam_hat) with H_hat = U diag(lam_hat) U^T, lam_hat descending."""
     H = np.asarray(H, np.float64)
+    return nystrom_from_sketch(H @ np.asarray(Omega, np.float64), Omega, rel_thresh)
+
+
+def nystrom_from_sketch(Y, Omega, rel_thresh=1e-12):
+    """The same (U, lam_hat) from the sketch Y = H Omega alone (H never formed)."""
+    Y = np.asarray(Y, np.float64)
     Omega = np.asarray(Omega, np.float64)
-    Y = H @ Omega
     Mm = Omega.T @ Y
     Mm = 0.5 * (Mm + Mm.T)
     ev, V = np.linalg.eigh(Mm)
     keep = ev > rel_thresh * max(ev.max(), 0.0) if ev.max() > 0 else np.zeros_like(ev, bool)
     if not keep.any():
-        return np.zeros((H.shape[0], 0)), np.zeros(0)
+        return np.zeros((Y.shape[0], 0)), np.zeros(0)
     # H_hat = Y V_k diag(1/ev_k) V_k^T Y^T = B B^T with B = Y V_k diag(ev_k^-1/2)
     B = (Y @ V[:, keep]) / np.sqrt(ev[keep])
     Ub, sv, _ = np.linalg.svd(B, full_matrices=False)

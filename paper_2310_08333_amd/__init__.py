@@ -268,6 +268,27 @@ def matvec(A, v, trans=False, A16=None):
     return out
 
 
+def hvp(A, p, d=None, A16=None):
+    """A^T diag(d) A p (d None: A^T A p) with the CG loop's product kernels."""
+    dev = A.device
+    M = _matrix(A, A16)
+    o = _abi.default_opts()
+    o.precision = _abi.PREC_BF16_ONLY if A16 is not None else (
+        _abi.PREC_F64 if A.dtype == torch.float64 else _abi.PREC_F32)
+    B, m, n = M.batch, M.m, M.n
+    _check_vec(p, "p", A.dtype, B * n, dev)
+    if d is not None:
+        _check_vec(d, "d", A.dtype, B * m, dev)
+    out = torch.empty((B, n) if A.dim() == 3 else (n,), dtype=A.dtype, device=dev)
+    ws = _attach_workspace(o, workspace_size(_abi.OP_HVP, M, o), dev)
+    rc = _lib.genios_hvp(C.byref(M), int(A16 is not None), _ptr(d), _ptr(p), _ptr(out),
+                         C.byref(o))
+    del ws
+    if rc < 0:
+        raise GeniosError(rc, "genios_hvp")
+    return out
+
+
 def cast_bf16(A: torch.Tensor) -> torch.Tensor:
     """Round-to-nearest-even BF16 copy of an FP32 tensor (returned as torch.bfloat16)."""
     if A.dtype != torch.float32 or not A.is_contiguous() or not A.is_cuda:

@@ -24,7 +24,7 @@ ERR_UNSUPPORTED = -7
 
 DT_F32, DT_BF16, DT_F64 = 0, 1, 2
 PREC_F64, PREC_F32, PREC_BF16_REFINE, PREC_BF16_ONLY = 0, 1, 2, 3
-OP_LASSO, OP_LOGREG, OP_NYSTROM, OP_BACKWARD, OP_MATVEC = 0, 1, 2, 3, 4
+OP_LASSO, OP_LOGREG, OP_NYSTROM, OP_BACKWARD, OP_MATVEC, OP_HVP = 0, 1, 2, 3, 4, 5
 
 HIST_FIELDS = 10
 HIST_NAMES = ("k", "r_p", "r_d", "r_kkt", "rho", "cg", "rtol", "phase", "time", "xnorm")
@@ -70,7 +70,8 @@ class Info(C.Structure):
                 ("t_to_target", C.c_double), ("t_matvec_n", C.c_double),
                 ("t_matvec_t", C.c_double), ("n_matvec_n", C.c_int32),
                 ("n_matvec_t", C.c_int32), ("bytes_matvec_n", C.c_int64),
-                ("bytes_matvec_t", C.c_int64)]
+                ("bytes_matvec_t", C.c_int64), ("t_hvp", C.c_double), ("n_hvp", C.c_int32),
+                ("reserved_info", C.c_int32), ("bytes_hvp", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -79,6 +80,7 @@ class Info(C.Structure):
 EXPORTED = (
     "genios_default_opts", "genios_workspace_size", "genios_lasso_solve", "genios_logreg_solve",
     "genios_nystrom_build", "genios_nystrom_apply", "genios_lasso_backward", "genios_matvec",
+    "genios_hvp",
     "genios_cast_bf16", "genios_gaussian_matrix", "genios_admm_update", "genios_status_string",
     "genios_last_error", "genios_abi_struct_sizes",
 )
@@ -114,6 +116,8 @@ def load(path: str | None = None):
     lib.genios_lasso_backward.restype = C.c_int
     lib.genios_matvec.argtypes = [P(Matrix), i32, i32, vp, vp, P(Opts)]
     lib.genios_matvec.restype = C.c_int
+    lib.genios_hvp.argtypes = [P(Matrix), i32, vp, vp, vp, P(Opts)]
+    lib.genios_hvp.restype = C.c_int
     lib.genios_cast_bf16.argtypes = [vp, vp, i64, P(Opts)]
     lib.genios_cast_bf16.restype = C.c_int
     lib.genios_gaussian_matrix.argtypes = [i64, i32, C.c_uint64, C.c_uint64, vp, P(Opts)]

@@ -129,7 +129,7 @@ int genios_default_opts(genios_opts* o) {
   o->inexact = 1;
   o->switch_tol = 0.0;
   o->stall_window = 10;
-  o->rhs_relative = 1;
+  o->rhs_relative = 0;
   o->seed = 0x5eed2310ull;
   return GENIOS_OK;
 }
@@ -153,6 +153,7 @@ size_t genios_workspace_size(int op, const genios_matrix* A, const genios_opts* 
       s = o->sketch_rank > 0 ? std::min<int>(o->sketch_rank, kMaxS) : effective_rank(o, A->n, A->m);
       break;
     case GENIOS_OP_MATVEC:
+    case GENIOS_OP_HVP:
       s = 0;
       break;
     default:
@@ -260,6 +261,16 @@ int genios_matvec(const genios_matrix* A, int32_t trans, int32_t use_bf16, const
   if (use_bf16 && A->A_bf16 == nullptr) FAIL(GENIOS_ERR_ARG, "use_bf16 needs A_bf16");
   if ((rc = check_ws(GENIOS_OP_MATVEC, A, o))) return rc;
   return run_matvec(A, trans, use_bf16, v, out, o);
+}
+
+int genios_hvp(const genios_matrix* A, int32_t use_bf16, const void* d, const void* p, void* out,
+               const genios_opts* o) {
+  int rc;
+  if ((rc = check_matrix(A)) || (rc = check_opts(o))) return rc;
+  if (p == nullptr || out == nullptr) FAIL(GENIOS_ERR_ARG, "p and out must be non-NULL");
+  if (use_bf16 && A->A_bf16 == nullptr) FAIL(GENIOS_ERR_ARG, "use_bf16 needs A_bf16");
+  if ((rc = check_ws(GENIOS_OP_HVP, A, o))) return rc;
+  return run_hvp(A, use_bf16, d, p, out, o);
 }
 
 int genios_cast_bf16(const float* src, uint16_t* dst, int64_t count, const genios_opts* o) {

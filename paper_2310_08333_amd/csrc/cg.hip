@@ -1,20 +1,24 @@
 // Vector kernels of the inexact ADMM / preconditioned CG loop.
 //
 // Per ADMM iteration (Sec. 2, M = I, c = 0):
-//   admm_begin   u <- u * scale (penalty change, Sec. 2.5); the x-system of
-//                eq. x-update-lin-sys, (H + nu I) x = rhs with
-//                rhs = (H + sigma I) x^k - grad f(x^k) + rho (z^k - u^k),
-//                warm-started at x^k, so r_0 = rho (z - u - x) - grad f(x^k);
-//                ||rhs||, ||r_0||, U^T r_0 and the CG tolerance.
-//   precond      w = P^-1 r (eq. preconditioner) and r^T w.
-//   cg_alpha     hp = H p (sum of gemv_t partials), q = hp + nu p, alpha.
-//   cg_update    x += alpha p, h += alpha hp (h tracks H x), r -= alpha q,
-//                ||r||, U^T r, stopping test.
-//   p_update     p = w + beta p.
-//   admm_end     over-relaxed z- and u-updates with the soft-threshold prox
-//                (Sec. 2.5, Sec. 3.1) and the residual norms of Sec. 2.3.
-// Reductions accumulate in FP64; each kernel's last block combines the block
-// partials of its problem in a fixed order (no floating-point atomics).
+//   admm_begin    u <- u * scale (penalty change, Sec. 2.5); the x-system of
+//                 eq. x-update-lin-sys, (H + nu I) x = rhs with
+//                 rhs = (H + sigma I) x^k - grad f(x^k) + rho (z^k - u^k),
+//                 warm-started at x^k, so r_0 = rho (z - u - x) - grad f(x^k).
+//   precond_coef  coefficients of P^-1 (eq. preconditioner) from U^T r.
+//   precond_step  stopping decision for the current residual (CG tolerance of
+//                 the schedule, iteration limit), then w = P^-1 r.
+//   p_update      p = w + beta p.
+//   cg_alpha      hp = H p (sum of gemv_t partials), q = hp + nu p.
+//   cg_update     alpha = r^T w / p^T q; x += alpha p, h += alpha hp (h tracks
+//                 H x), r -= alpha q.
+//   admm_end      over-relaxed z- and u-updates with the soft-threshold prox
+//                 (Sec. 2.5, Sec. 3.1) and the residual norms of Sec. 2.3.
+//   admm_finish   the residual sums into the problem state.
+// Reductions accumulate in FP64.  A kernel writes one partial per block; the
+// kernel that needs the sum reduces the partials itself, every block in the
+// same fixed order (bit-identical in every block), so no block of a grid waits
+// on another and no result depends on timing.
 #include <algorithm>
 
 #include "device.hpp"
@@ -38,44 +42,87 @@ __device__ __forceinline__ VT soft_threshold(VT v, VT k) {
 }
 
 // U^T r partials of this block: r values of the chunk are in LDS (rs).
+// Wave w owns columns w, w+4, ...; lane l rows l, l+64, ...  Columns go in
+// groups of G whose loads are all issued before the multiply-adds, so a block
+// pays the memory latency once per group rather than once per row.  Loads are
+// unconditional: rows past the chunk read its last row with weight 0 and
+// columns past s_eff re-read column `wave` (their sums are never stored).
 template <typename VT>
-__device__ void ut_r_partial(const VT* __restrict__ Ub, int64_t n, int s_eff, const Chunk& ch,
-                             const VT* rs, double* part_out) {
-  // wave w owns columns w, w+4, ...; each lane keeps one accumulator per column so
-  // the column loads of a row are independent and pipeline
-  constexpr int JMAX = kMaxS / 4;
+__device__ __forceinline__ void ut_r_partial(const VT* __restrict__ Ub, int64_t ldu, int s_eff,
+                                             const Chunk& ch, const VT* rs, double* part_out,
+                                             int64_t ostride = 1) {
+  constexpr int G = sizeof(VT) == 4 ? 8 : 4;
+  constexpr int T = 4;  // row loads per lane per column (one 256-row slab)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int len = (int)(ch.hi - ch.lo);
   const VT* base = Ub + ch.lo;
-  double acc[JMAX];
+  const int ncol = s_eff > wave ? (s_eff - wave + 3) / 4 : 0;
+  for (int g0 = 0; g0 < ncol; g0 += G) {
+    double acc[G];
 #pragma unroll
-  for (int jj = 0; jj < JMAX; ++jj) acc[jj] = 0.0;
-  for (int i = lane; i < len; i += 64) {
-    const double r = double(rs[i]);
+    for (int jj = 0; jj < G; ++jj) acc[jj] = 0.0;
+#pragma unroll 1
+    for (int i0 = 0; i0 < len; i0 += 64 * T) {
+      double rv[T];
+      int ii[T];
 #pragma unroll
-    for (int jj = 0; jj < JMAX; ++jj) {
-      const int j = wave + 4 * jj;
-      if (j < s_eff) acc[jj] += double(base[(int64_t)j * n + i]) * r;
+      for (int t = 0; t < T; ++t) {
+        const int i = i0 + lane + 64 * t;
+        ii[t] = i < len ? i : len - 1;
+        rv[t] = i < len ? double(rs[ii[t]]) : 0.0;
+      }
+      VT uv[G][T];
+#pragma unroll
+      for (int jj = 0; jj < G; ++jj) {
+        const int j = g0 + jj < ncol ? wave + 4 * (g0 + jj) : wave;
+        const VT* col = base + (int64_t)j * ldu;
+#pragma unroll
+        for (int t = 0; t < T; ++t) uv[jj][t] = col[ii[t]];
+      }
+#pragma unroll
+      for (int jj = 0; jj < G; ++jj)
+#pragma unroll
+        for (int t = 0; t < T; ++t) acc[jj] += double(uv[jj][t]) * rv[t];
     }
-  }
 #pragma unroll
-  for (int jj = 0; jj < JMAX; ++jj) {
-    const int j = wave + 4 * jj;
-    if (j < s_eff) {
+    for (int jj = 0; jj < G; ++jj) {
       const double v = wave_sum(acc[jj]);
-      if (lane == 0) part_out[j] = v;
+      if (g0 + jj < ncol && lane == 0) part_out[(int64_t)(wave + 4 * (g0 + jj)) * ostride] = v;
     }
   }
 }
 
-// Last block: w_j = sum over blocks, coef_j = ((lam_rr + nu)/(lam_j + nu) - 1) w_j.
-__device__ void finish_coef(const double* part_b, int nb, int s_eff, const double* lamhat_b,
+// Last block: w_j = sum over the nb block partials, then
+// coef_j = ((lam_rr + nu)/(lam_j + nu) - 1) w_j.  Wave q sums the q-th quarter
+// of the partials for columns lane and lane + 64; the quarters are combined in
+// order.  Called by every thread of the block (s_eff is uniform).
+__device__ __forceinline__ void finish_coef(const double* part_b, int nb, int s_eff, const double* lamhat_b,
                             double nu, double* coef_b) {
+  __shared__ double qs[4 * kMaxS];
   if (s_eff <= 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = (nb + 3) / 4;
+  const int k0 = min(nb, wave * q), k1 = min(nb, k0 + q);
+  for (int j = lane; j < s_eff; j += 64) {
+    double w = 0.0;
+    int k = k0;
+    for (; k + 4 <= k1; k += 4) {
+      const double a0 = load_partial(part_b + (int64_t)(k + 0) * kPartW + j);
+      const double a1 = load_partial(part_b + (int64_t)(k + 1) * kPartW + j);
+      const double a2 = load_partial(part_b + (int64_t)(k + 2) * kPartW + j);
+      const double a3 = load_partial(part_b + (int64_t)(k + 3) * kPartW + j);
+      w += a0;
+      w += a1;
+      w += a2;
+      w += a3;
+    }
+    for (; k < k1; ++k) w += load_partial(part_b + (int64_t)k * kPartW + j);
+    qs[wave * kMaxS + j] = w;
+  }
+  __syncthreads();
   const double lrr = lamhat_b[s_eff - 1];
   for (int j = threadIdx.x; j < s_eff; j += blockDim.x) {
-    double w = 0.0;
-    for (int k = 0; k < nb; ++k) w += load_partial(part_b + (int64_t)k * kPartW + j);
+    const double w = ((qs[j] + qs[kMaxS + j]) + qs[2 * kMaxS + j]) + qs[3 * kMaxS + j];
     coef_b[j] = ((lrr + nu) / (lamhat_b[j] + nu) - 1.0) * w;
   }
 }
@@ -94,12 +141,59 @@ __device__ void sum_slots(const double* part_b, int nb, int slot0, double (&v)[N
   block_sum<NV>(v, smem);
 }
 
+// Fixed-order sum of NV slot partials over the nb blocks of problem b.  Every
+// thread of the calling block gets the result; every block that calls it with
+// the same arguments gets the same bits (same loads, same tree).
+template <int NV>
+__device__ __forceinline__ void reduce_slots(const Ctrl& ctrl, int b, int nb, const int (&slot)[NV],
+                                             double (&out)[NV]) {
+  __shared__ double sm[4 * NV];
+  __shared__ double bc[NV];
+  const double* sp = ctrl.spart + (int64_t)b * kNumSlots * ctrl.pstride;
+  double v[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = 0.0;
+  for (int k = threadIdx.x; k < nb; k += blockDim.x)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] += sp[(int64_t)slot[q] * ctrl.pstride + k];
+  block_sum<NV>(v, sm);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) bc[q] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) out[q] = bc[q];
+}
+
+// Block-uniform read of the CG gate: thread 0 reads the flags and the block
+// follows its value, so a flag that block 0 of the same kernel clears can never
+// split a block between waves that saw it set and waves that saw it cleared.
+__device__ __forceinline__ bool block_gate_cg(const ProbParams& P, const ProbState* S) {
+  __shared__ int g;
+  if (threadIdx.x == 0) g = (P.run && S->cg_active) ? 1 : 0;
+  __syncthreads();
+  return g != 0;
+}
+
+__device__ __forceinline__ double* slot_ptr(const Ctrl& ctrl, int b, int slot) {
+  return ctrl.spart + ((int64_t)b * kNumSlots + slot) * ctrl.pstride;
+}
+
+// x-system set-up: u <- u * scale, r_0 = rho (z - u - x) - grad f(x^k) and the
+// partials of ||rhs||^2, ||r_0||^2 and U^T r_0.  Block 0 re-arms the problem's
+// flags (none of them is read by this kernel).
 template <typename VT>
 __global__ __launch_bounds__(256) void k_admm_begin(VecArgs a) {
   const int b = blockIdx.y;
   const ProbParams P = a.ctrl.params[b];
   if (!P.run) return;
   ProbState* S = a.ctrl.state + b;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S->admm_done = 0;
+    S->breakdown = 0;
+    S->cg_iters = 0;
+    S->cg_active = 1;
+  }
   const int64_t n = a.n;
   const Chunk ch = my_chunk(n, a.chunk);
   const int64_t off = (int64_t)b * n;
@@ -116,13 +210,14 @@ __global__ __launch_bounds__(256) void k_admm_begin(VecArgs a) {
   const VT rho = VT(P.rho), sig = VT(P.sigma), usc = VT(P.u_scale);
   double rhs2 = 0.0, rr = 0.0;
   for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) {
+    // all loads before the first store (the vectors are distinct)
     VT ui = u[i];
+    const VT xi = x[i], zi = z[i], hi = h[i];
+    const VT gi = c ? hi - c[i] : g[i];
     if (P.u_scale != 1.0) {
       ui *= usc;
       u[i] = ui;
     }
-    const VT xi = x[i], zi = z[i], hi = h[i];
-    const VT gi = c ? hi - c[i] : g[i];
     VT rhs = hi + sig * xi - gi + rho * (zi - ui);
     VT ri = rho * (zi - ui - xi) - gi;
     if (mask && !mask[i]) {
@@ -135,54 +230,88 @@ __global__ __launch_bounds__(256) void k_admm_begin(VecArgs a) {
     rr += double(ri) * double(ri);
   }
   __syncthreads();
-  double* part_b = a.ctrl.part + (int64_t)b * a.ctrl.part_stride;
   const int s_eff = a.U ? a.ctrl.s_eff[b] : 0;
   if (s_eff > 0)
     ut_r_partial<VT>(static_cast<const VT*>(a.U) + (int64_t)b * n * a.s_stride, n, s_eff, ch, rs,
-                     part_b + (int64_t)blockIdx.x * kPartW);
+                     a.ctrl.upart + (int64_t)b * kMaxS * a.ctrl.pstride + blockIdx.x,
+                     a.ctrl.pstride);
   double v[2] = {rhs2, rr};
   block_sum<2>(v, red);
   if (threadIdx.x == 0) {
-    part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 0] = v[0];
-    part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 1] = v[1];
-  }
-  if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntBegin, a.nb)) return;
-  finish_coef(part_b, a.nb, s_eff, a.ctrl.lamhat + (int64_t)b * a.ctrl.s_stride, P.nu,
-              a.ctrl.coef + (int64_t)b * kMaxS);
-  double tv[2];
-  sum_slots<2>(part_b, a.nb, 0, tv, red);
-  if (threadIdx.x == 0) {
-    const double trhs2 = tv[0];
-    const double tr2 = tv[1];
-    double tol2 = P.rtol * P.rtol * (P.rhs_rel ? trhs2 : tr2);
-    tol2 = fmax(tol2, P.tol_floor * P.tol_floor * trhs2);
-    S->rhs2 = trhs2;
-    S->r02 = tr2;
-    S->rr = tr2;
-    S->tol2 = tol2;
-    S->cg_iters = 0;
-    S->admm_done = 0;
-    S->breakdown = 0;
-    S->cg_active = (P.max_cg > 0 && tr2 > 0.0) ? 1 : 0;
-    if (!(trhs2 <= 1.0e300) || !(tr2 <= 1.0e300)) {  // NaN or Inf
-      S->breakdown = 1;
-      S->cg_active = 0;
-    }
+    slot_ptr(a.ctrl, b, kSlRhs2)[blockIdx.x] = v[0];
+    slot_ptr(a.ctrl, b, kSlRr)[blockIdx.x] = v[1];
   }
 }
 
+// coef_j = ((lam_rr + nu)/(lam_j + nu) - 1) (U^T r)_j, one block per column j:
+// the block sums the column's block partials in a fixed order.
+__global__ __launch_bounds__(256) void k_precond_coef(Ctrl ctrl, int nb) {
+  const int b = blockIdx.y, j = blockIdx.x;
+  const ProbParams P = ctrl.params[b];
+  if (!P.run || !ctrl.state[b].cg_active) return;
+  const int s_eff = ctrl.s_eff[b];
+  if (j >= s_eff) return;
+  __shared__ double sm[4];
+  const double* up = ctrl.upart + ((int64_t)b * kMaxS + j) * ctrl.pstride;
+  double v[1] = {0.0};
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) v[0] += up[k];
+  block_sum<1>(v, sm);
+  if (threadIdx.x == 0) {
+    const double* lam = ctrl.lamhat + (int64_t)b * ctrl.s_stride;
+    const double lrr = lam[s_eff - 1];
+    ctrl.coef[(int64_t)b * kMaxS + j] = ((lrr + P.nu) / (lam[j] + P.nu) - 1.0) * v[0];
+  }
+}
+
+// w = P^-1 r (eq. preconditioner) and the partials of r^T w.  It first takes the
+// stopping decision of the residual it is given: init -- the x-system's set-up
+// (tolerance of the CG schedule, empty or non-finite right-hand side); else the
+// residual of CG iteration t (tolerance reached or iteration limit).
 template <typename VT>
-__global__ __launch_bounds__(256) void k_precond_step(VecArgs a, int init) {
+__global__ __launch_bounds__(256) void k_precond_step(VecArgs a, int t, int init) {
   const int b = blockIdx.y;
   const ProbParams P = a.ctrl.params[b];
   ProbState* S = a.ctrl.state + b;
-  if (!P.run || !S->cg_active) return;
+  if (!block_gate_cg(P, S)) return;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  bool stop;
+  if (init) {
+    const int sl[2] = {kSlRhs2, kSlRr};
+    double tv[2];
+    reduce_slots<2>(a.ctrl, b, a.nb, sl, tv);
+    const double trhs2 = tv[0], tr2 = tv[1];
+    const bool bad = !(trhs2 <= 1.0e300) || !(tr2 <= 1.0e300);  // NaN or Inf
+    stop = bad || !(tr2 > 0.0) || P.max_cg <= 0;
+    if (lead) {
+      double tol2 = P.rtol * P.rtol * (P.rhs_rel ? trhs2 : tr2);
+      tol2 = fmax(tol2, P.tol_floor * P.tol_floor * trhs2);
+      S->rhs2 = trhs2;
+      S->r02 = tr2;
+      S->rr = tr2;
+      S->tol2 = tol2;
+      if (bad) S->breakdown = 1;
+      if (stop) S->cg_active = 0;
+    }
+  } else {
+    const int sl[1] = {kSlRr};
+    double tv[1];
+    reduce_slots<1>(a.ctrl, b, a.nb, sl, tv);
+    const double rr = tv[0];
+    const bool bad = !(rr <= 1.0e300);
+    stop = bad || rr <= S->tol2 || t + 1 >= P.max_cg;
+    if (lead) {
+      S->rr = rr;
+      S->cg_iters = t + 1;
+      if (bad) S->breakdown = 1;
+      if (stop) S->cg_active = 0;
+    }
+  }
+  if (stop) return;
   const int64_t n = a.n;
   const Chunk ch = my_chunk(n, a.chunk);
   const int64_t off = (int64_t)b * n;
   const VT* r = static_cast<const VT*>(a.r) + off;
   VT* w = static_cast<VT*>(a.w) + off;
-  VT* p = static_cast<VT*>(a.p) + off;
   __shared__ double cf[kMaxS];
   __shared__ double red[16];
   const int s_eff = a.U ? a.ctrl.s_eff[b] : 0;
@@ -192,36 +321,67 @@ __global__ __launch_bounds__(256) void k_precond_step(VecArgs a, int init) {
   const VT* Ub = a.U ? static_cast<const VT*>(a.U) + (int64_t)b * n * a.s_stride : nullptr;
   double rz = 0.0;
   for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) {
-    double acc = double(r[i]);
-    for (int j = 0; j < s_eff; ++j) acc += double(Ub[(int64_t)j * n + i]) * cf[j];
+    const double ri = double(r[i]);
+    double acc = ri;
+    int j = 0;
+    for (; j + 16 <= s_eff; j += 16) {  // 16 independent loads, then the adds in order
+      VT tq[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) tq[q] = Ub[(int64_t)(j + q) * n + i];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc += double(tq[q]) * cf[j + q];
+    }
+    for (; j < s_eff; ++j) acc += double(Ub[(int64_t)j * n + i]) * cf[j];
     const VT wi = VT(acc);
     w[i] = wi;
-    if (init) p[i] = wi;
-    rz += double(r[i]) * double(wi);
+    rz += ri * double(wi);
   }
   double v[1] = {rz};
   block_sum<1>(v, red);
-  double* part_b = a.ctrl.part + (int64_t)b * a.ctrl.part_stride;
-  if (threadIdx.x == 0) part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 2] = v[0];
-  if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntPrecond, a.nb)) return;
+  if (threadIdx.x == 0) slot_ptr(a.ctrl, b, kSlRz)[blockIdx.x] = v[0];
+}
+
+// p = w + beta p with beta = (r^T w)_new / (r^T w)_old (init: p = w).  The new
+// r^T w goes to the parity slot of the next iteration.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_p_update(VecArgs a, int t, int init) {
+  const int b = blockIdx.y;
+  const ProbParams P = a.ctrl.params[b];
+  ProbState* S = a.ctrl.state + b;
+  if (!P.run || !S->cg_active) return;
+  const int sl[1] = {kSlRz};
   double tv[1];
-  sum_slots<1>(part_b, a.nb, 2, tv, red);
-  if (threadIdx.x == 0) {
-    const double t = tv[0];
-    if (init) {
-      S->rz = t;
-    } else {
-      S->beta_cg = (S->rz != 0.0) ? t / S->rz : 0.0;
-      S->rz = t;
-    }
+  reduce_slots<1>(a.ctrl, b, a.nb, sl, tv);
+  const double rz_new = tv[0];
+  double beta = 0.0;
+  if (!init) {
+    const double rz_old = S->rz2[t & 1];
+    beta = rz_old != 0.0 ? rz_new / rz_old : 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S->rz2[init ? 0 : ((t + 1) & 1)] = rz_new;
+    S->beta_cg = beta;
+  }
+  const int64_t n = a.n;
+  const Chunk ch = my_chunk(n, a.chunk);
+  const int64_t off = (int64_t)b * n;
+  VT* p = static_cast<VT*>(a.p) + off;
+  const VT* w = static_cast<const VT*>(a.w) + off;
+  const VT be = VT(beta);
+  if (init) {
+    for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) p[i] = w[i];
+  } else {
+    for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) p[i] = w[i] + be * p[i];
   }
 }
 
+// hp = H p (sum of the gemv_t split partials) and the partials of p^T q,
+// q = hp + nu p (masked coordinates: q = p).
 template <typename VT>
 __global__ __launch_bounds__(256) void k_cg_alpha(VecArgs a) {
   const int b = blockIdx.y;
   const ProbParams P = a.ctrl.params[b];
-  ProbState* S = a.ctrl.state + b;
+  const ProbState* S = a.ctrl.state + b;
   if (!P.run || !S->cg_active) return;
   const int64_t n = a.n;
   const Chunk ch = my_chunk(n, a.chunk);
@@ -235,7 +395,15 @@ __global__ __launch_bounds__(256) void k_cg_alpha(VecArgs a) {
   double pq = 0.0;
   for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) {
     VT s = VT(0);
-    for (int k = 0; k < a.ksplit; ++k) s += yp[(int64_t)k * a.ypart_ks_stride + i];
+    int k = 0;
+    for (; k + 8 <= a.ksplit; k += 8) {  // 8 independent loads, then the adds in order
+      VT tq[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) tq[q] = yp[(int64_t)(k + q) * a.ypart_ks_stride + i];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += tq[q];
+    }
+    for (; k < a.ksplit; ++k) s += yp[(int64_t)k * a.ypart_ks_stride + i];
     const VT pi = p[i];
     VT q;
     if (mask && !mask[i]) {
@@ -249,30 +417,36 @@ __global__ __launch_bounds__(256) void k_cg_alpha(VecArgs a) {
   }
   double v[1] = {pq};
   block_sum<1>(v, red);
-  double* part_b = a.ctrl.part + (int64_t)b * a.ctrl.part_stride;
-  if (threadIdx.x == 0) part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 3] = v[0];
-  if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntAlpha, a.nb)) return;
-  double tv[1];
-  sum_slots<1>(part_b, a.nb, 3, tv, red);
-  if (threadIdx.x == 0) {
-    const double t = tv[0];
-    S->pq = t;
-    if (!(t > 0.0) || !(t <= 1.0e300)) {
-      S->breakdown = 1;
-      S->cg_active = 0;
-      S->alpha_cg = 0.0;
-    } else {
-      S->alpha_cg = S->rz / t;
-    }
-  }
+  if (threadIdx.x == 0) slot_ptr(a.ctrl, b, kSlPq)[blockIdx.x] = v[0];
 }
 
+// alpha = (r^T w)_t / p^T q, then x += alpha p, h += alpha hp (h tracks H x),
+// r -= alpha q, and the partials of ||r||^2 and U^T r.
 template <typename VT>
-__global__ __launch_bounds__(256) void k_cg_update(VecArgs a) {
+__global__ __launch_bounds__(256) void k_cg_update(VecArgs a, int t) {
   const int b = blockIdx.y;
   const ProbParams P = a.ctrl.params[b];
   ProbState* S = a.ctrl.state + b;
-  if (!P.run || !S->cg_active) return;
+  if (!block_gate_cg(P, S)) return;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  const int sl[1] = {kSlPq};
+  double tv[1];
+  reduce_slots<1>(a.ctrl, b, a.nb, sl, tv);
+  const double pq = tv[0];
+  if (!(pq > 0.0) || !(pq <= 1.0e300)) {  // not positive definite along p, or non-finite
+    if (lead) {
+      S->pq = pq;
+      S->alpha_cg = 0.0;
+      S->breakdown = 1;
+      S->cg_active = 0;
+    }
+    return;
+  }
+  const double alpha = S->rz2[t & 1] / pq;
+  if (lead) {
+    S->pq = pq;
+    S->alpha_cg = alpha;
+  }
   const int64_t n = a.n;
   const Chunk ch = my_chunk(n, a.chunk);
   const int64_t off = (int64_t)b * n;
@@ -284,71 +458,38 @@ __global__ __launch_bounds__(256) void k_cg_update(VecArgs a) {
   const uint8_t* mask = a.mask ? a.mask + off : nullptr;
   __shared__ VT rs[kVecChunk * 4];
   __shared__ double red[16];
-  const VT al = VT(S->alpha_cg), nu = VT(P.nu);
+  const VT al = VT(alpha), nu = VT(P.nu);
   double rr = 0.0;
   for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) {
-    const VT pi = p[i], hpi = hp[i];
+    // all loads before the first store (the vectors are distinct)
+    const VT pi = p[i], hpi = hp[i], xi = x[i], hi = h[i], r0 = r[i];
     const VT q = (mask && !mask[i]) ? pi : hpi + nu * pi;
-    x[i] += al * pi;
-    h[i] += al * hpi;
-    const VT ri = r[i] - al * q;
+    x[i] = xi + al * pi;
+    h[i] = hi + al * hpi;
+    const VT ri = r0 - al * q;
     r[i] = ri;
     rs[i - ch.lo] = ri;
     rr += double(ri) * double(ri);
   }
   __syncthreads();
-  double* part_b = a.ctrl.part + (int64_t)b * a.ctrl.part_stride;
   const int s_eff = a.U ? a.ctrl.s_eff[b] : 0;
   if (s_eff > 0)
     ut_r_partial<VT>(static_cast<const VT*>(a.U) + (int64_t)b * n * a.s_stride, n, s_eff, ch, rs,
-                     part_b + (int64_t)blockIdx.x * kPartW);
+                     a.ctrl.upart + (int64_t)b * kMaxS * a.ctrl.pstride + blockIdx.x,
+                     a.ctrl.pstride);
   double v[1] = {rr};
   block_sum<1>(v, red);
-  if (threadIdx.x == 0) part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 4] = v[0];
-  if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntUpdate, a.nb)) return;
-  __shared__ int s_go;
-  double tv[1];
-  sum_slots<1>(part_b, a.nb, 4, tv, red);
-  if (threadIdx.x == 0) {
-    const double t = tv[0];
-    S->rr = t;
-    S->cg_iters += 1;
-    int go = 1;
-    if (!(t <= 1.0e300)) {
-      S->breakdown = 1;
-      go = 0;
-    } else if (t <= S->tol2 || S->cg_iters >= P.max_cg) {
-      go = 0;
-    }
-    S->cg_active = go;
-    s_go = go;
-  }
-  __syncthreads();
-  if (s_go)
-    finish_coef(part_b, a.nb, s_eff, a.ctrl.lamhat + (int64_t)b * a.ctrl.s_stride, P.nu,
-                a.ctrl.coef + (int64_t)b * kMaxS);
+  if (threadIdx.x == 0) slot_ptr(a.ctrl, b, kSlRr)[blockIdx.x] = v[0];
 }
 
-template <typename VT>
-__global__ __launch_bounds__(256) void k_p_update(VecArgs a) {
-  const int b = blockIdx.y;
-  const ProbParams P = a.ctrl.params[b];
-  const ProbState* S = a.ctrl.state + b;
-  if (!P.run || !S->cg_active) return;
-  const int64_t n = a.n;
-  const Chunk ch = my_chunk(n, a.chunk);
-  const int64_t off = (int64_t)b * n;
-  VT* p = static_cast<VT*>(a.p) + off;
-  const VT* w = static_cast<const VT*>(a.w) + off;
-  const VT be = VT(S->beta_cg);
-  for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) p[i] = w[i] + be * p[i];
-}
-
+// Over-relaxed z- and u-updates with the soft-threshold prox (Sec. 2.5, Sec. 3.1)
+// and the partials of the residual norms of Sec. 2.3; runs once the x-solve of
+// the iteration has finished.
 template <typename VT>
 __global__ __launch_bounds__(256) void k_admm_end(VecArgs a) {
   const int b = blockIdx.y;
   const ProbParams P = a.ctrl.params[b];
-  ProbState* S = a.ctrl.state + b;
+  const ProbState* S = a.ctrl.state + b;
   if (!P.run || S->cg_active || S->admm_done) return;
   const int64_t n = a.n;
   const Chunk ch = my_chunk(n, a.chunk);
@@ -363,6 +504,7 @@ __global__ __launch_bounds__(256) void k_admm_end(VecArgs a) {
   double s_rp = 0, s_x = 0, s_z = 0, s_u = 0, s_rd = 0, s_z1 = 0, s_nnz = 0;
   for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) {
     const VT xi = x[i], zi = z[i], ui = u[i];
+    const VT hi = c ? h[i] : VT(0), ci = c ? c[i] : VT(0);
     const VT xh = al * xi + one_m * zi;
     const VT zn = soft_threshold<VT>(xh + ui, kap);
     const VT un = ui + xh - zn;
@@ -374,7 +516,7 @@ __global__ __launch_bounds__(256) void k_admm_end(VecArgs a) {
     s_z += double(zn) * double(zn);
     s_u += double(un) * double(un);
     if (c) {
-      const double rd = double(h[i] - c[i]) + double(rho) * double(un);
+      const double rd = double(hi - ci) + double(rho) * double(un);
       s_rd += rd * rd;
     }
     s_z1 += fabs(double(zn));
@@ -382,12 +524,21 @@ __global__ __launch_bounds__(256) void k_admm_end(VecArgs a) {
   }
   double v[7] = {s_rp, s_x, s_z, s_u, s_rd, s_z1, s_nnz};
   block_sum<7>(v, red);
-  double* part_b = a.ctrl.part + (int64_t)b * a.ctrl.part_stride;
   if (threadIdx.x == 0)
-    for (int k = 0; k < 7; ++k) part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 5 + k] = v[k];
-  if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntEnd, a.nb)) return;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) slot_ptr(a.ctrl, b, kSlEnd0 + k)[blockIdx.x] = v[k];
+}
+
+// One block per problem: the 7 sums of admm_end into the state, then admm_done.
+__global__ __launch_bounds__(256) void k_admm_finish(Ctrl ctrl, int nb) {
+  const int b = blockIdx.y;
+  const ProbParams P = ctrl.params[b];
+  ProbState* S = ctrl.state + b;
+  if (!P.run || S->cg_active || S->admm_done) return;
+  const int sl[7] = {kSlEnd0, kSlEnd0 + 1, kSlEnd0 + 2, kSlEnd0 + 3,
+                     kSlEnd0 + 4, kSlEnd0 + 5, kSlEnd0 + 6};
   double tv[7];
-  sum_slots<7>(part_b, a.nb, 5, tv, red);
+  reduce_slots<7>(ctrl, b, nb, sl, tv);
   if (threadIdx.x == 0) {
     for (int k = 0; k < 7; ++k) S->red[k] = tv[k];
     S->admm_done = 1;
@@ -399,7 +550,6 @@ __global__ __launch_bounds__(256) void k_dual_residual(VecArgs a) {
   const int b = blockIdx.y;
   const ProbParams P = a.ctrl.params[b];
   if (!P.run) return;
-  ProbState* S = a.ctrl.state + b;
   const int64_t n = a.n;
   const Chunk ch = my_chunk(n, a.chunk);
   const int64_t off = (int64_t)b * n;
@@ -416,12 +566,16 @@ __global__ __launch_bounds__(256) void k_dual_residual(VecArgs a) {
   }
   double v[1] = {s};
   block_sum<1>(v, red);
-  double* part_b = a.ctrl.part + (int64_t)b * a.ctrl.part_stride;
-  if (threadIdx.x == 0) part_b[(int64_t)blockIdx.x * kPartW + kMaxS + 12] = v[0];
-  if (!last_block_arrive(a.ctrl.counters + (int64_t)b * kNumCounters + kCntAux0, a.nb)) return;
+  if (threadIdx.x == 0) slot_ptr(a.ctrl, b, kSlDual)[blockIdx.x] = v[0];
+}
+
+__global__ __launch_bounds__(256) void k_dual_finish(Ctrl ctrl, int nb) {
+  const int b = blockIdx.y;
+  if (!ctrl.params[b].run) return;
+  const int sl[1] = {kSlDual};
   double tv[1];
-  sum_slots<1>(part_b, a.nb, 12, tv, red);
-  if (threadIdx.x == 0) S->red[kRedRd2] = tv[0];
+  reduce_slots<1>(ctrl, b, nb, sl, tv);
+  if (threadIdx.x == 0) ctrl.state[b].red[kRedRd2] = tv[0];
 }
 
 // Objective over the m samples from partials of t = A z.
@@ -620,16 +774,62 @@ __global__ __launch_bounds__(256) void k_masked_dot(int64_t n, const VT* __restr
     return hipGetLastError();                                                          \
   } while (0)
 
-hipError_t launch_admm_begin(const VecArgs& a, hipStream_t st) { GENIOS_VEC_LAUNCH(k_admm_begin); }
-hipError_t launch_precond_step(const VecArgs& a, int init, hipStream_t st) {
-  GENIOS_VEC_LAUNCH(k_precond_step, init);
+static bool vec_geometry_ok(const VecArgs& a) {
+  // every vector kernel writes one partial per block into pstride-sized slots
+  return a.nb >= 1 && a.nb <= a.ctrl.pstride && a.chunk >= 1 && a.chunk <= 4 * kVecChunk &&
+         (int64_t)a.nb * a.chunk >= a.n;
 }
-hipError_t launch_cg_alpha(const VecArgs& a, hipStream_t st) { GENIOS_VEC_LAUNCH(k_cg_alpha); }
-hipError_t launch_cg_update(const VecArgs& a, hipStream_t st) { GENIOS_VEC_LAUNCH(k_cg_update); }
-hipError_t launch_p_update(const VecArgs& a, hipStream_t st) { GENIOS_VEC_LAUNCH(k_p_update); }
-hipError_t launch_admm_end(const VecArgs& a, hipStream_t st) { GENIOS_VEC_LAUNCH(k_admm_end); }
+
+#define GENIOS_VEC_CHECK() \
+  do {                     \
+    if (!vec_geometry_ok(a)) return hipErrorInvalidValue; \
+  } while (0)
+
+hipError_t launch_admm_begin(const VecArgs& a, hipStream_t st) {
+  GENIOS_VEC_CHECK();
+  GENIOS_VEC_LAUNCH(k_admm_begin);
+}
+hipError_t launch_precond_coef(const VecArgs& a, hipStream_t st) {
+  GENIOS_VEC_CHECK();
+  if (a.U == nullptr) return hipSuccess;
+  hipLaunchKernelGGL(k_precond_coef, dim3((unsigned)kMaxS, (unsigned)a.batch), dim3(256), 0, st,
+                     a.ctrl, a.nb);
+  return hipGetLastError();
+}
+hipError_t launch_precond_step(const VecArgs& a, int t, int init, hipStream_t st) {
+  GENIOS_VEC_CHECK();
+  GENIOS_VEC_LAUNCH(k_precond_step, t, init);
+}
+hipError_t launch_cg_alpha(const VecArgs& a, hipStream_t st) {
+  GENIOS_VEC_CHECK();
+  GENIOS_VEC_LAUNCH(k_cg_alpha);
+}
+hipError_t launch_cg_update(const VecArgs& a, int t, hipStream_t st) {
+  GENIOS_VEC_CHECK();
+  GENIOS_VEC_LAUNCH(k_cg_update, t);
+}
+hipError_t launch_p_update(const VecArgs& a, int t, int init, hipStream_t st) {
+  GENIOS_VEC_CHECK();
+  GENIOS_VEC_LAUNCH(k_p_update, t, init);
+}
+hipError_t launch_admm_end(const VecArgs& a, hipStream_t st) {
+  GENIOS_VEC_CHECK();
+  GENIOS_VEC_LAUNCH(k_admm_end);
+}
+hipError_t launch_admm_finish(const VecArgs& a, hipStream_t st) {
+  GENIOS_VEC_CHECK();
+  hipLaunchKernelGGL(k_admm_finish, dim3(1, (unsigned)a.batch), dim3(256), 0, st, a.ctrl, a.nb);
+  return hipGetLastError();
+}
 hipError_t launch_dual_residual(const VecArgs& a, hipStream_t st) {
-  GENIOS_VEC_LAUNCH(k_dual_residual);
+  GENIOS_VEC_CHECK();
+  dim3 grid((unsigned)a.nb, (unsigned)a.batch);
+  if (a.vt == VT_F32)
+    hipLaunchKernelGGL(k_dual_residual<float>, grid, dim3(kVecBlock), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_dual_residual<double>, grid, dim3(kVecBlock), 0, st, a);
+  hipLaunchKernelGGL(k_dual_finish, dim3(1, (unsigned)a.batch), dim3(256), 0, st, a.ctrl, a.nb);
+  return hipGetLastError();
 }
 
 static int m_blocks(int64_t m) {

@@ -95,6 +95,9 @@ void Layout::carve(Arena& ar) {
   ctrl.s_stride = std::max(1, s);
   ctrl.part_stride = (int64_t)part_blocks * kPartW;
   ctrl.part = static_cast<double*>(ar.take(B * ctrl.part_stride * sizeof(double)));
+  ctrl.pstride = part_blocks;
+  ctrl.spart = static_cast<double*>(ar.take(B * kNumSlots * ctrl.pstride * sizeof(double)));
+  ctrl.upart = static_cast<double*>(ar.take(B * kMaxS * ctrl.pstride * sizeof(double)));
   ctrl_bytes_end = ar.off;
   core_status = static_cast<int32_t*>(ar.take(B * sizeof(int32_t)));
   shift = static_cast<double*>(ar.take(B * sizeof(double)));
@@ -103,7 +106,7 @@ void Layout::carve(Arena& ar) {
   auto vec = [&](int64_t len) { return ar.take((size_t)B * len * ve); };
   for (int k = 0; k < kNumNVec; ++k) nv[k] = n_vecs > k ? vec(n) : nullptr;
   tparts = ar.take((size_t)B * nsplit_n * m * ve);
-  ypart = ar.take((size_t)B * ksplit * nrhs * npad * ve);
+  ypart = ar.take((size_t)B * yprob() * ve);
   if (logistic || backward) {
     dvec = vec(m);
     cols = ar.take((size_t)B * 2 * m * ve);
@@ -141,7 +144,7 @@ int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_)
   s = s_;
   const int prec = o->precision;
   const bool uses_lo = (op == GENIOS_OP_LASSO || op == GENIOS_OP_LOGREG || op == GENIOS_OP_NYSTROM ||
-                        op == GENIOS_OP_MATVEC) &&
+                        op == GENIOS_OP_MATVEC || op == GENIOS_OP_HVP) &&
                        (prec == GENIOS_PREC_BF16_REFINE || prec == GENIOS_PREC_BF16_ONLY);
   need_a16 = uses_lo && A->A_bf16 == nullptr;
   // exact extent of the matrix elements (the padding after the last row is not read)
@@ -151,12 +154,16 @@ int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_)
   nsplit_n = std::max(gemv_n_splits(probe, batch), uses_lo ? gemv_n_splits(probe_lo, batch) : 1);
   nrhs = logistic ? 2 : 1;
   ksplit = std::max(gemv_t_splits(probe, batch), uses_lo ? gemv_t_splits(probe_lo, batch) : 1);
+  // partial slots of A^T products: gemv_t's row splits or the fused H p's blocks
+  const bool cg_op = op == GENIOS_OP_LASSO || op == GENIOS_OP_LOGREG ||
+                     op == GENIOS_OP_BACKWARD || op == GENIOS_OP_HVP;
+  yslots = std::max<int64_t>((int64_t)ksplit * (logistic ? 2 : 1),
+                             cg_op ? std::max<int64_t>(1, kHvpMaxBlocks / batch) : 1);
   npad = (n + 7) / 8 * 8;
-  chunk = std::max<int64_t>(256, ((n + 127) / 128 + 255) / 256 * 256);
-  chunk = std::min<int64_t>(chunk, 4 * kVecChunk);
+  chunk = vec_chunk(n);
   nb = (int)((n + chunk - 1) / chunk);
   part_blocks = std::max<int>(nb, std::max<int>(kMaxVecBlocks, (int)((n + kVecChunk - 1) / kVecChunk)));
-  n_vecs = (op == GENIOS_OP_MATVEC || op == GENIOS_OP_NYSTROM) ? 0 : kNumNVec;
+  n_vecs = (op == GENIOS_OP_MATVEC || op == GENIOS_OP_NYSTROM || op == GENIOS_OP_HVP) ? 0 : kNumNVec;
   ldS_max = backward ? (int)((std::min(m, n) + 7) / 8 * 8) : 0;
   if (s > 0) sketch_ws_bytes(m, n, s, batch, vt, &sk.ksW, &sk.ksY, &sk.nbG);
   Arena ar{nullptr, 0, 0, true};
@@ -199,9 +206,9 @@ struct Timer {
 struct KernelProf {
   bool on = false;
   std::vector<hipEvent_t> evs;
-  std::vector<int> kind;  // 0 = A v, 1 = A^T w
+  std::vector<int> kind;  // 0 = A v, 1 = A^T w, 2 = fused H p
   size_t used = 0;
-  double t[2] = {0, 0};
+  double t[3] = {0, 0, 0};
   ~KernelProf() {
     for (auto e : evs) (void)hipEventDestroy(e);
   }
@@ -249,8 +256,8 @@ struct Ctx {
   int32_t* gate_run = nullptr;   // &params[0].run
   int gs_state = sizeof(ProbState) / 4, gs_params = sizeof(ProbParams) / 4;
   KernelProf prof;
-  int64_t n_mv[2] = {0, 0};
-  int64_t bytes_kind[2] = {0, 0};  // matrix bytes of A v / A^T w products
+  int64_t n_mv[3] = {0, 0, 0};
+  int64_t bytes_kind[3] = {0, 0, 0};  // matrix bytes of A v / A^T w / fused H p products
 
   void* vecp(int k) const { return L.nv[k]; }
   VecArgs vargs(void* x, void* z, void* u, void* h, void* g, void* c, const uint8_t* mask) const {
@@ -276,7 +283,7 @@ struct Ctx {
     a.ypart = L.ypart;
     a.ksplit = L.ksplit;
     a.ypart_ks_stride = (int64_t)L.nrhs * L.npad;
-    a.ypart_prob_stride = (int64_t)L.ksplit * L.nrhs * L.npad;
+    a.ypart_prob_stride = L.yprob();
     a.mask = mask;
     return a;
   }
@@ -306,13 +313,36 @@ struct Ctx {
     const int ks = nsplit_for(op, 1);
     HC(launch_gemv_t(op, B, vt, L.tparts, nsplit_in, m, (int64_t)L.nsplit_n * m, 0, 1, d, m,
                      L.ypart, ks, (int64_t)L.nrhs * L.npad, L.npad,
-                     (int64_t)L.ksplit * L.nrhs * L.npad, gate, gstride, st));
+                     L.yprob(), gate, gstride, st));
     HC(prof.end(st));
     cur_ks = ks;
+    cur_ks_stride = (int64_t)L.nrhs * L.npad;
     account(op, 1);
     return 0;
   }
+  // ypart = H p = A^T (d o (A p)) (gated): one pass over A when it qualifies for
+  // the fused kernel, else gemv_n then gemv_t.
+  int hvp(const MatArg& op, const void* p, const void* d, const int32_t* gate, int gstride) {
+    if (vt == VT_F32) {
+      const HvpGeom g = hvp_geometry(op, B, true);
+      if (g.threads > 0 && g.blocks <= L.yslots) {
+        HC(prof.begin(st, 2));
+        HC(launch_hvp_fused(op, g, B, static_cast<const float*>(p), n,
+                            static_cast<const float*>(d), m, static_cast<float*>(L.ypart), L.npad,
+                            L.yprob(), gate, gstride, st));
+        HC(prof.end(st));
+        cur_ks = g.blocks;
+        cur_ks_stride = L.npad;
+        account(op, 2);
+        return 0;
+      }
+    }
+    int rc = gemv_n(op, p, gate, gstride);
+    if (rc) return rc;
+    return gemv_t_from_t(op, d, gate, gstride, nsplit_for(op, 0));
+  }
   int cur_ks = 1;
+  int64_t cur_ks_stride = 0;
 };
 
 int hvp_explicit(Ctx& c, const MatArg& op, const void* x, void* h, const void* d,
@@ -322,7 +352,7 @@ int hvp_explicit(Ctx& c, const MatArg& op, const void* x, void* h, const void* d
   rc = c.gemv_t_from_t(op, d, gate, gstride, c.nsplit_for(op, 0));
   if (rc) return rc;
   HC(launch_sum_splits(c.vt, c.B, c.n, c.L.ypart, c.cur_ks, (int64_t)c.L.nrhs * c.L.npad,
-                       (int64_t)c.L.ksplit * c.L.nrhs * c.L.npad, h, c.n, c.st, gate, gstride));
+                       c.L.yprob(), h, c.n, c.st, gate, gstride));
   return 0;
 }
 
@@ -370,19 +400,33 @@ hipError_t upload_params(Ctx& c, ProbParams* hp) {
   return hipMemcpyAsync(c.L.ctrl.params, hp, c.B * sizeof(ProbParams), hipMemcpyHostToDevice, c.st);
 }
 
-// One CG iteration for all problems (kernels gated on cg_active).
-int cg_iteration(Ctx& c, const MatArg& op, const VecArgs& va, const void* dscale) {
-  int rc = c.gemv_n(op, va.p, c.gate_cg, c.gs_state);
-  if (rc) return rc;
-  rc = c.gemv_t_from_t(op, dscale, c.gate_cg, c.gs_state, c.nsplit_for(op, 0));
+// The x-system set-up up to the first search direction (kernels gated on run).
+int cg_setup(Ctx& c, const VecArgs& va) {
+  HC(launch_admm_begin(va, c.st));
+  HC(launch_precond_coef(va, c.st));
+  HC(launch_precond_step(va, 0, 1, c.st));
+  HC(launch_p_update(va, 0, 1, c.st));
+  return 0;
+}
+
+// The vector part of CG iteration t (kernels gated on cg_active).
+int cg_vector_step(Ctx& c, const VecArgs& a, int t) {
+  HC(launch_cg_alpha(a, c.st));
+  HC(launch_cg_update(a, t, c.st));
+  HC(launch_precond_coef(a, c.st));
+  HC(launch_precond_step(a, t, 0, c.st));
+  HC(launch_p_update(a, t, 0, c.st));
+  return 0;
+}
+
+// CG iteration t for all problems.
+int cg_iteration(Ctx& c, const MatArg& op, const VecArgs& va, const void* dscale, int t) {
+  int rc = c.hvp(op, va.p, dscale, c.gate_cg, c.gs_state);
   if (rc) return rc;
   VecArgs a = va;
   a.ksplit = c.cur_ks;
-  HC(launch_cg_alpha(a, c.st));
-  HC(launch_cg_update(a, c.st));
-  HC(launch_precond_step(a, 0, c.st));
-  HC(launch_p_update(a, c.st));
-  return 0;
+  a.ypart_ks_stride = c.cur_ks_stride;
+  return cg_vector_step(c, a, t);
 }
 
 }  // namespace
@@ -478,17 +522,17 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     if (use_lo) {
       HC(launch_gemv_t(c.op_lo, B, c.vt, bvec, 1, 0, m, 0, 1, nullptr, 0, c.L.ypart,
                        c.nsplit_for(c.op_lo, 1), (int64_t)c.L.nrhs * c.L.npad, c.L.npad,
-                       (int64_t)c.L.ksplit * c.L.nrhs * c.L.npad, nullptr, 0, c.st));
+                       c.L.yprob(), nullptr, 0, c.st));
       HC(launch_sum_splits(c.vt, B, n, c.L.ypart, c.nsplit_for(c.op_lo, 1),
-                           (int64_t)c.L.nrhs * c.L.npad, (int64_t)c.L.ksplit * c.L.nrhs * c.L.npad,
+                           (int64_t)c.L.nrhs * c.L.npad, c.L.yprob(),
                            c_lo, n, c.st));
     }
     if (prec != GENIOS_PREC_BF16_ONLY || true) {
       HC(launch_gemv_t(c.op_hi, B, c.vt, bvec, 1, 0, m, 0, 1, nullptr, 0, c.L.ypart,
                        c.nsplit_for(c.op_hi, 1), (int64_t)c.L.nrhs * c.L.npad, c.L.npad,
-                       (int64_t)c.L.ksplit * c.L.nrhs * c.L.npad, nullptr, 0, c.st));
+                       c.L.yprob(), nullptr, 0, c.st));
       HC(launch_sum_splits(c.vt, B, n, c.L.ypart, c.nsplit_for(c.op_hi, 1),
-                           (int64_t)c.L.nrhs * c.L.npad, (int64_t)c.L.ksplit * c.L.nrhs * c.L.npad,
+                           (int64_t)c.L.nrhs * c.L.npad, c.L.yprob(),
                            c_hi, n, c.st));
     }
   }
@@ -506,14 +550,14 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     HC(c.prof.begin(c.st, 1));
     const int ks = c.nsplit_for(opx, 1);
     HC(launch_gemv_t(opx, B, c.vt, c.L.cols, 1, 0, 2 * m, m, 2, nullptr, 0, c.L.ypart, ks,
-                     (int64_t)2 * c.L.npad, c.L.npad, (int64_t)c.L.ksplit * 2 * c.L.npad, gate,
+                     (int64_t)2 * c.L.npad, c.L.npad, c.L.yprob(), gate,
                      gstride, c.st));
     HC(c.prof.end(c.st));
     c.account(opx, 1);
     HC(launch_sum_splits(c.vt, B, n, c.L.ypart, ks, (int64_t)2 * c.L.npad,
-                         (int64_t)c.L.ksplit * 2 * c.L.npad, h, n, c.st, gate, gstride));
+                         c.L.yprob(), h, n, c.st, gate, gstride));
     HC(launch_sum_splits(c.vt, B, n, static_cast<char*>(c.L.ypart) + c.L.npad * c.ve, ks,
-                         (int64_t)2 * c.L.npad, (int64_t)c.L.ksplit * 2 * c.L.npad, g, n, c.st,
+                         (int64_t)2 * c.L.npad, c.L.yprob(), g, n, c.st,
                          gate, gstride));
     return 0;
   };
@@ -582,8 +626,8 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     HC(upload_params(c, hp));
     VecArgs va = c.vargs(x, z, u, h, g, phase == 0 ? c_lo : c_hi, nullptr);
     HC(hipEventRecord(tm.ev[0], c.st));
-    HC(launch_admm_begin(va, c.st));
-    HC(launch_precond_step(va, 1, c.st));
+    rc = cg_setup(c, va);
+    if (rc) return rc;
     int chunk = 1;
     for (int64_t b = 0; b < B; ++b)
       if (!P[b].done) chunk = std::max(chunk, P[b].last_cg);
@@ -591,12 +635,13 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     int enq = 0;
     for (;;) {
       for (int it = 0; it < chunk; ++it) {
-        rc = cg_iteration(c, *op, va, logistic ? c.L.dvec : nullptr);
+        rc = cg_iteration(c, *op, va, logistic ? c.L.dvec : nullptr, enq + it);
         if (rc) return rc;
       }
       enq += chunk;
       HC(hipEventRecord(tm.ev[1], c.st));
       HC(launch_admm_end(va, c.st));
+      HC(launch_admm_finish(va, c.st));
       if (logistic) {
         // gradient pass at the new x (gated on the completed update)
         rc = gradient_pass(*op, c.gate_done, c.gs_state);
@@ -811,6 +856,9 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     I.t_to_target = q.t_target;
     I.t_matvec_n = c.prof.t[0];
     I.t_matvec_t = c.prof.t[1];
+    I.t_hvp = c.prof.t[2];
+    I.n_hvp = (int32_t)c.n_mv[2];
+    I.bytes_hvp = c.bytes_kind[2];
     I.n_matvec_n = (int32_t)c.n_mv[0];
     I.n_matvec_t = (int32_t)c.n_mv[1];
     I.bytes_matvec_n = c.bytes_kind[0];
@@ -906,10 +954,36 @@ int run_matvec(const genios_matrix* A, int trans, int use_bf16, const void* v, v
   } else {
     const int ks = std::min(c.L.ksplit, gemv_t_splits(op, c.B));
     HC(launch_gemv_t(op, c.B, c.vt, v, 1, 0, c.m, 0, 1, nullptr, 0, c.L.ypart, ks, c.L.npad,
-                     c.L.npad, (int64_t)c.L.ksplit * c.L.npad, nullptr, 0, c.st));
-    HC(launch_sum_splits(c.vt, c.B, c.n, c.L.ypart, ks, c.L.npad, (int64_t)c.L.ksplit * c.L.npad,
+                     c.L.npad, c.L.yprob(), nullptr, 0, c.st));
+    HC(launch_sum_splits(c.vt, c.B, c.n, c.L.ypart, ks, c.L.npad, c.L.yprob(),
                          out, c.n, c.st));
   }
+  HC(hipStreamSynchronize(c.st));
+  return 0;
+}
+
+int run_hvp(const genios_matrix* A, int use_bf16, const void* d, const void* p, void* out,
+            const genios_opts* o) {
+  Ctx c;
+  c.st = static_cast<hipStream_t>(o->stream);
+  c.B = A->batch;
+  c.m = A->m;
+  c.n = A->n;
+  c.vt = A->hi_dtype == GENIOS_DT_F64 ? VT_F64 : VT_F32;
+  c.ve = c.vt == VT_F32 ? 4 : 8;
+  genios_opts oo = *o;
+  oo.precision = use_bf16 ? GENIOS_PREC_BF16_ONLY : GENIOS_PREC_F32;
+  genios_matrix AA = *A;
+  c.L.setup(GENIOS_OP_HVP, &AA, &oo, 0);
+  int rc = c.L.bind(o->workspace, o->workspace_bytes);
+  if (rc) return rc;
+  MatArg op = use_bf16 ? MatArg{A->A_bf16, MT_BF16, A->m, A->n, A->lda, A->stride_A}
+                       : MatArg{A->A_hi, c.vt == VT_F64 ? MT_F64 : MT_F32, A->m, A->n, A->lda,
+                                A->stride_A};
+  rc = c.hvp(op, p, d, nullptr, 0);
+  if (rc) return rc;
+  HC(launch_sum_splits(c.vt, c.B, c.n, c.L.ypart, c.cur_ks, c.cur_ks_stride, c.L.yprob(), out,
+                       c.n, c.st));
   HC(hipStreamSynchronize(c.st));
   return 0;
 }
@@ -1024,21 +1098,39 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
   // vector-kernel geometry of the compact problem
   VecArgs va = c.vargs(w, zero_z, zero_u, h, negS, nullptr, c.L.maskS);
   va.n = ldS;
-  va.chunk = std::min<int64_t>(4 * kVecChunk, std::max<int64_t>(256, ((ldS + 127) / 128 + 255) / 256 * 256));
+  va.chunk = vec_chunk(ldS);
   va.nb = (int)((ldS + va.chunk - 1) / va.chunk);
   va.U = s > 0 ? c.L.U : nullptr;
   va.s_stride = std::max(1, s);
   const int nsS = std::min(gemv_n_splits(opS, B), c.L.nsplit_n);
   const int ksS = std::max(
-      1, std::min<int>(gemv_t_splits(opS, B), (int)((int64_t)c.L.ksplit * c.L.nrhs * c.L.npad / ldS)));
+      1, std::min<int>(gemv_t_splits(opS, B), (int)(c.L.yprob() / ldS)));
   va.ksplit = ksS;
   va.ypart_ks_stride = ldS;
   va.ypart_prob_stride = (int64_t)ksS * ldS;
   // the lamhat stride used by the kernels must match the compact sketch rank
   va.ctrl.s_stride = std::max(1, s);
-  HC(launch_admm_begin(va, c.st));
-  HC(launch_precond_step(va, 1, c.st));
+  rc = cg_setup(c, va);
+  if (rc) return rc;
+  int t_cg = 0;
+  // fused one-pass H p on the compact matrix when it qualifies
+  const HvpGeom gS = c.vt == VT_F32 ? hvp_geometry(opS, B, true) : HvpGeom{};
+  const bool fusedS = gS.threads > 0 && gS.blocks <= c.L.yslots;
+  if (fusedS) {
+    va.ksplit = gS.blocks;
+    va.ypart_ks_stride = ldS;
+    va.ypart_prob_stride = (int64_t)gS.blocks * ldS;
+  }
   auto hvp_cg = [&]() -> int {
+    if (fusedS) {
+      HC(c.prof.begin(c.st, 2));
+      HC(launch_hvp_fused(opS, gS, B, static_cast<const float*>(va.p), ldS, nullptr, 0,
+                          static_cast<float*>(c.L.ypart), ldS, va.ypart_prob_stride, c.gate_cg,
+                          c.gs_state, c.st));
+      HC(c.prof.end(c.st));
+      c.account(opS, 2);
+      return cg_vector_step(c, va, t_cg++);
+    }
     HC(c.prof.begin(c.st, 0));
     HC(launch_gemv_n(opS, B, c.vt, va.p, ldS, c.L.tparts, m, (int64_t)c.L.nsplit_n * m, nsS,
                      c.gate_cg, c.gs_state, c.st));
@@ -1049,11 +1141,7 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
                      c.L.ypart, ksS, ldS, ldS, (int64_t)ksS * ldS, c.gate_cg, c.gs_state, c.st));
     HC(c.prof.end(c.st));
     c.account(opS, 1);
-    HC(launch_cg_alpha(va, c.st));
-    HC(launch_cg_update(va, c.st));
-    HC(launch_precond_step(va, 0, c.st));
-    HC(launch_p_update(va, c.st));
-    return 0;
+    return cg_vector_step(c, va, t_cg++);
   };
   for (;;) {
     for (int it = 0; it < 8; ++it) {
@@ -1100,6 +1188,9 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
       info[b].n_matvec_t = (int32_t)c.n_mv[1];
       info[b].bytes_matvec_n = c.bytes_kind[0];
       info[b].bytes_matvec_t = c.bytes_kind[1];
+      info[b].t_hvp = c.prof.t[2];
+      info[b].n_hvp = (int32_t)c.n_mv[2];
+      info[b].bytes_hvp = c.bytes_kind[2];
     }
     if (st < 0 && (worst >= 0 || st < worst)) worst = st;
     if (worst >= 0 && st > worst) worst = st;

@@ -37,6 +37,8 @@ struct Layout {
   int64_t a16_elems = 0;
   int nsplit_n = 1, nrhs = 1, ksplit = 1;
   int64_t npad = 0, chunk = 256;
+  int64_t yslots = 1;  // n-vector partial slots per problem in `ypart`
+  int64_t yprob() const { return yslots * npad; }
   int nb = 1, part_blocks = 1, n_vecs = 0;
   SketchWs sk{};
   Ctrl ctrl{};
@@ -72,6 +74,8 @@ int run_nystrom_build(const genios_matrix* A, const void* d, int s, const void* 
                       const genios_opts* o, void* U, double* lamhat, genios_info* info);
 int run_matvec(const genios_matrix* A, int trans, int use_bf16, const void* v, void* out,
                const genios_opts* o);
+int run_hvp(const genios_matrix* A, int use_bf16, const void* d, const void* p, void* out,
+            const genios_opts* o);
 int run_backward(const genios_matrix* A, const void* zstar, const void* gz, const genios_opts* o,
                  void* grad_b, double* grad_lambda, genios_info* info);
 

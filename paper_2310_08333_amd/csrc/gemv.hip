@@ -343,6 +343,196 @@ hipError_t launch_gemv_t(const MatArg& A, int64_t batch, VType vt, const void* t
 
 // ---- small utility kernels ---------------------------------------------------
 
+// ---- fused Hessian-vector product ---------------------------------------------
+// hp = A^T (d o (A p)) in one pass over A (Sec. 3.1 HVP example, Sec. 3.3 ML
+// Hessian with D = diag(d)).  A block owns a contiguous row range.  p sits in
+// LDS (FP32); thread t owns the 16-byte column chunks c = V (t + THREADS k) and
+// keeps their share of the result in registers.  Each row's chunks are loaded
+// once (packed; the next row's loads are in flight while a row is processed),
+// the row's dot product is reduced over the block (shuffles, then one LDS
+// exchange and one barrier), scaled by d, and the same registers update the
+// owned result columns.  Each block writes one partial of hp; the partials are
+// summed in a fixed order by the consumer.
+// Requires n % V == 0, lda % V == 0 and 16-byte aligned rows.
+
+template <typename T>
+struct Raw;
+template <>
+struct Raw<uint16_t> {
+  using type = uint4;  // 8 BF16
+  __device__ static __forceinline__ float get(const uint4& q, int e) {
+    const uint32_t w = e < 2 ? q.x : (e < 4 ? q.y : (e < 6 ? q.z : q.w));
+    return __uint_as_float((e & 1) ? (w & 0xffff0000u) : (w << 16));
+  }
+  // The same value through a byte permute: a second, differently written unpack,
+  // so the compiler recomputes it instead of keeping the first one's results live.
+  __device__ static __forceinline__ float get2(const uint4& q, int e) {
+    const uint32_t w = e < 2 ? q.x : (e < 4 ? q.y : (e < 6 ? q.z : q.w));
+    return __uint_as_float(__builtin_amdgcn_perm(w, w, (e & 1) ? 0x07060c0cu : 0x05040c0cu));
+  }
+};
+template <>
+struct Raw<float> {
+  using type = float4;
+  __device__ static __forceinline__ float get(const float4& q, int e) {
+    return e == 0 ? q.x : (e == 1 ? q.y : (e == 2 ? q.z : q.w));
+  }
+  __device__ static __forceinline__ float get2(const float4& q, int e) { return get(q, e); }
+};
+
+// Fixed-order wavefront sum without LDS traffic: DPP butterflies inside each
+// 16-lane row (pairs, quads, then row rotations by 4 and 8), then the four row
+// sums read from lanes 0, 16, 32, 48 and added in that order.  Every lane gets
+// the total.  All 64 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov<0x124>(v);  // row_ror 4
+  v += dpp_mov<0x128>(v);  // row_ror 8
+  const int b = __float_as_int(v);
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(b, 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(b, 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(b, 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(b, 48));
+  return ((r0 + r1) + r2) + r3;
+}
+
+template <typename T, int THREADS, int EPT, int D>
+__global__ __launch_bounds__(THREADS) void k_hvp_fused(
+    const T* __restrict__ A, int64_t lda, int64_t strideA, int m, int n,
+    const float* __restrict__ p, int64_t p_stride, const float* __restrict__ d, int64_t d_stride,
+    float* __restrict__ ypart, int64_t ks_stride, int64_t prob_stride, int rows_per_block,
+    const int32_t* __restrict__ gate, int gate_stride) {
+  static_assert(D >= 0 && D <= 2, "prefetch depth 0..2");
+  constexpr int V = Elem<T>::V;
+  constexpr int NC = EPT / V;
+  constexpr int W = THREADS / 64;
+  using RT = typename Raw<T>::type;
+  extern __shared__ float ps[];  // n floats
+  __shared__ float red[2][W];
+  const int b = blockIdx.y;
+  if (gate != nullptr && gate[(int64_t)b * gate_stride] == 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = blockIdx.x * rows_per_block;
+  const int r1 = min(m, r0 + rows_per_block);
+  // p in LDS, owner-major: the first NC - 1 chunks of thread t at t (NC - 1) V,
+  // the (possibly partial) last chunk row after them, so a thread reads its
+  // values from one base with small immediate offsets.  Exactly n floats.
+  constexpr int HEAD = (NC - 1) * V;  // floats per thread in the first NC - 1 chunks
+  const float* pb = p + (int64_t)b * p_stride;
+  for (int c = tid; c < n; c += THREADS) {
+    const int ch = c / V, t = ch % THREADS, k = ch / THREADS;
+    ps[k < NC - 1 ? t * HEAD + k * V + c % V : THREADS * HEAD + t * V + c % V] = pb[c];
+  }
+  const T* Ab = A + (int64_t)b * strideA;
+  const float* db = d ? d + (int64_t)b * d_stride : nullptr;
+  // Chunks k < NC - 1 always lie inside the row (EPT is the least multiple of V
+  // with EPT * THREADS >= n); only the last one may fall past n (n % V == 0: a
+  // chunk is wholly inside or outside), and is then read from column 0.
+  const bool last_ok = V * (tid + THREADS * (NC - 1)) < n;
+  auto col = [&](int k) { return (k < NC - 1 || last_ok) ? V * (tid + THREADS * k) : 0; };
+  // (owner slices start at multiples of V floats: 16-byte aligned for float4 reads)
+  const float4* pmine = reinterpret_cast<const float4*>(ps + tid * HEAD);
+  const float4* plast = reinterpret_cast<const float4*>(ps + (last_ok ? THREADS * HEAD + tid * V : 0));
+  const float lmask = last_ok ? 1.f : 0.f;  // the last chunk's p, zeroed past n (no branch)
+  // A row's loads stay together and in chunk order (the scheduler may not move
+  // other work across them), so a buffer's first chunk is the first to arrive
+  // and the wait before each use covers only the loads issued before it.
+  auto load_row = [&](int row, RT (&dst)[NC]) {
+    const T* rp = Ab + (int64_t)row * lda;
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) dst[k] = *reinterpret_cast<const RT*>(rp + col(k));
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  float y[NC][V];
+#pragma unroll
+  for (int k = 0; k < NC; ++k)
+#pragma unroll
+    for (int e = 0; e < V; ++e) y[k][e] = 0.f;
+  int par = 0;
+  // one row: dot with p, block reduction, scale, rank-one update of the owned columns
+  auto process = [&](RT (&cur)[NC], int r) {
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+#pragma unroll
+      for (int e4 = 0; e4 < V / 4; ++e4) {
+        float4 q = k < NC - 1 ? pmine[k * (V / 4) + e4] : plast[e4];
+        if (k == NC - 1) q = make_float4(q.x * lmask, q.y * lmask, q.z * lmask, q.w * lmask);
+        s = fmaf(Raw<T>::get(cur[k], 4 * e4 + 0), q.x, s);
+        s = fmaf(Raw<T>::get(cur[k], 4 * e4 + 1), q.y, s);
+        s = fmaf(Raw<T>::get(cur[k], 4 * e4 + 2), q.z, s);
+        s = fmaf(Raw<T>::get(cur[k], 4 * e4 + 3), q.w, s);
+      }
+    }
+    s = wave_sum_dpp(s);
+    if (lane == 0) red[par][wave] = s;
+    __syncthreads();
+    float t = 0.f;
+#pragma unroll
+    for (int w = 0; w < W; ++w) t += red[par][w];
+    if (db) t *= db[__builtin_amdgcn_readfirstlane(r)];  // uniform: a scalar load
+    par ^= 1;
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+      for (int e = 0; e < V; ++e) y[k][e] = fmaf(Raw<T>::get2(cur[k], e), t, y[k][e]);
+  };
+  // Ring of D + 1 row buffers, loop rotated: each step first issues the row D
+  // ahead into the free buffer, then processes the oldest one, so rows r + 1 ..
+  // r + D are in flight while row r is processed and the wait before a buffer's
+  // use covers only it (the newer D rows stay in flight).  Loads are
+  // unconditional -- past the block's last row they re-read it -- so every path
+  // reaches the loop head with the same loads outstanding.  The prologue's rows
+  // are kept apart by a wavefront-scope fence (a compiler barrier only).
+  // (Every block owns at least one row: r0 < r1.)
+  auto clampr = [&](int r) { return r < r1 ? r : r1 - 1; };
+  RT b0[NC], b1[NC], b2[NC];
+  load_row(r0, b0);
+  if constexpr (D >= 2) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    load_row(clampr(r0 + 1), b1);
+  }
+  __syncthreads();  // p in LDS
+  if constexpr (D == 0) {
+    for (int r = r0; r < r1; ++r) {
+      process(b0, r);
+      load_row(clampr(r + 1), b0);
+    }
+  } else if constexpr (D == 1) {
+    for (int r = r0; r < r1; r += 2) {
+      load_row(clampr(r + 1), b1);
+      process(b0, r);
+      load_row(clampr(r + 2), b0);
+      if (r + 1 < r1) process(b1, r + 1);
+    }
+  } else {
+    for (int r = r0; r < r1; r += 3) {
+      load_row(clampr(r + 2), b2);
+      process(b0, r);
+      load_row(clampr(r + 3), b0);
+      if (r + 1 < r1) process(b1, r + 1);
+      load_row(clampr(r + 4), b1);
+      if (r + 2 < r1) process(b2, r + 2);
+    }
+  }
+  float* yb = ypart + (int64_t)b * prob_stride + (int64_t)blockIdx.x * ks_stride;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    if (k < NC - 1 || last_ok) {
+#pragma unroll
+      for (int e = 0; e < V; e += 4)
+        *reinterpret_cast<float4*>(yb + col(k) + e) =
+            make_float4(y[k][e], y[k][e + 1], y[k][e + 2], y[k][e + 3]);
+    }
+  }
+}
+
 template <typename VT>
 __global__ __launch_bounds__(256) void k_sum_splits(int64_t len, const VT* __restrict__ in,
                                                     int nsplit, int64_t split_stride,
@@ -446,4 +636,146 @@ hipError_t launch_copy(VType vt, const void* src, void* dst, int64_t count, hipS
   return hipGetLastError();
 }
 
+// ---- fused Hessian-vector product: geometry and dispatch ----------------------
+
+namespace {
+
+constexpr int kHvpLdsBytes = 160 * 1024 - 1024;  // dynamic LDS for p; 1 KB for statics
+
+template <typename T, int THREADS, int EPT, int D>
+hipError_t hvp_launch_one(const MatArg& A, const HvpGeom& g, int64_t batch, const float* p,
+                          int64_t p_stride, const float* d, int64_t d_stride, float* ypart,
+                          int64_t ks_stride, int64_t prob_stride, const int32_t* gate,
+                          int gate_stride, hipStream_t st) {
+  auto* fn = &k_hvp_fused<T, THREADS, EPT, D>;
+  const size_t lds = (size_t)A.n * sizeof(float);
+  static bool big_lds = false;  // the attribute is set once per instantiation
+  if (lds > 64 * 1024 && !big_lds) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kHvpLdsBytes);
+    if (e != hipSuccess) return e;
+    big_lds = true;
+  }
+  hipLaunchKernelGGL(fn, dim3((unsigned)g.blocks, (unsigned)batch), dim3(THREADS), lds, st,
+                     static_cast<const T*>(A.ptr), A.lda, A.strideA, (int)A.m, (int)A.n, p,
+                     p_stride, d, d_stride, ypart, ks_stride, prob_stride, g.rows_per_block, gate,
+                     gate_stride);
+  return hipGetLastError();
+}
+
+// Prefetch depth (rows in flight while one is processed) that fits the register
+// budget of the block size: D + 1 packed row buffers plus the EPT owned results.
+template <typename T, int THREADS, int EPT>
+constexpr int hvp_depth() {
+  constexpr int row_regs = EPT * (int)sizeof(T) / 4;
+  constexpr int budget = THREADS >= 1024 ? 80 : 210;
+  return (3 * row_regs + EPT <= budget) ? 2 : ((2 * row_regs + EPT <= budget) ? 1 : 0);
+}
+
+template <typename T, int THREADS, int... E>
+hipError_t hvp_dispatch(int ept, const MatArg& A, const HvpGeom& g, int64_t batch, const float* p,
+                        int64_t p_stride, const float* d, int64_t d_stride, float* ypart,
+                        int64_t ks_stride, int64_t prob_stride, const int32_t* gate,
+                        int gate_stride, hipStream_t st) {
+  hipError_t r = hipErrorInvalidValue;
+  bool hit = false;
+  ((ept == E && !hit
+        ? (hit = true,
+           r = hvp_launch_one<T, THREADS, E, hvp_depth<T, THREADS, E>()>(
+               A, g, batch, p, p_stride, d, d_stride, ypart, ks_stride, prob_stride, gate,
+               gate_stride, st))
+        : r),
+   ...);
+  return r;
+}
+
+int num_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+}  // namespace
+
+HvpGeom hvp_geometry(const MatArg& A, int64_t batch, bool query_device) {
+  HvpGeom g{};
+  if (A.mt == MT_F64 || A.m < 1 || A.n < 1) return g;
+  const int V = A.mt == MT_BF16 ? 8 : 4;
+  if (A.n % V || A.lda % V || (batch > 1 && A.strideA % V)) return g;
+  if (reinterpret_cast<uintptr_t>(A.ptr) % 16) return g;
+  if (A.n * (int64_t)sizeof(float) > kHvpLdsBytes) return g;
+  // 256 threads for short rows; 1024 while 32 (BF16) / 40 (FP32) owned columns per
+  // thread suffice; beyond, 512 threads with up to 80 owned columns (2 waves per
+  // SIMD leave room for deeper row prefetch).
+  const int e_small = A.mt == MT_BF16 ? 32 : 16, e_mid = A.mt == MT_BF16 ? 32 : 36;
+  if (A.n <= 256 * e_small)
+    g.threads = 256;
+  else if (A.n <= 1024 * e_mid)
+    g.threads = 1024;
+  else
+    g.threads = 512;
+  g.ept = (int)(V * ((A.n + (int64_t)V * g.threads - 1) / ((int64_t)V * g.threads)));
+  if (g.ept > 80) {
+    g.threads = 0;
+    return g;
+  }
+  g.rows = 1;
+  int per_cu = 1;
+  if (g.threads == 256)
+    per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(4, (160 * 1024) / (A.n * 4 + 1024)));
+  const int cus = query_device ? num_cus() : 256;
+  const int64_t cap = std::max<int64_t>(1, kHvpMaxBlocks / batch);
+  const int64_t groups = (A.m + g.rows - 1) / g.rows;
+  int64_t G = std::max<int64_t>(1, (int64_t)per_cu * cus / batch);
+  G = std::min<int64_t>(G, std::min<int64_t>(cap, groups));
+  int64_t rpb = (A.m + G - 1) / G;
+  rpb = (rpb + g.rows - 1) / g.rows * g.rows;
+  g.rows_per_block = (int)rpb;
+  g.blocks = (int)((A.m + rpb - 1) / rpb);
+  return g;
+}
+
+hipError_t launch_hvp_fused(const MatArg& A, const HvpGeom& g, int64_t batch, const float* p,
+                            int64_t p_stride, const float* d, int64_t d_stride, float* ypart,
+                            int64_t ks_stride, int64_t prob_stride, const int32_t* gate,
+                            int gate_stride, hipStream_t st) {
+  if (g.threads == 0 || g.blocks < 1 || g.blocks > kHvpMaxBlocks ||
+      (int64_t)g.blocks * g.rows_per_block < A.m ||
+      (int64_t)(g.blocks - 1) * g.rows_per_block >= A.m || ks_stride < A.n)  // no empty block
+    return hipErrorInvalidValue;
+  if (A.mt == MT_BF16) {
+    if (g.threads == 256)
+      return hvp_dispatch<uint16_t, 256, 8, 16, 24, 32>(g.ept, A, g, batch, p, p_stride, d,
+                                                           d_stride, ypart, ks_stride, prob_stride,
+                                                           gate, gate_stride, st);
+    if (g.threads == 1024)
+      return hvp_dispatch<uint16_t, 1024, 8, 16, 24, 32>(g.ept, A, g, batch, p, p_stride, d,
+                                                         d_stride, ypart, ks_stride, prob_stride,
+                                                         gate, gate_stride, st);
+    return hvp_dispatch<uint16_t, 512, 72, 80>(g.ept, A, g, batch, p, p_stride, d, d_stride, ypart,
+                                               ks_stride, prob_stride, gate, gate_stride, st);
+  }
+  if (A.mt == MT_F32) {
+    if (g.threads == 256)
+      return hvp_dispatch<float, 256, 4, 8, 12, 16>(g.ept, A, g, batch, p, p_stride, d,
+                                                       d_stride, ypart, ks_stride, prob_stride,
+                                                       gate, gate_stride, st);
+    if (g.threads == 1024)
+      return hvp_dispatch<float, 1024, 4, 8, 12, 16, 20, 24, 28, 32, 36>(
+          g.ept, A, g, batch, p, p_stride, d, d_stride, ypart, ks_stride, prob_stride, gate,
+          gate_stride, st);
+    return hvp_dispatch<float, 512, 76, 80>(g.ept, A, g, batch, p, p_stride, d, d_stride, ypart,
+                                        ks_stride, prob_stride, gate, gate_stride, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace genios
+

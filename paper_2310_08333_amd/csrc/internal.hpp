@@ -22,6 +22,16 @@ constexpr int kMaxVecBlocks = 128;    // blocks per problem of the vector kernel
 constexpr int kPartW = kMaxS + 16;    // doubles per block partial (U^T r + scalars)
 constexpr int kNumCounters = 16;      // last-block counters per problem
 
+// Rows per block of the CG/ADMM vector kernels: one row per thread, growing in
+// whole block widths only when a problem would otherwise need more than 1024
+// blocks (the last-block reductions scale with the block count).
+inline int64_t vec_chunk(int64_t n) {
+  const int64_t blocks = (n + kVecBlock - 1) / kVecBlock;
+  const int64_t q = blocks > 1024 ? (blocks + 1023) / 1024 : 1;
+  const int64_t c = (int64_t)kVecBlock * q;
+  return c < 4 * kVecChunk ? c : 4 * kVecChunk;
+}
+
 // Host-written parameters of one problem, uploaded before each ADMM iteration.
 struct alignas(128) ProbParams {
   double nu;         // CG shift rho + sigma
@@ -41,7 +51,7 @@ struct alignas(128) ProbParams {
 
 // Device-written state of one problem (read back by the host after each sync).
 struct alignas(128) ProbState {
-  double rz;         // r^T P^-1 r of the current CG iterate
+  double rz2[2];     // r^T P^-1 r, ping-pong by CG iteration parity (rz2[t & 1] at iteration t)
   double pq;         // p^T (H + nu I) p
   double rr;         // ||r||^2
   double tol2;       // squared absolute CG tolerance
@@ -67,6 +77,20 @@ enum {
   kRedAux = 7
 };
 
+// Slots of the block-partial array (slot-major: spart[b][slot][block]).  A kernel
+// writes one partial per block; the kernel that consumes the sum reduces the
+// partials itself, every block in the same fixed order, so no kernel waits on
+// another block of its own grid.
+enum {
+  kSlRhs2 = 0,   // ||rhs||^2 of the x-system
+  kSlRr,         // ||r||^2 (r_0 at admm_begin, r_{t+1} at cg_update)
+  kSlRz,         // r^T P^-1 r
+  kSlPq,         // p^T (H + nu I) p
+  kSlEnd0,       // the 7 reductions of admm_end (kRedRp2 .. kRedNnz order)
+  kSlDual = kSlEnd0 + 7,  // ||grad + rho u||^2
+  kNumSlots
+};
+
 // Counter slots for the last-block reductions.
 enum {
   kCntBegin = 0, kCntPrecond, kCntAlpha, kCntUpdate, kCntEnd, kCntAux0, kCntAux1, kCntAux2,
@@ -79,6 +103,9 @@ struct Ctrl {
   ProbState* state;     // [batch]
   double* part;         // [batch][part_stride] block partials (kPartW doubles per block)
   int64_t part_stride;  // doubles per problem in `part`
+  double* spart;        // [batch][kNumSlots][pstride] scalar block partials
+  double* upart;        // [batch][kMaxS][pstride] U^T r block partials (column-major)
+  int64_t pstride;      // blocks reserved per slot (>= blocks of any vector kernel)
   unsigned* counters;   // [batch][kNumCounters]
   double* coef;         // [batch][kMaxS] preconditioner coefficients of the current r
   int32_t* s_eff;       // [batch] retained sketch rank
@@ -107,6 +134,21 @@ hipError_t launch_gemv_t(const MatArg& A, int64_t batch, VType vt, const void* t
                          int nrhs, const void* dscale, int64_t d_stride, void* ypart, int ksplit,
                          int64_t ypart_ks_stride, int64_t ypart_col_stride, int64_t ypart_prob_stride,
                          const int32_t* gate, int gate_stride_ints, hipStream_t st);
+// Fused H p = A^T (d o (A p)) in one pass over A (FP32 vectors; A in BF16 or FP32).
+// One partial of hp per block: ypart[b][block][ks_stride].
+constexpr int kHvpMaxBlocks = 512;  // partials reserved across a batch
+struct HvpGeom {
+  int threads = 0;         // 0: A does not qualify (use gemv_n + gemv_t)
+  int ept = 0;             // owned columns per thread
+  int rows = 0;            // rows per group
+  int blocks = 0;          // blocks (partials) per problem
+  int rows_per_block = 0;
+};
+HvpGeom hvp_geometry(const MatArg& A, int64_t batch, bool query_device);
+hipError_t launch_hvp_fused(const MatArg& A, const HvpGeom& g, int64_t batch, const float* p,
+                            int64_t p_stride, const float* d, int64_t d_stride, float* ypart,
+                            int64_t ks_stride, int64_t prob_stride, const int32_t* gate,
+                            int gate_stride, hipStream_t st);
 int gemv_n_splits(const MatArg& A, int64_t batch);
 int gemv_t_splits(const MatArg& A, int64_t batch);
 int gemv_t_rows_per_split(const MatArg& A, int ksplit);
@@ -137,13 +179,19 @@ struct VecArgs {
   int64_t ypart_ks_stride, ypart_prob_stride;
   const uint8_t* mask;    // masked operator (adjoint): 1 = in the active set
 };
+// One x-solve: admm_begin; precond_coef, precond_step(init), p_update(init); then
+// per CG iteration t = 0, 1, ...: cg_alpha, cg_update(t), precond_coef,
+// precond_step(t), p_update(t); then admm_end, admm_finish.  Every kernel is gated
+// on the problem's flags, so surplus iterations are no-ops.
 hipError_t launch_admm_begin(const VecArgs& a, hipStream_t st);
-hipError_t launch_precond_step(const VecArgs& a, int init, hipStream_t st);
+hipError_t launch_precond_coef(const VecArgs& a, hipStream_t st);
+hipError_t launch_precond_step(const VecArgs& a, int t, int init, hipStream_t st);
 hipError_t launch_cg_alpha(const VecArgs& a, hipStream_t st);
-hipError_t launch_cg_update(const VecArgs& a, hipStream_t st);
-hipError_t launch_p_update(const VecArgs& a, hipStream_t st);
+hipError_t launch_cg_update(const VecArgs& a, int t, hipStream_t st);
+hipError_t launch_p_update(const VecArgs& a, int t, int init, hipStream_t st);
 hipError_t launch_admm_end(const VecArgs& a, hipStream_t st);
-// ||g + rho u||^2 into state.red[kRedRd2] with g = h - c or the given g.
+hipError_t launch_admm_finish(const VecArgs& a, hipStream_t st);
+// ||g + rho u||^2 into state.red[kRedRd2] with g = h - c or the given g (two kernels).
 hipError_t launch_dual_residual(const VecArgs& a, hipStream_t st);
 // Objective pieces: Lasso 1/2||t - b||^2 or logistic sum log(1+exp(-y t)), into red[kRedAux].
 hipError_t launch_objective_m(VType vt, int64_t m, int64_t batch, const void* tparts, int nsplit,

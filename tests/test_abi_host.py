@@ -46,6 +46,8 @@ def test_default_opts_are_the_papers(abi):
     assert o.sigma == 1e-6 and o.gamma == 1.2 and o.alpha == 1.6
     assert o.eps_abs == 1e-4 and o.eps_rel == 1e-4 and o.tau == 2.0 and o.mu == 10.0
     assert o.resketch_every == 20 and o.sketch_rank == 0 and o.rho_update_every == 25
+    # Sec. 2.1's relative CG tolerance is taken against the warm-started initial residual
+    assert o.rhs_relative == 0
 
 
 def _mat(abi, m=100, n=200, lda=None, batch=1, dt=None):

@@ -5,6 +5,7 @@ import torch
 
 import genios_data
 from oracle import bf16 as obf16
+from oracle import lasso as olasso
 from oracle import nystrom as onys
 from oracle import philox as ophilox
 from oracle import prox as oprox
@@ -83,6 +84,48 @@ def test_matvec_batched_and_bf16_vs_f32(g):
     t16 = g.matvec(At, _t(v[0]), A16=g.cast_bf16(At)).cpu().numpy()
     ref = A[0].astype(np.float64) @ v[0]
     assert np.all(np.abs(t16 - ref) <= 2.0 ** -8 * (np.abs(A[0]) @ np.abs(v[0])) * 1.01 + 1e-4)
+
+
+def _hvp_bound(Aref, p, d, m, n):
+    # FP32: A p accumulates n products, A^T (d o t) at most m + 512 (block partials
+    # included): |err| <= (n + m + 520) u |A|^T (|d| o (|A| |p|)) to first order.
+    dd = np.ones(m) if d is None else np.abs(d.astype(np.float64))
+    absA = np.abs(Aref)
+    return 1.01 * (n + m + 520) * 2.0 ** -24 * (absA.T @ (dd * (absA @ np.abs(p)))) + 1e-30
+
+
+@pytest.mark.parametrize("m,n,kind,weighted", [
+    (200, 1000, "bf16", False), (200, 1000, "f32", True),
+    (257, 1003, "f32", False),                              # n % 4 != 0: gemv_n + gemv_t
+    (3000, 520, "bf16", True), (3000, 520, "f32", False),   # 256-thread blocks
+    (33, 40704, "bf16", False), (33, 40704, "f32", True),   # largest n, ragged last chunk
+    (50, 9000, "f32", False), (5, 24, "bf16", True), (1, 8, "f32", False)])
+def test_hvp_parity(g, m, n, kind, weighted):
+    print("hvp", m, n, kind, weighted, flush=True)
+    rng = np.random.default_rng(m * 31 + n)
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    p = rng.standard_normal(n).astype(np.float32)
+    d = (0.25 * rng.random(m)).astype(np.float32) if weighted else None
+    At = _t(A)
+    A16 = g.cast_bf16(At) if kind == "bf16" else None
+    Aref = obf16.round_to_bf16(A).astype(np.float64) if kind == "bf16" else A.astype(np.float64)
+    got = g.hvp(At, _t(p), d=_t(d) if weighted else None, A16=A16).cpu().numpy()
+    ref = olasso.hessian_vector(Aref, p, d)
+    bound = _hvp_bound(Aref, p.astype(np.float64), d, m, n)
+    assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / bound)
+
+
+def test_hvp_batched(g):
+    print("hvp batched", flush=True)
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((3, 130, 264)).astype(np.float32)
+    p = rng.standard_normal((3, 264)).astype(np.float32)
+    d = (0.25 * rng.random((3, 130))).astype(np.float32)
+    got = g.hvp(_t(A), _t(p), d=_t(d)).cpu().numpy()
+    for b in range(3):
+        ref = olasso.hessian_vector(A[b], p[b], d[b])
+        bound = _hvp_bound(A[b].astype(np.float64), p[b].astype(np.float64), d[b], 130, 264)
+        assert np.all(np.abs(got[b] - ref) <= bound)
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])

@@ -141,3 +141,29 @@ def test_r_kkt_matches_paper_test():
         rk, _, _ = residuals.r_kkt(x, z, u, rho, g)
         eps = 10 ** rng.uniform(-7, -1)
         assert (rk <= eps) == residuals.paper_stop_test(x, z, u, rho, g, eps, eps)
+
+
+def test_hessian_vector_is_the_change_of_gradient():
+    # f is quadratic: grad f(x + p) - grad f(x) = A^T A p exactly (up to rounding)
+    A, b = _rand_lasso(40, 25, 11)
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal(25)
+    p = rng.standard_normal(25)
+    hv = lasso.hessian_vector(A, p)
+    ref = lasso.grad_f(A, b, x + p) - lasso.grad_f(A, b, x)
+    assert np.allclose(hv, ref, rtol=1e-12, atol=1e-12)
+    assert hv @ p > 0  # positive definite here (m > n)
+
+
+def test_hessian_vector_with_logistic_weights_matches_gradient_differences():
+    # H(x) p = A^T diag(s(1 - s)) A p: central differences of the logistic gradient
+    from oracle import logreg
+    rng = np.random.default_rng(13)
+    A = rng.standard_normal((60, 15))
+    y = np.where(rng.random(60) < 0.5, 1.0, -1.0)
+    x = 0.3 * rng.standard_normal(15)
+    p = rng.standard_normal(15)
+    hv = lasso.hessian_vector(A, p, logreg.hess_diag(A, y, x))
+    h = 1e-5
+    fd = (logreg.grad_f(A, y, x + h * p) - logreg.grad_f(A, y, x - h * p)) / (2 * h)
+    assert np.allclose(hv, fd, rtol=1e-7, atol=1e-8)
