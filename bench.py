@@ -9,13 +9,22 @@ and its certification) followed by the adjoint (masked Nystrom PCG) of the loss
 ||z* - x0||^2.  The data are synthetic and resident in HBM before timing.
 
 Prints one JSON line: value = ADMM iterations per second over the timed steps,
-plus time-to-1e-4 for BF16-A + refine and for plain FP32 A, the matrix-vector
-kernels' bandwidth against the HBM roofline (HIP events on the solver's
-stream), and the CPU FP64 oracle on a bounded sample of the same workload.
+plus time-to-1e-4 for BF16-A + refine and for plain FP32 A, the dominant
+kernel's bandwidth against the HBM roofline (the fused one-pass Hessian-vector
+product on the BF16 copy, timed with HIP events on the solver's stream; its
+measured HBM traffic per launch comes from the rocprofv3 counter summary under
+profiles/), and the CPU FP64 oracle on a bounded sample of the same workload.
+
+    python bench.py --probe-traffic
+
+runs only a plain copy of known size and a few fused products on the workload,
+for the two counter passes (FETCH_SIZE, WRITE_SIZE) that calibrate and measure
+the traffic.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import statistics
@@ -35,7 +44,53 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(P, rows=5000, cols=10000, budget_iters=60):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hvp_fused_bf16_lasso_20000x40000_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2310_08333_amd", "csrc", "gemv.hip")
+
+
+def measured_traffic():
+    """HBM bytes per fused-product launch from the committed counter summary, or
+    None when the summary is missing or the kernel source changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        if kv.get("kernel_source_sha256") != sha:
+            return None
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def probe_traffic(workload):
+    """A plain device copy of known size, then fused products on the workload."""
+    import torch
+
+    import genios_data
+    import paper_2310_08333_amd as g
+    dev = torch.device("cuda:0")
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy of {nbytes} bytes done")
+    del src, dst
+    P = genios_data.config(workload)
+    A = torch.from_numpy(P["A"]).to(dev)
+    A16 = g.cast_bf16(A)
+    p = torch.from_numpy(np.random.default_rng(0).standard_normal(P["A"].shape[1])
+                         .astype(np.float32)).to(dev)
+    for i in range(3):
+        g.hvp(A, p, A16=A16)
+    torch.cuda.synchronize()
+    log("3 fused products done")
+
+
+def cpu_baseline(P, rows=8000, cols=16000, budget_iters=100):
     """The oracle's GeNIOS ADMM (exact Cholesky x-steps) on the leading rows x cols
     block of the workload's matrix: ADMM iterations per second on the host."""
     import threadpoolctl
@@ -68,11 +123,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--probe-traffic", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path "
               f"(--gpus {args.gpus} requested)", file=sys.stderr)
         sys.exit(2)
+
+    if args.probe_traffic:
+        probe_traffic(args.workload)
+        return
 
     import torch
 
@@ -120,25 +180,27 @@ def main():
     elapsed = time.perf_counter() - t_start
     ms_per_step = 1e3 * elapsed / args.steps
 
-    # matrix-vector kernels measured with HIP events on the solver's stream
-    tn = sum(i["t_matvec_n"] for i in infos) + sum(i["t_matvec_n"] for i in binfos)
-    tt = sum(i["t_matvec_t"] for i in infos) + sum(i["t_matvec_t"] for i in binfos)
-    bn = sum(i["bytes_matvec_n"] for i in infos) + sum(i["bytes_matvec_n"] for i in binfos)
-    bt = sum(i["bytes_matvec_t"] for i in infos) + sum(i["bytes_matvec_t"] for i in binfos)
-    nn = sum(i["n_matvec_n"] for i in infos) + sum(i["n_matvec_n"] for i in binfos)
-    nt = sum(i["n_matvec_t"] for i in infos) + sum(i["n_matvec_t"] for i in binfos)
-    gbs_n = bn / tn / 1e9 if tn > 0 else None
-    gbs_t = bt / tt / 1e9 if tt > 0 else None
-    dom = "gemv_t (A^T w)" if tt >= tn else "gemv_n (A v)"
-    ach = gbs_t if tt >= tn else gbs_n
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1) if ach else None,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4) if ach else None, "traffic": None,
-                "gemv_n_GBps": round(gbs_n, 1) if gbs_n else None,
-                "gemv_t_GBps": round(gbs_t, 1) if gbs_t else None,
-                "launches": {"gemv_n": nn, "gemv_t": nt},
-                "avg_us": {"gemv_n": round(1e6 * tn / max(nn, 1), 2),
-                           "gemv_t": round(1e6 * tt / max(nt, 1), 2)}}
+    # The dominant kernel: the fused Hessian-vector product on the BF16 copy,
+    # timed with HIP events on the solver's stream inside the timed steps.
+    allinf = infos + binfos
+    tot = lambda key: sum(i[key] for i in allinf)
+    t_h, n_h, b_h = tot("t_hvp"), tot("n_hvp"), tot("bytes_hvp")
+    t_hh, n_hh, b_hh = tot("t_hvp_hi"), tot("n_hvp_hi"), tot("bytes_hvp_hi")
+    ach = b_h / t_h / 1e9 if t_h > 0 else None
+    per = b_h / max(n_h, 1)
+    traffic = measured_traffic()
+    roofline = {
+        "bound": "hbm", "kernel": "k_hvp_fused: H p = A^T A p, BF16 A, one pass over A",
+        "achieved": round(ach, 1) if ach else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(ach / HBM_PEAK_GBS, 4) if ach else None, "traffic": traffic,
+        "bytes_per_launch": int(per), "launches": n_h,
+        "avg_us": round(1e6 * t_h / max(n_h, 1), 2),
+        "two_stream_equivalent_GBps": round(2 * m * n * 2 / (t_h / max(n_h, 1)) / 1e9, 1)
+        if t_h > 0 else None,
+        "master_copy_hvp": {"achieved_GBps": round(b_hh / t_hh / 1e9, 1) if t_hh > 0 else None,
+                            "launches": n_hh,
+                            "avg_us": round(1e6 * t_hh / max(n_hh, 1), 2)},
+    }
 
     fp32 = None
     if not args.no_fp32:

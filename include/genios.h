@@ -180,10 +180,12 @@ typedef struct {
   int64_t bytes_matvec_n;    /* matrix bytes streamed by the A v products (BF16 or master copy) */
   int64_t bytes_matvec_t;    /* matrix bytes streamed by the A^T w products */
   double t_hvp;              /* with profile_kernels: summed duration of the fused H p products
-                                (A^T D A p in one pass over A) */
-  int32_t n_hvp;             /* number of fused H p launches */
-  int32_t reserved_info;
-  int64_t bytes_hvp;         /* matrix bytes streamed by the fused H p products */
+                                (A^T D A p in one pass over A) on the BF16 copy */
+  int32_t n_hvp;             /* number of those launches */
+  int32_t n_hvp_hi;          /* number of fused H p launches on the master copy */
+  int64_t bytes_hvp;         /* bytes they must move: A once, p in, H p out (BF16 copy) */
+  double t_hvp_hi;           /* the same for the fused products on the master copy */
+  int64_t bytes_hvp_hi;
 } genios_info;
 
 /* Fill *o with the defaults listed above.  Returns GENIOS_OK. */
@@ -251,9 +253,11 @@ int genios_nystrom_apply(int64_t n, int32_t s, int64_t batch, int32_t dtype, con
  * support of z_star and s its signs,
  *   grad_b      = A_S (A_S^T A_S)^-1 grad_z_S          (m per problem, written)
  *   grad_lambda = -s^T (A_S^T A_S)^-1 grad_z_S          (host, batch, written)
- * The system is solved by Nystrom-preconditioned CG on the masked operator
- * P_S A^T A P_S + (I - P_S) with the FP32 (or FP64) master copy, to relative
- * residual opts->cg_tol_floor (default 1e-7 here as well).
+ * The active columns of the FP32 (or FP64) master copy are gathered, in order,
+ * into an m x |S| block in the workspace (padded to a multiple of 8 with
+ * identity columns), and the system is solved there by Nystrom-preconditioned
+ * CG (sketch of A_S^T A_S) to relative residual opts->cg_tol_floor (default 1e-7
+ * here as well); info->iters reports |S|, info->cg_iters the CG iterations.
  *   z_star, grad_z  n per problem.  lambda (host) is accepted for symmetry with
  *   the forward call and checked to be >= 0. */
 int genios_lasso_backward(const genios_matrix* A, const void* z_star, const void* grad_z,

@@ -206,9 +206,9 @@ struct Timer {
 struct KernelProf {
   bool on = false;
   std::vector<hipEvent_t> evs;
-  std::vector<int> kind;  // 0 = A v, 1 = A^T w, 2 = fused H p
+  std::vector<int> kind;  // 0 = A v, 1 = A^T w, 2 / 3 = fused H p on the BF16 / master copy
   size_t used = 0;
-  double t[3] = {0, 0, 0};
+  double t[4] = {0, 0, 0, 0};
   ~KernelProf() {
     for (auto e : evs) (void)hipEventDestroy(e);
   }
@@ -256,8 +256,10 @@ struct Ctx {
   int32_t* gate_run = nullptr;   // &params[0].run
   int gs_state = sizeof(ProbState) / 4, gs_params = sizeof(ProbParams) / 4;
   KernelProf prof;
-  int64_t n_mv[3] = {0, 0, 0};
-  int64_t bytes_kind[3] = {0, 0, 0};  // matrix bytes of A v / A^T w / fused H p products
+  int64_t n_mv[4] = {0, 0, 0, 0};
+  // bytes of A v / A^T w (the matrix) and of the fused H p on the BF16 / master copy
+  // (the matrix once, p read, H p written)
+  int64_t bytes_kind[4] = {0, 0, 0, 0};
 
   void* vecp(int k) const { return L.nv[k]; }
   VecArgs vargs(void* x, void* z, void* u, void* h, void* g, void* c, const uint8_t* mask) const {
@@ -291,6 +293,26 @@ struct Ctx {
   void account(const MatArg& op, int kind) {
     n_mv[kind] += B;
     bytes_kind[kind] += (int64_t)B * op.m * op.n * elem_size(op.mt);
+    if (kind >= 2) bytes_kind[kind] += (int64_t)B * op.n * 2 * (int64_t)ve;
+  }
+  static int hvp_kind(const MatArg& op) { return op.mt == MT_BF16 ? 2 : 3; }
+  // Remove `count` problem-launches of the last CG product (gated off on the device:
+  // enqueued but skipped because the problem's CG had already stopped).
+  int last_hvp_kind = -1;  // 2 / 3: fused; 0: gemv_n + gemv_t
+  MatArg last_hvp_op{};
+  void unaccount_gated(int64_t count) {
+    if (count <= 0 || last_hvp_kind < 0) return;
+    const MatArg& op = last_hvp_op;
+    const int64_t mat = (int64_t)op.m * op.n * elem_size(op.mt);
+    if (last_hvp_kind >= 2) {
+      n_mv[last_hvp_kind] -= count;
+      bytes_kind[last_hvp_kind] -= count * (mat + (int64_t)op.n * 2 * (int64_t)ve);
+    } else {
+      n_mv[0] -= count;
+      n_mv[1] -= count;
+      bytes_kind[0] -= count * mat;
+      bytes_kind[1] -= count * mat;
+    }
   }
 
   // tparts = A v (gated)
@@ -326,17 +348,21 @@ struct Ctx {
     if (vt == VT_F32) {
       const HvpGeom g = hvp_geometry(op, B, true);
       if (g.threads > 0 && g.blocks <= L.yslots) {
-        HC(prof.begin(st, 2));
+        HC(prof.begin(st, hvp_kind(op)));
         HC(launch_hvp_fused(op, g, B, static_cast<const float*>(p), n,
                             static_cast<const float*>(d), m, static_cast<float*>(L.ypart), L.npad,
                             L.yprob(), gate, gstride, st));
         HC(prof.end(st));
         cur_ks = g.blocks;
         cur_ks_stride = L.npad;
-        account(op, 2);
+        account(op, hvp_kind(op));
+        last_hvp_kind = hvp_kind(op);
+        last_hvp_op = op;
         return 0;
       }
     }
+    last_hvp_kind = 0;
+    last_hvp_op = op;
     int rc = gemv_n(op, p, gate, gstride);
     if (rc) return rc;
     return gemv_t_from_t(op, d, gate, gstride, nsplit_for(op, 0));
@@ -655,7 +681,14 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
       bool more = false;
       for (int64_t b = 0; b < B; ++b)
         if (hp[b].run && !hs[b].admm_done) more = true;
-      if (!more) break;
+      if (!more) {
+        // products enqueued for problems whose CG had stopped ran as no-ops
+        int64_t gated = 0;
+        for (int64_t b = 0; b < B; ++b)
+          gated += hp[b].run ? std::max<int64_t>(0, enq - hs[b].cg_iters) : enq;
+        c.unaccount_gated(gated);
+        break;
+      }
       chunk = std::max(1, std::min(2, o->max_cg_iter - enq));
     }
     float ms1 = 0.f, ms2 = 0.f;
@@ -859,6 +892,9 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     I.t_hvp = c.prof.t[2];
     I.n_hvp = (int32_t)c.n_mv[2];
     I.bytes_hvp = c.bytes_kind[2];
+    I.t_hvp_hi = c.prof.t[3];
+    I.n_hvp_hi = (int32_t)c.n_mv[3];
+    I.bytes_hvp_hi = c.bytes_kind[3];
     I.n_matvec_n = (int32_t)c.n_mv[0];
     I.n_matvec_t = (int32_t)c.n_mv[1];
     I.bytes_matvec_n = c.bytes_kind[0];
@@ -1122,13 +1158,15 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
     va.ypart_prob_stride = (int64_t)gS.blocks * ldS;
   }
   auto hvp_cg = [&]() -> int {
+    c.last_hvp_op = opS;
+    c.last_hvp_kind = fusedS ? Ctx::hvp_kind(opS) : 0;
     if (fusedS) {
-      HC(c.prof.begin(c.st, 2));
+      HC(c.prof.begin(c.st, Ctx::hvp_kind(opS)));
       HC(launch_hvp_fused(opS, gS, B, static_cast<const float*>(va.p), ldS, nullptr, 0,
                           static_cast<float*>(c.L.ypart), ldS, va.ypart_prob_stride, c.gate_cg,
                           c.gs_state, c.st));
       HC(c.prof.end(c.st));
-      c.account(opS, 2);
+      c.account(opS, Ctx::hvp_kind(opS));
       return cg_vector_step(c, va, t_cg++);
     }
     HC(c.prof.begin(c.st, 0));
@@ -1153,7 +1191,12 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
     bool more = false;
     for (int64_t b = 0; b < B; ++b)
       if (hs[b].cg_active) more = true;
-    if (!more) break;
+    if (!more) {
+      int64_t gated = 0;
+      for (int64_t b = 0; b < B; ++b) gated += std::max<int64_t>(0, t_cg - hs[b].cg_iters);
+      c.unaccount_gated(gated);
+      break;
+    }
   }
   // grad_b = A_S w_S; grad_lambda = -s_S^T w_S
   rc = 0;
@@ -1191,6 +1234,9 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
       info[b].t_hvp = c.prof.t[2];
       info[b].n_hvp = (int32_t)c.n_mv[2];
       info[b].bytes_hvp = c.bytes_kind[2];
+      info[b].t_hvp_hi = c.prof.t[3];
+      info[b].n_hvp_hi = (int32_t)c.n_mv[3];
+      info[b].bytes_hvp_hi = c.bytes_kind[3];
     }
     if (st < 0 && (worst >= 0 || st < worst)) worst = st;
     if (worst >= 0 && st > worst) worst = st;

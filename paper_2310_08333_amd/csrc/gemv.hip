@@ -714,7 +714,7 @@ HvpGeom hvp_geometry(const MatArg& A, int64_t batch, bool query_device) {
   // 256 threads for short rows; 1024 while 32 (BF16) / 40 (FP32) owned columns per
   // thread suffice; beyond, 512 threads with up to 80 owned columns (2 waves per
   // SIMD leave room for deeper row prefetch).
-  const int e_small = A.mt == MT_BF16 ? 32 : 16, e_mid = A.mt == MT_BF16 ? 32 : 36;
+  const int e_small = A.mt == MT_BF16 ? 32 : 16, e_mid = A.mt == MT_BF16 ? 32 : 40;
   if (A.n <= 256 * e_small)
     g.threads = 256;
   else if (A.n <= 1024 * e_mid)
@@ -768,7 +768,7 @@ hipError_t launch_hvp_fused(const MatArg& A, const HvpGeom& g, int64_t batch, co
                                                        d_stride, ypart, ks_stride, prob_stride,
                                                        gate, gate_stride, st);
     if (g.threads == 1024)
-      return hvp_dispatch<float, 1024, 4, 8, 12, 16, 20, 24, 28, 32, 36>(
+      return hvp_dispatch<float, 1024, 4, 8, 12, 16, 20, 24, 28, 32, 36, 40>(
           g.ept, A, g, batch, p, p_stride, d, d_stride, ypart, ks_stride, prob_stride, gate,
           gate_stride, st);
     return hvp_dispatch<float, 512, 76, 80>(g.ept, A, g, batch, p, p_stride, d, d_stride, ypart,
