@@ -14,10 +14,22 @@ Reading (pseudo-inverse): eigenvalues of Omega^T H Omega below
 ``rel_thresh`` times the largest are treated as zero.  Lam_hat_rr is the
 smallest retained eigenvalue (Lam_hat sorted descending).
 
+Stabilised form (the randomized Nystrom algorithm that Sec. 2.2 cites): with
+a shift mu >= 0 and Y_mu = H Omega + mu Omega,
+    C = chol(sym(Omega^T Y_mu)),  B = Y_mu C^-T = U Sigma V^T (thin SVD),
+    Lam_hat = max(Sigma^2 - mu, 0),
+i.e. the Nystrom approximation of H + mu I with mu taken back off its
+eigenvalues.  Reading (shift size): mu = u ||Y||_F, u the unit roundoff of
+the arithmetic that formed Y, the equivalent for a Gaussian Omega of the
+published sqrt(n) u ||Y|| for an orthonormal one.  mu = 0 is the plain
+definition above when Omega^T H Omega is nonsingular.
+
 Pins (tests/test_oracle_nystrom.py): H_hat = H when rank(H) <= r;
 0 <= H_hat <= H (Loewner order); H_hat invariant under Omega -> Omega R;
 P^-1 SPD; for rank(H) <= r, P^-1 (H + nu I) has eigenvalues {Lam_rr + nu, nu};
-the condition-number bound holds (numpy.linalg.eigvalsh).
+the condition-number bound holds (numpy.linalg.eigvalsh); the stabilised form
+at mu = 0 equals the plain one, and at mu > 0 U diag(Lam_hat + mu) U^T is the
+dense definition applied to H + mu I.
 """
 import numpy as np
 
@@ -42,6 +54,26 @@ def nystrom_from_sketch(Y, Omega, rel_thresh=1e-12):
     B = (Y @ V[:, keep]) / np.sqrt(ev[keep])
     Ub, sv, _ = np.linalg.svd(B, full_matrices=False)
     return Ub, sv ** 2
+
+
+def stabilising_shift(Y, unit_roundoff):
+    """mu = u ||Y||_F (reading of the shift size for a Gaussian test matrix)."""
+    return float(unit_roundoff) * float(np.linalg.norm(np.asarray(Y, np.float64)))
+
+
+def nystrom_stabilised(Y, Omega, mu):
+    """(U, lam_hat) of the shifted algorithm from the sketch Y = H Omega:
+    the Nystrom approximation of H + mu I through a Cholesky factor of
+    Omega^T Y_mu and a thin SVD, eigenvalues reduced by mu and clipped at 0."""
+    Y = np.asarray(Y, np.float64)
+    Omega = np.asarray(Omega, np.float64)
+    Ymu = Y + mu * Omega
+    M = Omega.T @ Ymu
+    M = 0.5 * (M + M.T)
+    C = np.linalg.cholesky(M)                  # M = C C^T, C lower triangular
+    B = np.linalg.solve(C, Ymu.T).T            # B = Y_mu C^-T
+    U, sv, _ = np.linalg.svd(B, full_matrices=False)
+    return U, np.maximum(sv ** 2 - mu, 0.0)
 
 
 def nystrom_dense(H, Omega, rel_thresh=1e-12):

@@ -129,6 +129,11 @@ void Layout::carve(Arena& ar) {
     sk.gpart = static_cast<double*>(ar.take((size_t)B * 3 * sk.nbG * sp * sp * sizeof(double)));
     sk.gram = static_cast<double*>(ar.take((size_t)B * 3 * sp * sp * sizeof(double)));
     sk.core = static_cast<double*>(ar.take((size_t)B * 5 * sp * sp * sizeof(double)));
+    if (vt == VT_F32) {  // BF16 operands of the matrix-core sketch products
+      const int64_t kpn = (n + 31) / 32 * 32, kpm = (m + 31) / 32 * 32;
+      sk.o16 = static_cast<uint16_t*>(ar.take((size_t)B * sp * kpn * sizeof(uint16_t)));
+      sk.w16 = static_cast<uint16_t*>(ar.take((size_t)2 * B * sp * kpm * sizeof(uint16_t)));
+    }
   }
   total = ar.off + 256;
 }

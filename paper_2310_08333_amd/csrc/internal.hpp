@@ -232,8 +232,14 @@ struct SketchWs {
   double* gpart;    // Gram partials
   double* gram;     // 3 x s x s per problem
   double* core;     // core scratch per problem (C, X, V, T, ...)
+  uint16_t* o16;    // BF16 Omega [c][kpad(n)] per problem (matrix-core path), or NULL
+  uint16_t* w16;    // BF16 hi then lo parts of d o W [c][kpad(m)] (matrix-core path), or NULL
   int ksW, ksY, nbG;
 };
+// The sketch products on the matrix cores (BF16 operand, FP32 vectors).
+bool sketch_mfma_eligible(const MatArg& A, VType vt, const SketchWs& ws);
+hipError_t launch_sketch_mfma(const MatArg& A, int64_t batch, int sp, const float* d,
+                              int64_t d_stride, const SketchWs& ws, hipStream_t st);
 int sketch_pad(int s);
 size_t sketch_ws_bytes(int64_t m, int64_t n, int s, int64_t batch, VType vt, int* ksW, int* ksY,
                        int* nbG);

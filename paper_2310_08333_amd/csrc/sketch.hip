@@ -17,6 +17,7 @@
 // Steps 2-3 stream A twice, the cost the paper quotes for the sketch
 // ("about a matrix-vector product with A" per column block).
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 #include "device.hpp"
@@ -924,6 +925,10 @@ int pad_rank(int s) { return s <= 16 ? 16 : (s <= 32 ? 32 : (s <= 64 ? 64 : 128)
 template <typename T, typename VT, int SP>
 hipError_t sketch_gemms(const MatArg& A, int64_t batch, const VT* d, int64_t d_stride,
                         const SketchWs& ws, hipStream_t st) {
+  if constexpr (std::is_same<T, uint16_t>::value && std::is_same<VT, float>::value) {
+    if (sketch_mfma_eligible(A, VT_F32, ws))
+      return launch_sketch_mfma(A, batch, SP, d, d_stride, ws, st);
+  }
   const int m = (int)A.m, n = (int)A.n;
   const T* Ap = static_cast<const T*>(A.ptr);
   // W = A Omega, split over n

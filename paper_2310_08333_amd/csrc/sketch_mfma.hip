@@ -1,0 +1,374 @@
+// Sketch products on the matrix cores (BF16 operand, FP32 accumulation).
+//
+// The Nystrom sketch Y = A^T diag(d) A Omega (Sec. 2.2, Sec. 3.3 for the
+// logistic D) is two skinny products with s right-hand columns:
+//   W = A Omega      (m x s, K = n)   k_sketch_w_mfma
+//   Y = A^T (d o W)  (n x s, K = m)   k_sketch_y_mfma
+// Each is bandwidth-bound on A (intensity s flop/B in BF16, below the MFMA
+// ridge), so the goal is one HBM stream of A per product with the s-wide
+// arithmetic on v_mfma_f32_16x16x32_bf16.
+//
+// Operand layout of that instruction (lane l of a wavefront): the A operand
+// holds row l % 16, k = 8 (l / 16) + i; the B operand holds column l % 16,
+// k = 8 (l / 16) + i; the 16x16 FP32 result holds row 4 (l / 16) + i, column
+// l % 16 (i = 0..7 for the operands, 0..3 for the result).
+//
+// * Omega is rounded to BF16 once (k_omega_bf16), in place as well, so the
+//   s x s core uses exactly the test matrix the products used; the BF16 copy is
+//   column-major [c][k], zero past n and past s.
+// * W = A Omega: a block owns 128 rows (a wavefront 32: two row tiles) and all
+//   s columns for a K range; A fragments go straight from HBM to registers
+//   (16 contiguous bytes of a row per lane), the Omega tile of each 32-wide K
+//   step is staged in LDS (double-buffered) and shared by the four wavefronts.
+// * d o W is split into BF16 hi + lo parts (k_w_split): the product with both
+//   keeps ~16 significant bits of d o W, so Y carries FP32-level error.
+// * Y = A^T (d o W): A's rows are contiguous in j, but the instruction needs 8
+//   consecutive k = r per lane, so each 32-row x 128-column A tile is written
+//   to LDS transposed ([j][r]) and read back as 16-byte fragments; the hi/lo
+//   tiles of d o W are staged in LDS beside it.
+// Results are per-K-split partials, summed in a fixed order by the consumers.
+#include <algorithm>
+
+#include "device.hpp"
+
+namespace genios {
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+
+constexpr int kMK = 32;        // K step of one instruction
+constexpr int kPitch = 40;     // LDS row pitch in 16-bit elements (32 + 8: 80 bytes)
+constexpr int kWRows = 128;    // rows of A per block in W = A Omega
+constexpr int kYCols = 128;    // columns of A per block in Y = A^T W
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return 0x7fc0;  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(const uint4& q) {
+  return __builtin_bit_cast(bf16x8, q);
+}
+
+__device__ __forceinline__ floatx4 mfma(const uint4& a, const uint4& b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a), as_bf16x8(b), c, 0, 0, 0);
+}
+
+// Omega (n x SP column-major, FP32) -> BF16 copy [c][kpad] (zero past n) and
+// Omega rounded to the same values in place.
+__global__ __launch_bounds__(256) void k_omega_bf16(int64_t n, int sp, int64_t kpad,
+                                                    float* __restrict__ omega,
+                                                    uint16_t* __restrict__ o16) {
+  const int b = blockIdx.y;
+  float* Ob = omega + (int64_t)b * n * sp;
+  uint16_t* O16 = o16 + (int64_t)b * sp * kpad;
+  const int64_t total = (int64_t)sp * kpad;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / kpad);
+    const int64_t k = e - (int64_t)c * kpad;
+    uint16_t h = 0;
+    if (k < n) {
+      h = f32_to_bf16_rne(Ob[(int64_t)c * n + k]);
+      Ob[(int64_t)c * n + k] = __uint_as_float((uint32_t)h << 16);
+    }
+    O16[e] = h;
+  }
+}
+
+// Wpart[b][ks][c][r] = sum_{k in split ks} A[r][k] Omega[k][c]
+template <int SP>
+__global__ __launch_bounds__(256) void k_sketch_w_mfma(const uint16_t* __restrict__ A,
+                                                       int64_t lda, int64_t strideA, int m, int n,
+                                                       const uint16_t* __restrict__ o16,
+                                                       int64_t kpad, float* __restrict__ wpart,
+                                                       int kchunk, int64_t ks_stride,
+                                                       int64_t prob_stride) {
+  constexpr int NT = SP / 16;  // column tiles
+  __shared__ __align__(16) uint16_t os[2][SP * kPitch];
+  const int b = blockIdx.z, ks = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int row0 = blockIdx.x * kWRows + wave * 32;
+  const int k0 = ks * kchunk;
+  const int k1 = min(n, k0 + kchunk);
+  const uint16_t* Ab = A + (int64_t)b * strideA;
+  const uint16_t* Ob = o16 + (int64_t)b * SP * kpad;
+  // this lane's A rows (clamped: rows past m are computed but not stored)
+  const uint16_t* arow[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) arow[t] = Ab + (int64_t)min(row0 + 16 * t + (lane & 15), m - 1) * lda;
+  const int kl = 8 * (lane >> 4);  // this lane's k offset inside a step
+  floatx4 acc[2][NT];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // Omega tile loader: SP columns x 32 k = SP * 4 chunks of 16 bytes
+  constexpr int OCH = SP * 4;
+  // (loads are unconditional -- chunk indices past the tile re-read chunk 0 -- so
+  // the staging registers stay registers; only the LDS stores are guarded)
+  auto load_omega = [&](int kk, uint4 (&reg)[(OCH + 255) / 256]) {
+#pragma unroll
+    for (int q = 0; q < (OCH + 255) / 256; ++q) {
+      const int ch = tid + 256 * q < OCH ? tid + 256 * q : 0;
+      const int c = ch >> 2, part = ch & 3;
+      reg[q] = *reinterpret_cast<const uint4*>(Ob + (int64_t)c * kpad + kk + 8 * part);
+    }
+  };
+  auto store_omega = [&](int buf, const uint4 (&reg)[(OCH + 255) / 256]) {
+#pragma unroll
+    for (int q = 0; q < (OCH + 255) / 256; ++q) {
+      const int ch = tid + 256 * q;
+      if (ch < OCH) {
+        const int c = ch >> 2, part = ch & 3;
+        *reinterpret_cast<uint4*>(&os[buf][c * kPitch + 8 * part]) = reg[q];
+      }
+    }
+  };
+  // A fragments of a step: columns past n read column 0 (their Omega rows are 0)
+  auto load_a = [&](int kk, uint4 (&fa)[2]) {
+    const int k = kk + kl;
+    const int kc = k < n ? k : 0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) fa[t] = *reinterpret_cast<const uint4*>(arow[t] + kc);
+  };
+  uint4 oreg[(OCH + 255) / 256];
+  uint4 fa[2], fn[2];
+  if (k0 < k1) {
+    load_omega(k0, oreg);
+    store_omega(0, oreg);
+    load_a(k0, fa);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int kk = k0; kk < k1; kk += kMK) {
+    const bool more = kk + kMK < k1;
+    const int kn = more ? kk + kMK : kk;  // the last step re-reads its own tile (unused)
+    load_omega(kn, oreg);
+    load_a(kn, fn);
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+      const uint4 fb = *reinterpret_cast<const uint4*>(&os[buf][(16 * c + (lane & 15)) * kPitch + kl]);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) acc[t][c] = mfma(fa[t], fb, acc[t][c]);
+    }
+    if (more) store_omega(buf ^ 1, oreg);
+    __syncthreads();
+    buf ^= 1;
+    fa[0] = fn[0];
+    fa[1] = fn[1];
+  }
+  float* Wb = wpart + (int64_t)b * prob_stride + (int64_t)ks * ks_stride;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = row0 + 16 * t + 4 * (lane >> 4) + i;
+        if (r < m) Wb[(int64_t)(16 * c + (lane & 15)) * m + r] = acc[t][c][i];
+      }
+}
+
+// (d o sum_ks Wpart) -> BF16 hi and lo parts [c][kpad], zero past m.
+__global__ __launch_bounds__(256) void k_w_split(int64_t m, int sp, int ksW,
+                                                 const float* __restrict__ wpart,
+                                                 int64_t ks_stride, int64_t prob_stride,
+                                                 const float* __restrict__ d, int64_t d_stride,
+                                                 int64_t kpad, uint16_t* __restrict__ hi,
+                                                 uint16_t* __restrict__ lo) {
+  const int b = blockIdx.y;
+  const float* Wp = wpart + (int64_t)b * prob_stride;
+  const float* db = d ? d + (int64_t)b * d_stride : nullptr;
+  uint16_t* H = hi + (int64_t)b * sp * kpad;
+  uint16_t* L = lo + (int64_t)b * sp * kpad;
+  const int64_t total = (int64_t)sp * kpad;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / kpad);
+    const int64_t r = e - (int64_t)c * kpad;
+    uint16_t h = 0, l = 0;
+    if (r < m) {
+      float w = 0.f;
+      for (int k = 0; k < ksW; ++k) w += Wp[(int64_t)k * ks_stride + (int64_t)c * m + r];
+      if (db) w *= db[r];
+      h = f32_to_bf16_rne(w);
+      l = f32_to_bf16_rne(w - __uint_as_float((uint32_t)h << 16));
+    }
+    H[e] = h;
+    L[e] = l;
+  }
+}
+
+// Ypart[b][ks][c][j] = sum_{r in split ks} A[r][j] (hi + lo)[c][r]
+template <int SP>
+__global__ __launch_bounds__(256) void k_sketch_y_mfma(const uint16_t* __restrict__ A,
+                                                       int64_t lda, int64_t strideA, int m, int n,
+                                                       const uint16_t* __restrict__ whi,
+                                                       const uint16_t* __restrict__ wlo,
+                                                       int64_t kpad, float* __restrict__ ypart,
+                                                       int rchunk, int64_t ks_stride,
+                                                       int64_t prob_stride) {
+  constexpr int NT = SP / 16;
+  __shared__ __align__(16) uint16_t at[kYCols * kPitch];       // A tile transposed: [j][r]
+  // hi, lo tiles [c][r], plus one spare row that threads past the tile write into
+  // (never read), so every staging store is unconditional
+  __shared__ __align__(16) uint16_t ws[2][(SP + 1) * kPitch];
+  const int b = blockIdx.z, ks = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j0 = blockIdx.x * kYCols;
+  const int r0 = ks * rchunk;
+  const int r1 = min(m, r0 + rchunk);
+  const uint16_t* Ab = A + (int64_t)b * strideA;
+  const uint16_t* Hb = whi + (int64_t)b * SP * kpad;
+  const uint16_t* Lb = wlo + (int64_t)b * SP * kpad;
+  const int kl = 8 * (lane >> 4);
+  floatx4 acc[2][NT];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // A tile: 32 rows x 128 columns = 512 chunks of 8 columns, 2 per thread.
+  // Thread -> (row tr, chunk tc): rows past m are clamped (their W rows are 0),
+  // chunks past n read column 0 (their results are not stored).
+  for (int rr = r0; rr < r1; rr += kMK) {
+    auto load_chunk = [&](int ch) {
+      const int tr = ch >> 4, tc = ch & 15;
+      const int row = min(rr + tr, m - 1);
+      const int j = j0 + 8 * tc;
+      return *reinterpret_cast<const uint4*>(Ab + (int64_t)row * lda + (j < n ? j : 0));
+    };
+    const uint4 av0 = load_chunk(tid), av1 = load_chunk(tid + 256);
+    // hi / lo tiles: SP columns x 32 r each = WCH chunks of 16 bytes, at most two
+    // per thread (named registers; chunk indices past the tile re-read chunk 0)
+    constexpr int WCH = SP * 4;
+    static_assert(WCH <= 512, "at most two staging chunks per thread");
+    auto wchunk = [&](int ch) { return ch < WCH ? ch : 0; };
+    auto wload = [&](const uint16_t* base, int ch) {
+      const int c = wchunk(ch) >> 2, part = wchunk(ch) & 3;
+      return *reinterpret_cast<const uint4*>(base + (int64_t)c * kpad + rr + 8 * part);
+    };
+    const uint4 wh0 = wload(Hb, tid), wl0 = wload(Lb, tid);
+    uint4 wh1{}, wl1{};
+    if constexpr (WCH > 256) {
+      wh1 = wload(Hb, tid + 256);
+      wl1 = wload(Lb, tid + 256);
+    }
+    __syncthreads();  // previous step's reads of the LDS tiles are done
+    auto store_transposed = [&](int ch, const uint4& v) {
+      const int tr = ch >> 4, tc = ch & 15;
+      uint16_t* dst = &at[(8 * tc) * kPitch + tr];
+      dst[0 * kPitch] = (uint16_t)(v.x & 0xffffu);
+      dst[1 * kPitch] = (uint16_t)(v.x >> 16);
+      dst[2 * kPitch] = (uint16_t)(v.y & 0xffffu);
+      dst[3 * kPitch] = (uint16_t)(v.y >> 16);
+      dst[4 * kPitch] = (uint16_t)(v.z & 0xffffu);
+      dst[5 * kPitch] = (uint16_t)(v.z >> 16);
+      dst[6 * kPitch] = (uint16_t)(v.w & 0xffffu);
+      dst[7 * kPitch] = (uint16_t)(v.w >> 16);
+    };
+    store_transposed(tid, av0);
+    store_transposed(tid + 256, av1);
+    auto wstore = [&](int ch, const uint4& h, const uint4& l) {
+      const int o = ch < WCH ? (ch >> 2) * kPitch + 8 * (ch & 3) : SP * kPitch;
+      *reinterpret_cast<uint4*>(&ws[0][o]) = h;
+      *reinterpret_cast<uint4*>(&ws[1][o]) = l;
+    };
+    wstore(tid, wh0, wl0);
+    if constexpr (WCH > 256) wstore(tid + 256, wh1, wl1);
+    __syncthreads();
+    uint4 fa[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      fa[t] = *reinterpret_cast<const uint4*>(&at[(32 * wave + 16 * t + (lane & 15)) * kPitch + kl]);
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+      const uint4 fh = *reinterpret_cast<const uint4*>(&ws[0][(16 * c + (lane & 15)) * kPitch + kl]);
+      const uint4 fl = *reinterpret_cast<const uint4*>(&ws[1][(16 * c + (lane & 15)) * kPitch + kl]);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        acc[t][c] = mfma(fa[t], fh, acc[t][c]);
+        acc[t][c] = mfma(fa[t], fl, acc[t][c]);
+      }
+    }
+  }
+  float* Yb = ypart + (int64_t)b * prob_stride + (int64_t)ks * ks_stride;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = j0 + 32 * wave + 16 * t + 4 * (lane >> 4) + i;
+        if (j < n) Yb[(int64_t)(16 * c + (lane & 15)) * n + j] = acc[t][c][i];
+      }
+}
+
+template <int SP>
+hipError_t sketch_mfma_sp(const MatArg& A, int64_t batch, const float* d, int64_t d_stride,
+                          const SketchWs& ws, hipStream_t st) {
+  const int m = (int)A.m, n = (int)A.n;
+  const uint16_t* Ap = static_cast<const uint16_t*>(A.ptr);
+  const int64_t kpn = (A.n + kMK - 1) / kMK * kMK, kpm = (A.m + kMK - 1) / kMK * kMK;
+  {
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((SP * kpn + 255) / 256, 2048));
+    hipLaunchKernelGGL(k_omega_bf16, dim3(nb, (unsigned)batch), dim3(256), 0, st, A.n, SP, kpn,
+                       static_cast<float*>(ws.omega), ws.o16);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    int kchunk = (int)((A.n + ws.ksW - 1) / ws.ksW);
+    kchunk = (kchunk + kMK - 1) / kMK * kMK;
+    dim3 grid((unsigned)((m + kWRows - 1) / kWRows), (unsigned)ws.ksW, (unsigned)batch);
+    hipLaunchKernelGGL(k_sketch_w_mfma<SP>, grid, dim3(256), 0, st, Ap, A.lda, A.strideA, m, n,
+                       ws.o16, kpn, static_cast<float*>(ws.Wpart), kchunk, (int64_t)m * SP,
+                       (int64_t)ws.ksW * m * SP);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((SP * kpm + 255) / 256, 2048));
+    hipLaunchKernelGGL(k_w_split, dim3(nb, (unsigned)batch), dim3(256), 0, st, A.m, SP, ws.ksW,
+                       static_cast<const float*>(ws.Wpart), (int64_t)m * SP,
+                       (int64_t)ws.ksW * m * SP, d, d_stride, kpm, ws.w16,
+                       ws.w16 + (size_t)batch * SP * kpm);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    int rchunk = (int)((A.m + ws.ksY - 1) / ws.ksY);
+    rchunk = (rchunk + kMK - 1) / kMK * kMK;
+    dim3 grid((unsigned)((n + kYCols - 1) / kYCols), (unsigned)ws.ksY, (unsigned)batch);
+    hipLaunchKernelGGL(k_sketch_y_mfma<SP>, grid, dim3(256), 0, st, Ap, A.lda, A.strideA, m, n,
+                       ws.w16, ws.w16 + (size_t)batch * SP * kpm, kpm,
+                       static_cast<float*>(ws.Ypart), rchunk, (int64_t)n * SP,
+                       (int64_t)ws.ksY * n * SP);
+    return hipGetLastError();
+  }
+}
+
+}  // namespace
+
+bool sketch_mfma_eligible(const MatArg& A, VType vt, const SketchWs& ws) {
+  return vt == VT_F32 && A.mt == MT_BF16 && ws.o16 != nullptr && ws.w16 != nullptr &&
+         A.n % 8 == 0 && A.lda % 8 == 0 && A.strideA % 8 == 0 &&
+         reinterpret_cast<uintptr_t>(A.ptr) % 16 == 0;
+}
+
+hipError_t launch_sketch_mfma(const MatArg& A, int64_t batch, int sp, const float* d,
+                              int64_t d_stride, const SketchWs& ws, hipStream_t st) {
+  switch (sp) {
+    case 16: return sketch_mfma_sp<16>(A, batch, d, d_stride, ws, st);
+    case 32: return sketch_mfma_sp<32>(A, batch, d, d_stride, ws, st);
+    case 64: return sketch_mfma_sp<64>(A, batch, d, d_stride, ws, st);
+    case 128: return sketch_mfma_sp<128>(A, batch, d, d_stride, ws, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace genios

@@ -177,8 +177,12 @@ def _nys_case(m, n, s, seed, decay=True):
     return A.astype(np.float32)
 
 
-def _compare_nystrom(U, lamhat, Href, Om, s_eff_expect=None, tol=2e-4):
-    Uo, lo = onys.nystrom(Href, Om)
+def _compare_nystrom(U, lamhat, Href, Om, s_eff_expect=None, tol=2e-4, u=2.0 ** -24):
+    # the device core runs the stabilised algorithm with mu = u ||Y||_F, u the
+    # unit roundoff of Y (FP32 here); the reference is the oracle's stabilised
+    # form with the same shift rule on its own FP64 sketch
+    Y = Href @ Om
+    Uo, lo = onys.nystrom_stabilised(Y, Om, onys.stabilising_shift(Y, u))
     k = min(len(lo), lamhat.size)
     assert np.allclose(lamhat[:k], lo[:k], rtol=tol, atol=tol * lo[0])
     # compare the preconditioners on random vectors (U is defined up to rotations
@@ -220,6 +224,50 @@ def test_nystrom_build_weighted_and_bf16(g):
     H = Ab.T @ (d.astype(np.float64)[:, None] * Ab)
     _compare_nystrom(U[0].cpu().numpy().astype(np.float64).T[:, :k], lamhat[0].cpu().numpy()[:k],
                      H, Om.astype(np.float64))
+
+
+@pytest.mark.parametrize("m,n,s,weighted", [
+    (400, 152, 32, True),      # SP 32, one K step tail
+    (257, 512, 16, False),     # SP 16, ragged m
+    (1000, 2048, 100, True),   # SP 128, several K steps and splits
+    (3001, 520, 64, False),    # SP 64, ragged m over many row blocks
+    (70, 9000, 50, True)])     # K = n long, few rows
+def test_nystrom_build_bf16_matrix_cores(g, m, n, s, weighted):
+    # BF16 operand with n % 8 == 0: the sketch products run on the matrix cores.
+    # The test matrix is rounded to BF16 once and used for both the products and
+    # the core, so the reference is the oracle's Nystrom of the BF16-rounded
+    # operator with the BF16-rounded test matrix.
+    print("nystrom_build bf16 mfma", m, n, s, weighted, flush=True)
+    A = _nys_case(m, n, s, seed=m * 3 + n)
+    rng = np.random.default_rng(m + 7)
+    d = (0.25 * rng.random(m)).astype(np.float32) if weighted else None
+    Om = genios_data.gaussian_test_matrix(n, s, seed=11)
+    U, lamhat, info = g.nystrom_build(_t(A), s, d=_t(d) if weighted else None,
+                                      omega=_t(Om.T.copy()), precision="bf16_only")
+    assert info[0]["status"] == 0, info
+    k = info[0]["precond_rank"]
+    Ab = obf16.round_to_bf16(A).astype(np.float64)
+    dd = np.ones(m) if d is None else d.astype(np.float64)
+    H = Ab.T @ (dd[:, None] * Ab)
+    Omb = obf16.round_to_bf16(Om).astype(np.float64)
+    _compare_nystrom(U[0].cpu().numpy().astype(np.float64).T[:, :k], lamhat[0].cpu().numpy()[:k],
+                     H, Omb)
+
+
+def test_nystrom_bf16_matrix_cores_exact_low_rank(g):
+    # rank(H) = 6 <= s: the approximation reproduces H exactly (to rounding)
+    print("nystrom bf16 mfma low rank", flush=True)
+    rng = np.random.default_rng(21)
+    m, n, s = 6, 256, 32
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    U, lamhat, info = g.nystrom_build(_t(A), s, precision="bf16_only", seed=5)
+    k = info[0]["precond_rank"]
+    assert k == m, info
+    Ab = obf16.round_to_bf16(A).astype(np.float64)
+    H = Ab.T @ Ab
+    Ug = U[0].cpu().numpy().astype(np.float64).T[:, :k]
+    Hg = (Ug * lamhat[0].cpu().numpy()[:k]) @ Ug.T
+    assert np.max(np.abs(Hg - H)) <= 1e-4 * np.max(np.abs(H))
 
 
 def test_nystrom_device_omega_is_the_oracle_philox(g):

@@ -99,3 +99,41 @@ def test_solve_shifted():
     r = rng.standard_normal(30)
     x = nystrom.solve_shifted(H, 0.5, r)
     assert np.allclose(H @ x + 0.5 * x, r)
+
+
+def test_stabilised_at_zero_shift_is_the_plain_definition():
+    # Cholesky + SVD route against the eigendecomposition route of the definition
+    rng = np.random.default_rng(31)
+    G = rng.standard_normal((25, 60)) * np.logspace(0, -2, 60)
+    H = G.T @ G
+    Om = rng.standard_normal((60, 12))
+    U0, l0 = nystrom.nystrom(H, Om)
+    U1, l1 = nystrom.nystrom_stabilised(H @ Om, Om, 0.0)
+    assert np.allclose(l1, l0, rtol=1e-9, atol=1e-12 * l0[0])
+    assert np.allclose((U1 * l1) @ U1.T, nystrom.nystrom_dense(H, Om), atol=1e-9 * np.abs(H).max())
+
+
+@pytest.mark.parametrize("mu", [1e-3, 0.2])
+def test_stabilised_is_the_definition_for_the_shifted_matrix(mu):
+    # U diag(lam_hat + mu) U^T = (H + mu I)_hat, the dense pseudo-inverse formula
+    # on H + mu I; Lam_hat is that minus mu (no clipping at these sizes)
+    rng = np.random.default_rng(32)
+    G = rng.standard_normal((20, 50)) * np.logspace(0, -1.5, 50)
+    H = G.T @ G
+    Om = rng.standard_normal((50, 10))
+    U, lam = nystrom.nystrom_stabilised(H @ Om, Om, mu)
+    Hs = H + mu * np.eye(50)
+    ref = nystrom.nystrom_dense(Hs, Om)
+    assert np.allclose((U * (lam + mu)) @ U.T, ref, atol=1e-9 * np.abs(Hs).max())
+    ev = np.sort(np.linalg.eigvalsh(ref))[::-1][:10]
+    assert np.allclose(lam, ev - mu, rtol=1e-9, atol=1e-12 * ev[0])
+    assert np.allclose(U.T @ U, np.eye(10), atol=1e-10)
+    # (H + mu I)_hat <= H + mu I in the Loewner order, i.e.
+    # U Lam_hat U^T <= H + mu (I - U U^T)
+    E = H + mu * (np.eye(50) - U @ U.T) - (U * lam) @ U.T
+    assert np.linalg.eigvalsh(0.5 * (E + E.T)).min() >= -1e-9 * np.abs(H).max()
+
+
+def test_stabilising_shift_is_unit_roundoff_times_frobenius_norm():
+    Y = np.array([[3.0, 0.0], [0.0, 4.0]])
+    assert nystrom.stabilising_shift(Y, 2.0 ** -24) == 5.0 * 2.0 ** -24
