@@ -37,6 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # dense BF16 matrix-core peak
 METRIC = "time-to-1e-4 KKT resid & ADMM iters/s: FP32 vs BF16-A; matvec HBM GB/s"
 
 
@@ -202,6 +203,24 @@ def main():
                             "avg_us": round(1e6 * t_hh / max(n_hh, 1), 2)},
     }
 
+    # The sketch products W = A Omega, Y = A^T W on the matrix cores: algorithmic
+    # flops 4 m n s per sketch over their event-timed duration, against the BF16
+    # matrix-core peak and against the HBM bound of two BF16 streams of A.
+    t_sk, f_sk, n_sk = tot("t_sketch_mc"), tot("flops_sketch_mc"), tot("n_sketch_mc")
+    sketch = None
+    if t_sk > 0 and n_sk > 0:
+        tfl = f_sk / t_sk / 1e12
+        intensity = (4.0 * m * n * s) / (2.0 * m * n * 2)  # flop per byte of A read
+        attainable = min(MFMA_BF16_PEAK_TFLOPS, intensity * HBM_PEAK_GBS / 1e3)
+        sketch = {"kernels": "k_sketch_w_mfma + k_sketch_y_mfma (v_mfma_f32_16x16x32_bf16)",
+                  "achieved_TFLOPs": round(tfl, 1), "peak_TFLOPs": MFMA_BF16_PEAK_TFLOPS,
+                  "mfma_utilisation": round(tfl / MFMA_BF16_PEAK_TFLOPS, 4),
+                  "bound": "hbm", "attainable_TFLOPs": round(attainable, 1),
+                  "frac_of_attainable": round(tfl / attainable, 4),
+                  "flop_per_byte": intensity, "sketches": n_sk,
+                  "avg_ms": round(1e3 * t_sk / n_sk, 3),
+                  "hbm_GBps": round(n_sk * 2.0 * m * n * 2 / t_sk / 1e9, 1)}
+
     fp32 = None
     if not args.no_fp32:
         o32 = g.lasso_solve(A, b, lam, precision="f32", **opts)["info"][0]
@@ -229,6 +248,7 @@ def main():
         "admm_iters": statistics.median(iters),
         "fp32": fp32,
         "roofline": roofline,
+        "sketch_gemm": sketch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -186,6 +186,13 @@ typedef struct {
   int64_t bytes_hvp;         /* bytes they must move: A once, p in, H p out (BF16 copy) */
   double t_hvp_hi;           /* the same for the fused products on the master copy */
   int64_t bytes_hvp_hi;
+  double t_sketch_mc;        /* with profile_kernels: summed duration of the sketch products
+                                W = A Omega, Y = A^T D W on the matrix cores (BF16 operand) */
+  int64_t flops_sketch_mc;   /* their algorithmic flops, 4 m n s per problem and sketch */
+  int32_t n_sketch_mc;       /* sketches whose products ran on the matrix cores */
+  int32_t n_sketch_fma;      /* sketches whose products ran on the vector units */
+  double t_sketch_fma;       /* the same for the vector-unit products */
+  int64_t flops_sketch_fma;
 } genios_info;
 
 /* Fill *o with the defaults listed above.  Returns GENIOS_OK. */

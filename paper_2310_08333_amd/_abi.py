@@ -72,7 +72,10 @@ class Info(C.Structure):
                 ("n_matvec_t", C.c_int32), ("bytes_matvec_n", C.c_int64),
                 ("bytes_matvec_t", C.c_int64), ("t_hvp", C.c_double), ("n_hvp", C.c_int32),
                 ("n_hvp_hi", C.c_int32), ("bytes_hvp", C.c_int64), ("t_hvp_hi", C.c_double),
-                ("bytes_hvp_hi", C.c_int64)]
+                ("bytes_hvp_hi", C.c_int64), ("t_sketch_mc", C.c_double),
+                ("flops_sketch_mc", C.c_int64), ("n_sketch_mc", C.c_int32),
+                ("n_sketch_fma", C.c_int32), ("t_sketch_fma", C.c_double),
+                ("flops_sketch_fma", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

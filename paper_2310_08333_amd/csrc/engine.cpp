@@ -211,25 +211,43 @@ struct Timer {
 struct KernelProf {
   bool on = false;
   std::vector<hipEvent_t> evs;
-  std::vector<int> kind;  // 0 = A v, 1 = A^T w, 2 / 3 = fused H p on the BF16 / master copy
+  // 0 = A v, 1 = A^T w, 2 / 3 = fused H p on the BF16 / master copy,
+  // 4 / 5 = sketch products on the matrix cores / vector units
+  std::vector<int> kind;
   size_t used = 0;
-  double t[4] = {0, 0, 0, 0};
+  double t[6] = {0, 0, 0, 0, 0, 0};
   ~KernelProf() {
     for (auto e : evs) (void)hipEventDestroy(e);
   }
+  hipError_t grow() {
+    if (used + 2 <= evs.size()) return hipSuccess;
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      evs.push_back(e);
+    }
+    kind.resize(evs.size() / 2 + 1);
+    return hipSuccess;
+  }
   hipError_t begin(hipStream_t st, int k) {
     if (!on) return hipSuccess;
-    if (used + 2 > evs.size()) {
-      for (int i = 0; i < 64; ++i) {
-        hipEvent_t e;
-        hipError_t r = hipEventCreate(&e);
-        if (r != hipSuccess) return r;
-        evs.push_back(e);
-      }
-      kind.resize(evs.size() / 2 + 1);
-    }
+    hipError_t r = grow();
+    if (r != hipSuccess) return r;
     kind[used / 2] = k;
     return hipEventRecord(evs[used], st);
+  }
+  // a begin / end pair that the callee records (both null when off)
+  hipError_t reserve(int k, hipEvent_t* b, hipEvent_t* e) {
+    *b = *e = nullptr;
+    if (!on) return hipSuccess;
+    hipError_t r = grow();
+    if (r != hipSuccess) return r;
+    kind[used / 2] = k;
+    *b = evs[used];
+    *e = evs[used + 1];
+    used += 2;
+    return hipSuccess;
   }
   hipError_t end(hipStream_t st) {
     if (!on) return hipSuccess;
@@ -265,6 +283,26 @@ struct Ctx {
   // bytes of A v / A^T w (the matrix) and of the fused H p on the BF16 / master copy
   // (the matrix once, p read, H p written)
   int64_t bytes_kind[4] = {0, 0, 0, 0};
+  // sketches on the matrix cores / vector units and their algorithmic flops (4 m n s)
+  int64_t n_sketch[2] = {0, 0};
+  int64_t flops_sketch[2] = {0, 0};
+
+  // the sketch-product timer of one Nystrom build of operator op at rank s
+  hipError_t sketch_timer(const MatArg& op, int s, SketchWs* skc) {
+    const int k = sketch_mfma_eligible(op, vt, *skc) ? 0 : 1;
+    n_sketch[k] += 1;
+    flops_sketch[k] += B * 4 * op.m * op.n * (int64_t)s;
+    return prof.reserve(4 + k, &skc->ev_gemm[0], &skc->ev_gemm[1]);
+  }
+  template <typename I>
+  void fill_sketch_info(I& info) const {
+    info.t_sketch_mc = prof.t[4];
+    info.flops_sketch_mc = flops_sketch[0];
+    info.n_sketch_mc = (int32_t)n_sketch[0];
+    info.t_sketch_fma = prof.t[5];
+    info.flops_sketch_fma = flops_sketch[1];
+    info.n_sketch_fma = (int32_t)n_sketch[1];
+  }
 
   void* vecp(int k) const { return L.nv[k]; }
   VecArgs vargs(void* x, void* z, void* u, void* h, void* g, void* c, const uint8_t* mask) const {
@@ -605,8 +643,10 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
   double t_precond = 0.0;
   auto build_sketch = [&](const MatArg& opx, const void* d) -> int {
     if (s <= 0) return 0;
+    SketchWs skx = c.L.sk;
+    HC(c.sketch_timer(opx, s, &skx));
     HC(hipEventRecord(tm.ev[0], c.st));
-    HC(run_nystrom(opx, B, c.vt, d, m, s, nullptr, o->seed, 0, nullptr, c.L.sk, c.L.U,
+    HC(run_nystrom(opx, B, c.vt, d, m, s, nullptr, o->seed, 0, nullptr, skx, c.L.U,
                    c.L.ctrl.lamhat, c.L.ctrl.s_eff, c.L.core_status, c.L.shift, c.st));
     HC(hipEventRecord(tm.ev[1], c.st));
     HC(hipEventSynchronize(tm.ev[1]));
@@ -900,6 +940,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     I.t_hvp_hi = c.prof.t[3];
     I.n_hvp_hi = (int32_t)c.n_mv[3];
     I.bytes_hvp_hi = c.bytes_kind[3];
+    c.fill_sketch_info(I);
     I.n_matvec_n = (int32_t)c.n_mv[0];
     I.n_matvec_t = (int32_t)c.n_mv[1];
     I.bytes_matvec_n = c.bytes_kind[0];
@@ -949,12 +990,16 @@ int run_nystrom_build(const genios_matrix* A, const void* d, int s, const void* 
                 A->lda, A->stride_A};
   }
   HC(launch_fill(c.L.ctrl.params, c.L.ctrl_bytes_end, c.st));
-  HC(run_nystrom(op, c.B, c.vt, d, A->m, s, omega, o->seed, 0, nullptr, c.L.sk, U, lamhat,
+  c.prof.on = o->profile_kernels != 0;
+  SketchWs skx = c.L.sk;
+  HC(c.sketch_timer(op, s, &skx));
+  HC(run_nystrom(op, c.B, c.vt, d, A->m, s, omega, o->seed, 0, nullptr, skx, U, lamhat,
                  c.L.ctrl.s_eff, c.L.core_status, c.L.shift, c.st));
   std::vector<int32_t> se(c.B), cs(c.B);
   HC(hipMemcpyAsync(se.data(), c.L.ctrl.s_eff, c.B * 4, hipMemcpyDeviceToHost, c.st));
   HC(hipMemcpyAsync(cs.data(), c.L.core_status, c.B * 4, hipMemcpyDeviceToHost, c.st));
   HC(hipStreamSynchronize(c.st));
+  c.prof.harvest();
   int worst = 0;
   for (int64_t b = 0; b < c.B; ++b) {
     if (info) {
@@ -962,6 +1007,7 @@ int run_nystrom_build(const genios_matrix* A, const void* d, int s, const void* 
       info[b].status = cs[b];
       info[b].precond_rank = se[b];
       info[b].resketches = 1;
+      c.fill_sketch_info(info[b]);
     }
     worst = std::max(worst, cs[b]);
   }
@@ -1114,6 +1160,7 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
     skc.ksY = std::max(1, std::min<int>(ky, (int)((int64_t)c.L.sk.ksY * n / ldS)));
     skc.nbG = std::max(1, std::min(ng, c.L.sk.nbG));
     if (sketch_pad(s) > sketch_pad(c.L.s)) return GENIOS_ERR_DEVICE;  // cannot happen: s <= s_req
+    HC(c.sketch_timer(opS, s, &skc));
     HC(run_nystrom(opS, B, c.vt, nullptr, m, s, nullptr, o->seed, 0, c.L.maskS, skc, c.L.U,
                    c.L.ctrl.lamhat, c.L.ctrl.s_eff, c.L.core_status, c.L.shift, c.st));
   }
@@ -1242,6 +1289,7 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
       info[b].t_hvp_hi = c.prof.t[3];
       info[b].n_hvp_hi = (int32_t)c.n_mv[3];
       info[b].bytes_hvp_hi = c.bytes_kind[3];
+      c.fill_sketch_info(info[b]);
     }
     if (st < 0 && (worst >= 0 || st < worst)) worst = st;
     if (worst >= 0 && st > worst) worst = st;

@@ -235,6 +235,7 @@ struct SketchWs {
   uint16_t* o16;    // BF16 Omega [c][kpad(n)] per problem (matrix-core path), or NULL
   uint16_t* w16;    // BF16 hi then lo parts of d o W [c][kpad(m)] (matrix-core path), or NULL
   int ksW, ksY, nbG;
+  hipEvent_t ev_gemm[2];  // recorded before and after the sketch products when non-null
 };
 // The sketch products on the matrix cores (BF16 operand, FP32 vectors).
 bool sketch_mfma_eligible(const MatArg& A, VType vt, const SketchWs& ws);

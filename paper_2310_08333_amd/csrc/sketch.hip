@@ -235,59 +235,73 @@ __global__ __launch_bounds__(256) void k_sketch_y(const T* __restrict__ A, int64
 }
 
 // ---- Grams ----------------------------------------------------------------------
-// which = 0: Omega^T Y, 1: Omega^T Omega, 2: Y^T Y; block g covers a row range.
-// Blocks with which == 0 also write Y = sum of the split partials (masked rows zero).
+// Y = sum of the split partials, rows outside the mask zero.
 template <typename VT, int SP>
-__global__ __launch_bounds__(256) void k_gram(int64_t n, const VT* __restrict__ omega,
-                                              const VT* __restrict__ ypart, int ksY,
-                                              int64_t ypart_ks_stride, int64_t ypart_prob_stride,
-                                              const uint8_t* __restrict__ mask,
-                                              VT* __restrict__ Y, double* __restrict__ gpart,
-                                              int nbG) {
+__global__ __launch_bounds__(256) void k_y_sum(int64_t n, const VT* __restrict__ ypart, int ksY,
+                                               int64_t ks_stride, int64_t prob_stride,
+                                               const uint8_t* __restrict__ mask,
+                                               VT* __restrict__ Y) {
+  const int b = blockIdx.y;
+  const VT* Yp = ypart + (int64_t)b * prob_stride;
+  const uint8_t* mb = mask ? mask + (int64_t)b * n : nullptr;
+  VT* Yb = Y + (int64_t)b * n * SP;
+  const int64_t total = n * SP;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    VT acc = VT(0);
+    for (int k = 0; k < ksY; ++k) acc += Yp[(int64_t)k * ks_stride + e];
+    if (mb && !mb[e % n]) acc = VT(0);
+    Yb[e] = acc;
+  }
+}
+
+// which = 0: Omega^T Y, 1: Omega^T Omega, 2: Y^T Y (FP64 accumulation); block g
+// covers a row range.  Tiles of RT rows x SP columns are staged in LDS as
+// doubles; the loads of the next tile are issued before the current tile is
+// used (unconditional, rows clamped, values past the range or past s zeroed).
+template <typename VT, int SP>
+__global__ __launch_bounds__(256) void k_gram(int64_t n, int s, const VT* __restrict__ omega,
+                                              const VT* __restrict__ Y,
+                                              double* __restrict__ gpart, int nbG) {
   constexpr int SB = SP / 16;
-  constexpr int RT = 16;  // rows per LDS tile
-  __shared__ double L1[RT][SP + 1];
-  __shared__ double L2[RT][SP + 1];
+  constexpr int RT = 16;              // rows per LDS tile
+  constexpr int LP = SP + 2;          // LDS pitch in doubles (rows 16-byte aligned)
+  constexpr int EPT = RT * SP / 256;  // staged elements per thread per matrix
+  __shared__ __align__(16) double L1[RT][LP];
+  __shared__ __align__(16) double L2[RT][LP];
   const int b = blockIdx.z, which = blockIdx.y, g = blockIdx.x;
   const int64_t rows_per = (n + nbG - 1) / nbG;
-  const int64_t lo = (int64_t)g * rows_per, hi = min(n, lo + rows_per);
-  const VT* Ob = omega + (int64_t)b * n * SP;
-  const VT* Yp = ypart + (int64_t)b * ypart_prob_stride;
-  VT* Yb = Y + (int64_t)b * n * SP;
-  const uint8_t* mb = mask ? mask + (int64_t)b * n : nullptr;
+  const int64_t lo = min(n, (int64_t)g * rows_per), hi = min(n, lo + rows_per);
+  const VT* M1 = (which == 2 ? Y : omega) + (int64_t)b * n * SP;
+  const VT* M2 = (which == 1 ? omega : Y) + (int64_t)b * n * SP;
+  const bool same = which != 0;
   const int tid = threadIdx.x, ti = tid % 16, tj = tid / 16;
   double acc[SB][SB];
 #pragma unroll
   for (int i = 0; i < SB; ++i)
 #pragma unroll
     for (int j = 0; j < SB; ++j) acc[i][j] = 0.0;
+  VT r1[EPT], r2[EPT];
+  auto load = [&](int64_t r0) {
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = tid + 256 * q, c = e / RT, rr = e % RT;
+      const int64_t r = min(r0 + rr, hi - 1);
+      r1[q] = M1[(int64_t)c * n + r];
+      r2[q] = same ? r1[q] : M2[(int64_t)c * n + r];
+    }
+  };
+  if (lo < hi) load(lo);
   for (int64_t r0 = lo; r0 < hi; r0 += RT) {
-    for (int e = tid; e < RT * SP; e += 256) {
-      const int j = e / RT, rr = e % RT;
-      const int64_t r = r0 + rr;
-      double om = 0.0, yv = 0.0;
-      if (r < hi) {
-        om = double(Ob[(int64_t)j * n + r]);
-        if (which != 1) {
-          VT s = VT(0);
-          for (int k = 0; k < ksY; ++k) s += Yp[(int64_t)k * ypart_ks_stride + (int64_t)j * n + r];
-          if (mb && !mb[r]) s = VT(0);
-          if (which == 0) Yb[(int64_t)j * n + r] = s;
-          yv = double(s);
-        }
-      }
-      if (which == 0) {
-        L1[rr][j] = om;
-        L2[rr][j] = yv;
-      } else if (which == 1) {
-        L1[rr][j] = om;
-        L2[rr][j] = om;
-      } else {
-        L1[rr][j] = yv;
-        L2[rr][j] = yv;
-      }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = tid + 256 * q, c = e / RT, rr = e % RT;
+      const bool ok = r0 + rr < hi && c < s;
+      L1[rr][c] = ok ? double(r1[q]) : 0.0;
+      L2[rr][c] = ok ? double(r2[q]) : 0.0;
     }
     __syncthreads();
+    if (r0 + RT < hi) load(r0 + RT);
 #pragma unroll 2
     for (int rr = 0; rr < RT; ++rr) {
       double a[SB], bb[SB];
@@ -457,31 +471,17 @@ __global__ __launch_bounds__(256) void k_nystrom_core(int s, int64_t n, double e
     M[i * LD + j] = 0.5 * (Gg[(int64_t)j * SP + i] + Gg[(int64_t)i * SP + j]);
     Vg[(int64_t)j * SP + i] = (i == j) ? 1.0 : 0.0;
   }
+  __shared__ int s_rot[2];  // a rotation happened in the sweep of this parity
+  if (tid == 0) s_rot[0] = 0;
   __syncthreads();
 
   // Cyclic Jacobi with round-robin pairing; S players (s rounded up to even).
+  // A pair is rotated only while |g_pq| > tol sqrt(g_pp g_qq), and g_pq is
+  // then set to zero; the iteration ends after a sweep without a rotation.
+  constexpr double tol = 1.0e-14;
   const int S = (s + 1) & ~1;
   const int npairs = S / 2;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    if (tid < 64) {
-      double off = 0.0, dia = 0.0;
-      for (int e = tid; e < s * s; e += 64) {
-        const int i = e / s, j = e % s;
-        const double v = M[i * LD + j];
-        if (i == j)
-          dia += v * v;
-        else
-          off += v * v;
-      }
-      off = wave_sum(off);
-      dia = wave_sum(dia);
-      if (tid == 0) {
-        s_red[1] = off;
-        s_red[2] = dia;
-      }
-    }
-    __syncthreads();
-    if (!(s_red[1] > 1.0e-30 * s_red[2])) break;
     for (int round = 0; round < S - 1; ++round) {
       if (tid < npairs) {
         auto player = [&](int pos) { return pos == 0 ? 0 : 1 + ((pos - 1 + round) % (S - 1)); };
@@ -494,12 +494,13 @@ __global__ __launch_bounds__(256) void k_nystrom_core(int s, int64_t n, double e
         double c = 1.0, sn = 0.0;
         if (q < s) {
           const double apq = M[p * LD + q];
-          if (apq != 0.0) {
-            const double app = M[p * LD + p], aqq = M[q * LD + q];
+          const double app = M[p * LD + p], aqq = M[q * LD + q];
+          if (fabs(apq) > tol * sqrt(fabs(app * aqq))) {
             const double theta = (aqq - app) / (2.0 * apq);
             const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
             c = 1.0 / sqrt(t * t + 1.0);
             sn = t * c;
+            s_rot[sweep & 1] = 1;
           }
         }
         pr_p[tid] = p;
@@ -508,6 +509,7 @@ __global__ __launch_bounds__(256) void k_nystrom_core(int s, int64_t n, double e
         cs_s[tid] = sn;
       }
       __syncthreads();
+      if (round == 0 && tid == 0) s_rot[(sweep + 1) & 1] = 0;
       // rows: (M_pk, M_qk) <- (c M_pk - s M_qk, s M_pk + c M_qk)
       for (int e = tid; e < npairs * s; e += nt) {
         const int pi = e / s, k = e % s;
@@ -526,14 +528,15 @@ __global__ __launch_bounds__(256) void k_nystrom_core(int s, int64_t n, double e
         if (q >= s || cs_s[pi] == 0.0) continue;
         const double c = cs_c[pi], sn = cs_s[pi];
         const double a = M[k * LD + p], bq = M[k * LD + q];
-        M[k * LD + p] = c * a - sn * bq;
-        M[k * LD + q] = sn * a + c * bq;
+        M[k * LD + p] = k == q ? 0.0 : c * a - sn * bq;
+        M[k * LD + q] = k == p ? 0.0 : sn * a + c * bq;
         const double va = Vg[(int64_t)p * SP + k], vb = Vg[(int64_t)q * SP + k];
         Vg[(int64_t)p * SP + k] = c * va - sn * vb;
         Vg[(int64_t)q * SP + k] = sn * va + c * vb;
       }
       __syncthreads();
     }
+    if (s_rot[sweep & 1] == 0) break;
   }
   // Sort eigenvalues descending.
   if (tid == 0) {
@@ -621,6 +624,7 @@ __global__ __launch_bounds__(kCoreThreads) void k_nystrom_core_lds(
   __shared__ double s_red[4];
   __shared__ double s_shift;
   __shared__ int s_flag;
+  __shared__ int s_jac_rot[2];  // a rotation happened in the sweep of this parity
   const int b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   const int LG = s + 1;
   double* R1 = lds;          // s * s
@@ -741,50 +745,55 @@ __global__ __launch_bounds__(kCoreThreads) void k_nystrom_core_lds(
     const int p = e / s, k = e % s;
     R1[p * s + k] = (p == k) ? 1.0 : 0.0;
   }
+  if (tid == 0) s_jac_rot[0] = 0;
   __syncthreads();
 
   // ---- cyclic Jacobi, round-robin pairs ----
+  // A round rotates the disjoint pairs (p_i, q_i) of the round-robin schedule
+  // at once: G <- R G R^T, V <- V R^T with R the direct sum of the 2 x 2
+  // rotations.  Phase 1: thread i computes the rotation of pair i.  Phase 2:
+  // every 2 x 2 block G[I, J] (rows of pair I, columns of pair J) becomes
+  // R_I G[I, J] R_J^T, and every pair of V entries V[k, (p_J, q_J)] becomes
+  // V[k, .] R_J^T; the blocks partition G, so phase 2 needs no ordering.  A
+  // pair is rotated only while |g_pq| > tol sqrt(g_pp g_qq) (the threshold form
+  // for positive semidefinite matrices) and g_pq is then set to zero; an idle
+  // player (odd s) is paired with itself under the identity.  The iteration
+  // ends after a sweep without a rotation.
+  constexpr double tol = 1.0e-14;
   const int S = (s + 1) & ~1;
   const int npairs = S / 2;
+  int* s_rot = s_jac_rot;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    if (tid < 64) {
-      double off = 0.0, dia = 0.0;
-      for (int e = tid; e < s * s; e += 64) {
-        const int i = e / s, j = e % s;
-        const double v = R2[i * LG + j];
-        if (i == j)
-          dia += v * v;
-        else
-          off += v * v;
-      }
-      off = wave_sum(off);
-      dia = wave_sum(dia);
-      if (tid == 0) {
-        s_red[1] = off;
-        s_red[2] = dia;
-      }
-    }
-    __syncthreads();
-    if (!(s_red[1] > 1.0e-28 * s_red[2])) break;
     for (int round = 0; round < S - 1; ++round) {
       if (tid < npairs) {
         const int a0 = tid, a1 = S - 1 - tid;
-        int p = a0 == 0 ? 0 : 1 + ((a0 - 1 + round) % (S - 1));
-        int q = a1 == 0 ? 0 : 1 + ((a1 - 1 + round) % (S - 1));
+        int t0 = a0 - 1 + round, t1 = a1 - 1 + round;
+        if (t0 >= S - 1) t0 -= S - 1;
+        if (t1 >= S - 1) t1 -= S - 1;
+        int p = a0 == 0 ? 0 : 1 + t0;
+        int q = a1 == 0 ? 0 : 1 + t1;
         if (p > q) {
           const int t = p;
           p = q;
           q = t;
         }
         double c = 1.0, sn = 0.0;
-        if (q < s) {
+        if (q >= s) {
+          q = p;  // idle player
+        } else {
           const double apq = R2[p * LG + q];
-          if (apq != 0.0) {
-            const double app = R2[p * LG + p], aqq = R2[q * LG + q];
-            const double theta = (aqq - app) / (2.0 * apq);
-            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            sn = t * c;
+          const double app = R2[p * LG + p], aqq = R2[q * LG + q];
+          if (fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+            // tan of the angle: t = sign(h) g / (|h| + r), h = g_qq - g_pp,
+            // g = 2 g_pq, r = sqrt(h^2 + g^2); with d = |h| + r,
+            // c = d / sqrt(2 r d) and s = sign(h) g / sqrt(2 r d).
+            const double h = aqq - app, g2 = 2.0 * apq;
+            const double r = sqrt(h * h + g2 * g2);
+            const double d = fabs(h) + r;
+            const double inv = 1.0 / sqrt(2.0 * r * d);
+            c = d * inv;
+            sn = (h >= 0.0 ? g2 : -g2) * inv;
+            s_rot[sweep & 1] = 1;
           }
         }
         pr_p[tid] = (int16_t)p;
@@ -793,51 +802,89 @@ __global__ __launch_bounds__(kCoreThreads) void k_nystrom_core_lds(
         cs_s[tid] = sn;
       }
       __syncthreads();
-      for (int e = tid; e < npairs * s; e += nt) {  // rows of G
-        const int pi = e / s, k = e % s;
-        const int p = pr_p[pi], q = pr_q[pi];
-        const double sn = cs_s[pi];
-        if (q >= s || sn == 0.0) continue;
-        const double c = cs_c[pi];
-        const double a = R2[p * LG + k], bq = R2[q * LG + k];
-        R2[p * LG + k] = c * a - sn * bq;
-        R2[q * LG + k] = sn * a + c * bq;
-      }
-      __syncthreads();
-      for (int e = tid; e < npairs * s; e += nt) {  // columns of G, and V <- V P
-        const int pi = e / s, k = e % s;
-        const int p = pr_p[pi], q = pr_q[pi];
-        const double sn = cs_s[pi];
-        if (q >= s || sn == 0.0) continue;
-        const double c = cs_c[pi];
-        const double a = R2[k * LG + p], bq = R2[k * LG + q];
-        R2[k * LG + p] = c * a - sn * bq;
-        R2[k * LG + q] = sn * a + c * bq;
-        const double va = R1[p * s + k], vb = R1[q * s + k];
-        R1[p * s + k] = c * va - sn * vb;
-        R1[q * s + k] = sn * va + c * vb;
+      if (round == 0 && tid == 0) s_rot[(sweep + 1) & 1] = 0;
+      {
+        constexpr int BPT = (kCoreLdsMaxS / 2) * (kCoreLdsMaxS / 2) / kCoreThreads + 1;
+        constexpr int VPT = kCoreLdsMaxS * (kCoreLdsMaxS / 2) / kCoreThreads + 1;
+        const int nblk = npairs * npairs;
+        const int nv = npairs * s;
+        double g[BPT][4], v[VPT][2];
+        // loads
+#pragma unroll
+        for (int t = 0; t < BPT; ++t) {
+          const int bi = tid + t * kCoreThreads;
+          const int I = bi < nblk ? bi / npairs : 0, J = bi < nblk ? bi - I * npairs : 0;
+          const int pI = pr_p[I], qI = pr_q[I], pJ = pr_p[J], qJ = pr_q[J];
+          g[t][0] = R2[pI * LG + pJ];
+          g[t][1] = R2[pI * LG + qJ];
+          g[t][2] = R2[qI * LG + pJ];
+          g[t][3] = R2[qI * LG + qJ];
+        }
+        // rotate and store
+#pragma unroll
+        for (int t = 0; t < BPT; ++t) {
+          const int bi = tid + t * kCoreThreads;
+          if (bi >= nblk) continue;
+          const int I = bi / npairs, J = bi - I * npairs;
+          const double cI = cs_c[I], sI = cs_s[I], cJ = cs_c[J], sJ = cs_s[J];
+          if (sI == 0.0 && sJ == 0.0) continue;
+          const int pI = pr_p[I], qI = pr_q[I], pJ = pr_p[J], qJ = pr_q[J];
+          // rows: R_I = [[c, -s], [s, c]]
+          const double r00 = cI * g[t][0] - sI * g[t][2], r01 = cI * g[t][1] - sI * g[t][3];
+          const double r10 = sI * g[t][0] + cI * g[t][2], r11 = sI * g[t][1] + cI * g[t][3];
+          // columns: times R_J^T = [[c, s], [-s, c]]
+          double o00 = cJ * r00 - sJ * r01, o01 = sJ * r00 + cJ * r01;
+          double o10 = cJ * r10 - sJ * r11, o11 = sJ * r10 + cJ * r11;
+          if (I == J) {  // the rotated pair's off-diagonal entries are zero
+            o01 = 0.0;
+            o10 = 0.0;
+          }
+          // an idle player has qI == pI (or qJ == pJ): the identity writes the
+          // same value twice from this thread
+          R2[qI * LG + qJ] = o11;
+          R2[qI * LG + pJ] = o10;
+          R2[pI * LG + qJ] = o01;
+          R2[pI * LG + pJ] = o00;
+        }
+#pragma unroll
+        for (int t = 0; t < VPT; ++t) {
+          const int vi = tid + t * kCoreThreads;
+          const int J = vi < nv ? vi / s : 0, k = vi < nv ? vi - J * s : 0;
+          v[t][0] = R1[pr_p[J] * s + k];
+          v[t][1] = R1[pr_q[J] * s + k];
+        }
+#pragma unroll
+        for (int t = 0; t < VPT; ++t) {
+          const int vi = tid + t * kCoreThreads;
+          if (vi >= nv) continue;
+          const int J = vi / s, k = vi - J * s;
+          const double cJ = cs_c[J], sJ = cs_s[J];
+          if (sJ == 0.0) continue;
+          R1[pr_p[J] * s + k] = cJ * v[t][0] - sJ * v[t][1];
+          R1[pr_q[J] * s + k] = sJ * v[t][0] + cJ * v[t][1];
+        }
       }
       __syncthreads();
     }
+    if (s_rot[sweep & 1] == 0) break;
   }
-  // eigenvalues (diagonal of G) sorted descending
+  // eigenvalues (diagonal of G) sorted descending: thread j finds the rank of
+  // g_jj under the order (value descending, index ascending) with NaN taken as
+  // -inf, a total order, so perm is a permutation of 0..s-1
+  for (int j = tid; j < s; j += nt) {
+    const double vj = R2[j * LG + j];
+    const double kj = vj == vj ? vj : -INFINITY;
+    int rank = 0;
+    for (int i = 0; i < s; ++i) {
+      const double vi = R2[i * LG + i];
+      const double ki = vi == vi ? vi : -INFINITY;
+      rank += (ki > kj || (ki == kj && i < j)) ? 1 : 0;
+    }
+    perm[rank] = (int16_t)j;
+    evals[rank] = vj;
+  }
+  __syncthreads();
   if (tid == 0) {
-    for (int j = 0; j < s; ++j) {
-      perm[j] = (int16_t)j;
-      evals[j] = R2[j * LG + j];
-    }
-    for (int i = 1; i < s; ++i) {
-      const double ev = evals[i];
-      const int16_t pv = perm[i];
-      int k = i - 1;
-      while (k >= 0 && evals[k] < ev) {
-        evals[k + 1] = evals[k];
-        perm[k + 1] = perm[k];
-        --k;
-      }
-      evals[k + 1] = ev;
-      perm[k + 1] = pv;
-    }
     const double top = evals[0] - mu;
     int keep = 0;
     for (int j = 0; j < s; ++j) {
@@ -923,7 +970,7 @@ __global__ __launch_bounds__(256) void k_form_u(int64_t n, int s, const VT* __re
 int pad_rank(int s) { return s <= 16 ? 16 : (s <= 32 ? 32 : (s <= 64 ? 64 : 128)); }
 
 template <typename T, typename VT, int SP>
-hipError_t sketch_gemms(const MatArg& A, int64_t batch, const VT* d, int64_t d_stride,
+hipError_t sketch_gemms_impl(const MatArg& A, int64_t batch, const VT* d, int64_t d_stride,
                         const SketchWs& ws, hipStream_t st) {
   if constexpr (std::is_same<T, uint16_t>::value && std::is_same<VT, float>::value) {
     if (sketch_mfma_eligible(A, VT_F32, ws))
@@ -958,18 +1005,34 @@ hipError_t sketch_gemms(const MatArg& A, int64_t batch, const VT* d, int64_t d_s
   }
 }
 
+template <typename T, typename VT, int SP>
+hipError_t sketch_gemms(const MatArg& A, int64_t batch, const VT* d, int64_t d_stride,
+                        const SketchWs& ws, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (ws.ev_gemm[0] != nullptr && (e = hipEventRecord(ws.ev_gemm[0], st)) != hipSuccess) return e;
+  e = sketch_gemms_impl<T, VT, SP>(A, batch, d, d_stride, ws, st);
+  if (e != hipSuccess) return e;
+  if (ws.ev_gemm[1] != nullptr) e = hipEventRecord(ws.ev_gemm[1], st);
+  return e;
+}
+
 template <typename VT, int SP>
 hipError_t run_core(const MatArg& A, int64_t batch, int s, const uint8_t* mask, const SketchWs& ws,
                     void* U, double* lamhat, int32_t* s_eff, int32_t* status, double* shift,
                     hipStream_t st) {
   const int64_t n = A.n;
   {
-    dim3 grid((unsigned)ws.nbG, 3u, (unsigned)batch);
-    hipLaunchKernelGGL((k_gram<VT, SP>), grid, dim3(256), 0, st, n,
-                       static_cast<const VT*>(ws.omega), static_cast<const VT*>(ws.Ypart), ws.ksY,
-                       (int64_t)n * SP, (int64_t)ws.ksY * n * SP, mask, static_cast<VT*>(ws.Y),
-                       ws.gpart, ws.nbG);
+    const unsigned nby = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n * SP + 255) / 256, 2048));
+    hipLaunchKernelGGL((k_y_sum<VT, SP>), dim3(nby, (unsigned)batch), dim3(256), 0, st, n,
+                       static_cast<const VT*>(ws.Ypart), ws.ksY, (int64_t)n * SP,
+                       (int64_t)ws.ksY * n * SP, mask, static_cast<VT*>(ws.Y));
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 grid((unsigned)ws.nbG, 3u, (unsigned)batch);
+    hipLaunchKernelGGL((k_gram<VT, SP>), grid, dim3(256), 0, st, n, s,
+                       static_cast<const VT*>(ws.omega), static_cast<const VT*>(ws.Y), ws.gpart,
+                       ws.nbG);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 g2((unsigned)((SP * SP + 255) / 256), 3u, (unsigned)batch);
     hipLaunchKernelGGL(k_gram_reduce, g2, dim3(256), 0, st, SP * SP, ws.gpart, ws.nbG, ws.gram);

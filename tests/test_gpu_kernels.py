@@ -197,18 +197,28 @@ def _compare_nystrom(U, lamhat, Href, Om, s_eff_expect=None, tol=2e-4, u=2.0 ** 
     assert np.allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-4)
 
 
-@pytest.mark.parametrize("m,n,s", [(60, 200, 20), (300, 130, 50), (80, 1003, 100)])
-def test_nystrom_build_given_omega(g, m, n, s):
-    print("nystrom_build", m, n, s, flush=True)
+@pytest.mark.parametrize("m,n,s,prec", [(60, 200, 20, "f32"), (300, 130, 50, "f32"),
+                                         (80, 1003, 100, "f32"), (90, 400, 37, "f32"),
+                                         (90, 400, 37, "f64"), (120, 700, 1, "f32"),
+                                         (200, 300, 99, "f64"), (150, 400, 120, "f32"),
+                                         (150, 400, 113, "f64")])
+def test_nystrom_build_given_omega(g, m, n, s, prec):
+    # odd s leaves one idle player per Jacobi round; s = 1 has no rotation;
+    # s > 100 takes the core whose matrices live in global memory
+    print("nystrom_build", m, n, s, prec, flush=True)
     A = _nys_case(m, n, s, seed=m + n)
-    Om = genios_data.gaussian_test_matrix(n, s, seed=3)
-    U, lamhat, info = g.nystrom_build(_t(A), s, omega=_t(Om.T.copy()), precision="f32")
+    if prec == "f64":
+        A = A.astype(np.float64)
+    Om = genios_data.gaussian_test_matrix(n, s, seed=3).astype(A.dtype)
+    U, lamhat, info = g.nystrom_build(_t(A), s, omega=_t(Om.T.copy()), precision=prec)
     U = U[0].cpu().numpy().astype(np.float64).T
     lamhat = lamhat[0].cpu().numpy()
     k = info[0]["precond_rank"]
     assert k >= 1
     H = A.astype(np.float64).T @ A.astype(np.float64)
-    _compare_nystrom(U[:, :k], lamhat[:k], H, Om.astype(np.float64))
+    _compare_nystrom(U[:, :k], lamhat[:k], H, Om.astype(np.float64),
+                     u=2.0 ** -53 if prec == "f64" else 2.0 ** -24,
+                     tol=1e-9 if prec == "f64" else 2e-4)
 
 
 def test_nystrom_build_weighted_and_bf16(g):
@@ -243,8 +253,12 @@ def test_nystrom_build_bf16_matrix_cores(g, m, n, s, weighted):
     d = (0.25 * rng.random(m)).astype(np.float32) if weighted else None
     Om = genios_data.gaussian_test_matrix(n, s, seed=11)
     U, lamhat, info = g.nystrom_build(_t(A), s, d=_t(d) if weighted else None,
-                                      omega=_t(Om.T.copy()), precision="bf16_only")
+                                      omega=_t(Om.T.copy()), precision="bf16_only",
+                                      profile_kernels=1)
     assert info[0]["status"] == 0, info
+    # the products ran on the matrix cores, timed on the stream
+    assert info[0]["n_sketch_mc"] == 1 and info[0]["n_sketch_fma"] == 0, info
+    assert info[0]["flops_sketch_mc"] == 4 * m * n * s and info[0]["t_sketch_mc"] > 0, info
     k = info[0]["precond_rank"]
     Ab = obf16.round_to_bf16(A).astype(np.float64)
     dd = np.ones(m) if d is None else d.astype(np.float64)
