@@ -20,6 +20,11 @@ profiles/), and the CPU FP64 oracle on a bounded sample of the same workload.
 runs only a plain copy of known size and a few fused products on the workload,
 for the two counter passes (FETCH_SIZE, WRITE_SIZE) that calibrate and measure
 the traffic.
+
+    python bench.py --probe-sketch
+
+runs only a few Nystrom builds of the workload's BF16 operator (the sketch
+products on the matrix cores), for counter passes over those kernels.
 """
 from __future__ import annotations
 
@@ -91,6 +96,22 @@ def probe_traffic(workload):
     log("3 fused products done")
 
 
+def probe_sketch(workload):
+    """A few Nystrom builds on the workload's BF16 copy at its sketch rank."""
+    import torch
+
+    import genios_data
+    import paper_2310_08333_amd as g
+    dev = torch.device("cuda:0")
+    P = genios_data.config(workload)
+    A = torch.from_numpy(P["A"]).to(dev)
+    for i in range(3):
+        U, lam, info = g.nystrom_build(A, P["s"], precision="bf16_only", profile_kernels=1)
+        torch.cuda.synchronize()
+        log(f"sketch {i}: rank {info[0]['precond_rank']} products "
+            f"{1e3 * info[0]['t_sketch_mc']:.3f} ms on the matrix cores")
+
+
 def cpu_baseline(P, rows=8000, cols=16000, budget_iters=100):
     """The oracle's GeNIOS ADMM (exact Cholesky x-steps) on the leading rows x cols
     block of the workload's matrix: ADMM iterations per second on the host."""
@@ -125,6 +146,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--probe-traffic", action="store_true")
+    ap.add_argument("--probe-sketch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path "
@@ -133,6 +155,9 @@ def main():
 
     if args.probe_traffic:
         probe_traffic(args.workload)
+        return
+    if args.probe_sketch:
+        probe_sketch(args.workload)
         return
 
     import torch

@@ -390,7 +390,7 @@ struct Ctx {
   int hvp(const MatArg& op, const void* p, const void* d, const int32_t* gate, int gstride) {
     if (vt == VT_F32) {
       const HvpGeom g = hvp_geometry(op, B, true);
-      if (g.threads > 0 && g.blocks <= L.yslots) {
+      if (g.threads > 0 && g.blocks <= L.yslots && hvp_p_aligned(p, n, B)) {
         HC(prof.begin(st, hvp_kind(op)));
         HC(launch_hvp_fused(op, g, B, static_cast<const float*>(p), n,
                             static_cast<const float*>(d), m, static_cast<float*>(L.ypart), L.npad,
@@ -1203,7 +1203,7 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
   int t_cg = 0;
   // fused one-pass H p on the compact matrix when it qualifies
   const HvpGeom gS = c.vt == VT_F32 ? hvp_geometry(opS, B, true) : HvpGeom{};
-  const bool fusedS = gS.threads > 0 && gS.blocks <= c.L.yslots;
+  const bool fusedS = gS.threads > 0 && gS.blocks <= c.L.yslots && hvp_p_aligned(va.p, ldS, B);
   if (fusedS) {
     va.ksplit = gS.blocks;
     va.ypart_ks_stride = ldS;

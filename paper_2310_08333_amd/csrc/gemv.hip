@@ -353,7 +353,8 @@ hipError_t launch_gemv_t(const MatArg& A, int64_t batch, VType vt, const void* t
 // exchange and one barrier), scaled by d, and the same registers update the
 // owned result columns.  Each block writes one partial of hp; the partials are
 // summed in a fixed order by the consumer.
-// Requires n % V == 0, lda % V == 0 and 16-byte aligned rows.
+// Requires n % V == 0, lda % V == 0, 16-byte aligned rows and a 16-byte
+// aligned p (with p_stride % 4 == 0 between problems).
 
 template <typename T>
 struct Raw;
@@ -423,11 +424,6 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
   // the (possibly partial) last chunk row after them, so a thread reads its
   // values from one base with small immediate offsets.  Exactly n floats.
   constexpr int HEAD = (NC - 1) * V;  // floats per thread in the first NC - 1 chunks
-  const float* pb = p + (int64_t)b * p_stride;
-  for (int c = tid; c < n; c += THREADS) {
-    const int ch = c / V, t = ch % THREADS, k = ch / THREADS;
-    ps[k < NC - 1 ? t * HEAD + k * V + c % V : THREADS * HEAD + t * V + c % V] = pb[c];
-  }
   const T* Ab = A + (int64_t)b * strideA;
   const float* db = d ? d + (int64_t)b * d_stride : nullptr;
   // Chunks k < NC - 1 always lie inside the row (EPT is the least multiple of V
@@ -493,7 +489,30 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
   // (Every block owns at least one row: r0 < r1.)
   auto clampr = [&](int r) { return r < r1 ? r : r1 - 1; };
   RT b0[NC], b1[NC], b2[NC];
-  load_row(r0, b0);
+  // Prologue: each thread loads the p values of the chunks it owns (16-byte
+  // loads, all independent), then the first row's loads go out, then p is
+  // written to LDS.  Loads retire in issue order, so the wait for p leaves
+  // the row loads in flight.
+  {
+    const float* pb = p + (int64_t)b * p_stride;
+    float4 pv[NC][V / 4];
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+      for (int e4 = 0; e4 < V / 4; ++e4)
+        pv[k][e4] = *reinterpret_cast<const float4*>(pb + col(k) + 4 * e4);
+    load_row(r0, b0);
+#pragma unroll
+    for (int k = 0; k < NC - 1; ++k)
+#pragma unroll
+      for (int e4 = 0; e4 < V / 4; ++e4)
+        *reinterpret_cast<float4*>(ps + tid * HEAD + k * V + 4 * e4) = pv[k][e4];
+    if (last_ok) {
+#pragma unroll
+      for (int e4 = 0; e4 < V / 4; ++e4)
+        *reinterpret_cast<float4*>(ps + THREADS * HEAD + tid * V + 4 * e4) = pv[NC - 1][e4];
+    }
+  }
   if constexpr (D >= 2) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     load_row(clampr(r0 + 1), b1);
@@ -704,6 +723,10 @@ int num_cus() {
 
 }  // namespace
 
+bool hvp_p_aligned(const void* p, int64_t p_stride, int64_t batch) {
+  return reinterpret_cast<uintptr_t>(p) % 16 == 0 && (batch == 1 || p_stride % 4 == 0);
+}
+
 HvpGeom hvp_geometry(const MatArg& A, int64_t batch, bool query_device) {
   HvpGeom g{};
   if (A.mt == MT_F64 || A.m < 1 || A.n < 1) return g;
@@ -748,7 +771,8 @@ hipError_t launch_hvp_fused(const MatArg& A, const HvpGeom& g, int64_t batch, co
                             int gate_stride, hipStream_t st) {
   if (g.threads == 0 || g.blocks < 1 || g.blocks > kHvpMaxBlocks ||
       (int64_t)g.blocks * g.rows_per_block < A.m ||
-      (int64_t)(g.blocks - 1) * g.rows_per_block >= A.m || ks_stride < A.n)  // no empty block
+      (int64_t)(g.blocks - 1) * g.rows_per_block >= A.m || ks_stride < A.n ||  // no empty block
+      !hvp_p_aligned(p, p_stride, batch))
     return hipErrorInvalidValue;
   if (A.mt == MT_BF16) {
     if (g.threads == 256)

@@ -145,6 +145,8 @@ struct HvpGeom {
   int rows_per_block = 0;
 };
 HvpGeom hvp_geometry(const MatArg& A, int64_t batch, bool query_device);
+// the fused product reads p in 16-byte pieces
+bool hvp_p_aligned(const void* p, int64_t p_stride, int64_t batch);
 hipError_t launch_hvp_fused(const MatArg& A, const HvpGeom& g, int64_t batch, const float* p,
                             int64_t p_stride, const float* d, int64_t d_stride, float* ypart,
                             int64_t ks_stride, int64_t prob_stride, const int32_t* gate,

@@ -115,6 +115,28 @@ def test_hvp_parity(g, m, n, kind, weighted):
     assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / bound)
 
 
+@pytest.mark.parametrize("kind", ["bf16", "f32"])
+def test_hvp_unaligned_p(g, kind):
+    # p 4 bytes past a 16-byte boundary: the fused kernel's 16-byte p loads do not
+    # apply, the product takes the two-pass path and agrees all the same
+    print("hvp unaligned p", kind, flush=True)
+    m, n = 300, 2048
+    rng = np.random.default_rng(17)
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    p = rng.standard_normal(n).astype(np.float32)
+    At = _t(A)
+    A16 = g.cast_bf16(At) if kind == "bf16" else None
+    big = torch.zeros(n + 4, dtype=torch.float32, device=DEV)
+    pv = big[1:n + 1]
+    pv.copy_(_t(p))
+    assert pv.data_ptr() % 16 != 0 and pv.is_contiguous()
+    got = g.hvp(At, pv, A16=A16).cpu().numpy()
+    Aref = obf16.round_to_bf16(A).astype(np.float64) if kind == "bf16" else A.astype(np.float64)
+    ref = olasso.hessian_vector(Aref, p, None)
+    bound = _hvp_bound(Aref, p.astype(np.float64), None, m, n)
+    assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / bound)
+
+
 def test_hvp_batched(g):
     print("hvp batched", flush=True)
     rng = np.random.default_rng(9)
