@@ -215,10 +215,17 @@ def main():
     ach = b_h / t_h / 1e9 if t_h > 0 else None
     per = b_h / max(n_h, 1)
     traffic = measured_traffic()
+    # the read rate a plain streaming kernel reaches on this GPU (the FP32 master,
+    # 3.2 GB, read 10 times): the attainable HBM rate for a bandwidth-bound kernel
+    read_s = g.stream_read_seconds(A, reps=10)
+    attainable = 10 * A.numel() * 4 / read_s / 1e9
+    log(f"streaming read: {attainable:.0f} GB/s")
     roofline = {
         "bound": "hbm", "kernel": "k_hvp_fused: H p = A^T A p, BF16 A, one pass over A",
         "achieved": round(ach, 1) if ach else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(ach / HBM_PEAK_GBS, 4) if ach else None, "traffic": traffic,
+        "attainable_read_GBps": round(attainable, 1),
+        "frac_of_attainable": round(ach / attainable, 4) if ach else None,
         "bytes_per_launch": int(per), "launches": n_h,
         "avg_us": round(1e6 * t_h / max(n_h, 1), 2),
         "two_stream_equivalent_GBps": round(2 * m * n * 2 / (t_h / max(n_h, 1)) / 1e9, 1)

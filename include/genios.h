@@ -138,7 +138,13 @@ typedef struct {
   void* stream;                /* hipStream_t */
   double* history;             /* (host, optional) per-iteration log, see GENIOS_HIST_* */
   int32_t history_cap;         /* rows per problem in `history` */
-  int32_t reserved1;
+  int32_t termination;         /* 0 (default): the residual tests of Sec. 2.3;
+                                  1: the relative duality gap of Sec. 3.3 / App. A at z,
+                                  (l(z) - g(nu)) / min(l(z), |g(nu)|) <= eps_gap, evaluated
+                                  with the master copy (BF16_REFINE: in the FP32 phase;
+                                  BF16_ONLY: with the BF16 copy) every gap_every iterations */
+  int32_t gap_every;           /* iterations between gap evaluations, default 1 */
+  double eps_gap;              /* relative duality gap tolerance, default 1e-4 */
 } genios_opts;
 
 /* Per-iteration history row layout (doubles); problem p, iteration k (1-based)
@@ -193,6 +199,12 @@ typedef struct {
   int32_t n_sketch_fma;      /* sketches whose products ran on the vector units */
   double t_sketch_fma;       /* the same for the vector-unit products */
   int64_t flops_sketch_fma;
+  double rel_gap;            /* relative duality gap (Sec. 3.3, App. A) at the returned z with the
+                                master copy: (l(z) - g(nu)) / min(l(z), |g(nu)|) */
+  double gap_primal;         /* l(z) */
+  double gap_dual;           /* g(nu), nu = min(1, lambda / ||A^T f'(A z - b)||_inf) f'(A z - b) */
+  int32_t gap_checks;        /* gap evaluations during the solve (termination = 1) */
+  int32_t reserved2;
 } genios_info;
 
 /* Fill *o with the defaults listed above.  Returns GENIOS_OK. */
@@ -289,6 +301,16 @@ int genios_hvp(const genios_matrix* A, int32_t use_bf16, const void* d, const vo
 
 /* Round `count` FP32 values to BF16, nearest-even, NaN -> 0x7FC0 (device). */
 int genios_cast_bf16(const float* src, uint16_t* dst, int64_t count, const genios_opts* o);
+
+/* Measurement reference, not part of the method: the HBM read rate a kernel
+ * that only streams reaches.  Reads `bytes` (a positive multiple of 16) at the
+ * 16-byte aligned device address p once per repetition with a plain streaming
+ * kernel, after one untimed warm-up, and stores in *seconds (host) the HIP-event
+ * time of the `reps` timed reads on o->stream (synchronised).  scratch: device,
+ * GENIOS_STREAM_READ_SCRATCH words, receives one XOR checksum per block. */
+#define GENIOS_STREAM_READ_SCRATCH 4096
+int genios_stream_read(const void* p, int64_t bytes, int32_t reps, uint32_t* scratch,
+                       double* seconds, const genios_opts* o);
 
 /* Draw the n x s (column-major) standard normal test matrix the sketch uses,
  * for key (seed, stream_id): Philox4x64-10 + Box-Muller, rounded to FP32. */

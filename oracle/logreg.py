@@ -134,6 +134,12 @@ def duality_gap(A, y, lam, x):
     return primal - dual, primal, dual
 
 
+def relative_gap(A, y, lam, x):
+    """The relative duality gap of Sec. 3.3: (l(x) - g(nu)) / min(l(x), |g(nu)|)."""
+    gap, p, d = duality_gap(A, y, lam, x)
+    return gap / min(p, abs(d))
+
+
 def kkt_violation(A, y, lam, x):
     x = _f64(x)
     g = grad_f(A, y, x)

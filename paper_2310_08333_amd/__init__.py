@@ -289,6 +289,25 @@ def hvp(A, p, d=None, A16=None):
     return out
 
 
+STREAM_READ_SCRATCH = 4096  # GENIOS_STREAM_READ_SCRATCH
+
+
+def stream_read_seconds(t: torch.Tensor, reps: int = 10) -> float:
+    """HIP-event time of `reps` plain streaming reads of tensor t's bytes (the
+    HBM read-rate reference for the bandwidth-bound kernels)."""
+    if not t.is_cuda or not t.is_contiguous():
+        raise TypeError("stream_read needs a contiguous GPU tensor")
+    scratch = torch.empty(STREAM_READ_SCRATCH, dtype=torch.int32, device=t.device)
+    o = _abi.default_opts()
+    o.stream = _stream(t.device)
+    sec = C.c_double(0.0)
+    nbytes = t.numel() * t.element_size() // 16 * 16
+    rc = _lib.genios_stream_read(_ptr(t), nbytes, int(reps), _ptr(scratch), C.byref(sec), C.byref(o))
+    if rc < 0:
+        raise GeniosError(rc, "genios_stream_read")
+    return sec.value
+
+
 def cast_bf16(A: torch.Tensor) -> torch.Tensor:
     """Round-to-nearest-even BF16 copy of an FP32 tensor (returned as torch.bfloat16)."""
     if A.dtype != torch.float32 or not A.is_contiguous() or not A.is_cuda:

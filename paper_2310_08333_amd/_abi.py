@@ -56,7 +56,8 @@ class Opts(C.Structure):
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("stream", C.c_void_p),
                 ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
-                ("reserved1", C.c_int32)]
+                ("termination", C.c_int32), ("gap_every", C.c_int32),
+                ("eps_gap", C.c_double)]
 
 
 class Info(C.Structure):
@@ -75,7 +76,9 @@ class Info(C.Structure):
                 ("bytes_hvp_hi", C.c_int64), ("t_sketch_mc", C.c_double),
                 ("flops_sketch_mc", C.c_int64), ("n_sketch_mc", C.c_int32),
                 ("n_sketch_fma", C.c_int32), ("t_sketch_fma", C.c_double),
-                ("flops_sketch_fma", C.c_int64)]
+                ("flops_sketch_fma", C.c_int64), ("rel_gap", C.c_double),
+                ("gap_primal", C.c_double), ("gap_dual", C.c_double),
+                ("gap_checks", C.c_int32), ("reserved2", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -85,7 +88,7 @@ EXPORTED = (
     "genios_default_opts", "genios_workspace_size", "genios_lasso_solve", "genios_logreg_solve",
     "genios_nystrom_build", "genios_nystrom_apply", "genios_lasso_backward", "genios_matvec",
     "genios_hvp",
-    "genios_cast_bf16", "genios_gaussian_matrix", "genios_admm_update", "genios_status_string",
+    "genios_cast_bf16", "genios_stream_read", "genios_gaussian_matrix", "genios_admm_update", "genios_status_string",
     "genios_last_error", "genios_abi_struct_sizes",
 )
 
@@ -124,6 +127,8 @@ def load(path: str | None = None):
     lib.genios_hvp.restype = C.c_int
     lib.genios_cast_bf16.argtypes = [vp, vp, i64, P(Opts)]
     lib.genios_cast_bf16.restype = C.c_int
+    lib.genios_stream_read.argtypes = [vp, i64, C.c_int32, vp, P(C.c_double), P(Opts)]
+    lib.genios_stream_read.restype = C.c_int
     lib.genios_gaussian_matrix.argtypes = [i64, i32, C.c_uint64, C.c_uint64, vp, P(Opts)]
     lib.genios_gaussian_matrix.restype = C.c_int
     lib.genios_admm_update.argtypes = [i64, i32, dbl, dbl, vp, vp, vp, P(dbl), P(Opts)]

@@ -45,6 +45,9 @@ int check_opts(const genios_opts* o) {
   if (!(o->switch_tol >= 0.0)) FAIL(GENIOS_ERR_ARG, "switch_tol must be >= 0");
   if (o->history != nullptr && o->history_cap < 1)
     FAIL(GENIOS_ERR_ARG, "history_cap must be >= 1 when history is given");
+  if (o->termination < 0 || o->termination > 1) FAIL(GENIOS_ERR_ARG, "termination must be 0 or 1");
+  if (o->gap_every < 1) FAIL(GENIOS_ERR_ARG, "gap_every must be >= 1");
+  if (!(o->eps_gap > 0.0) || !std::isfinite(o->eps_gap)) FAIL(GENIOS_ERR_ARG, "eps_gap must be > 0");
   return GENIOS_OK;
 }
 
@@ -131,6 +134,9 @@ int genios_default_opts(genios_opts* o) {
   o->stall_window = 10;
   o->rhs_relative = 0;
   o->seed = 0x5eed2310ull;
+  o->termination = 0;
+  o->gap_every = 1;
+  o->eps_gap = 1e-4;
   return GENIOS_OK;
 }
 
@@ -281,6 +287,39 @@ int genios_cast_bf16(const float* src, uint16_t* dst, int64_t count, const genio
   hipError_t e = launch_cast_bf16(src, dst, count, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) FAIL(GENIOS_ERR_DEVICE, std::string("HIP error: ") + hipGetErrorString(e));
+  return GENIOS_OK;
+}
+
+constexpr int64_t kStreamReadMaxBlocks = GENIOS_STREAM_READ_SCRATCH;
+
+int genios_stream_read(const void* p, int64_t bytes, int32_t reps, uint32_t* scratch,
+                       double* seconds, const genios_opts* o) {
+  if (o == nullptr || o->struct_size != sizeof(genios_opts)) FAIL(GENIOS_ERR_ARG, "bad opts");
+  if (p == nullptr || scratch == nullptr || seconds == nullptr) FAIL(GENIOS_ERR_ARG, "NULL pointer");
+  if (bytes < 16 || bytes % 16 || reinterpret_cast<uintptr_t>(p) % 16)
+    FAIL(GENIOS_ERR_SHAPE, "bytes must be a positive multiple of 16 at a 16-byte aligned address");
+  if (reps < 1) FAIL(GENIOS_ERR_ARG, "reps must be >= 1");
+  hipStream_t st = static_cast<hipStream_t>(o->stream);
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t want = std::max<int64_t>(1, (bytes / 16 + 1023) / 1024);
+  const int blocks = (int)std::min<int64_t>(want, std::min<int64_t>(kStreamReadMaxBlocks,
+                                                                     16 * (int64_t)std::max(cus, 1)));
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  if (e == hipSuccess) e = launch_stream_read(p, bytes, scratch, blocks, st);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_stream_read(p, bytes, scratch, blocks, st);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (e != hipSuccess) FAIL(GENIOS_ERR_DEVICE, std::string("HIP error: ") + hipGetErrorString(e));
+  *seconds = ms * 1e-3;
   return GENIOS_OK;
 }
 

@@ -107,6 +107,12 @@ void Layout::carve(Arena& ar) {
   for (int k = 0; k < kNumNVec; ++k) nv[k] = n_vecs > k ? vec(n) : nullptr;
   tparts = ar.take((size_t)B * nsplit_n * m * ve);
   ypart = ar.take((size_t)B * yprob() * ve);
+  if (gap) {
+    gapf = vec(m);
+    gaps = vec(m);
+    gpart = static_cast<double*>(ar.take((size_t)B * 4 * kGapPStride * sizeof(double)));
+    gstate = static_cast<GapState*>(ar.take((size_t)B * sizeof(GapState)));
+  }
   if (logistic || backward) {
     dvec = vec(m);
     cols = ar.take((size_t)B * 2 * m * ve);
@@ -146,6 +152,7 @@ int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_)
   vt = A->hi_dtype == GENIOS_DT_F64 ? VT_F64 : VT_F32;
   logistic = op == GENIOS_OP_LOGREG;
   backward = op == GENIOS_OP_BACKWARD;
+  gap = op == GENIOS_OP_LASSO || op == GENIOS_OP_LOGREG;
   s = s_;
   const int prec = o->precision;
   const bool uses_lo = (op == GENIOS_OP_LASSO || op == GENIOS_OP_LOGREG || op == GENIOS_OP_NYSTROM ||
@@ -442,6 +449,7 @@ struct HostProb {
   double rkkt = INFINITY, rp = 0, rd = 0, xn = 0, zn = 0, un = 0;
   double t_target = -1.0;
   int switch_iter = -1, resketches = 0;
+  int gap_checks = 0;
   std::vector<double> rk_hist;
 };
 
@@ -547,12 +555,14 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
   const MatArg* op = phase == 0 ? &c.op_lo : &c.op_hi;
 
   std::vector<ProbParams> hpv(B);
-  ProbParams* hp = static_cast<ProbParams*>(pinned(B * (sizeof(ProbParams) + sizeof(ProbState))));
+  ProbParams* hp = static_cast<ProbParams*>(
+      pinned(B * (sizeof(ProbParams) + sizeof(ProbState) + sizeof(GapState))));
   if (!hp) {
     set_error("pinned host staging allocation failed");
     return GENIOS_ERR_DEVICE;
   }
   ProbState* hs = reinterpret_cast<ProbState*>(hp + B);
+  GapState* hg = reinterpret_cast<GapState*>(hs + B);
   std::vector<HostProb> P(B);
   for (int64_t b = 0; b < B; ++b) {
     P[b].lambda = lambda[b];
@@ -628,6 +638,49 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     HC(launch_sum_splits(c.vt, B, n, static_cast<char*>(c.L.ypart) + c.L.npad * c.ve, ks,
                          (int64_t)2 * c.L.npad, c.L.yprob(), g, n, c.st,
                          gate, gstride));
+    return 0;
+  };
+  // Relative duality gap at v with operator opx (App. A): t = A v, f'(t), A^T f'(t),
+  // then the reductions; the result lands in hg after read_gap().
+  auto eval_gap = [&](const MatArg& opx, const void* v, const int32_t* gate, int gstride) -> int {
+    int r = c.gemv_n(opx, v, gate, gstride);
+    if (r) return r;
+    // every field is set before the first launch
+    const int ks = c.nsplit_for(opx, 1);
+    GapArgs ga{};
+    ga.vt = c.vt;
+    ga.m = m;
+    ga.n = n;
+    ga.batch = B;
+    ga.tparts = c.L.tparts;
+    ga.nsplit = c.nsplit_for(opx, 0);
+    ga.split_stride = m;
+    ga.prob_stride = (int64_t)c.L.nsplit_n * m;
+    ga.bvec = bvec;
+    ga.logistic = logistic ? 1 : 0;
+    ga.fprime = c.L.gapf;
+    ga.sfold = c.L.gaps;
+    ga.ypart = c.L.ypart;
+    ga.ks = ks;
+    ga.ks_stride = (int64_t)c.L.nrhs * c.L.npad;
+    ga.yprob = c.L.yprob();
+    ga.v = v;
+    ga.params = c.L.ctrl.params;
+    ga.part = c.L.gpart;
+    ga.state = c.L.gstate;
+    HC(launch_gap_elem(ga, c.st));
+    HC(c.prof.begin(c.st, 1));
+    HC(launch_gemv_t(opx, B, c.vt, c.L.gapf, 1, 0, m, 0, 1, nullptr, 0, c.L.ypart, ks,
+                     (int64_t)c.L.nrhs * c.L.npad, c.L.npad, c.L.yprob(), gate, gstride, c.st));
+    HC(c.prof.end(c.st));
+    c.account(opx, 1);
+    HC(launch_gap_after_t(ga, c.st));
+    return 0;
+  };
+  auto read_gap = [&]() -> int {
+    HC(hipMemcpyAsync(hg, c.L.gstate, B * sizeof(GapState), hipMemcpyDeviceToHost, c.st));
+    HC(hipStreamSynchronize(c.st));
+    c.prof.harvest();
     return 0;
   };
   if (logistic) {
@@ -793,7 +846,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
           if (q.rkkt > 0.9 * old) ready = true;  // < 10% decrease over the window
         }
         if (!ready) all_ready_to_switch = false;
-      } else if (conv) {
+      } else if (conv && o->termination == 0) {
         want_cert[b] = 1;
         any_certify = true;
       }
@@ -863,6 +916,32 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
         }
       }
     }
+    // Relative duality gap test at z (Sec. 3.3, App. A) in the operator's final phase.
+    if (o->termination == 1 && !(phase == 0 && prec == GENIOS_PREC_BF16_REFINE) &&
+        k % o->gap_every == 0) {
+      bool any = false;
+      for (int64_t b = 0; b < B; ++b)
+        if (hp[b].run && !P[b].done) any = true;
+      if (any) {
+        rc = eval_gap(*op, z, c.gate_run, c.gs_params);
+        if (rc) return rc;
+        rc = read_gap();
+        if (rc) return rc;
+        for (int64_t b = 0; b < B; ++b) {
+          if (!hp[b].run || P[b].done) continue;
+          HostProb& q = P[b];
+          ++q.gap_checks;
+          if (std::isfinite(hg[b].rel_gap) && hg[b].rel_gap <= o->eps_gap) {
+            q.done = 1;
+            q.t_target = now_s() - t0;
+            q.status = GENIOS_OK;
+            // undo a penalty change decided in this iteration (u was not rescaled yet)
+            q.rho = hp[b].rho;
+            q.u_scale = 1.0;
+          }
+        }
+      }
+    }
     active = 0;
     for (int64_t b = 0; b < B; ++b)
       if (!P[b].done) ++active;
@@ -906,6 +985,11 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
                         (int64_t)c.L.nsplit_n * m, bvec, logistic ? 1 : 0, c.L.ctrl, c.st));
   rc = sync_state(c, hs);
   if (rc) return rc;
+  // relative duality gap at the returned z with the master copy
+  rc = eval_gap(c.op_hi, z, nullptr, 0);
+  if (rc) return rc;
+  rc = read_gap();
+  if (rc) return rc;
   const double t_total = now_s() - t0;
   int worst = GENIOS_OK;
   for (int64_t b = 0; b < B; ++b) {
@@ -925,6 +1009,10 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     I.r_d = std::sqrt(hs[b].red[kRedRd2]);
     I.r_kkt = kkt_from(I.r_p, I.r_d, q.xn, q.zn, q.rho * q.un, n);
     I.obj = hs[b].red[kRedAux] + q.lambda * hs[b].red[kRedZ1];
+    I.rel_gap = hg[b].rel_gap;
+    I.gap_primal = hg[b].primal;
+    I.gap_dual = hg[b].dual;
+    I.gap_checks = q.gap_checks;
     I.t_setup = t_setup;
     I.t_precond = t_precond;
     I.t_solve = t_solve;

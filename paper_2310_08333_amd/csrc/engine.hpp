@@ -60,6 +60,12 @@ struct Layout {
   int32_t* cnt = nullptr;   // [batch] active-set sizes
   void* AS = nullptr;       // [batch][m][ldS] gathered columns of the master copy
   uint8_t* maskS = nullptr; // [batch][ldS] 1 for real columns, 0 for padding
+  // relative duality gap (solves)
+  bool gap = false;
+  void* gapf = nullptr;       // [batch][m] f'(t)
+  void* gaps = nullptr;       // [batch][m] r or sigmoid(w)
+  double* gpart = nullptr;    // [batch][4][kGapPStride]
+  GapState* gstate = nullptr; // [batch]
   size_t total = 0;
 
   int setup(int op, const genios_matrix* A, const genios_opts* o, int s);

@@ -162,6 +162,8 @@ hipError_t launch_sum_splits(VType vt, int64_t batch, int64_t len, const void* i
                              const int32_t* gate = nullptr, int gate_stride = 0);
 
 hipError_t launch_cast_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t st);
+hipError_t launch_stream_read(const void* p, int64_t bytes, uint32_t* out, int blocks,
+                              hipStream_t st);
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);  // zero fill (no memset nodes)
 hipError_t launch_copy(VType vt, const void* src, void* dst, int64_t count, hipStream_t st);
 
@@ -205,6 +207,42 @@ hipError_t launch_logistic_elem(VType vt, int64_t m, int64_t batch, const void* 
                                 int64_t split_stride, int64_t prob_stride, const void* y, void* d,
                                 void* cols, int64_t col_stride, const int32_t* gate,
                                 int gate_stride, hipStream_t st);
+// ---- relative duality gap (App. A), gap.hip ----
+struct GapState {
+  double loss;      // sum_i f(t_i)
+  double grad_inf;  // ||A^T f'(t)||_inf
+  double l1;        // ||v||_1
+  double kappa;     // min(1, lambda / grad_inf)
+  double primal;    // l(v) = loss + lambda ||v||_1
+  double dual;      // g(nu)
+  double gap;       // primal - dual
+  double rel_gap;   // gap / min(primal, |dual|)
+};
+constexpr int kGapPStride = 256;  // block partials per reduction and problem
+struct GapArgs {
+  VType vt;
+  int64_t m, n, batch;
+  const void* tparts;  // t = A v column-split partials
+  int nsplit;
+  int64_t split_stride, prob_stride;
+  const void* bvec;    // b (Lasso) or the labels y (logistic), m per problem
+  int logistic;
+  void* fprime;        // [batch][m] f'(t), the input of A^T
+  void* sfold;         // [batch][m] r (Lasso) or sigmoid(w) (logistic)
+  const void* ypart;   // A^T f'(t) row-split partials
+  int ks;
+  int64_t ks_stride, yprob;
+  const void* v;       // the point, n per problem
+  const ProbParams* params;  // lambda
+  double* part;        // [batch][4][kGapPStride]
+  GapState* state;     // [batch]
+};
+int gap_blocks(int64_t len);
+// f'(t), the folded s and the loss partials from the t partials.
+hipError_t launch_gap_elem(const GapArgs& a, hipStream_t st);
+// After A^T f'(t) is in ypart: ||.||_inf, ||v||_1, kappa, primal, dual, gap.
+hipError_t launch_gap_after_t(const GapArgs& a, hipStream_t st);
+
 // Stand-alone fused ADMM update test hook.
 hipError_t launch_admm_update_hook(VType vt, int64_t n, double alpha, double kappa, const void* x,
                                    void* z, void* u, double* part, unsigned* counter,

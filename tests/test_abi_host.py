@@ -143,3 +143,32 @@ def test_nystrom_and_apply_validation(abi):
 def test_status_strings(abi):
     for code in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7):
         assert abi.status_string(code) != "unknown status"
+
+
+def test_stream_read_rejects_bad_arguments_before_any_device_call(abi):
+    lib = abi.load()
+    o = abi.default_opts()
+    sec = C.c_double(0.0)
+    dummy = C.c_void_p(16)  # never dereferenced: the checks come first
+    assert lib.genios_stream_read(dummy, 15, 1, dummy, C.byref(sec), C.byref(o)) == abi.ERR_SHAPE
+    assert lib.genios_stream_read(C.c_void_p(8), 32, 1, dummy, C.byref(sec), C.byref(o)) == abi.ERR_SHAPE
+    assert lib.genios_stream_read(dummy, 32, 0, dummy, C.byref(sec), C.byref(o)) == abi.ERR_ARG
+    assert lib.genios_stream_read(None, 32, 1, dummy, C.byref(sec), C.byref(o)) == abi.ERR_ARG
+
+
+def test_termination_options_defaults_and_checks(abi):
+    o = abi.default_opts()
+    assert o.termination == 0 and o.gap_every == 1 and o.eps_gap == 1e-4
+    lib = abi.load()
+    M = abi.Matrix()
+    M.m, M.n, M.lda, M.batch = 4, 8, 8, 1
+    M.hi_dtype = abi.DT_F32
+    M.A_hi = C.c_void_p(16)  # never dereferenced: the option checks come first
+    lam = (C.c_double * 1)(0.1)
+    info = (abi.Info * 1)()
+    for field, bad in (("termination", 2), ("gap_every", 0), ("eps_gap", 0.0)):
+        q = abi.default_opts()
+        setattr(q, field, bad)
+        rc = lib.genios_lasso_solve(C.byref(M), C.c_void_p(16), lam, 1.0, C.byref(q),
+                                    C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), info)
+        assert rc == abi.ERR_ARG, (field, rc)

@@ -333,3 +333,22 @@ def test_nystrom_exact_low_rank_and_zero(g):
     U0, l0, info0 = g.nystrom_build(torch.zeros((20, 40), device=DEV), 8, precision="f32")
     assert info0[0]["precond_rank"] == 0
     assert torch.all(l0 == 0) and torch.all(U0 == 0)
+
+
+def test_stream_read_reads_every_word(g):
+    # the XOR of the per-block checksums is the XOR of every 32-bit word read
+    print("stream read", flush=True)
+    import ctypes as C
+    from paper_2310_08333_amd import _abi
+    rng = np.random.default_rng(23)
+    words = rng.integers(0, 2 ** 31, size=(1 << 20) + 12, dtype=np.int64).astype(np.int32)
+    t = _t(words)
+    scratch = torch.zeros(g.STREAM_READ_SCRATCH, dtype=torch.int32, device=DEV)
+    o = _abi.default_opts()
+    sec = C.c_double(0.0)
+    rc = g._lib.genios_stream_read(C.c_void_p(t.data_ptr()), words.size * 4, 3,
+                                   C.c_void_p(scratch.data_ptr()), C.byref(sec), C.byref(o))
+    assert rc == 0 and sec.value > 0
+    got = np.bitwise_xor.reduce(scratch.cpu().numpy().view(np.uint32))
+    assert got == np.bitwise_xor.reduce(words.view(np.uint32))
+    assert g.stream_read_seconds(t, reps=2) > 0

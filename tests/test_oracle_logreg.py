@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 from scipy.optimize import minimize
 
+import genios_data
 from oracle import logreg
 
 
@@ -91,3 +92,17 @@ def test_genios_second_order_admm_reaches_optimum():
                                      max_iter=2000, eps=1e-11, xstep="approx")
     assert abs(logreg.objective(A, y, lam, z) - sol["F"]) <= 1e-9 * sol["F"]
     assert np.allclose(z, sol["x"], atol=1e-6)
+
+
+def test_relative_gap_bounds_relative_suboptimality():
+    # (l(x) - g(nu)) / min(l(x), |g(nu)|) >= (l(x) - l*) / min(l(x), |g(nu)|) >= 0
+    P = genios_data.logreg_factor(300, 30, nnz_frac=0.1, seed=3, s=5)
+    sol = logreg.solve(P["A"], P["y"], P["lam"])
+    rng = np.random.default_rng(4)
+    for scale in (0.0, 1e-3, 1e-1):
+        x = sol["x"] + scale * rng.standard_normal(sol["x"].size)
+        gap, pr, du = logreg.duality_gap(P["A"], P["y"], P["lam"], x)
+        rel = logreg.relative_gap(P["A"], P["y"], P["lam"], x)
+        assert rel == gap / min(pr, abs(du))
+        assert rel >= (logreg.objective(P["A"], P["y"], P["lam"], x) - sol["F"]) / min(pr, abs(du)) - 1e-12
+        assert rel >= -1e-12
