@@ -2,9 +2,11 @@
 
 Test infrastructure only (never imported by the product library).
 
-Problem (Sec. 3.1, Lasso example, and Sec. 4.1 with lam2 = 0):
-    minimize (1/2)||A x - b||_2^2 + lam ||x||_1,
-split as f(x) = (1/2)||Ax - b||^2, g(z) = lam ||z||_1, M = I, c = 0.
+Problem (Sec. 3.1, Lasso example; Sec. 4.1 elastic net with lam2 >= 0, the
+ML problem of Sec. 3.3 with the squared loss):
+    minimize (1/2)||A x - b||_2^2 + lam ||x||_1 + (lam2/2)||x||_2^2,
+split as f(x) = (1/2)||Ax - b||^2 + (lam2/2)||x||^2, g(z) = lam ||z||_1,
+M = I, c = 0.  Every function takes lam2 (default 0: the Lasso).
 
 What is here
 ------------
@@ -17,17 +19,19 @@ What is here
   alpha; the penalty update rule of Sec. 2.5 (tau, mu, every k iterations,
   stopping after a fixed iteration) with u rescaled by rho_old / rho_new.
   With alpha = 1, sigma = 0 this is classic ADMM.
-* ``duality_gap``: App. A with loss f(w) = w^2/2, conjugate f*(v) = v^2/2 and
-  lam2 = 0; the dual point nu = (Ax - b) min(1, lam / ||A^T (Ax - b)||_inf)
+* ``duality_gap``: App. A with loss f(w) = w^2/2, conjugate f*(v) = v^2/2.
+  lam2 = 0: the dual point nu = (Ax - b) min(1, lam / ||A^T (Ax - b)||_inf)
   (reading: App. A scales by lam/||.||_inf; scaling by the min keeps the point
-  feasible and equals it whenever ||.||_inf >= lam).
+  feasible and equals it whenever ||.||_inf >= lam).  lam2 > 0: nu = Ax - b
+  and g(nu) = -||nu||^2/2 - b^T nu - (1/(2 lam2)) sum_i ((|A^T nu|_i - lam)_+)^2.
 * ``polish``: on the support S of z with signs s, the optimality conditions
   of App. A with f'(w) = w give A_S^T (A_S x_S - b) + lam s = 0; accept if the
   signs agree and |A_i^T (A x - b)| <= lam off S.
 * ``brute_force``: enumerates all 3^n sign patterns (n <= 10).
 * ``solve``: classic ADMM + polish, certified by the duality gap.
 
-Pins (tests/test_oracle_lasso.py): orthonormal A gives x* = S_lam(A^T b);
+Pins (tests/test_oracle_lasso.py, tests/test_oracle_elastic_net.py):
+orthonormal A gives x* = S_lam(A^T b) / (1 + lam2);
 brute force at n <= 8; lam >= ||A^T b||_inf gives x* = 0 (App. A); lam -> 0
 with m >= n gives numpy.linalg.lstsq; duality gap >= 0 and -> 0; KKT; the
 exact-solve ADMM fixed point equals the brute-force optimum.
@@ -45,16 +49,18 @@ def _f64(a):
     return np.asarray(a, dtype=np.float64)
 
 
-def objective(A, b, lam, x):
+def objective(A, b, lam, x, lam2=0.0):
     A = _f64(A)
-    r = A @ _f64(x) - _f64(b)
-    return 0.5 * float(r @ r) + lam * float(np.sum(np.abs(x)))
+    x = _f64(x)
+    r = A @ x - _f64(b)
+    return 0.5 * float(r @ r) + lam * float(np.sum(np.abs(x))) + 0.5 * lam2 * float(x @ x)
 
 
-def grad_f(A, b, x):
-    """grad f(x) = A^T (A x - b)  (Sec. 3.1)."""
+def grad_f(A, b, x, lam2=0.0):
+    """grad f(x) = A^T (A x - b) + lam2 x  (Sec. 3.1; Sec. 3.3 with lam2)."""
     A = _f64(A)
-    return A.T @ (A @ _f64(x) - _f64(b))
+    x = _f64(x)
+    return A.T @ (A @ x - _f64(b)) + lam2 * x
 
 
 def hessian_vector(A, p, d=None):
@@ -103,7 +109,7 @@ class ShiftedGramSolve:
 
 def admm(A, b, lam, rho=1.0, alpha=1.0, sigma=0.0, max_iter=1000, eps=None,
          rho_update_every=0, rho_update_until=500, tau=2.0, mu=10.0,
-         x0=None, z0=None, u0=None, record=True):
+         x0=None, z0=None, u0=None, record=True, lam2=0.0):
     """Scaled ADMM of Sec. 2 with exact x-steps.  Returns (x, z, u, rho, hist).
 
     hist has one row per iteration k = 1..K:
@@ -118,19 +124,19 @@ def admm(A, b, lam, rho=1.0, alpha=1.0, sigma=0.0, max_iter=1000, eps=None,
     x = np.zeros(n) if x0 is None else _f64(x0).copy()
     z = np.zeros(n) if z0 is None else _f64(z0).copy()
     u = np.zeros(n) if u0 is None else _f64(u0).copy()
-    solver = ShiftedGramSolve(A, rho + sigma)
+    solver = ShiftedGramSolve(A, rho + sigma + lam2)
     hist = []
     for k in range(1, max_iter + 1):
-        # eq. x-update-lin-sys with H = A^T A, M = I, c = 0
-        Hx = A.T @ (A @ x)
-        g = A.T @ (A @ x - b)
+        # eq. x-update-lin-sys with H = A^T A + lam2 I, M = I, c = 0
+        Hx = A.T @ (A @ x) + lam2 * x
+        g = grad_f(A, b, x, lam2)
         rhs = Hx + sigma * x - g + rho * (z - u)
         x = solver.solve(rhs)
         # over-relaxation (Sec. 2.5), z-update (prox), u-update
         xh = alpha * x + (1.0 - alpha) * z
         z = soft_threshold(xh + u, lam / rho)
         u = u + xh - z
-        gx = A.T @ (A @ x - b)
+        gx = grad_f(A, b, x, lam2)
         rk, rp, rd = r_kkt(x, z, u, rho, gx)
         rho_used = rho
         if rho_update_every > 0 and k % rho_update_every == 0 and k <= rho_update_until:
@@ -142,7 +148,7 @@ def admm(A, b, lam, rho=1.0, alpha=1.0, sigma=0.0, max_iter=1000, eps=None,
             if new != rho:
                 u = u * (rho / new)
                 rho = new
-                solver = ShiftedGramSolve(A, rho + sigma)
+                solver = ShiftedGramSolve(A, rho + sigma + lam2)
         if record:
             hist.append((k, rp, rd, rk, rho_used, rho))
         if eps is not None and rk <= eps:
@@ -150,37 +156,42 @@ def admm(A, b, lam, rho=1.0, alpha=1.0, sigma=0.0, max_iter=1000, eps=None,
     return x, z, u, rho, np.array(hist)
 
 
-def duality_gap(A, b, lam, x):
-    """(gap, primal, dual) per App. A with f(w) = w^2/2, f*(v) = v^2/2, lam2 = 0."""
+def duality_gap(A, b, lam, x, lam2=0.0):
+    """(gap, primal, dual) per App. A with f(w) = w^2/2, f*(v) = v^2/2."""
     A = _f64(A)
     b = _f64(b)
     x = _f64(x)
     r = A @ x - b
+    primal = objective(A, b, lam, x, lam2)
+    if lam2 > 0.0:
+        nu = r
+        excess = np.maximum(np.abs(A.T @ nu) - lam, 0.0)
+        dual = -0.5 * float(nu @ nu) - float(b @ nu) - float(excess @ excess) / (2.0 * lam2)
+        return primal - dual, primal, dual
     g = A.T @ r
     ginf = float(np.max(np.abs(g))) if g.size else 0.0
     scale = 1.0 if ginf <= lam else lam / ginf
     nu = scale * r
-    primal = 0.5 * float(r @ r) + lam * float(np.sum(np.abs(x)))
     dual = -0.5 * float(nu @ nu) - float(b @ nu)
     return primal - dual, primal, dual
 
 
-def relative_gap(A, b, lam, x):
+def relative_gap(A, b, lam, x, lam2=0.0):
     """The relative duality gap of Sec. 3.3: (l(x) - g(nu)) / min(l(x), |g(nu)|)."""
-    gap, p, d = duality_gap(A, b, lam, x)
+    gap, p, d = duality_gap(A, b, lam, x, lam2)
     return gap / min(p, abs(d))
 
 
-def kkt_violation(A, b, lam, x):
+def kkt_violation(A, b, lam, x, lam2=0.0):
     """max_i violation of the optimality conditions of App. A, relative to lam."""
     x = _f64(x)
-    g = grad_f(A, b, x)
+    g = grad_f(A, b, x, lam2)
     on = x != 0
     v = np.where(on, np.abs(g + lam * np.sign(x)), np.maximum(np.abs(g) - lam, 0.0))
     return float(np.max(v)) / lam if v.size else 0.0
 
 
-def polish(A, b, lam, z, tol=1e-12):
+def polish(A, b, lam, z, tol=1e-12, lam2=0.0):
     """Solve the KKT system on the support of z; returns x or None if not optimal."""
     A = _f64(A)
     b = _f64(b)
@@ -192,7 +203,7 @@ def polish(A, b, lam, z, tol=1e-12):
         return x if np.max(np.abs(g)) <= lam * (1 + tol) else None
     s = np.sign(np.asarray(z, np.float64)[S])
     AS = A[:, S]
-    G = AS.T @ AS
+    G = AS.T @ AS + lam2 * np.eye(S.size)
     try:
         c = sla.cho_factor(G, lower=True)
     except np.linalg.LinAlgError:
@@ -210,7 +221,7 @@ def polish(A, b, lam, z, tol=1e-12):
 
 
 def solve(A, b, lam, rhos=(1.0, 0.1, 0.01), iters_per_rho=1500, gap_rel=1e-12,
-          check_every=10):
+          check_every=10, lam2=0.0):
     """Certified Lasso optimum: classic ADMM (alpha = 1, sigma = 0), then polish.
 
     The optimum does not depend on the penalty, so the penalty is lowered
@@ -233,7 +244,7 @@ def solve(A, b, lam, rhos=(1.0, 0.1, 0.01), iters_per_rho=1500, gap_rel=1e-12,
         if prev is not None:
             u = u * (prev / rho)
         prev = rho
-        solver = ShiftedGramSolve(A, rho)
+        solver = ShiftedGramSolve(A, rho + lam2)
         budget = iters_per_rho * (10 if i == len(rhos) - 1 else 1)
         for k in range(1, budget + 1):
             total += 1
@@ -241,16 +252,16 @@ def solve(A, b, lam, rhos=(1.0, 0.1, 0.01), iters_per_rho=1500, gap_rel=1e-12,
             z = soft_threshold(x + u, lam / rho)
             u = u + x - z
             if k % check_every == 0:
-                xp = polish(A, b, lam, z)
+                xp = polish(A, b, lam, z, lam2=lam2)
                 cand = xp if xp is not None else z
-                gap, F, _ = duality_gap(A, b, lam, cand)
+                gap, F, _ = duality_gap(A, b, lam, cand, lam2)
                 if gap <= gap_rel * max(F, 1e-300):
                     best = (cand, F, gap, xp is not None, total)
                     break
         if best is not None:
             break
     if best is None:
-        gap, F, _ = duality_gap(A, b, lam, z)
+        gap, F, _ = duality_gap(A, b, lam, z, lam2)
         best = (z, F, gap, False, total)
     cand, F, gap, pol, k = best
     S = np.flatnonzero(cand != 0)
@@ -258,11 +269,11 @@ def solve(A, b, lam, rhos=(1.0, 0.1, 0.01), iters_per_rho=1500, gap_rel=1e-12,
                 polished=pol)
 
 
-def brute_force(A, b, lam):
+def brute_force(A, b, lam, lam2=0.0):
     """Enumerate all 3^n sign patterns; returns (x_kkt_list, x_minF, F_min).
 
     For each pattern s in {-1, 0, +1}^n with support S, solve
-    A_S^T A_S x_S = A_S^T b - lam s_S; keep sign-consistent candidates.
+    (A_S^T A_S + lam2 I) x_S = A_S^T b - lam s_S; keep sign-consistent candidates.
     """
     A = _f64(A)
     b = _f64(b)
@@ -275,16 +286,16 @@ def brute_force(A, b, lam):
         x = np.zeros(n)
         if S.size:
             AS = A[:, S]
-            G = AS.T @ AS
+            G = AS.T @ AS + lam2 * np.eye(S.size)
             if np.linalg.matrix_rank(G) < S.size:
                 continue
             xs = np.linalg.solve(G, AS.T @ b - lam * s[S])
             if not np.all(np.sign(xs) == s[S]):
                 continue
             x[S] = xs
-        F = objective(A, b, lam, x)
+        F = objective(A, b, lam, x, lam2)
         if F < bestF:
             bestF, bestx = F, x
-        if kkt_violation(A, b, lam, x) <= 1e-9:
+        if kkt_violation(A, b, lam, x, lam2) <= 1e-9:
             kkt.append(x)
     return kkt, bestx, bestF

@@ -43,14 +43,18 @@ def margins(A, y, x):
     return -_f64(y) * (_f64(A) @ _f64(x))
 
 
-def objective(A, y, lam, x):
+def objective(A, y, lam, x, lam2=0.0):
+    """sum_i l(w_i) + lam ||x||_1 + (lam2/2)||x||^2 (Sec. 3.3 with the l2 term)."""
+    x = _f64(x)
     w = margins(A, y, x)
-    return float(np.sum(np.logaddexp(0.0, w))) + lam * float(np.sum(np.abs(x)))
+    return (float(np.sum(np.logaddexp(0.0, w))) + lam * float(np.sum(np.abs(x))) +
+            0.5 * lam2 * float(x @ x))
 
 
-def grad_f(A, y, x):
+def grad_f(A, y, x, lam2=0.0):
+    x = _f64(x)
     w = margins(A, y, x)
-    return _f64(A).T @ (-_f64(y) * expit(w))
+    return _f64(A).T @ (-_f64(y) * expit(w)) + lam2 * x
 
 
 def hess_diag(A, y, x):
@@ -58,21 +62,22 @@ def hess_diag(A, y, x):
     return s * (1.0 - s)
 
 
-def _newton_prox(A, y, rho, v, x0, tol=1e-12, max_newton=100):
+def _newton_prox(A, y, rho, v, x0, tol=1e-12, max_newton=100, lam2=0.0):
     """argmin_x f(x) + (rho/2)||x - v||^2 by damped Newton with Armijo backtracking."""
     A = _f64(A)
     x = _f64(x0).copy()
 
     def phi(xx):
         w = margins(A, y, xx)
-        return float(np.sum(np.logaddexp(0.0, w))) + 0.5 * rho * float((xx - v) @ (xx - v))
+        return (float(np.sum(np.logaddexp(0.0, w))) + 0.5 * lam2 * float(xx @ xx) +
+                0.5 * rho * float((xx - v) @ (xx - v)))
 
     for _ in range(max_newton):
-        g = grad_f(A, y, x) + rho * (x - v)
+        g = grad_f(A, y, x, lam2) + rho * (x - v)
         if np.linalg.norm(g) <= tol * max(1.0, np.linalg.norm(x)):
             break
         d = hess_diag(A, y, x)
-        step = -ShiftedGramSolve(A, rho, d).solve(g)
+        step = -ShiftedGramSolve(A, rho + lam2, d).solve(g)
         t, f0, slope = 1.0, phi(x), float(g @ step)
         while phi(x + t * step) > f0 + 1e-4 * t * slope and t > 1e-12:
             t *= 0.5
@@ -81,7 +86,8 @@ def _newton_prox(A, y, rho, v, x0, tol=1e-12, max_newton=100):
 
 
 def admm(A, y, lam, rho=1.0, alpha=1.0, sigma=0.0, max_iter=500, eps=None,
-         xstep="approx", rho_update_every=0, rho_update_until=500, tau=2.0, mu=10.0):
+         xstep="approx", rho_update_every=0, rho_update_until=500, tau=2.0, mu=10.0,
+         lam2=0.0):
     """ADMM of Sec. 2 / Sec. 3.3 for l1-logistic; returns (x, z, u, rho, hist)."""
     A = _f64(A)
     y = _f64(y)
@@ -93,16 +99,16 @@ def admm(A, y, lam, rho=1.0, alpha=1.0, sigma=0.0, max_iter=500, eps=None,
     for k in range(1, max_iter + 1):
         if xstep == "approx":
             d = hess_diag(A, y, x)
-            g = grad_f(A, y, x)
-            Hx = A.T @ (d * (A @ x))
+            g = grad_f(A, y, x, lam2)
+            Hx = A.T @ (d * (A @ x)) + lam2 * x
             rhs = Hx + sigma * x - g + rho * (z - u)
-            x = ShiftedGramSolve(A, rho + sigma, d).solve(rhs)
+            x = ShiftedGramSolve(A, rho + sigma + lam2, d).solve(rhs)
         else:
-            x = _newton_prox(A, y, rho, z - u, x)
+            x = _newton_prox(A, y, rho, z - u, x, lam2=lam2)
         xh = alpha * x + (1.0 - alpha) * z
         z = soft_threshold(xh + u, lam / rho)
         u = u + xh - z
-        rk, rp, rd = r_kkt(x, z, u, rho, grad_f(A, y, x))
+        rk, rp, rd = r_kkt(x, z, u, rho, grad_f(A, y, x, lam2))
         rho_used = rho
         if rho_update_every > 0 and k % rho_update_every == 0 and k <= rho_update_until:
             new = rho
@@ -119,36 +125,45 @@ def admm(A, y, lam, rho=1.0, alpha=1.0, sigma=0.0, max_iter=500, eps=None,
     return x, z, u, rho, np.array(hist)
 
 
-def duality_gap(A, y, lam, x):
-    """(gap, primal, dual): App. A with the logistic conjugate and lam2 = 0."""
+def duality_gap(A, y, lam, x, lam2=0.0):
+    """(gap, primal, dual): App. A with the logistic conjugate h(v) = v log v +
+    (1 - v) log(1 - v).  lam2 = 0: nu = s min(1, lam / ||A^T (y o s)||_inf);
+    lam2 > 0: nu = s and g(nu) = -sum h(nu_i) - (1/(2 lam2)) ||(|A^T (y o nu)| - lam)_+||^2
+    (s = sigmoid of the margins; the folded rows -y_i a_i make A~^T nu = -A^T (y o nu))."""
     A = _f64(A)
     y = _f64(y)
     w = margins(A, y, x)
     s = expit(w)
+    primal = objective(A, y, lam, x, lam2)
+    if lam2 > 0.0:
+        nu = s
+        excess = np.maximum(np.abs(A.T @ (y * nu)) - lam, 0.0)
+        dual = (-float(np.sum(xlogy(nu, nu) + xlogy(1.0 - nu, 1.0 - nu))) -
+                float(excess @ excess) / (2.0 * lam2))
+        return primal - dual, primal, dual
     g = A.T @ (y * s)
     ginf = float(np.max(np.abs(g)))
     scale = 1.0 if ginf <= lam else lam / ginf
     nu = scale * s
     dual = -float(np.sum(xlogy(nu, nu) + xlogy(1.0 - nu, 1.0 - nu)))
-    primal = objective(A, y, lam, x)
     return primal - dual, primal, dual
 
 
-def relative_gap(A, y, lam, x):
+def relative_gap(A, y, lam, x, lam2=0.0):
     """The relative duality gap of Sec. 3.3: (l(x) - g(nu)) / min(l(x), |g(nu)|)."""
-    gap, p, d = duality_gap(A, y, lam, x)
+    gap, p, d = duality_gap(A, y, lam, x, lam2)
     return gap / min(p, abs(d))
 
 
-def kkt_violation(A, y, lam, x):
+def kkt_violation(A, y, lam, x, lam2=0.0):
     x = _f64(x)
-    g = grad_f(A, y, x)
+    g = grad_f(A, y, x, lam2)
     on = x != 0
     v = np.where(on, np.abs(g + lam * np.sign(x)), np.maximum(np.abs(g) - lam, 0.0))
     return float(np.max(v)) / lam
 
 
-def solve(A, y, lam, rho=1.0, max_iter=5000, gap_rel=1e-12, check_every=5):
+def solve(A, y, lam, rho=1.0, max_iter=5000, gap_rel=1e-12, check_every=5, lam2=0.0):
     """Certified optimum by classic ADMM (exact Newton x-step, fixed rho)."""
     A = _f64(A)
     y = _f64(y)
@@ -158,16 +173,16 @@ def solve(A, y, lam, rho=1.0, max_iter=5000, gap_rel=1e-12, check_every=5):
     u = np.zeros(n)
     out = None
     for k in range(1, max_iter + 1):
-        x = _newton_prox(A, y, rho, z - u, x)
+        x = _newton_prox(A, y, rho, z - u, x, lam2=lam2)
         z = soft_threshold(x + u, lam / rho)
         u = u + x - z
         if k % check_every == 0:
-            gap, F, _ = duality_gap(A, y, lam, z)
+            gap, F, _ = duality_gap(A, y, lam, z, lam2)
             if gap <= gap_rel * F:
                 out = (z, F, gap, k)
                 break
     if out is None:
-        gap, F, _ = duality_gap(A, y, lam, z)
+        gap, F, _ = duality_gap(A, y, lam, z, lam2)
         out = (z, F, gap, max_iter)
     z, F, gap, k = out
     return dict(x=z, F=F, gap=gap, iters=k)

@@ -106,3 +106,32 @@ def test_relative_gap_bounds_relative_suboptimality():
         assert rel == gap / min(pr, abs(du))
         assert rel >= (logreg.objective(P["A"], P["y"], P["lam"], x) - sol["F"]) / min(pr, abs(du)) - 1e-12
         assert rel >= -1e-12
+
+
+def test_l2_term_optimum_satisfies_kkt_and_matches_lbfgs():
+    # lam2 > 0: the certified optimum satisfies App. A's conditions and agrees with
+    # L-BFGS-B on the split (x+, x-) >= 0 form with the l2 term
+    P = genios_data.logreg_factor(300, 30, nnz_frac=0.1, seed=3, s=5)
+    A, y, lam, lam2 = P["A"], P["y"], P["lam"], 0.5
+    sol = logreg.solve(A, y, lam, lam2=lam2)
+    assert logreg.kkt_violation(A, y, lam, sol["x"], lam2) <= 1e-5
+    gap, pr, du = logreg.duality_gap(A, y, lam, sol["x"], lam2)
+    assert 0.0 <= gap <= 1e-8 * pr
+    n = A.shape[1]
+
+    def fun(v):
+        xp, xm = v[:n], v[n:]
+        x = xp - xm
+        w = logreg.margins(A, y, x)
+        g = logreg.grad_f(A, y, x, lam2)
+        f = float(np.sum(np.logaddexp(0.0, w))) + lam * float(np.sum(v)) + 0.5 * lam2 * float(x @ x)
+        return f, np.concatenate([g + lam, -g + lam])
+    res = minimize(fun, np.zeros(2 * n), jac=True, method="L-BFGS-B",
+                   bounds=[(0, None)] * (2 * n), options=dict(maxiter=5000, ftol=1e-15, gtol=1e-12))
+    x_lb = res.x[:n] - res.x[n:]
+    assert logreg.objective(A, y, lam, x_lb, lam2) >= sol["F"] - 1e-9
+    assert abs(logreg.objective(A, y, lam, x_lb, lam2) - sol["F"]) <= 1e-6 * sol["F"]
+    # weak duality away from the optimum
+    x = sol["x"] + 0.1 * np.random.default_rng(1).standard_normal(n)
+    gap, pr, du = logreg.duality_gap(A, y, lam, x, lam2)
+    assert gap >= logreg.objective(A, y, lam, x, lam2) - sol["F"] - 1e-12
