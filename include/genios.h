@@ -145,6 +145,9 @@ typedef struct {
                                   BF16_ONLY: with the BF16 copy) every gap_every iterations */
   int32_t gap_every;           /* iterations between gap evaluations, default 1 */
   double eps_gap;              /* relative duality gap tolerance, default 1e-4 */
+  double lambda2;              /* (lambda2 / 2) ||x||^2 added to the loss (elastic net, Sec. 4.1,
+                                  App. A), >= 0, default 0; the x-system shift becomes
+                                  rho + sigma + lambda2, the adjoint's lambda2 */
 } genios_opts;
 
 /* Per-iteration history row layout (doubles); problem p, iteration k (1-based)
@@ -267,11 +270,13 @@ int genios_nystrom_apply(int64_t n, int32_t s, int64_t batch, int32_t dtype, con
                          const double* lambda_hat, double nu, const void* r, void* z,
                          const genios_opts* o);
 
-/* Adjoint of the Lasso solution map (implicit differentiation on the active
- * set, from the optimality conditions of App. A with f'(w) = w): with S the
- * support of z_star and s its signs,
- *   grad_b      = A_S (A_S^T A_S)^-1 grad_z_S          (m per problem, written)
- *   grad_lambda = -s^T (A_S^T A_S)^-1 grad_z_S          (host, batch, written)
+/* Adjoint of the Lasso (elastic-net) solution map (implicit differentiation on
+ * the active set, from the optimality conditions of App. A with f'(w) = w): with
+ * S the support of z_star, s its signs and G = A_S^T A_S + opts->lambda2 I,
+ *   grad_b      = A_S G^-1 grad_z_S                     (m per problem, written)
+ *   grad_lambda = -s^T G^-1 grad_z_S                     (host, batch, written)
+ * Without the l2 term |S| must not exceed min(m, n) (else G is singular:
+ * GENIOS_ERR_NUMERIC).
  * The active columns of the FP32 (or FP64) master copy are gathered, in order,
  * into an m x |S| block in the workspace (padded to a multiple of 8 with
  * identity columns), and the system is solved there by Nystrom-preconditioned

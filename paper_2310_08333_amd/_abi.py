@@ -57,7 +57,7 @@ class Opts(C.Structure):
                 ("stream", C.c_void_p),
                 ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
                 ("termination", C.c_int32), ("gap_every", C.c_int32),
-                ("eps_gap", C.c_double)]
+                ("eps_gap", C.c_double), ("lambda2", C.c_double)]
 
 
 class Info(C.Structure):

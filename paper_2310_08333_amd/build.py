@@ -22,8 +22,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libgenios.so")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 
-SOURCES = ["gemv.hip", "cg.hip", "sketch.hip", "sketch_mfma.hip", "gap.hip", "engine.cpp",
-           "abi.cpp"]
+SOURCES = ["gemv.hip", "cg.hip", "sketch.hip", "sketch_mfma.hip", "gap.hip", "stream.hip",
+           "engine.cpp", "abi.cpp"]
 ARCH = os.environ.get("GENIOS_OFFLOAD_ARCH", "gfx950")
 
 

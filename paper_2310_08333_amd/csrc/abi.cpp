@@ -48,6 +48,8 @@ int check_opts(const genios_opts* o) {
   if (o->termination < 0 || o->termination > 1) FAIL(GENIOS_ERR_ARG, "termination must be 0 or 1");
   if (o->gap_every < 1) FAIL(GENIOS_ERR_ARG, "gap_every must be >= 1");
   if (!(o->eps_gap > 0.0) || !std::isfinite(o->eps_gap)) FAIL(GENIOS_ERR_ARG, "eps_gap must be > 0");
+  if (!(o->lambda2 >= 0.0) || !std::isfinite(o->lambda2))
+    FAIL(GENIOS_ERR_ARG, "lambda2 must be finite and >= 0");
   return GENIOS_OK;
 }
 
@@ -137,6 +139,7 @@ int genios_default_opts(genios_opts* o) {
   o->termination = 0;
   o->gap_every = 1;
   o->eps_gap = 1e-4;
+  o->lambda2 = 0.0;
   return GENIOS_OK;
 }
 
@@ -303,9 +306,7 @@ int genios_stream_read(const void* p, int64_t bytes, int32_t reps, uint32_t* scr
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int64_t want = std::max<int64_t>(1, (bytes / 16 + 1023) / 1024);
-  const int blocks = (int)std::min<int64_t>(want, std::min<int64_t>(kStreamReadMaxBlocks,
-                                                                     16 * (int64_t)std::max(cus, 1)));
+  const int blocks = stream_read_blocks(bytes, cus, (int)kStreamReadMaxBlocks);
   hipEvent_t ev[2] = {nullptr, nullptr};
   if (e == hipSuccess) e = hipEventCreate(&ev[0]);
   if (e == hipSuccess) e = hipEventCreate(&ev[1]);

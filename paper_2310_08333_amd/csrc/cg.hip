@@ -207,18 +207,19 @@ __global__ __launch_bounds__(256) void k_admm_begin(VecArgs a) {
   const uint8_t* mask = a.mask ? a.mask + off : nullptr;
   __shared__ VT rs[kVecChunk * 4];
   __shared__ double red[16];
-  const VT rho = VT(P.rho), sig = VT(P.sigma), usc = VT(P.u_scale);
+  const VT rho = VT(P.rho), sig = VT(P.sigma), usc = VT(P.u_scale), l2 = VT(P.lambda2);
   double rhs2 = 0.0, rr = 0.0;
   for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) {
     // all loads before the first store (the vectors are distinct)
     VT ui = u[i];
     const VT xi = x[i], zi = z[i], hi = h[i];
-    const VT gi = c ? hi - c[i] : g[i];
+    // grad f(x^k) with the l2 term; (H + sigma I) x^k with H's lambda2 I
+    const VT gi = (c ? hi - c[i] : g[i]) + l2 * xi;
     if (P.u_scale != 1.0) {
       ui *= usc;
       u[i] = ui;
     }
-    VT rhs = hi + sig * xi - gi + rho * (zi - ui);
+    VT rhs = hi + l2 * xi + sig * xi - gi + rho * (zi - ui);
     VT ri = rho * (zi - ui - xi) - gi;
     if (mask && !mask[i]) {
       rhs = VT(0);
@@ -516,7 +517,7 @@ __global__ __launch_bounds__(256) void k_admm_end(VecArgs a) {
     s_z += double(zn) * double(zn);
     s_u += double(un) * double(un);
     if (c) {
-      const double rd = double(hi - ci) + double(rho) * double(un);
+      const double rd = double(hi - ci) + P.lambda2 * double(xi) + double(rho) * double(un);
       s_rd += rd * rd;
     }
     s_z1 += fabs(double(zn));
@@ -554,13 +555,14 @@ __global__ __launch_bounds__(256) void k_dual_residual(VecArgs a) {
   const Chunk ch = my_chunk(n, a.chunk);
   const int64_t off = (int64_t)b * n;
   const VT* u = static_cast<const VT*>(a.u) + off;
+  const VT* x = static_cast<const VT*>(a.x) + off;
   const VT* h = static_cast<const VT*>(a.h) + off;
   const VT* c = P.use_c ? static_cast<const VT*>(a.c) + off : nullptr;
   const VT* g = P.use_c ? nullptr : static_cast<const VT*>(a.g) + off;
   __shared__ double red[4];
   double s = 0.0;
   for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) {
-    const double gi = c ? double(h[i] - c[i]) : double(g[i]);
+    const double gi = (c ? double(h[i] - c[i]) : double(g[i])) + P.lambda2 * double(x[i]);
     const double rd = gi + P.rho * double(u[i]);
     s += rd * rd;
   }

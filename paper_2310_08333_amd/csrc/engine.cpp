@@ -110,7 +110,7 @@ void Layout::carve(Arena& ar) {
   if (gap) {
     gapf = vec(m);
     gaps = vec(m);
-    gpart = static_cast<double*>(ar.take((size_t)B * 4 * kGapPStride * sizeof(double)));
+    gpart = static_cast<double*>(ar.take((size_t)B * kGapSlots * kGapPStride * sizeof(double)));
     gstate = static_cast<GapState*>(ar.take((size_t)B * sizeof(GapState)));
   }
   if (logistic || backward) {
@@ -176,7 +176,9 @@ int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_)
   nb = (int)((n + chunk - 1) / chunk);
   part_blocks = std::max<int>(nb, std::max<int>(kMaxVecBlocks, (int)((n + kVecChunk - 1) / kVecChunk)));
   n_vecs = (op == GENIOS_OP_MATVEC || op == GENIOS_OP_NYSTROM || op == GENIOS_OP_HVP) ? 0 : kNumNVec;
-  ldS_max = backward ? (int)((std::min(m, n) + 7) / 8 * 8) : 0;
+  // columns of the gathered A_S: |S| <= min(m, n) without the l2 term (else A_S^T A_S
+  // is singular and the call fails), up to n with it
+  ldS_max = backward ? (int)(((o->lambda2 > 0.0 ? n : std::min(m, n)) + 7) / 8 * 8) : 0;
   if (s > 0) sketch_ws_bytes(m, n, s, batch, vt, &sk.ksW, &sk.ksY, &sk.nbG);
   Arena ar{nullptr, 0, 0, true};
   carve(ar);
@@ -575,7 +577,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
       q.run = (run_all || !P[b].done) ? 1 : 0;
       q.rho = P[b].rho;
       q.sigma = o->sigma;
-      q.nu = P[b].rho + o->sigma;
+      q.nu = P[b].rho + o->sigma + o->lambda2;
       q.kappa = P[b].lambda / P[b].rho;
       q.alpha = o->alpha;
       q.u_scale = P[b].u_scale;
@@ -590,6 +592,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
       q.rtol = rtol;
       q.tol_floor = o->cg_tol_floor;
       q.lambda = P[b].lambda;
+      q.lambda2 = o->lambda2;
       q.max_cg = o->max_cg_iter;
       q.rhs_rel = o->rhs_relative;
       q.use_c = logistic ? 0 : 1;
@@ -1008,7 +1011,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     I.r_p = q.rp;
     I.r_d = std::sqrt(hs[b].red[kRedRd2]);
     I.r_kkt = kkt_from(I.r_p, I.r_d, q.xn, q.zn, q.rho * q.un, n);
-    I.obj = hs[b].red[kRedAux] + q.lambda * hs[b].red[kRedZ1];
+    I.obj = hs[b].red[kRedAux] + q.lambda * hs[b].red[kRedZ1] + 0.5 * o->lambda2 * hs[b].red[kRedZ2];
     I.rel_gap = hg[b].rel_gap;
     I.gap_primal = hg[b].primal;
     I.gap_dual = hg[b].dual;
@@ -1202,7 +1205,8 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
   HC(hipStreamSynchronize(c.st));
   int cmax = 0;
   for (int64_t b = 0; b < B; ++b) cmax = std::max(cmax, cnt[b]);
-  if (cmax > std::min<int64_t>(m, n)) {
+  // (A_S^T A_S + lambda2 I) is singular only without the l2 term
+  if (o->lambda2 == 0.0 && cmax > std::min<int64_t>(m, n)) {
     set_error("active set larger than the number of rows: A_S^T A_S is singular");
     return GENIOS_ERR_NUMERIC;
   }
@@ -1222,6 +1226,10 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
   // padded to a multiple of 8 (vector loads) but never beyond n, the capacity of
   // the n-vector workspace slots reused for the compact vectors
   const int ldS = (int)std::min<int64_t>((cmax + 7) / 8 * 8, n);
+  if (ldS > c.L.ldS_max) {  // never gather beyond the reserved block
+    set_error("active set exceeds the reserved compact block");
+    return GENIOS_ERR_NUMERIC;
+  }
   // compact problem: A_S (m x ldS), g_S, signs, padding mask
   void* sgnS = c.L.nv[kVCH];
   void* negS = c.L.nv[kVG];
@@ -1260,7 +1268,7 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
     q.run = 1;
     q.rho = 1.0;
     q.sigma = 0.0;
-    q.nu = 0.0;
+    q.nu = o->lambda2;  // (A_S^T A_S + lambda2 I) w = g_S
     q.kappa = 0.0;
     q.alpha = 1.0;
     q.u_scale = 1.0;

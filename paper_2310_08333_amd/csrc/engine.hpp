@@ -64,7 +64,7 @@ struct Layout {
   bool gap = false;
   void* gapf = nullptr;       // [batch][m] f'(t)
   void* gaps = nullptr;       // [batch][m] r or sigmoid(w)
-  double* gpart = nullptr;    // [batch][4][kGapPStride]
+  double* gpart = nullptr;    // [batch][kGapSlots][kGapPStride]
   GapState* gstate = nullptr; // [batch]
   size_t total = 0;
 

@@ -8,7 +8,10 @@
 // ||A^T nu||_inf <= lam, and the dual function is
 //   Lasso:     g(nu) = -||nu||^2 / 2 - b^T nu,
 //   logistic:  g(nu) = -sum_i h(kappa s_i),  h(v) = v log v + (1 - v) log(1 - v),
-//              with s_i = sigmoid(w_i) (the folded rows' nu),
+//              with s_i = sigmoid(w_i) (the folded rows' nu);
+// with the l2 term (lambda2 > 0) the dual is finite for every nu: kappa = 1
+// and g gains -(1 / (2 lambda2)) ||(|A^T nu| - lam)_+||^2, while l(x) gains
+// (lambda2 / 2) ||x||^2,
 // so l(x) - g(nu) >= l(x) - l(x*) and the relative gap is
 // (l(x) - g(nu)) / min(l(x), |g(nu)|) (Sec. 3.3).
 //
@@ -113,52 +116,70 @@ __global__ __launch_bounds__(kGapThreads) void k_gap_elem(
     }
   }
   loss = block_sum1(loss, sm);
-  if (threadIdx.x == 0) part[((int64_t)b * 4 + 0) * pstride + blockIdx.x] = loss;
+  if (threadIdx.x == 0) part[((int64_t)b * kGapSlots + 0) * pstride + blockIdx.x] = loss;
 }
 
-// ||A^T f'(t)||_inf from the row-split partials, and ||v||_1.
+// ||A^T f'(t)||_inf and ||(|A^T f'(t)| - lambda)_+||^2 from the row-split
+// partials, and ||v||_1, ||v||^2.
 template <typename VT>
 __global__ __launch_bounds__(kGapThreads) void k_gap_inf(
     int64_t n, const VT* __restrict__ ypart, int ks, int64_t ks_stride, int64_t prob_stride,
-    const VT* __restrict__ v, double* __restrict__ part, int pstride) {
+    const VT* __restrict__ v, const ProbParams* __restrict__ params, double* __restrict__ part,
+    int pstride) {
   __shared__ double sm[4];
   const int b = blockIdx.y;
+  const double lam = params[b].lambda;
   const VT* yp = ypart + (int64_t)b * prob_stride;
   const VT* vb = v + (int64_t)b * n;
-  double gmax = 0.0, l1 = 0.0;
+  double gmax = 0.0, l1 = 0.0, x2 = 0.0, ex2 = 0.0;
   for (int64_t j = (int64_t)blockIdx.x * kGapThreads + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * kGapThreads) {
     double g = 0.0;
     for (int k = 0; k < ks; ++k) g += (double)yp[(int64_t)k * ks_stride + j];
     gmax = fmax(gmax, fabs(g));
-    l1 += fabs((double)vb[j]);
+    const double e = fmax(fabs(g) - lam, 0.0);
+    ex2 += e * e;
+    const double vj = (double)vb[j];
+    l1 += fabs(vj);
+    x2 += vj * vj;
   }
   gmax = block_max1(gmax, sm);
   l1 = block_sum1(l1, sm);
+  x2 = block_sum1(x2, sm);
+  ex2 = block_sum1(ex2, sm);
   if (threadIdx.x == 0) {
-    part[((int64_t)b * 4 + 1) * pstride + blockIdx.x] = gmax;
-    part[((int64_t)b * 4 + 2) * pstride + blockIdx.x] = l1;
+    double* pb = part + (int64_t)b * kGapSlots * pstride + blockIdx.x;
+    pb[1 * pstride] = gmax;
+    pb[2 * pstride] = l1;
+    pb[4 * pstride] = x2;
+    pb[5 * pstride] = ex2;
   }
 }
 
-// kappa and the primal value (one 64-thread block per problem).
+// kappa, the primal value and the dual's l2 part (one 64-thread block per problem).
 __global__ __launch_bounds__(64) void k_gap_kappa(const double* __restrict__ part, int pstride,
                                                   int nb_m, int nb_n,
                                                   const ProbParams* __restrict__ params,
                                                   GapState* __restrict__ gs) {
   const int b = blockIdx.x;
-  const double* pb = part + (int64_t)b * 4 * pstride;
+  const double* pb = part + (int64_t)b * kGapSlots * pstride;
   const double loss = wave_fixed_sum(pb, nb_m, 1);
   const double ginf = wave_fixed_max(pb + pstride, nb_n, 1);
   const double l1 = wave_fixed_sum(pb + 2 * pstride, nb_n, 1);
+  const double x2 = wave_fixed_sum(pb + 4 * pstride, nb_n, 1);
+  const double ex2 = wave_fixed_sum(pb + 5 * pstride, nb_n, 1);
   if (threadIdx.x == 0) {
-    const double lam = params[b].lambda;
+    const double lam = params[b].lambda, lam2 = params[b].lambda2;
     GapState& G = gs[b];
     G.loss = loss;
     G.grad_inf = ginf;
     G.l1 = l1;
-    G.kappa = ginf > lam ? lam / ginf : 1.0;
-    G.primal = loss + lam * l1;
+    G.x2 = x2;
+    G.excess2 = ex2;
+    // lambda2 > 0: g is finite for every nu, nu = f'(t) unscaled (App. A)
+    G.kappa = lam2 > 0.0 ? 1.0 : (ginf > lam ? lam / ginf : 1.0);
+    G.reg = lam2 > 0.0 ? -ex2 / (2.0 * lam2) : 0.0;
+    G.primal = loss + lam * l1 + 0.5 * lam2 * x2;
   }
 }
 
@@ -180,16 +201,16 @@ __global__ __launch_bounds__(kGapThreads) void k_gap_dual(
     acc += logistic ? neg_entropy(v) : 0.5 * v * v + (double)bb[i] * v;
   }
   acc = block_sum1(acc, sm);
-  if (threadIdx.x == 0) part[((int64_t)b * 4 + 3) * pstride + blockIdx.x] = acc;
+  if (threadIdx.x == 0) part[((int64_t)b * kGapSlots + 3) * pstride + blockIdx.x] = acc;
 }
 
 __global__ __launch_bounds__(64) void k_gap_final(const double* __restrict__ part, int pstride,
                                                   int nb_m, GapState* __restrict__ gs) {
   const int b = blockIdx.x;
-  const double conj = wave_fixed_sum(part + ((int64_t)b * 4 + 3) * pstride, nb_m, 1);
+  const double conj = wave_fixed_sum(part + ((int64_t)b * kGapSlots + 3) * pstride, nb_m, 1);
   if (threadIdx.x == 0) {
     GapState& G = gs[b];
-    G.dual = -conj;
+    G.dual = -conj + G.reg;
     const double den = fmin(G.primal, fabs(G.dual));
     G.gap = G.primal - G.dual;
     G.rel_gap = den > 0.0 ? G.gap / den : (G.gap == 0.0 ? 0.0 : INFINITY);
@@ -211,7 +232,7 @@ hipError_t gap_after_t_vt(const GapArgs& a, hipStream_t st) {
   const int nbm = gap_blocks(a.m), nbn = gap_blocks(a.n);
   hipLaunchKernelGGL((k_gap_inf<VT>), dim3(nbn, (unsigned)a.batch), dim3(kGapThreads), 0, st,
                      a.n, static_cast<const VT*>(a.ypart), a.ks, a.ks_stride, a.yprob,
-                     static_cast<const VT*>(a.v), a.part, kGapPStride);
+                     static_cast<const VT*>(a.v), a.params, a.part, kGapPStride);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gap_kappa, dim3((unsigned)a.batch), dim3(64), 0, st, a.part, kGapPStride,

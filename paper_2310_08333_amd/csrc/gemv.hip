@@ -612,38 +612,6 @@ __global__ __launch_bounds__(256) void k_cast_bf16(const float* __restrict__ src
   }
 }
 
-// ---- streaming read (measurement reference) ------------------------------------
-// Reads `words` 16-byte words once, four independent loads in flight per thread,
-// and writes the XOR of each block's words to out[block], so no load is dead.
-__global__ __launch_bounds__(256) void k_stream_read(const uint4* __restrict__ p, int64_t words,
-                                                     uint32_t* __restrict__ out) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t acc = 0;
-  for (; i + 3 * stride < words; i += 4 * stride) {
-    const uint4 a = p[i], b = p[i + stride], c = p[i + 2 * stride], d = p[i + 3 * stride];
-    acc ^= (a.x ^ a.y ^ a.z ^ a.w) ^ (b.x ^ b.y ^ b.z ^ b.w) ^ (c.x ^ c.y ^ c.z ^ c.w) ^
-           (d.x ^ d.y ^ d.z ^ d.w);
-  }
-  for (; i < words; i += stride) {
-    const uint4 a = p[i];
-    acc ^= a.x ^ a.y ^ a.z ^ a.w;
-  }
-  __shared__ uint32_t red[4];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) acc ^= (uint32_t)__shfl_xor((int)acc, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) out[blockIdx.x] = red[0] ^ red[1] ^ red[2] ^ red[3];
-}
-
-hipError_t launch_stream_read(const void* p, int64_t bytes, uint32_t* out, int blocks,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(k_stream_read, dim3((unsigned)blocks), dim3(256), 0, st,
-                     static_cast<const uint4*>(p), bytes / 16, out);
-  return hipGetLastError();
-}
-
 hipError_t launch_cast_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   const int64_t groups = (count + 7) / 8;

@@ -43,6 +43,7 @@ struct alignas(128) ProbParams {
   double rtol;       // CG relative tolerance of this iteration
   double tol_floor;  // CG tolerance floor, relative to ||rhs||
   double lambda;
+  double lambda2;    // (lambda2 / 2) ||x||^2 in the loss: grad f gains lambda2 x
   int32_t run;       // problem takes part in this iteration
   int32_t max_cg;
   int32_t rhs_rel;   // 1: tolerance relative to ||rhs||, 0: relative to ||r_0||
@@ -162,6 +163,8 @@ hipError_t launch_sum_splits(VType vt, int64_t batch, int64_t len, const void* i
                              const int32_t* gate = nullptr, int gate_stride = 0);
 
 hipError_t launch_cast_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t st);
+// Streaming-read reference (stream.hip): blocks for `bytes` on `cus` CUs, at most max_blocks.
+int stream_read_blocks(int64_t bytes, int cus, int max_blocks);
 hipError_t launch_stream_read(const void* p, int64_t bytes, uint32_t* out, int blocks,
                               hipStream_t st);
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);  // zero fill (no memset nodes)
@@ -212,13 +215,17 @@ struct GapState {
   double loss;      // sum_i f(t_i)
   double grad_inf;  // ||A^T f'(t)||_inf
   double l1;        // ||v||_1
-  double kappa;     // min(1, lambda / grad_inf)
-  double primal;    // l(v) = loss + lambda ||v||_1
+  double x2;        // ||v||^2
+  double excess2;   // ||(|A^T f'(t)| - lambda)_+||^2
+  double kappa;     // lambda2 = 0: min(1, lambda / grad_inf); lambda2 > 0: 1
+  double reg;       // lambda2 > 0: -excess2 / (2 lambda2), the dual's l2 part; else 0
+  double primal;    // l(v) = loss + lambda ||v||_1 + (lambda2 / 2) ||v||^2
   double dual;      // g(nu)
   double gap;       // primal - dual
   double rel_gap;   // gap / min(primal, |dual|)
 };
 constexpr int kGapPStride = 256;  // block partials per reduction and problem
+constexpr int kGapSlots = 6;      // loss, inf, l1, conjugate sum, x2, excess2
 struct GapArgs {
   VType vt;
   int64_t m, n, batch;
@@ -234,7 +241,7 @@ struct GapArgs {
   int64_t ks_stride, yprob;
   const void* v;       // the point, n per problem
   const ProbParams* params;  // lambda
-  double* part;        // [batch][4][kGapPStride]
+  double* part;        // [batch][kGapSlots][kGapPStride]
   GapState* state;     // [batch]
 };
 int gap_blocks(int64_t len);

@@ -317,3 +317,95 @@ def test_logreg_duality_gap_termination(g, logsmall):
     assert rel <= eps_gap * 1.05, rel
     F = ologreg.objective(P["A"], P["y"], P["lam"], z)
     assert (F - P["sol"]["F"]) / P["sol"]["F"] <= rel + 1e-9
+
+
+# ---- elastic net: the l2 term (Sec. 4.1, App. A with lambda2 > 0) ----
+
+@pytest.fixture(scope="module")
+def cfg1_en(cfg1):
+    P = dict(cfg1)
+    P["lam2"] = 0.3
+    P["sol_en"] = olasso.solve(P["A"], P["b"], P["lam"], lam2=P["lam2"])
+    return P
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16_refine"])
+def test_elastic_net_objective_residuals_and_gap(g, cfg1_en, prec):
+    print("elastic net", prec, flush=True)
+    P = cfg1_en
+    lam2 = P["lam2"]
+    A = P["A"].astype(np.float64) if prec == "f64" else P["A"]
+    b = P["b"].astype(np.float64) if prec == "f64" else P["b"]
+    eps = 1e-8 if prec == "f64" else 1e-5
+    out = g.lasso_solve(_t(A), _t(b), P["lam"], precision=prec, eps=eps, sketch_rank=P["s"],
+                        lambda2=lam2)
+    info = out["info"][0]
+    assert out["status"] == 0, info
+    A64, b64 = P["A"].astype(np.float64), P["b"].astype(np.float64)
+    z = out["z"].cpu().numpy().astype(np.float64)
+    F = olasso.objective(A64, b64, P["lam"], z, lam2)
+    Fs = P["sol_en"]["F"]
+    assert _rel(F, Fs) <= (1e-10 if prec == "f64" else 1e-6), (F, Fs)
+    assert _rel(info["obj"], F) <= (1e-12 if prec == "f64" else 1e-5)
+    # the residuals of Sec. 2.3 with grad f = A^T (A x - b) + lambda2 x
+    x = out["x"].cpu().numpy().astype(np.float64)
+    u = out["u"].cpu().numpy().astype(np.float64)
+    rk, rp, rd = ores.r_kkt(x, z, u, info["rho"], olasso.grad_f(A64, b64, x, lam2))
+    assert rk <= eps * 1.01
+    tol = 1e-11 if prec == "f64" else 2e-6
+    _, pr, du = olasso.duality_gap(A64, b64, P["lam"], z, lam2)
+    assert abs(info["gap_primal"] - pr) <= tol * abs(pr), (info["gap_primal"], pr)
+    assert abs(info["gap_dual"] - du) <= tol * abs(du), (info["gap_dual"], du)
+
+
+def test_elastic_net_gap_termination(g, cfg1_en):
+    print("elastic net gap termination", flush=True)
+    P = cfg1_en
+    eps_gap = 1e-5
+    out = g.lasso_solve(_t(P["A"]), _t(P["b"]), P["lam"], precision="f32", termination=1,
+                        eps_gap=eps_gap, sketch_rank=P["s"], lambda2=P["lam2"], max_iter=5000)
+    info = out["info"][0]
+    assert out["status"] == 0 and info["rel_gap"] <= eps_gap * 1.05, info
+    A64, b64 = P["A"].astype(np.float64), P["b"].astype(np.float64)
+    z = out["z"].cpu().numpy().astype(np.float64)
+    rel = olasso.relative_gap(A64, b64, P["lam"], z, P["lam2"])
+    assert rel <= eps_gap * 1.05 + 2e-6, rel
+    F = olasso.objective(A64, b64, P["lam"], z, P["lam2"])
+    assert (F - P["sol_en"]["F"]) / P["sol_en"]["F"] <= rel + 1e-12
+
+
+def test_logreg_l2_objective_and_gap(g, logsmall):
+    print("logreg l2", flush=True)
+    P = logsmall
+    lam2 = 0.5
+    sol = ologreg.solve(P["A"], P["y"], P["lam"], lam2=lam2)
+    out = g.logreg_solve(_t(P["A"]), _t(P["y"]), P["lam"], precision="f32", eps=1e-5,
+                         sketch_rank=P["s"], resketch_every=20, lambda2=lam2)
+    info = out["info"][0]
+    assert out["status"] == 0, info
+    z = out["z"].cpu().numpy().astype(np.float64)
+    F = ologreg.objective(P["A"], P["y"], P["lam"], z, lam2)
+    assert _rel(F, sol["F"]) <= 1e-6, (F, sol["F"])
+    _, pr, du = ologreg.duality_gap(P["A"], P["y"], P["lam"], z, lam2)
+    assert abs(info["gap_primal"] - pr) <= 2e-6 * abs(pr)
+    assert abs(info["gap_dual"] - du) <= 2e-6 * abs(du)
+
+
+def test_elastic_net_backward_fp64_vs_oracle_adjoint(g):
+    print("elastic net backward f64", flush=True)
+    P = genios_data.lasso_decay(120, 300, 8, seed=31, s=16)
+    A64 = P["A"].astype(np.float64)
+    lam2 = 0.2
+    out = g.lasso_solve(_t(A64), _t(P["b"].astype(np.float64)), P["lam"], precision="f64",
+                        eps=1e-10, sketch_rank=16, lambda2=lam2, max_iter=20000)
+    assert out["status"] == 0, out["info"][0]
+    z = out["z"]
+    gz = (2.0 * (z - _t(P["x0"].astype(np.float64)))).contiguous()
+    grad_b, grad_lam, info = g.lasso_backward(_t(A64), z, gz, P["lam"], sketch_rank=16,
+                                              lambda2=lam2, cg_tol_floor=1e-13)
+    assert info[0]["status"] == 0, info
+    zn = z.cpu().numpy()
+    db, dl, _ = oadj.lasso_adjoint(A64, zn, gz.cpu().numpy(), lam2)
+    got = grad_b.cpu().numpy()
+    assert np.linalg.norm(got - db) <= 1e-9 * np.linalg.norm(db), info
+    assert abs(float(grad_lam[0]) - dl) <= 1e-9 * abs(dl)

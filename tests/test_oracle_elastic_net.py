@@ -73,3 +73,25 @@ def test_lam2_zero_is_the_lasso():
     x = np.random.default_rng(8).standard_normal(15)
     assert lasso.objective(A, b, lam, x, 0.0) == lasso.objective(A, b, lam, x)
     assert lasso.duality_gap(A, b, lam, x, 0.0) == lasso.duality_gap(A, b, lam, x)
+
+
+def test_adjoint_with_l2_matches_central_differences():
+    # L = ||x* - x0||^2: x* is affine in (b, lam) on a fixed support, so central
+    # differences of the certified solution map are exact up to solver error
+    from oracle import adjoint
+    A, b = _data(30, 12, 9)
+    lam = 0.15 * np.max(np.abs(A.T @ b))
+    lam2 = 0.25
+    x0 = np.random.default_rng(10).standard_normal(12)
+    sol = lasso.solve(A, b, lam, lam2=lam2)
+    assert adjoint.strict_complementarity_margin(A, b, lam, sol["x"]) > 1e-3
+    gb, gl, _ = adjoint.lasso_adjoint(A, sol["x"], 2.0 * (sol["x"] - x0), lam2)
+    L = lambda bb, ll: float(np.sum((lasso.solve(A, bb, ll, lam2=lam2)["x"] - x0) ** 2))
+    h = 1e-4
+    for i in (0, 5, 17):
+        e = np.zeros(30)
+        e[i] = h
+        fd = (L(b + e, lam) - L(b - e, lam)) / (2 * h)
+        assert abs(fd - gb[i]) <= 1e-6 * (1 + abs(gb[i]))
+    fdl = (L(b, lam + h) - L(b, lam - h)) / (2 * h)
+    assert abs(fdl - gl) <= 1e-6 * (1 + abs(gl))
