@@ -166,6 +166,31 @@ def logreg_factor(m: int = 20000, n: int = 5000, nnz_frac: float = 0.02, rank: i
                 name=f"logreg_factor_{m}x{n}")
 
 
+def huber_outliers(n: int = 2000, seed: int = 6, s: int = 0) -> dict:
+    """Huber-fitting data (the paper's recipe): N = n/2 samples of n iid N(0, 1)
+    features, columns centred and scaled to unit l2 norm; x0 with 10 % N(0, 1)
+    nonzeros; b = A x0 + 0.1 v, then 5 % of the entries shifted by +-10;
+    lam = 0.1 ||A^T b||_inf.  s = 0: the paper runs this problem unpreconditioned."""
+    m = n // 2
+    G = _gaussian_rows(seed, _STREAM_MATRIX, m, n).astype(np.float64)
+    G -= G.mean(axis=0, keepdims=True)
+    G /= np.linalg.norm(G, axis=0, keepdims=True)
+    A = G.astype(np.float32)
+    del G
+    rng = np.random.default_rng([seed, _STREAM_MISC])
+    k = max(1, n // 10)
+    supp = np.sort(rng.choice(n, size=k, replace=False))
+    x0 = np.zeros(n)
+    x0[supp] = rng.standard_normal(k)
+    b64 = A[:, supp].astype(np.float64) @ x0[supp] + 0.1 * rng.standard_normal(m)
+    out = np.sort(rng.choice(m, size=max(1, m // 20), replace=False))
+    b64[out] += rng.choice(np.array([-10.0, 10.0]), size=out.size)
+    b = b64.astype(np.float32)
+    lam = 0.1 * float(np.max(np.abs(rmatvec_f64(A, b))))
+    return dict(kind="huber", A=A, b=b, lam=lam, x0=x0, s=s, rho=1.0, delta=1.0,
+                name=f"huber_{m}x{n}")
+
+
 def lasso_batch(batch: int = 64, m: int = 2000, n: int = 8000, k: int = 80,
                 seed0: int = 5000, s: int = 50) -> dict:
     """`batch` independent decaying-spectrum Lasso problems, problem j seeded seed0 + j."""
