@@ -83,7 +83,8 @@ typedef enum {
   GENIOS_OP_NYSTROM = 2,
   GENIOS_OP_BACKWARD = 3,
   GENIOS_OP_MATVEC = 4,
-  GENIOS_OP_HVP = 5
+  GENIOS_OP_HVP = 5,
+  GENIOS_OP_HUBER = 6
 } genios_op;
 
 /* Dense data matrix (or a batch of them).  m rows (samples) by n columns
@@ -148,6 +149,9 @@ typedef struct {
   double lambda2;              /* (lambda2 / 2) ||x||^2 added to the loss (elastic net, Sec. 4.1,
                                   App. A), >= 0, default 0; the x-system shift becomes
                                   rho + sigma + lambda2, the adjoint's lambda2 */
+  double huber_delta;          /* genios_huber_solve: the loss is quadratic for |r| <= delta and
+                                  linear beyond, l(r) = r^2 or 2 delta |r| - delta^2 (Sec. 4.3
+                                  uses delta = 1, the default); > 0 */
 } genios_opts;
 
 /* Per-iteration history row layout (doubles); problem p, iteration k (1-based)
@@ -238,6 +242,17 @@ int genios_lasso_solve(const genios_matrix* A, const void* b, const double* lamb
  * arguments as genios_lasso_solve. */
 int genios_logreg_solve(const genios_matrix* A, const void* y, const double* lambda, double rho,
                         const genios_opts* o, void* x, void* z, void* u, genios_info* info);
+
+/* l1-regularised Huber fitting (Sec. 4.3, Huber fitting, with the machine-learning
+ * interface of Sec. 3.3):
+ *   minimize sum_i l(a_i^T x - b_i) + lambda ||x||_1 (+ (lambda2 / 2) ||x||^2),
+ *   l(r) = r^2 for |r| <= delta, 2 delta |r| - delta^2 otherwise, delta = opts->huber_delta.
+ * The x-system uses H = A^T D A with D = l''(A x^k - b) = 2 [|r_i| <= delta]; the
+ * Nystrom sketch of it (opts->precondition, off in the paper's Huber runs) is refreshed
+ * every opts->resketch_every iterations.  The duality gap uses l*(v) = v^2 / 4 on
+ * |v| <= 2 delta (App. A).  b m per problem; other arguments as genios_lasso_solve. */
+int genios_huber_solve(const genios_matrix* A, const void* b, const double* lambda, double rho,
+                       const genios_opts* o, void* x, void* z, void* u, genios_info* info);
 
 /* Randomized Nystrom approximation (Sec. 2.2) of H = A^T diag(d) A (d == NULL:
  * H = A^T A) with an n x s test matrix Omega:

@@ -7,7 +7,9 @@ kernels; importing this package fails if the library has not been built.
 
 Functions
 ---------
-lasso_solve, logreg_solve      the solvers (Sec. 3.1 / Sec. 4.1 Lasso, Sec. 4.2 logistic)
+lasso_solve, logreg_solve, huber_solve
+                               the solvers (Sec. 3.1 / Sec. 4.1 Lasso, Sec. 4.2 logistic,
+                               Sec. 4.3 Huber fitting)
 nystrom_build, nystrom_apply   the randomized Nystrom preconditioner (Sec. 2.2)
 lasso_backward, GeniosLasso    adjoint of the Lasso solution map (torch.autograd.Function)
 matvec, cast_bf16, gaussian_matrix, admm_update   single-kernel entry points
@@ -22,7 +24,7 @@ import torch
 from . import _abi
 from ._abi import GeniosError, Info
 
-__all__ = ["lasso_solve", "logreg_solve", "nystrom_build", "nystrom_apply", "lasso_backward",
+__all__ = ["lasso_solve", "logreg_solve", "huber_solve", "nystrom_build", "nystrom_apply", "lasso_backward",
            "GeniosLasso", "lasso", "matvec", "cast_bf16", "gaussian_matrix", "admm_update",
            "workspace_size", "make_opts", "GeniosError"]
 
@@ -104,7 +106,7 @@ def _solve(kind, A, vec, lam, rho, A16, x0, z0, u0, history, **kw):
     M = _matrix(A, A16)
     o = make_opts(A.dtype, **kw)
     B, m, n = M.batch, M.m, M.n
-    _check_vec(vec, "b" if kind == "lasso" else "y", A.dtype, B * m, dev)
+    _check_vec(vec, "y" if kind == "logreg" else "b", A.dtype, B * m, dev)
     lam_h = np.ascontiguousarray(np.broadcast_to(np.asarray(lam, dtype=np.float64), (B,)))
     shape = (n,) if A.dim() == 2 else (B, n)
     if x0 is not None:
@@ -119,10 +121,10 @@ def _solve(kind, A, vec, lam, rho, A16, x0, z0, u0, history, **kw):
         hist = np.zeros((B, int(history), _abi.HIST_FIELDS))
         o.history = hist.ctypes.data_as(C.POINTER(C.c_double))
         o.history_cap = int(history)
-    op = _abi.OP_LASSO if kind == "lasso" else _abi.OP_LOGREG
+    op = {"lasso": _abi.OP_LASSO, "logreg": _abi.OP_LOGREG, "huber": _abi.OP_HUBER}[kind]
     ws = _attach_workspace(o, workspace_size(op, M, o), dev)
     infos = (Info * B)()
-    fn = _lib.genios_lasso_solve if kind == "lasso" else _lib.genios_logreg_solve
+    fn = getattr(_lib, f"genios_{kind}_solve")
     rc = fn(C.byref(M), _ptr(vec), lam_h.ctypes.data_as(C.POINTER(C.c_double)), float(rho),
             C.byref(o), _ptr(x), _ptr(z), _ptr(u), infos)
     del ws
@@ -148,6 +150,12 @@ def lasso_solve(A, b, lam, rho=1.0, A16=None, x0=None, z0=None, u0=None, history
 def logreg_solve(A, y, lam, rho=1.0, A16=None, x0=None, z0=None, u0=None, history=0, **kw):
     """l1-logistic regression sum log(1 + exp(-y_i a_i^T x)) + lam ||x||_1 (labels +-1)."""
     return _solve("logreg", A, y, lam, rho, A16, x0, z0, u0, history, **kw)
+
+
+def huber_solve(A, b, lam, rho=1.0, A16=None, x0=None, z0=None, u0=None, history=0, **kw):
+    """l1-regularised Huber fitting sum l(a_i^T x - b_i) + lam ||x||_1, l(r) = r^2 for
+    |r| <= huber_delta (default 1), 2 delta |r| - delta^2 beyond (Sec. 4.3)."""
+    return _solve("huber", A, b, lam, rho, A16, x0, z0, u0, history, **kw)
 
 
 def nystrom_build(A, s, d=None, omega=None, A16=None, **kw):

@@ -24,7 +24,7 @@ ERR_UNSUPPORTED = -7
 
 DT_F32, DT_BF16, DT_F64 = 0, 1, 2
 PREC_F64, PREC_F32, PREC_BF16_REFINE, PREC_BF16_ONLY = 0, 1, 2, 3
-OP_LASSO, OP_LOGREG, OP_NYSTROM, OP_BACKWARD, OP_MATVEC, OP_HVP = 0, 1, 2, 3, 4, 5
+OP_LASSO, OP_LOGREG, OP_NYSTROM, OP_BACKWARD, OP_MATVEC, OP_HVP, OP_HUBER = 0, 1, 2, 3, 4, 5, 6
 
 HIST_FIELDS = 10
 HIST_NAMES = ("k", "r_p", "r_d", "r_kkt", "rho", "cg", "rtol", "phase", "time", "xnorm")
@@ -57,7 +57,8 @@ class Opts(C.Structure):
                 ("stream", C.c_void_p),
                 ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
                 ("termination", C.c_int32), ("gap_every", C.c_int32),
-                ("eps_gap", C.c_double), ("lambda2", C.c_double)]
+                ("eps_gap", C.c_double), ("lambda2", C.c_double),
+                ("huber_delta", C.c_double)]
 
 
 class Info(C.Structure):
@@ -86,6 +87,7 @@ class Info(C.Structure):
 
 EXPORTED = (
     "genios_default_opts", "genios_workspace_size", "genios_lasso_solve", "genios_logreg_solve",
+    "genios_huber_solve",
     "genios_nystrom_build", "genios_nystrom_apply", "genios_lasso_backward", "genios_matvec",
     "genios_hvp",
     "genios_cast_bf16", "genios_stream_read", "genios_gaussian_matrix", "genios_admm_update", "genios_status_string",
@@ -111,7 +113,7 @@ def load(path: str | None = None):
     lib.genios_default_opts.restype = C.c_int
     lib.genios_workspace_size.argtypes = [C.c_int, P(Matrix), P(Opts)]
     lib.genios_workspace_size.restype = C.c_size_t
-    for name in ("genios_lasso_solve", "genios_logreg_solve"):
+    for name in ("genios_lasso_solve", "genios_logreg_solve", "genios_huber_solve"):
         f = getattr(lib, name)
         f.argtypes = [P(Matrix), vp, P(dbl), dbl, P(Opts), vp, vp, vp, P(Info)]
         f.restype = C.c_int

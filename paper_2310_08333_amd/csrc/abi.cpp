@@ -50,6 +50,8 @@ int check_opts(const genios_opts* o) {
   if (!(o->eps_gap > 0.0) || !std::isfinite(o->eps_gap)) FAIL(GENIOS_ERR_ARG, "eps_gap must be > 0");
   if (!(o->lambda2 >= 0.0) || !std::isfinite(o->lambda2))
     FAIL(GENIOS_ERR_ARG, "lambda2 must be finite and >= 0");
+  if (!(o->huber_delta > 0.0) || !std::isfinite(o->huber_delta))
+    FAIL(GENIOS_ERR_ARG, "huber_delta must be finite and > 0");
   return GENIOS_OK;
 }
 
@@ -140,6 +142,7 @@ int genios_default_opts(genios_opts* o) {
   o->gap_every = 1;
   o->eps_gap = 1e-4;
   o->lambda2 = 0.0;
+  o->huber_delta = 1.0;
   return GENIOS_OK;
 }
 
@@ -155,6 +158,7 @@ size_t genios_workspace_size(int op, const genios_matrix* A, const genios_opts* 
   switch (op) {
     case GENIOS_OP_LASSO:
     case GENIOS_OP_LOGREG:
+    case GENIOS_OP_HUBER:
     case GENIOS_OP_BACKWARD:
       s = o->precondition ? effective_rank(o, A->n, A->m) : 0;
       break;
@@ -182,7 +186,7 @@ int genios_lasso_solve(const genios_matrix* A, const void* b, const double* lamb
   if ((rc = check_lambda(lambda, A->batch))) return rc;
   if (!(rho > 0.0) || !std::isfinite(rho)) FAIL(GENIOS_ERR_ARG, "rho must be finite and > 0");
   if ((rc = check_ws(GENIOS_OP_LASSO, A, o))) return rc;
-  return run_admm(A, b, lambda, rho, o, x, z, u, info, false);
+  return run_admm(A, b, lambda, rho, o, x, z, u, info, kLossSquare);
 }
 
 int genios_logreg_solve(const genios_matrix* A, const void* y, const double* lambda, double rho,
@@ -195,7 +199,20 @@ int genios_logreg_solve(const genios_matrix* A, const void* y, const double* lam
   if ((rc = check_lambda(lambda, A->batch))) return rc;
   if (!(rho > 0.0) || !std::isfinite(rho)) FAIL(GENIOS_ERR_ARG, "rho must be finite and > 0");
   if ((rc = check_ws(GENIOS_OP_LOGREG, A, o))) return rc;
-  return run_admm(A, y, lambda, rho, o, x, z, u, info, true);
+  return run_admm(A, y, lambda, rho, o, x, z, u, info, kLossLogistic);
+}
+
+int genios_huber_solve(const genios_matrix* A, const void* b, const double* lambda, double rho,
+                       const genios_opts* o, void* x, void* z, void* u, genios_info* info) {
+  int rc;
+  if ((rc = check_matrix(A)) || (rc = check_opts(o)) || (rc = check_precision_vs_dtype(A, o)))
+    return rc;
+  if (b == nullptr || x == nullptr || z == nullptr || u == nullptr || info == nullptr)
+    FAIL(GENIOS_ERR_ARG, "b, x, z, u and info must be non-NULL");
+  if ((rc = check_lambda(lambda, A->batch))) return rc;
+  if (!(rho > 0.0) || !std::isfinite(rho)) FAIL(GENIOS_ERR_ARG, "rho must be finite and > 0");
+  if ((rc = check_ws(GENIOS_OP_HUBER, A, o))) return rc;
+  return run_admm(A, b, lambda, rho, o, x, z, u, info, kLossHuber);
 }
 
 int genios_nystrom_build(const genios_matrix* A, const void* d, int32_t s, const void* omega,

@@ -585,8 +585,8 @@ template <typename VT>
 __global__ __launch_bounds__(256) void k_objective_m(int64_t m, const VT* __restrict__ tparts,
                                                      int nsplit, int64_t split_stride,
                                                      int64_t prob_stride,
-                                                     const VT* __restrict__ bvec, int logistic,
-                                                     Ctrl ctrl, int nb) {
+                                                     const VT* __restrict__ bvec, int loss,
+                                                     double delta, Ctrl ctrl, int nb) {
   const int b = blockIdx.y;
   const int64_t chunk = (m + nb - 1) / nb;
   const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(m, lo + chunk);
@@ -597,9 +597,12 @@ __global__ __launch_bounds__(256) void k_objective_m(int64_t m, const VT* __rest
     for (int k = 0; k < nsplit; ++k)
       t += double(tparts[(int64_t)b * prob_stride + (int64_t)k * split_stride + i]);
     const double bi = double(bvec[(int64_t)b * m + i]);
-    if (logistic) {
+    if (loss == kLossLogistic) {
       const double w = -bi * t;  // log(1 + e^w), computed stably
       s += (w > 0.0 ? w + log1p(exp(-w)) : log1p(exp(w)));
+    } else if (loss == kLossHuber) {
+      const double r = t - bi, a = fabs(r);
+      s += a <= delta ? r * r : 2.0 * delta * a - delta * delta;
     } else {
       s += 0.5 * (t - bi) * (t - bi);
     }
@@ -614,35 +617,45 @@ __global__ __launch_bounds__(256) void k_objective_m(int64_t m, const VT* __rest
   if (threadIdx.x == 0) ctrl.state[b].red[kRedAux] = tv[0];
 }
 
-// Logistic elementwise terms: w = -y t, s = sigmoid(w), d = s (1 - s),
-// col0 = d o t (for H x), col1 = -y o s (for grad f).
-template <typename VT>
-__global__ __launch_bounds__(256) void k_logistic_elem(int64_t m, const VT* __restrict__ tparts,
-                                                       int nsplit, int64_t split_stride,
-                                                       int64_t prob_stride,
-                                                       const VT* __restrict__ y,
-                                                       VT* __restrict__ d, VT* __restrict__ cols,
-                                                       int64_t col_stride,
-                                                       const int32_t* __restrict__ gate,
-                                                       int gate_stride) {
+// Elementwise terms of the ML x-system: d = f''(t), col0 = d o t (for H x),
+// col1 = f'(t) (for grad f).  Logistic (LOSS = kLossLogistic): w = -y t,
+// s = sigmoid(w), d = s (1 - s), f' = -y s.  Huber: r = t - b, d = 2 [|r| <= delta],
+// f' = 2 clip(r, -delta, delta).
+template <typename VT, int LOSS>
+__global__ __launch_bounds__(256) void k_loss_elem(int64_t m, const VT* __restrict__ tparts,
+                                                   int nsplit, int64_t split_stride,
+                                                   int64_t prob_stride,
+                                                   const VT* __restrict__ bv, VT delta,
+                                                   VT* __restrict__ d, VT* __restrict__ cols,
+                                                   int64_t col_stride,
+                                                   const int32_t* __restrict__ gate,
+                                                   int gate_stride) {
   const int b = blockIdx.y;
   if (gate != nullptr && gate[(int64_t)b * gate_stride] == 0) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
        i += (int64_t)gridDim.x * blockDim.x) {
     VT t = VT(0);
     for (int k = 0; k < nsplit; ++k) t += tparts[(int64_t)b * prob_stride + (int64_t)k * split_stride + i];
-    const VT yi = y[(int64_t)b * m + i];
-    const VT w = -yi * t;
-    VT s;
-    if constexpr (sizeof(VT) == 4)
-      s = 1.0f / (1.0f + expf(-w));
-    else
-      s = 1.0 / (1.0 + exp(-w));
-    const VT di = s * (VT(1) - s);
+    const VT bi = bv[(int64_t)b * m + i];
+    VT di, fi;
+    if constexpr (LOSS == kLossLogistic) {
+      const VT w = -bi * t;
+      VT s;
+      if constexpr (sizeof(VT) == 4)
+        s = 1.0f / (1.0f + expf(-w));
+      else
+        s = 1.0 / (1.0 + exp(-w));
+      di = s * (VT(1) - s);
+      fi = -bi * s;
+    } else {
+      const VT r = t - bi;
+      di = fabs(r) <= delta ? VT(2) : VT(0);
+      fi = VT(2) * fmin(fmax(r, -delta), delta);
+    }
     d[(int64_t)b * m + i] = di;
     VT* cb = cols + (int64_t)b * 2 * col_stride;
     cb[i] = di * t;
-    cb[col_stride + i] = -yi * s;
+    cb[col_stride + i] = fi;
   }
 }
 
@@ -840,36 +853,54 @@ static int m_blocks(int64_t m) {
 
 hipError_t launch_objective_m(VType vt, int64_t m, int64_t batch, const void* tparts, int nsplit,
                               int64_t split_stride, int64_t prob_stride, const void* bvec,
-                              int logistic, Ctrl ctrl, hipStream_t st) {
+                              int loss, double delta, Ctrl ctrl, hipStream_t st) {
   const int nb = m_blocks(m);
   dim3 grid((unsigned)nb, (unsigned)batch);
   if (vt == VT_F32)
     hipLaunchKernelGGL(k_objective_m<float>, grid, dim3(256), 0, st, m,
                        static_cast<const float*>(tparts), nsplit, split_stride, prob_stride,
-                       static_cast<const float*>(bvec), logistic, ctrl, nb);
+                       static_cast<const float*>(bvec), loss, delta, ctrl, nb);
   else
     hipLaunchKernelGGL(k_objective_m<double>, grid, dim3(256), 0, st, m,
                        static_cast<const double*>(tparts), nsplit, split_stride, prob_stride,
-                       static_cast<const double*>(bvec), logistic, ctrl, nb);
+                       static_cast<const double*>(bvec), loss, delta, ctrl, nb);
   return hipGetLastError();
 }
 
-hipError_t launch_logistic_elem(VType vt, int64_t m, int64_t batch, const void* tparts, int nsplit,
-                                int64_t split_stride, int64_t prob_stride, const void* y, void* d,
-                                void* cols, int64_t col_stride, const int32_t* gate,
-                                int gate_stride, hipStream_t st) {
+template <typename VT, int LOSS>
+static void loss_elem_vt(dim3 grid, int64_t m, const void* tparts, int nsplit,
+                         int64_t split_stride, int64_t prob_stride, const void* bvec, double delta,
+                         void* d, void* cols, int64_t col_stride, const int32_t* gate,
+                         int gate_stride, hipStream_t st) {
+  hipLaunchKernelGGL((k_loss_elem<VT, LOSS>), grid, dim3(256), 0, st, m,
+                     static_cast<const VT*>(tparts), nsplit, split_stride, prob_stride,
+                     static_cast<const VT*>(bvec), VT(delta), static_cast<VT*>(d),
+                     static_cast<VT*>(cols), col_stride, gate, gate_stride);
+}
+
+hipError_t launch_loss_elem(VType vt, int loss, double delta, int64_t m, int64_t batch,
+                            const void* tparts, int nsplit, int64_t split_stride,
+                            int64_t prob_stride, const void* bvec, void* d, void* cols,
+                            int64_t col_stride, const int32_t* gate, int gate_stride,
+                            hipStream_t st) {
+  if (loss != kLossLogistic && loss != kLossHuber) return hipErrorInvalidValue;
   const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((m + 255) / 256, 512));
   dim3 grid(nb, (unsigned)batch);
-  if (vt == VT_F32)
-    hipLaunchKernelGGL(k_logistic_elem<float>, grid, dim3(256), 0, st, m,
-                       static_cast<const float*>(tparts), nsplit, split_stride, prob_stride,
-                       static_cast<const float*>(y), static_cast<float*>(d),
-                       static_cast<float*>(cols), col_stride, gate, gate_stride);
-  else
-    hipLaunchKernelGGL(k_logistic_elem<double>, grid, dim3(256), 0, st, m,
-                       static_cast<const double*>(tparts), nsplit, split_stride, prob_stride,
-                       static_cast<const double*>(y), static_cast<double*>(d),
-                       static_cast<double*>(cols), col_stride, gate, gate_stride);
+  if (vt == VT_F32) {
+    if (loss == kLossLogistic)
+      loss_elem_vt<float, kLossLogistic>(grid, m, tparts, nsplit, split_stride, prob_stride, bvec,
+                                         delta, d, cols, col_stride, gate, gate_stride, st);
+    else
+      loss_elem_vt<float, kLossHuber>(grid, m, tparts, nsplit, split_stride, prob_stride, bvec,
+                                      delta, d, cols, col_stride, gate, gate_stride, st);
+  } else {
+    if (loss == kLossLogistic)
+      loss_elem_vt<double, kLossLogistic>(grid, m, tparts, nsplit, split_stride, prob_stride,
+                                          bvec, delta, d, cols, col_stride, gate, gate_stride, st);
+    else
+      loss_elem_vt<double, kLossHuber>(grid, m, tparts, nsplit, split_stride, prob_stride, bvec,
+                                       delta, d, cols, col_stride, gate, gate_stride, st);
+  }
   return hipGetLastError();
 }
 

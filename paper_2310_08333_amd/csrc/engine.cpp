@@ -4,7 +4,7 @@
 // GPU needs (CG alpha/beta, tolerances, preconditioner coefficients) live in
 // per-problem device control blocks; each kernel of a CG iteration is gated by
 // the problem's `cg_active` flag, so the host can enqueue several CG
-// iterations, the fused z/u update and (for logistic regression) the next
+// iterations, the fused z/u update and (for the logistic and Huber losses) the next
 // gradient pass without waiting.  The host synchronises once per ADMM
 // iteration (more only when a CG solve outlasts its enqueued iterations) to
 // read the residual norms, apply the stopping test and the penalty rule of
@@ -113,7 +113,7 @@ void Layout::carve(Arena& ar) {
     gpart = static_cast<double*>(ar.take((size_t)B * kGapSlots * kGapPStride * sizeof(double)));
     gstate = static_cast<GapState*>(ar.take((size_t)B * sizeof(GapState)));
   }
-  if (logistic || backward) {
+  if (ml || backward) {
     dvec = vec(m);
     cols = ar.take((size_t)B * 2 * m * ve);
   }
@@ -150,12 +150,12 @@ int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_)
   n = A->n;
   batch = A->batch;
   vt = A->hi_dtype == GENIOS_DT_F64 ? VT_F64 : VT_F32;
-  logistic = op == GENIOS_OP_LOGREG;
+  ml = op == GENIOS_OP_LOGREG || op == GENIOS_OP_HUBER;
   backward = op == GENIOS_OP_BACKWARD;
-  gap = op == GENIOS_OP_LASSO || op == GENIOS_OP_LOGREG;
+  gap = op == GENIOS_OP_LASSO || ml;
   s = s_;
   const int prec = o->precision;
-  const bool uses_lo = (op == GENIOS_OP_LASSO || op == GENIOS_OP_LOGREG || op == GENIOS_OP_NYSTROM ||
+  const bool uses_lo = (op == GENIOS_OP_LASSO || ml || op == GENIOS_OP_NYSTROM ||
                         op == GENIOS_OP_MATVEC || op == GENIOS_OP_HVP) &&
                        (prec == GENIOS_PREC_BF16_REFINE || prec == GENIOS_PREC_BF16_ONLY);
   need_a16 = uses_lo && A->A_bf16 == nullptr;
@@ -164,12 +164,12 @@ int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_)
   MatArg probe{nullptr, vt == VT_F64 ? MT_F64 : MT_F32, m, n, A->lda, A->stride_A};
   MatArg probe_lo{nullptr, MT_BF16, m, n, A->lda, A->stride_A};
   nsplit_n = std::max(gemv_n_splits(probe, batch), uses_lo ? gemv_n_splits(probe_lo, batch) : 1);
-  nrhs = logistic ? 2 : 1;
+  nrhs = ml ? 2 : 1;
   ksplit = std::max(gemv_t_splits(probe, batch), uses_lo ? gemv_t_splits(probe_lo, batch) : 1);
   // partial slots of A^T products: gemv_t's row splits or the fused H p's blocks
-  const bool cg_op = op == GENIOS_OP_LASSO || op == GENIOS_OP_LOGREG ||
+  const bool cg_op = op == GENIOS_OP_LASSO || ml ||
                      op == GENIOS_OP_BACKWARD || op == GENIOS_OP_HVP;
-  yslots = std::max<int64_t>((int64_t)ksplit * (logistic ? 2 : 1),
+  yslots = std::max<int64_t>((int64_t)ksplit * (ml ? 2 : 1),
                              cg_op ? std::max<int64_t>(1, kHvpMaxBlocks / batch) : 1);
   npad = (n + 7) / 8 * 8;
   chunk = vec_chunk(n);
@@ -437,7 +437,7 @@ int hvp_explicit(Ctx& c, const MatArg& op, const void* x, void* h, const void* d
 }  // namespace
 
 // ---------------------------------------------------------------------------------
-// ADMM driver shared by the Lasso and the logistic regression.
+// ADMM driver shared by the Lasso, the logistic regression and Huber fitting.
 
 namespace {
 
@@ -511,7 +511,10 @@ int cg_iteration(Ctx& c, const MatArg& op, const VecArgs& va, const void* dscale
 }  // namespace
 
 int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, double rho0,
-             const genios_opts* o, void* x, void* z, void* u, genios_info* info, bool logistic) {
+             const genios_opts* o, void* x, void* z, void* u, genios_info* info, int loss) {
+  // ml: the loss has curvature D = f''(A x - b) that changes with x (Sec. 3.3)
+  const bool ml = loss != kLossSquare;
+  const double delta = o->huber_delta;
   const double t0 = now_s();
   Ctx c;
   c.A = A;
@@ -523,7 +526,9 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
   c.vt = A->hi_dtype == GENIOS_DT_F64 ? VT_F64 : VT_F32;
   c.ve = c.vt == VT_F32 ? 4 : 8;
   const int s = o->precondition ? effective_rank(o, A->n, A->m) : 0;
-  c.L.setup(logistic ? GENIOS_OP_LOGREG : GENIOS_OP_LASSO, A, o, s);
+  c.L.setup(loss == kLossLogistic ? GENIOS_OP_LOGREG
+                                  : (loss == kLossHuber ? GENIOS_OP_HUBER : GENIOS_OP_LASSO),
+            A, o, s);
   int rc = c.L.bind(o->workspace, o->workspace_bytes);
   if (rc) return rc;
   c.prof.on = o->profile_kernels != 0;
@@ -595,12 +600,12 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
       q.lambda2 = o->lambda2;
       q.max_cg = o->max_cg_iter;
       q.rhs_rel = o->rhs_relative;
-      q.use_c = logistic ? 0 : 1;
+      q.use_c = ml ? 0 : 1;
     }
   };
 
   // Right-hand sides c = A^T b for the Lasso (per operator in use).
-  if (!logistic) {
+  if (!ml) {
     if (use_lo) {
       HC(launch_gemv_t(c.op_lo, B, c.vt, bvec, 1, 0, m, 0, 1, nullptr, 0, c.L.ypart,
                        c.nsplit_for(c.op_lo, 1), (int64_t)c.L.nrhs * c.L.npad, c.L.npad,
@@ -623,12 +628,12 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
   HC(upload_params(c, hp));
   // h = H x (zero for a cold start)
   auto gradient_pass = [&](const MatArg& opx, const int32_t* gate, int gstride) -> int {
-    // logistic: t = A x, d, columns, [A^T (d o t), A^T(-y o s)] -> h, g
+    // ML losses: t = A x, d = f''(t), columns, [A^T (d o t), A^T f'(t)] -> h, g
     int r = c.gemv_n(opx, x, gate, gstride);
     if (r) return r;
-    HC(launch_logistic_elem(c.vt, m, B, c.L.tparts, c.nsplit_for(opx, 0), m,
-                            (int64_t)c.L.nsplit_n * m, bvec, c.L.dvec, c.L.cols, m, gate,
-                            gstride, c.st));
+    HC(launch_loss_elem(c.vt, loss, delta, m, B, c.L.tparts, c.nsplit_for(opx, 0), m,
+                        (int64_t)c.L.nsplit_n * m, bvec, c.L.dvec, c.L.cols, m, gate,
+                        gstride, c.st));
     HC(c.prof.begin(c.st, 1));
     const int ks = c.nsplit_for(opx, 1);
     HC(launch_gemv_t(opx, B, c.vt, c.L.cols, 1, 0, 2 * m, m, 2, nullptr, 0, c.L.ypart, ks,
@@ -660,7 +665,8 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     ga.split_stride = m;
     ga.prob_stride = (int64_t)c.L.nsplit_n * m;
     ga.bvec = bvec;
-    ga.logistic = logistic ? 1 : 0;
+    ga.loss = loss;
+    ga.delta = delta;
     ga.fprime = c.L.gapf;
     ga.sfold = c.L.gaps;
     ga.ypart = c.L.ypart;
@@ -686,7 +692,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     c.prof.harvest();
     return 0;
   };
-  if (logistic) {
+  if (ml) {
     rc = gradient_pass(*op, nullptr, 0);
     if (rc) return rc;
   } else if (o->warm_start) {
@@ -695,7 +701,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
   } else {
     HC(launch_fill(h, B * n * c.ve, c.st));
   }
-  // Nystrom sketch of the operator in use (Lasso: once; logistic: at k = 1, 1 + every, ...).
+  // Nystrom sketch of the operator in use (Lasso: once; ML losses: at k = 1, 1 + every, ...).
   double t_precond = 0.0;
   auto build_sketch = [&](const MatArg& opx, const void* d) -> int {
     if (s <= 0) return 0;
@@ -712,12 +718,12 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     for (int64_t b = 0; b < B; ++b) P[b].resketches++;
     return 0;
   };
-  if (!logistic) {
+  if (!ml) {
     rc = build_sketch(*op, nullptr);
     if (rc) return rc;
   }
   HC(hipStreamSynchronize(c.st));
-  const double t_setup = now_s() - t0 - (logistic ? 0.0 : 0.0);
+  const double t_setup = now_s() - t0;
 
   // ---- ADMM loop ----
   const double eps_abs = o->eps_abs, eps_rel = o->eps_rel;
@@ -736,13 +742,13 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     sketch_checked = true;
     return 0;
   };
-  if (!logistic && s > 0) {
+  if (!ml && s > 0) {
     rc = check_sketch();
     if (rc) return rc;
   }
   while (active > 0 && k < o->max_iter) {
     ++k;
-    if (logistic && s > 0 && (k - 1) % std::max(1, o->resketch_every) == 0) {
+    if (ml && s > 0 && (k - 1) % std::max(1, o->resketch_every) == 0) {
       rc = build_sketch(*op, c.L.dvec);
       if (rc) return rc;
       rc = check_sketch();
@@ -762,14 +768,14 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     int enq = 0;
     for (;;) {
       for (int it = 0; it < chunk; ++it) {
-        rc = cg_iteration(c, *op, va, logistic ? c.L.dvec : nullptr, enq + it);
+        rc = cg_iteration(c, *op, va, ml ? c.L.dvec : nullptr, enq + it);
         if (rc) return rc;
       }
       enq += chunk;
       HC(hipEventRecord(tm.ev[1], c.st));
       HC(launch_admm_end(va, c.st));
       HC(launch_admm_finish(va, c.st));
-      if (logistic) {
+      if (ml) {
         // gradient pass at the new x (gated on the completed update)
         rc = gradient_pass(*op, c.gate_done, c.gs_state);
         if (rc) return rc;
@@ -877,10 +883,10 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
           P[b].switch_iter = k + 1;
           P[b].rk_hist.clear();
         }
-      // refresh H x (and the logistic gradient) with the FP32 operator
+      // refresh H x (and the ML gradient) with the FP32 operator
       set_params(k, false);
       HC(upload_params(c, hp));
-      if (logistic) {
+      if (ml) {
         rc = gradient_pass(*op, c.gate_run, c.gs_params);
       } else {
         rc = hvp_explicit(c, *op, x, h, nullptr, c.gate_run, c.gs_params);
@@ -892,7 +898,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     if (any_certify) {
       for (int64_t b = 0; b < B; ++b) hp[b].run = want_cert[b];
       HC(upload_params(c, hp));
-      if (!logistic) {
+      if (!ml) {
         rc = hvp_explicit(c, *op, x, h, nullptr, c.gate_run, c.gs_params);
         if (rc) return rc;
         VecArgs vr = c.vargs(x, z, u, h, g, phase == 0 ? c_lo : c_hi, nullptr);
@@ -903,7 +909,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
       for (int64_t b = 0; b < B; ++b) {
         if (!want_cert[b]) continue;
         HostProb& q = P[b];
-        if (!logistic) q.rd = std::sqrt(hs[b].red[kRedRd2]);
+        if (!ml) q.rd = std::sqrt(hs[b].red[kRedRd2]);
         // the certifying residuals use the rho of the finished iteration
         const double rho_it = hp[b].rho;
         const double rhou = rho_it * q.un;
@@ -970,7 +976,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
   // ---- final report with the master-copy operator ----
   set_params(k, true);
   HC(upload_params(c, hp));
-  if (logistic) {
+  if (ml) {
     rc = gradient_pass(c.op_hi, nullptr, 0);
     if (rc) return rc;
   } else {
@@ -985,7 +991,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
   rc = c.gemv_n(c.op_hi, z, nullptr, 0);
   if (rc) return rc;
   HC(launch_objective_m(c.vt, m, B, c.L.tparts, c.nsplit_for(c.op_hi, 0), m,
-                        (int64_t)c.L.nsplit_n * m, bvec, logistic ? 1 : 0, c.L.ctrl, c.st));
+                        (int64_t)c.L.nsplit_n * m, bvec, loss, delta, c.L.ctrl, c.st));
   rc = sync_state(c, hs);
   if (rc) return rc;
   // relative duality gap at the returned z with the master copy

@@ -12,7 +12,7 @@ namespace genios {
 // Internal n-vector slots of the workspace.
 enum {
   kVH = 0,   // h = H x (tracked through CG)
-  kVG,       // gradient of the smooth part (logistic) / -rhs (adjoint)
+  kVG,       // gradient of the smooth part (logistic, Huber) / -rhs (adjoint)
   kVCH,      // c = A^T b with the master copy (adjoint: signs of z*)
   kVCL,      // c = A^T b with the BF16 copy
   kVR,       // CG residual
@@ -31,7 +31,7 @@ struct Layout {
   int op = 0;
   int64_t m = 0, n = 0, batch = 1;
   VType vt = VT_F32;
-  bool logistic = false, backward = false;
+  bool ml = false, backward = false;  // ml: the logistic or Huber loss (Sec. 3.3)
   int s = 0;
   bool need_a16 = false;
   int64_t a16_elems = 0;
@@ -75,7 +75,7 @@ struct Layout {
 
 int effective_rank(const genios_opts* o, int64_t n, int64_t m);
 int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, double rho0,
-             const genios_opts* o, void* x, void* z, void* u, genios_info* info, bool logistic);
+             const genios_opts* o, void* x, void* z, void* u, genios_info* info, int loss);
 int run_nystrom_build(const genios_matrix* A, const void* d, int s, const void* omega,
                       const genios_opts* o, void* U, double* lamhat, genios_info* info);
 int run_matvec(const genios_matrix* A, int trans, int use_bf16, const void* v, void* out,

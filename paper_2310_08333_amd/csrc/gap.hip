@@ -3,12 +3,16 @@
 // For  l(x) = sum_i f(t_i) + lam ||x||_1,  t = A x,
 //   Lasso:     f(t_i) = (t_i - b_i)^2 / 2,        f'(t_i) = t_i - b_i,
 //   logistic:  f(t_i) = log(1 + e^{w_i}), w_i = -y_i t_i,  f'(t_i) = -y_i sigmoid(w_i)
-// (the logistic labels folded into the rows, so b = 0 there), the dual point is
+//   (the logistic labels folded into the rows, so b = 0 there),
+//   Huber:     f(t_i) = l(t_i - b_i),  f'(t_i) = 2 clip(t_i - b_i, -delta, delta),
+// the dual point is
 // nu = kappa f'(t) with kappa = min(1, lam / ||A^T f'(t)||_inf), which makes
 // ||A^T nu||_inf <= lam, and the dual function is
 //   Lasso:     g(nu) = -||nu||^2 / 2 - b^T nu,
 //   logistic:  g(nu) = -sum_i h(kappa s_i),  h(v) = v log v + (1 - v) log(1 - v),
 //              with s_i = sigmoid(w_i) (the folded rows' nu);
+//   Huber:     g(nu) = -||nu||^2 / 4 - b^T nu  (l*(v) = v^2 / 4 on |v| <= 2 delta,
+//              where every kappa f'(t_i) lies);
 // with the l2 term (lambda2 > 0) the dual is finite for every nu: kappa = 1
 // and g gains -(1 / (2 lambda2)) ||(|A^T nu| - lam)_+||^2, while l(x) gains
 // (lambda2 / 2) ||x||^2,
@@ -82,13 +86,14 @@ __device__ __forceinline__ double neg_entropy(double v) {
   return a + b;
 }
 
-// t from its column-split partials; nu_i = f'(t_i) (Lasso: t - b; logistic: the
-// folded s_i = sigmoid(-y_i t_i), with f'(t_i) = -y_i s_i formed for A^T);
-// partial sums of the loss.
+// t from its column-split partials; nu_i = f'(t_i) (Lasso: t - b; Huber:
+// 2 clip(t - b, -delta, delta); logistic: the folded s_i = sigmoid(-y_i t_i), with
+// f'(t_i) = -y_i s_i formed for A^T); partial sums of the loss.
 template <typename VT>
 __global__ __launch_bounds__(kGapThreads) void k_gap_elem(
     int64_t m, const VT* __restrict__ tparts, int nsplit, int64_t split_stride,
-    int64_t prob_stride, const VT* __restrict__ bvec, int logistic, VT* __restrict__ fprime,
+    int64_t prob_stride, const VT* __restrict__ bvec, int lossk, double delta,
+    VT* __restrict__ fprime,
     VT* __restrict__ sfold, double* __restrict__ part, int pstride) {
   __shared__ double sm[4];
   const int b = blockIdx.y;
@@ -102,12 +107,18 @@ __global__ __launch_bounds__(kGapThreads) void k_gap_elem(
     double t = 0.0;
     for (int k = 0; k < nsplit; ++k) t += (double)tp[(int64_t)k * split_stride + i];
     const double bi = (double)bb[i];
-    if (logistic) {
+    if (lossk == kLossLogistic) {
       const double w = -bi * t;
       const double s = sigmoid_d(w);
       loss += softplus_d(w);
       fp[i] = VT(-bi * s);
       sf[i] = VT(s);
+    } else if (lossk == kLossHuber) {
+      const double r = t - bi, a = fabs(r);
+      loss += a <= delta ? r * r : 2.0 * delta * a - delta * delta;
+      const double f1 = 2.0 * fmin(fmax(r, -delta), delta);
+      fp[i] = VT(f1);
+      sf[i] = VT(f1);
     } else {
       const double r = t - bi;
       loss += 0.5 * r * r;
@@ -183,11 +194,11 @@ __global__ __launch_bounds__(64) void k_gap_kappa(const double* __restrict__ par
   }
 }
 
-// Conjugate terms at kappa: Lasso kappa^2 r_i^2 / 2 + kappa b_i r_i; logistic
-// h(kappa s_i).  Their sum is -g(nu).
+// Conjugate terms at kappa: Lasso v^2 / 2 + b_i v, Huber v^2 / 4 + b_i v with
+// v = kappa f'(t_i); logistic h(kappa s_i).  Their sum is -g(nu).
 template <typename VT>
 __global__ __launch_bounds__(kGapThreads) void k_gap_dual(
-    int64_t m, const VT* __restrict__ sfold, const VT* __restrict__ bvec, int logistic,
+    int64_t m, const VT* __restrict__ sfold, const VT* __restrict__ bvec, int lossk,
     const GapState* __restrict__ gs, double* __restrict__ part, int pstride) {
   __shared__ double sm[4];
   const int b = blockIdx.y;
@@ -198,7 +209,8 @@ __global__ __launch_bounds__(kGapThreads) void k_gap_dual(
   for (int64_t i = (int64_t)blockIdx.x * kGapThreads + threadIdx.x; i < m;
        i += (int64_t)gridDim.x * kGapThreads) {
     const double v = kap * (double)sf[i];
-    acc += logistic ? neg_entropy(v) : 0.5 * v * v + (double)bb[i] * v;
+    acc += lossk == kLossLogistic ? neg_entropy(v)
+           : (lossk == kLossHuber ? 0.25 : 0.5) * v * v + (double)bb[i] * v;
   }
   acc = block_sum1(acc, sm);
   if (threadIdx.x == 0) part[((int64_t)b * kGapSlots + 3) * pstride + blockIdx.x] = acc;
@@ -222,7 +234,7 @@ hipError_t gap_elem_vt(const GapArgs& a, hipStream_t st) {
   const int nb = gap_blocks(a.m);
   hipLaunchKernelGGL((k_gap_elem<VT>), dim3(nb, (unsigned)a.batch), dim3(kGapThreads), 0, st,
                      a.m, static_cast<const VT*>(a.tparts), a.nsplit, a.split_stride,
-                     a.prob_stride, static_cast<const VT*>(a.bvec), a.logistic,
+                     a.prob_stride, static_cast<const VT*>(a.bvec), a.loss, a.delta,
                      static_cast<VT*>(a.fprime), static_cast<VT*>(a.sfold), a.part, kGapPStride);
   return hipGetLastError();
 }
@@ -241,7 +253,7 @@ hipError_t gap_after_t_vt(const GapArgs& a, hipStream_t st) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_gap_dual<VT>), dim3(nbm, (unsigned)a.batch), dim3(kGapThreads), 0, st,
                      a.m, static_cast<const VT*>(a.sfold), static_cast<const VT*>(a.bvec),
-                     a.logistic, a.state, a.part, kGapPStride);
+                     a.loss, a.state, a.part, kGapPStride);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gap_final, dim3((unsigned)a.batch), dim3(64), 0, st, a.part, kGapPStride,
@@ -259,6 +271,7 @@ int gap_blocks(int64_t len) {
 // Every buffer the kernels touch must be given (checked on the host).
 static bool gap_args_complete(const GapArgs& a) {
   return a.m >= 1 && a.n >= 1 && a.batch >= 1 && a.tparts && a.nsplit >= 1 && a.bvec &&
+         a.loss >= kLossSquare && a.loss <= kLossHuber && (a.loss != kLossHuber || a.delta > 0.0) &&
          a.fprime && a.sfold && a.ypart && a.ks >= 1 && a.ks_stride >= a.n && a.v && a.params &&
          a.part && a.state;
 }

@@ -200,16 +200,24 @@ hipError_t launch_admm_end(const VecArgs& a, hipStream_t st);
 hipError_t launch_admm_finish(const VecArgs& a, hipStream_t st);
 // ||g + rho u||^2 into state.red[kRedRd2] with g = h - c or the given g (two kernels).
 hipError_t launch_dual_residual(const VecArgs& a, hipStream_t st);
-// Objective pieces: Lasso 1/2||t - b||^2 or logistic sum log(1+exp(-y t)), into red[kRedAux].
+// Smooth losses of the ML interface (Sec. 3.3), per sample with t = a_i^T x:
+//   square    (t - b)^2 / 2 (the Lasso),
+//   logistic  log(1 + exp(-y t)) (Sec. 4.2),
+//   Huber     l(t - b), l(r) = r^2 (|r| <= delta), 2 delta |r| - delta^2 (Sec. 4.3).
+enum LossKind : int { kLossSquare = 0, kLossLogistic = 1, kLossHuber = 2 };
+// Objective pieces sum_i f(t_i) at t = A z (FP64 sum) into red[kRedAux].
 hipError_t launch_objective_m(VType vt, int64_t m, int64_t batch, const void* tparts, int nsplit,
                               int64_t split_stride, int64_t prob_stride, const void* bvec,
-                              int logistic, Ctrl ctrl, hipStream_t st);
-// Logistic elementwise (margins, sigmoid, curvature): from t = A x partials compute
-// d = s(1-s) and the two right-hand columns: col0 = d o t, col1 = -y o s.
-hipError_t launch_logistic_elem(VType vt, int64_t m, int64_t batch, const void* tparts, int nsplit,
-                                int64_t split_stride, int64_t prob_stride, const void* y, void* d,
-                                void* cols, int64_t col_stride, const int32_t* gate,
-                                int gate_stride, hipStream_t st);
+                              int loss, double delta, Ctrl ctrl, hipStream_t st);
+// Elementwise terms of the ML x-system from the t = A x partials: the curvature
+// d = f''(t) and the two right-hand columns col0 = d o t (for H x) and
+// col1 = f'(t) (for grad f).  Logistic: d = s (1 - s), f' = -y s with s = sigmoid(-y t);
+// Huber: d = 2 [|t - b| <= delta], f' = 2 clip(t - b, -delta, delta).
+hipError_t launch_loss_elem(VType vt, int loss, double delta, int64_t m, int64_t batch,
+                            const void* tparts, int nsplit, int64_t split_stride,
+                            int64_t prob_stride, const void* bvec, void* d, void* cols,
+                            int64_t col_stride, const int32_t* gate, int gate_stride,
+                            hipStream_t st);
 // ---- relative duality gap (App. A), gap.hip ----
 struct GapState {
   double loss;      // sum_i f(t_i)
@@ -232,10 +240,11 @@ struct GapArgs {
   const void* tparts;  // t = A v column-split partials
   int nsplit;
   int64_t split_stride, prob_stride;
-  const void* bvec;    // b (Lasso) or the labels y (logistic), m per problem
-  int logistic;
+  const void* bvec;    // b (Lasso, Huber) or the labels y (logistic), m per problem
+  int loss;            // LossKind
+  double delta;        // Huber threshold
   void* fprime;        // [batch][m] f'(t), the input of A^T
-  void* sfold;         // [batch][m] r (Lasso) or sigmoid(w) (logistic)
+  void* sfold;         // [batch][m] f'(t) (Lasso, Huber) or sigmoid(w) (logistic)
   const void* ypart;   // A^T f'(t) row-split partials
   int ks;
   int64_t ks_stride, yprob;

@@ -63,7 +63,8 @@ def test_workspace_sizes(abi):
     lib = abi.load()
     M = _mat(abi)
     o = abi.default_opts()
-    for op in (abi.OP_LASSO, abi.OP_LOGREG, abi.OP_NYSTROM, abi.OP_BACKWARD, abi.OP_MATVEC):
+    for op in (abi.OP_LASSO, abi.OP_LOGREG, abi.OP_NYSTROM, abi.OP_BACKWARD, abi.OP_MATVEC,
+               abi.OP_HUBER):
         assert lib.genios_workspace_size(op, C.byref(M), C.byref(o)) > 0
     assert lib.genios_workspace_size(99, C.byref(M), C.byref(o)) == 0
     # the BF16 copy lives in the workspace when the caller gives none
@@ -172,3 +173,24 @@ def test_termination_options_defaults_and_checks(abi):
         rc = lib.genios_lasso_solve(C.byref(M), C.c_void_p(16), lam, 1.0, C.byref(q),
                                     C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), info)
         assert rc == abi.ERR_ARG, (field, rc)
+
+
+def test_huber_entry_point_checks_its_arguments(abi):
+    o = abi.default_opts()
+    assert o.huber_delta == 1.0  # the loss of Sec. 4.3
+    lib = abi.load()
+    M = _mat(abi)
+    lam = (C.c_double * 1)(0.1)
+    info = (abi.Info * 1)()
+    p = C.c_void_p(0x20000000)  # never dereferenced: the argument checks come first
+    for bad in (0.0, -1.0, float("inf"), float("nan")):
+        q = abi.default_opts()
+        q.huber_delta = bad
+        assert lib.genios_huber_solve(C.byref(M), p, lam, 1.0, C.byref(q), p, p, p, info) == abi.ERR_ARG
+    q = abi.default_opts()
+    assert lib.genios_huber_solve(C.byref(M), None, lam, 1.0, C.byref(q), p, p, p, info) == abi.ERR_ARG
+    assert lib.genios_huber_solve(C.byref(M), p, lam, 1.0, C.byref(q), p, p, p, info) == abi.ERR_WORKSPACE
+    # the Huber path carries the curvature vector and two right-hand columns like the logistic one
+    a = lib.genios_workspace_size(abi.OP_HUBER, C.byref(M), C.byref(q))
+    b = lib.genios_workspace_size(abi.OP_LOGREG, C.byref(M), C.byref(q))
+    assert a == b > 0

@@ -5,6 +5,7 @@ import torch
 
 import genios_data
 from oracle import adjoint as oadj
+from oracle import huber as ohuber
 from oracle import lasso as olasso
 from oracle import logreg as ologreg
 from oracle import residuals as ores
@@ -409,3 +410,112 @@ def test_elastic_net_backward_fp64_vs_oracle_adjoint(g):
     got = grad_b.cpu().numpy()
     assert np.linalg.norm(got - db) <= 1e-9 * np.linalg.norm(db), info
     assert abs(float(grad_lam[0]) - dl) <= 1e-9 * abs(dl)
+
+
+# ---- Huber fitting (Sec. 4.3, App. A with l*(v) = v^2 / 4) ----
+
+@pytest.fixture(scope="module")
+def hubsmall():
+    # 201 x 402: several row and column tiles with ragged tails
+    P = genios_data.huber_outliers(402, seed=6)
+    P["sol"] = ohuber.solve(P["A"], P["b"], P["lam"])
+    return P
+
+
+def _hub_data(P, prec):
+    if prec == "f64":
+        return P["A"].astype(np.float64), P["b"].astype(np.float64)
+    return P["A"], P["b"]
+
+
+@pytest.mark.parametrize("prec,pc", [("f64", 0), ("f32", 0), ("bf16_refine", 0), ("f32", 1)])
+def test_huber_objective_residuals_and_gap(g, hubsmall, prec, pc):
+    print("huber", prec, "precondition", pc, flush=True)
+    P = hubsmall
+    A, b = _hub_data(P, prec)
+    eps = 1e-8 if prec == "f64" else 1e-5
+    out = g.huber_solve(_t(A), _t(b), P["lam"], precision=prec, eps=eps, precondition=pc,
+                        sketch_rank=10, resketch_every=20)
+    info = out["info"][0]
+    assert out["status"] == 0, info
+    A64, b64 = P["A"].astype(np.float64), P["b"].astype(np.float64)
+    z = out["z"].cpu().numpy().astype(np.float64)
+    F = ohuber.objective(A64, b64, P["lam"], z)
+    Fs = P["sol"]["F"]
+    assert _rel(F, Fs) <= (1e-10 if prec == "f64" else 1e-6), (F, Fs, info)
+    assert _rel(info["obj"], F) <= (1e-12 if prec == "f64" else 1e-5)
+    # the residuals of Sec. 2.3 with grad f = A^T l'(A x - b)
+    x = out["x"].cpu().numpy().astype(np.float64)
+    u = out["u"].cpu().numpy().astype(np.float64)
+    rk, rp, rd = ores.r_kkt(x, z, u, info["rho"], ohuber.grad_f(A64, b64, x))
+    assert rk <= eps * 1.01 + (0 if prec == "f64" else 2e-6), (rk, info["r_kkt"])
+    tol = 1e-11 if prec == "f64" else 2e-6
+    _, pr, du = ohuber.duality_gap(A64, b64, P["lam"], z)
+    assert abs(info["gap_primal"] - pr) <= tol * abs(pr), (info["gap_primal"], pr)
+    assert abs(info["gap_dual"] - du) <= tol * abs(du), (info["gap_dual"], du)
+    if pc:
+        assert info["resketches"] >= 1
+
+
+def test_huber_f64_lockstep_with_oracle_admm(g, hubsmall):
+    # exact x-solves (tight CG), fixed penalty, 60 iterations: the iterates follow the
+    # oracle's ADMM of Sec. 3.3 to rounding
+    print("huber f64 lockstep", flush=True)
+    P = hubsmall
+    A, b = _hub_data(P, "f64")
+    K = 60
+    out = g.huber_solve(_t(A), _t(b), P["lam"], precision="f64", eps=1e-30, max_iter=K,
+                        precondition=0, inexact=0, cg_tol_floor=1e-14, max_cg_iter=400,
+                        rho_update_every=0)
+    assert out["status"] == 1  # MAX_ITER
+    x, z, u, rho, hist = ohuber.admm(A, b, P["lam"], rho=1.0, alpha=1.6, sigma=1e-6, max_iter=K)
+    zg = out["z"].cpu().numpy()
+    assert np.max(np.abs(zg - z)) <= 1e-9 * max(1.0, np.max(np.abs(z))), np.max(np.abs(zg - z))
+
+
+def test_huber_gap_termination(g, hubsmall):
+    print("huber gap termination", flush=True)
+    P = hubsmall
+    eps_gap = 1e-5
+    out = g.huber_solve(_t(P["A"]), _t(P["b"]), P["lam"], precision="f32", termination=1,
+                        eps_gap=eps_gap, precondition=0, max_iter=20000)
+    info = out["info"][0]
+    assert out["status"] == 0 and info["rel_gap"] <= eps_gap * 1.01, info
+    A64, b64 = P["A"].astype(np.float64), P["b"].astype(np.float64)
+    z = out["z"].cpu().numpy().astype(np.float64)
+    rel = ohuber.relative_gap(A64, b64, P["lam"], z)
+    assert rel <= eps_gap * 1.05 + 2e-6, rel
+    F = ohuber.objective(A64, b64, P["lam"], z)
+    assert (F - P["sol"]["F"]) / P["sol"]["F"] <= rel + 1e-12
+
+
+def test_huber_l2_and_delta(g, hubsmall):
+    print("huber l2 and delta", flush=True)
+    P = hubsmall
+    lam2, delta = 0.2, 0.5
+    sol = ohuber.solve(P["A"], P["b"], P["lam"], delta=delta, lam2=lam2)
+    A, b = _hub_data(P, "f64")
+    out = g.huber_solve(_t(A), _t(b), P["lam"], precision="f64", eps=1e-9, precondition=0,
+                        lambda2=lam2, huber_delta=delta)
+    info = out["info"][0]
+    assert out["status"] == 0, info
+    z = out["z"].cpu().numpy()
+    F = ohuber.objective(A, b, P["lam"], z, delta, lam2)
+    assert _rel(F, sol["F"]) <= 1e-10, (F, sol["F"])
+    _, pr, du = ohuber.duality_gap(A, b, P["lam"], z, delta, lam2)
+    assert abs(info["gap_primal"] - pr) <= 1e-11 * abs(pr)
+    assert abs(info["gap_dual"] - du) <= 1e-11 * abs(du)
+
+
+def test_huber_with_large_delta_is_twice_the_lasso(g, cfg1):
+    # no residual reaches delta: l(r) = r^2, so the optimum is the Lasso's at lam / 2
+    print("huber large delta", flush=True)
+    P = cfg1
+    A, b = P["A"].astype(np.float64), P["b"].astype(np.float64)
+    out = g.huber_solve(_t(A), _t(b), 2.0 * P["lam"], precision="f64", eps=1e-9,
+                        sketch_rank=P["s"], huber_delta=1e6)
+    assert out["status"] == 0, out["info"][0]
+    z = out["z"].cpu().numpy()
+    F = olasso.objective(A, b, P["lam"], z)
+    assert _rel(F, P["sol"]["F"]) <= 1e-10, (F, P["sol"]["F"])
+    assert abs(out["info"][0]["obj"] - 2.0 * F) <= 1e-10 * F
