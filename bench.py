@@ -25,6 +25,10 @@ the traffic.
 
 runs only a few Nystrom builds of the workload's BF16 operator (the sketch
 products on the matrix cores), for counter passes over those kernels.
+
+After the timed steps, `next_rows` times (once warm, outside the timed region)
+the elastic net and the duality-gap termination on the same workload and
+Huber fitting at n = 16000 under the paper's stopping rule (--no-next skips them).
 """
 from __future__ import annotations
 
@@ -136,6 +140,59 @@ def cpu_baseline(P, rows=8000, cols=16000, budget_iters=100):
                       f"incl. factorisation, {dt:.1f} s"}
 
 
+def _hvp_rate(info):
+    """Event-timed bandwidth of the fused H p launches of one solve (BF16 and master copy)."""
+    t = info["t_hvp"] + info["t_hvp_hi"]
+    by = info["bytes_hvp"] + info["bytes_hvp_hi"]
+    if t <= 0:
+        return None, None
+    gbs = by / t / 1e9
+    return round(gbs, 1), round(gbs / HBM_PEAK_GBS, 4)
+
+
+def _solve_record(info, target_key="t_to_target"):
+    gbs, frac = _hvp_rate(info)
+    return {"status_ok": info["status"] == 0, "time_s": round(info[target_key], 4),
+            "iters": info["iters"], "cg_iters": info["cg_iters"],
+            "iters_per_s": round(info["iters"] / info["t_total"], 2),
+            "linsys_ms_per_iter": round(1e3 * info["t_linsys"] / max(info["iters"], 1), 3),
+            "hvp_GBps": gbs, "hvp_frac_of_peak": frac}
+
+
+def next_rows(g, torch, A, b, lam, s):
+    """The rows built after the headline path, each measured once warm:
+    elastic net (Sec. 4.1's lambda2 = lambda1) and duality-gap termination on the
+    headline workload, and Huber fitting at the paper's largest size (n = 16000,
+    N = 8000, no preconditioner) under its own stopping rule, dist(0, dF(z)) <= 1e-4."""
+    import genios_data
+    out = {}
+    kw = dict(precision="bf16_refine", sketch_rank=s, profile_kernels=1)
+    for _ in range(2):
+        en = g.lasso_solve(A, b, lam, eps=1e-4, lambda2=lam, **kw)["info"][0]
+    out["elastic_net"] = dict(_solve_record(en), lambda2=lam, eps=1e-4,
+                              rel_gap=en["rel_gap"])
+    log(f"elastic net: {out['elastic_net']}")
+    # (thousands of iterations here: one run, the kernels are warm from the one above)
+    gp = g.lasso_solve(A, b, lam, termination=1, eps_gap=1e-4, **kw)["info"][0]
+    out["gap_termination"] = dict(_solve_record(gp), eps_gap=1e-4, rel_gap=gp["rel_gap"],
+                                  gap_checks=gp["gap_checks"])
+    log(f"gap termination: {out['gap_termination']}")
+    t0 = time.time()
+    H = genios_data.huber_outliers(16000, seed=6)
+    Ah = torch.from_numpy(H["A"]).to(A.device)
+    bh = torch.from_numpy(H["b"]).to(A.device)
+    log(f"generated {H['name']} in {time.time() - t0:.1f}s")
+    for prec in ("bf16_refine", "f32"):
+        for _ in range(2):
+            hu = g.huber_solve(Ah, bh, H["lam"], precision=prec, precondition=0, termination=2,
+                               eps_gap=1e-4, profile_kernels=1, max_iter=5000)["info"][0]
+        out[f"huber_{prec}"] = dict(_solve_record(hu), workload=H["name"],
+                                    subgrad_dist=hu["subgrad_dist"], obj=hu["obj"])
+        log(f"huber {prec}: {out[f'huber_{prec}']}")
+    del Ah, bh
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +202,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-next", action="store_true")
     ap.add_argument("--probe-traffic", action="store_true")
     ap.add_argument("--probe-sketch", action="store_true")
     args = ap.parse_args()
@@ -261,6 +319,10 @@ def main():
                 "cg_iters": o32["cg_iters"], "iters_per_s": round(o32["iters"] / o32["t_total"], 2)}
         log(f"fp32: {fp32}")
 
+    nxt = None
+    if not args.no_next:
+        nxt = next_rows(g, torch, A, b, lam, s)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(P)
@@ -281,6 +343,7 @@ def main():
         "fp32": fp32,
         "roofline": roofline,
         "sketch_gemm": sketch,
+        "next_rows": nxt,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

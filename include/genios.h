@@ -143,9 +143,14 @@ typedef struct {
                                   1: the relative duality gap of Sec. 3.3 / App. A at z,
                                   (l(z) - g(nu)) / min(l(z), |g(nu)|) <= eps_gap, evaluated
                                   with the master copy (BF16_REFINE: in the FP32 phase;
-                                  BF16_ONLY: with the BF16 copy) every gap_every iterations */
+                                  BF16_ONLY: with the BF16 copy) every gap_every iterations;
+                                  2: the same pass's distance from 0 to the subdifferential
+                                  of the objective at z, ||grad f(z) + lambda v||_2 for the
+                                  best v in d||z||_1, <= eps_gap (the criterion of the
+                                  Huber comparison in Sec. 4.3) */
   int32_t gap_every;           /* iterations between gap evaluations, default 1 */
-  double eps_gap;              /* relative duality gap tolerance, default 1e-4 */
+  double eps_gap;              /* tolerance of termination 1 (relative) or 2 (absolute),
+                                  default 1e-4 */
   double lambda2;              /* (lambda2 / 2) ||x||^2 added to the loss (elastic net, Sec. 4.1,
                                   App. A), >= 0, default 0; the x-system shift becomes
                                   rho + sigma + lambda2, the adjoint's lambda2 */
@@ -210,8 +215,10 @@ typedef struct {
                                 master copy: (l(z) - g(nu)) / min(l(z), |g(nu)|) */
   double gap_primal;         /* l(z) */
   double gap_dual;           /* g(nu), nu = min(1, lambda / ||A^T f'(A z - b)||_inf) f'(A z - b) */
-  int32_t gap_checks;        /* gap evaluations during the solve (termination = 1) */
+  int32_t gap_checks;        /* gap evaluations during the solve (termination = 1 or 2) */
   int32_t reserved2;
+  double subgrad_dist;       /* at the returned z with the master copy: the distance from 0 to
+                                grad f(z) + lambda d||z||_1 (l2 norm) */
 } genios_info;
 
 /* Fill *o with the defaults listed above.  Returns GENIOS_OK. */

@@ -51,3 +51,14 @@ def subgradient_residual(g, z, lam):
     on = z != 0
     v = np.where(on, g + lam * np.sign(z), np.maximum(np.abs(g) - lam, 0.0))
     return float(np.max(np.abs(v))) / lam
+
+
+def subdifferential_distance(g, z, lam):
+    """dist(0, g + lam d||z||_1) in the l2 norm: the stopping criterion of the Huber
+    comparison (Sec. 4.3), with g the gradient of the smooth part at z.  Per entry
+    the closest point of g_i + lam [-1, 1] (z_i = 0) or g_i + lam sign(z_i) to 0."""
+    g = np.asarray(g, np.float64)
+    z = np.asarray(z, np.float64)
+    on = z != 0
+    v = np.where(on, g + lam * np.sign(z), np.maximum(np.abs(g) - lam, 0.0))
+    return float(np.linalg.norm(v))

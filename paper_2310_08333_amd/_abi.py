@@ -79,7 +79,8 @@ class Info(C.Structure):
                 ("n_sketch_fma", C.c_int32), ("t_sketch_fma", C.c_double),
                 ("flops_sketch_fma", C.c_int64), ("rel_gap", C.c_double),
                 ("gap_primal", C.c_double), ("gap_dual", C.c_double),
-                ("gap_checks", C.c_int32), ("reserved2", C.c_int32)]
+                ("gap_checks", C.c_int32), ("reserved2", C.c_int32),
+                ("subgrad_dist", C.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

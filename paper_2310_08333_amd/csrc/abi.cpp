@@ -45,7 +45,8 @@ int check_opts(const genios_opts* o) {
   if (!(o->switch_tol >= 0.0)) FAIL(GENIOS_ERR_ARG, "switch_tol must be >= 0");
   if (o->history != nullptr && o->history_cap < 1)
     FAIL(GENIOS_ERR_ARG, "history_cap must be >= 1 when history is given");
-  if (o->termination < 0 || o->termination > 1) FAIL(GENIOS_ERR_ARG, "termination must be 0 or 1");
+  if (o->termination < 0 || o->termination > 2)
+    FAIL(GENIOS_ERR_ARG, "termination must be 0, 1 or 2");
   if (o->gap_every < 1) FAIL(GENIOS_ERR_ARG, "gap_every must be >= 1");
   if (!(o->eps_gap > 0.0) || !std::isfinite(o->eps_gap)) FAIL(GENIOS_ERR_ARG, "eps_gap must be > 0");
   if (!(o->lambda2 >= 0.0) || !std::isfinite(o->lambda2))

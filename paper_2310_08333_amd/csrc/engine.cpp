@@ -925,8 +925,9 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
         }
       }
     }
-    // Relative duality gap test at z (Sec. 3.3, App. A) in the operator's final phase.
-    if (o->termination == 1 && !(phase == 0 && prec == GENIOS_PREC_BF16_REFINE) &&
+    // Gap pass at z in the operator's final phase: the relative duality gap (Sec. 3.3,
+    // App. A; termination 1) or the subdifferential distance (Sec. 4.3; termination 2).
+    if (o->termination != 0 && !(phase == 0 && prec == GENIOS_PREC_BF16_REFINE) &&
         k % o->gap_every == 0) {
       bool any = false;
       for (int64_t b = 0; b < B; ++b)
@@ -940,7 +941,8 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
           if (!hp[b].run || P[b].done) continue;
           HostProb& q = P[b];
           ++q.gap_checks;
-          if (std::isfinite(hg[b].rel_gap) && hg[b].rel_gap <= o->eps_gap) {
+          const double crit = o->termination == 1 ? hg[b].rel_gap : hg[b].subgrad;
+          if (std::isfinite(crit) && crit <= o->eps_gap) {
             q.done = 1;
             q.t_target = now_s() - t0;
             q.status = GENIOS_OK;
@@ -1022,6 +1024,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     I.gap_primal = hg[b].primal;
     I.gap_dual = hg[b].dual;
     I.gap_checks = q.gap_checks;
+    I.subgrad_dist = hg[b].subgrad;
     I.t_setup = t_setup;
     I.t_precond = t_precond;
     I.t_solve = t_solve;

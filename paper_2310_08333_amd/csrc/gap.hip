@@ -131,7 +131,9 @@ __global__ __launch_bounds__(kGapThreads) void k_gap_elem(
 }
 
 // ||A^T f'(t)||_inf and ||(|A^T f'(t)| - lambda)_+||^2 from the row-split
-// partials, and ||v||_1, ||v||^2.
+// partials, ||v||_1, ||v||^2, and the squared distance from 0 to
+// grad f(v) + lambda d||v||_1 (grad f = A^T f'(t) + lambda2 v): per entry
+// grad_j + lambda sign(v_j) where v_j != 0, (|grad_j| - lambda)_+ where v_j = 0.
 template <typename VT>
 __global__ __launch_bounds__(kGapThreads) void k_gap_inf(
     int64_t n, const VT* __restrict__ ypart, int ks, int64_t ks_stride, int64_t prob_stride,
@@ -139,10 +141,10 @@ __global__ __launch_bounds__(kGapThreads) void k_gap_inf(
     int pstride) {
   __shared__ double sm[4];
   const int b = blockIdx.y;
-  const double lam = params[b].lambda;
+  const double lam = params[b].lambda, lam2 = params[b].lambda2;
   const VT* yp = ypart + (int64_t)b * prob_stride;
   const VT* vb = v + (int64_t)b * n;
-  double gmax = 0.0, l1 = 0.0, x2 = 0.0, ex2 = 0.0;
+  double gmax = 0.0, l1 = 0.0, x2 = 0.0, ex2 = 0.0, sd2 = 0.0;
   for (int64_t j = (int64_t)blockIdx.x * kGapThreads + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * kGapThreads) {
     double g = 0.0;
@@ -153,17 +155,22 @@ __global__ __launch_bounds__(kGapThreads) void k_gap_inf(
     const double vj = (double)vb[j];
     l1 += fabs(vj);
     x2 += vj * vj;
+    const double gf = g + lam2 * vj;
+    const double sd = vj != 0.0 ? gf + copysign(lam, vj) : fmax(fabs(gf) - lam, 0.0);
+    sd2 += sd * sd;
   }
   gmax = block_max1(gmax, sm);
   l1 = block_sum1(l1, sm);
   x2 = block_sum1(x2, sm);
   ex2 = block_sum1(ex2, sm);
+  sd2 = block_sum1(sd2, sm);
   if (threadIdx.x == 0) {
     double* pb = part + (int64_t)b * kGapSlots * pstride + blockIdx.x;
     pb[1 * pstride] = gmax;
     pb[2 * pstride] = l1;
     pb[4 * pstride] = x2;
     pb[5 * pstride] = ex2;
+    pb[6 * pstride] = sd2;
   }
 }
 
@@ -179,6 +186,7 @@ __global__ __launch_bounds__(64) void k_gap_kappa(const double* __restrict__ par
   const double l1 = wave_fixed_sum(pb + 2 * pstride, nb_n, 1);
   const double x2 = wave_fixed_sum(pb + 4 * pstride, nb_n, 1);
   const double ex2 = wave_fixed_sum(pb + 5 * pstride, nb_n, 1);
+  const double sd2 = wave_fixed_sum(pb + 6 * pstride, nb_n, 1);
   if (threadIdx.x == 0) {
     const double lam = params[b].lambda, lam2 = params[b].lambda2;
     GapState& G = gs[b];
@@ -187,6 +195,7 @@ __global__ __launch_bounds__(64) void k_gap_kappa(const double* __restrict__ par
     G.l1 = l1;
     G.x2 = x2;
     G.excess2 = ex2;
+    G.subgrad = sqrt(sd2);
     // lambda2 > 0: g is finite for every nu, nu = f'(t) unscaled (App. A)
     G.kappa = lam2 > 0.0 ? 1.0 : (ginf > lam ? lam / ginf : 1.0);
     G.reg = lam2 > 0.0 ? -ex2 / (2.0 * lam2) : 0.0;

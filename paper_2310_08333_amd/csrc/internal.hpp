@@ -231,9 +231,10 @@ struct GapState {
   double dual;      // g(nu)
   double gap;       // primal - dual
   double rel_gap;   // gap / min(primal, |dual|)
+  double subgrad;   // ||.||_2 of the least-norm element of grad f(v) + lambda d||v||_1
 };
 constexpr int kGapPStride = 256;  // block partials per reduction and problem
-constexpr int kGapSlots = 6;      // loss, inf, l1, conjugate sum, x2, excess2
+constexpr int kGapSlots = 7;      // loss, inf, l1, conjugate sum, x2, excess2, subgrad^2
 struct GapArgs {
   VType vt;
   int64_t m, n, batch;

@@ -167,7 +167,7 @@ def test_termination_options_defaults_and_checks(abi):
     M.A_hi = C.c_void_p(16)  # never dereferenced: the option checks come first
     lam = (C.c_double * 1)(0.1)
     info = (abi.Info * 1)()
-    for field, bad in (("termination", 2), ("gap_every", 0), ("eps_gap", 0.0)):
+    for field, bad in (("termination", 3), ("termination", -1), ("gap_every", 0), ("eps_gap", 0.0)):
         q = abi.default_opts()
         setattr(q, field, bad)
         rc = lib.genios_lasso_solve(C.byref(M), C.c_void_p(16), lam, 1.0, C.byref(q),

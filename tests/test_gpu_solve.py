@@ -455,6 +455,28 @@ def test_huber_objective_residuals_and_gap(g, hubsmall, prec, pc):
     assert abs(info["gap_dual"] - du) <= tol * abs(du), (info["gap_dual"], du)
     if pc:
         assert info["resketches"] >= 1
+    # the subdifferential distance of Sec. 4.3 at z, with the master copy
+    sd = ores.subdifferential_distance(ohuber.grad_f(A64, b64, z), z, P["lam"])
+    assert abs(info["subgrad_dist"] - sd) <= (1e-9 if prec == "f64" else 1e-4) * P["lam"], \
+        (info["subgrad_dist"], sd)
+
+
+@pytest.mark.parametrize("prec,eps", [("f64", 1e-7), ("f32", 1e-4), ("bf16_refine", 1e-4)])
+def test_huber_subdifferential_termination(g, hubsmall, prec, eps):
+    # the stopping rule of the paper's Huber comparison: ||dist(0, dF(z))||_2 <= eps
+    print("huber subdifferential termination", prec, flush=True)
+    P = hubsmall
+    A, b = _hub_data(P, prec)
+    out = g.huber_solve(_t(A), _t(b), P["lam"], precision=prec, termination=2, eps_gap=eps,
+                        precondition=0, max_iter=20000)
+    info = out["info"][0]
+    assert out["status"] == 0 and info["subgrad_dist"] <= eps, info
+    A64, b64 = P["A"].astype(np.float64), P["b"].astype(np.float64)
+    z = out["z"].cpu().numpy().astype(np.float64)
+    sd = ores.subdifferential_distance(ohuber.grad_f(A64, b64, z), z, P["lam"])
+    # FP32 products of A^T l'(r): about 3e-6 per support entry, ~100 entries
+    assert sd <= eps * 1.01 + (0.0 if prec == "f64" else 5e-5), sd
+    assert info["gap_checks"] >= 1
 
 
 def test_huber_f64_lockstep_with_oracle_admm(g, hubsmall):

@@ -91,3 +91,20 @@ def test_generator_follows_the_recipe():
     big = np.abs(b - A @ P["x0"]) > 5.0
     assert big.sum() == 10
     assert abs(P["lam"] - 0.1 * np.max(np.abs(A.T @ b))) <= 1e-6 * P["lam"]
+
+
+def test_subdifferential_distance_brute_force_and_optimum():
+    from oracle import residuals
+    rng = np.random.default_rng(9)
+    g = rng.standard_normal(12)
+    z = np.where(rng.random(12) < 0.5, rng.standard_normal(12), 0.0)
+    lam = 0.7
+    # brute force: every v in d||z||_1 on a fine grid of [-1, 1] for the zero entries
+    grid = np.linspace(-1, 1, 200001)
+    best = np.where(z != 0, np.abs(g + lam * np.sign(z)),
+                    np.array([np.min(np.abs(gi + lam * grid)) for gi in g]))
+    assert abs(residuals.subdifferential_distance(g, z, lam) - np.linalg.norm(best)) <= 1e-5
+    P = genios_data.huber_outliers(60, seed=3)
+    sol = huber.solve(P["A"], P["b"], P["lam"])
+    d = residuals.subdifferential_distance(huber.grad_f(P["A"], P["b"], sol["x"]), sol["x"], P["lam"])
+    assert d <= 1e-6 * P["lam"]
