@@ -157,6 +157,17 @@ typedef struct {
   double huber_delta;          /* genios_huber_solve: the loss is quadratic for |r| <= delta and
                                   linear beyond, l(r) = r^2 or 2 delta |r| - delta^2 (Sec. 4.3
                                   uses delta = 1, the default); > 0 */
+  int32_t adaptive_sketch;     /* 1: choose the Nystrom size at each build by the doubling rule of
+                                  Sec. 2.2 (adaptive sketch size): sizes sketch_rank_init,
+                                  2 sketch_rank_init, ... capped at the sketch size s above,
+                                  until 1 + (lam_hat_rr + ||E||) / nu <= sketch_kappa for every
+                                  problem, ||E|| = ||H - H_hat|| estimated by power_iters steps
+                                  of the randomized power method (start vector: Philox with key
+                                  (seed, 0x706F776572 + problem)); 0 (default): fixed size s */
+  int32_t sketch_rank_init;    /* first size of the doubling rule, default 8, >= 1 */
+  double sketch_kappa;         /* target of the condition-number bound, default 10, > 1 */
+  int32_t power_iters;         /* power-method steps per size, default 10, >= 1 */
+  int32_t reserved3;
 } genios_opts;
 
 /* Per-iteration history row layout (doubles); problem p, iteration k (1-based)
@@ -180,7 +191,7 @@ typedef struct {
   int32_t cg_iters;          /* total CG iterations */
   int32_t phase_switch_iter; /* first FP32-operator iteration (BF16_REFINE), else -1 */
   int32_t resketches;        /* Nystrom builds performed */
-  int32_t precond_rank;      /* retained sketch rank of the last build */
+  int32_t precond_rank;      /* retained sketch rank of the last build (eigenpairs kept) */
   double obj;                /* objective at z with the master-copy data (FP64 reduction) */
   double r_p, r_d, r_kkt;    /* final residuals (r_d with the master-copy operator) */
   double rho;                /* final penalty */
@@ -219,6 +230,11 @@ typedef struct {
   int32_t reserved2;
   double subgrad_dist;       /* at the returned z with the master copy: the distance from 0 to
                                 grad f(z) + lambda d||z||_1 (l2 norm) */
+  double sketch_err;         /* adaptive_sketch: power-method estimate of ||H - H_hat|| for the
+                                last Nystrom build, else 0 */
+  double kappa_bound;        /* adaptive_sketch: 1 + (lam_hat_rr + sketch_err) / nu of that build */
+  int32_t sketch_rounds;     /* sizes tried in the last build (1 without adaptive_sketch) */
+  int32_t reserved4;
 } genios_info;
 
 /* Fill *o with the defaults listed above.  Returns GENIOS_OK. */

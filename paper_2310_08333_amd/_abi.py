@@ -58,7 +58,9 @@ class Opts(C.Structure):
                 ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
                 ("termination", C.c_int32), ("gap_every", C.c_int32),
                 ("eps_gap", C.c_double), ("lambda2", C.c_double),
-                ("huber_delta", C.c_double)]
+                ("huber_delta", C.c_double), ("adaptive_sketch", C.c_int32),
+                ("sketch_rank_init", C.c_int32), ("sketch_kappa", C.c_double),
+                ("power_iters", C.c_int32), ("reserved3", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -80,7 +82,9 @@ class Info(C.Structure):
                 ("flops_sketch_fma", C.c_int64), ("rel_gap", C.c_double),
                 ("gap_primal", C.c_double), ("gap_dual", C.c_double),
                 ("gap_checks", C.c_int32), ("reserved2", C.c_int32),
-                ("subgrad_dist", C.c_double)]
+                ("subgrad_dist", C.c_double), ("sketch_err", C.c_double),
+                ("kappa_bound", C.c_double), ("sketch_rounds", C.c_int32),
+                ("reserved4", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

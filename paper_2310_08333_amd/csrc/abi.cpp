@@ -53,6 +53,13 @@ int check_opts(const genios_opts* o) {
     FAIL(GENIOS_ERR_ARG, "lambda2 must be finite and >= 0");
   if (!(o->huber_delta > 0.0) || !std::isfinite(o->huber_delta))
     FAIL(GENIOS_ERR_ARG, "huber_delta must be finite and > 0");
+  if (o->adaptive_sketch < 0 || o->adaptive_sketch > 1)
+    FAIL(GENIOS_ERR_ARG, "adaptive_sketch must be 0 or 1");
+  if (o->sketch_rank_init < 1) FAIL(GENIOS_ERR_ARG, "sketch_rank_init must be >= 1");
+  if (!(o->sketch_kappa > 1.0) || !std::isfinite(o->sketch_kappa))
+    FAIL(GENIOS_ERR_ARG, "sketch_kappa must be finite and > 1");
+  if (o->power_iters < 1 || o->power_iters > 1000)
+    FAIL(GENIOS_ERR_ARG, "power_iters must lie in [1, 1000]");
   return GENIOS_OK;
 }
 
@@ -144,6 +151,10 @@ int genios_default_opts(genios_opts* o) {
   o->eps_gap = 1e-4;
   o->lambda2 = 0.0;
   o->huber_delta = 1.0;
+  o->adaptive_sketch = 0;
+  o->sketch_rank_init = 8;
+  o->sketch_kappa = 10.0;
+  o->power_iters = 10;
   return GENIOS_OK;
 }
 

@@ -125,6 +125,7 @@ void Layout::carve(Arena& ar) {
     maskS = static_cast<uint8_t*>(ar.take((size_t)B * ldS_max));
   }
   if (s > 0) {
+    pm_est = static_cast<double*>(ar.take((size_t)B * sizeof(double)));
     U = vec(n * (int64_t)s);
     const int sp = sketch_pad(s);
     sk.omega = vec(n * (int64_t)sp);
@@ -452,6 +453,8 @@ struct HostProb {
   double t_target = -1.0;
   int switch_iter = -1, resketches = 0;
   int gap_checks = 0;
+  int precond_rank = 0, sketch_rounds = 0;
+  double sketch_err = 0.0, kappa_bound = 0.0;
   std::vector<double> rk_hist;
 };
 
@@ -702,20 +705,100 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     HC(launch_fill(h, B * n * c.ve, c.st));
   }
   // Nystrom sketch of the operator in use (Lasso: once; ML losses: at k = 1, 1 + every, ...).
+  // With adaptive_sketch the size doubles from sketch_rank_init up to s until the bound
+  // 1 + (lam_hat_rr + ||E||) / nu of Sec. 2.2 is <= sketch_kappa for every problem of the
+  // batch, ||E|| from power_iters steps of the power method on E = H - U lam_hat U^T.
   double t_precond = 0.0;
+  std::vector<int32_t> se_h(B, 0);
+  std::vector<double> lam_h, est_h(B, 0.0);
+  int sketch_rounds = 0;
+  auto build_at = [&](const MatArg& opx, const void* d, int r) -> int {
+    SketchWs skx = c.L.sk;
+    HC(c.sketch_timer(opx, r, &skx));
+    HC(run_nystrom(opx, B, c.vt, d, m, r, nullptr, o->seed, 0, nullptr, skx, c.L.U,
+                   c.L.ctrl.lamhat, c.L.ctrl.s_eff, c.L.core_status, c.L.shift, c.st));
+    // U (n x r per problem) and lam_hat (r per problem) are packed at the built rank
+    c.L.s = r;
+    c.L.ctrl.s_stride = r;
+    return 0;
+  };
+  auto sketch_error = [&](const MatArg& opx, const void* d) -> int {
+    PowerArgs pa{};
+    pa.vt = c.vt;
+    pa.n = n;
+    pa.batch = B;
+    pa.U = c.L.U;
+    pa.s_stride = c.L.s;
+    pa.lamhat = c.L.ctrl.lamhat;
+    pa.s_eff = c.L.ctrl.s_eff;
+    pa.h = c.L.nv[kVHP];
+    pa.v = c.L.nv[kVR];
+    pa.ev = c.L.nv[kVW];
+    pa.ut_part = c.L.ctrl.upart;
+    pa.part2 = c.L.ctrl.spart;
+    pa.pstride = c.L.ctrl.pstride;
+    pa.nb = power_blocks(n, c.L.ctrl.pstride);
+    pa.est = c.L.pm_est;
+    HC(launch_gaussian(c.vt, n, 1, 1, B, o->seed, kPowerStream, nullptr, pa.ev, c.st));
+    HC(launch_power_start(pa, c.st));
+    for (int it = 0; it < o->power_iters; ++it) {
+      int r = hvp_explicit(c, opx, pa.v, c.L.nv[kVHP], d, nullptr, 0);
+      if (r) return r;
+      HC(launch_power_step(pa, c.st));
+    }
+    return 0;
+  };
+  auto read_sketch = [&](bool with_est) -> int {
+    const int r = c.L.s;
+    lam_h.assign((size_t)B * r, 0.0);
+    HC(hipMemcpyAsync(se_h.data(), c.L.ctrl.s_eff, B * sizeof(int32_t), hipMemcpyDeviceToHost, c.st));
+    HC(hipMemcpyAsync(lam_h.data(), c.L.ctrl.lamhat, (size_t)B * r * sizeof(double),
+                      hipMemcpyDeviceToHost, c.st));
+    if (with_est)
+      HC(hipMemcpyAsync(est_h.data(), c.L.pm_est, B * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HC(hipStreamSynchronize(c.st));
+    for (int64_t b = 0; b < B; ++b) {
+      P[b].precond_rank = se_h[b];
+      if (!with_est) continue;
+      const double lrr = se_h[b] > 0 ? lam_h[(size_t)b * r + se_h[b] - 1] : 0.0;
+      P[b].sketch_err = std::max(0.0, est_h[b]);
+      P[b].kappa_bound = 1.0 + (lrr + P[b].sketch_err) / (P[b].rho + o->sigma + o->lambda2);
+    }
+    return 0;
+  };
   auto build_sketch = [&](const MatArg& opx, const void* d) -> int {
     if (s <= 0) return 0;
-    SketchWs skx = c.L.sk;
-    HC(c.sketch_timer(opx, s, &skx));
     HC(hipEventRecord(tm.ev[0], c.st));
-    HC(run_nystrom(opx, B, c.vt, d, m, s, nullptr, o->seed, 0, nullptr, skx, c.L.U,
-                   c.L.ctrl.lamhat, c.L.ctrl.s_eff, c.L.core_status, c.L.shift, c.st));
+    int r = o->adaptive_sketch ? std::min(s, std::max(1, o->sketch_rank_init)) : s;
+    sketch_rounds = 0;
+    for (;;) {
+      ++sketch_rounds;
+      int rc2 = build_at(opx, d, r);
+      if (rc2) return rc2;
+      if (!o->adaptive_sketch) {
+        rc2 = read_sketch(false);
+        if (rc2) return rc2;
+        break;
+      }
+      rc2 = sketch_error(opx, d);
+      if (rc2) return rc2;
+      rc2 = read_sketch(true);
+      if (rc2) return rc2;
+      bool met = true;
+      for (int64_t b = 0; b < B; ++b)
+        if (!(P[b].kappa_bound <= o->sketch_kappa)) met = false;
+      if (met || r >= s) break;
+      r = std::min(2 * r, s);
+    }
     HC(hipEventRecord(tm.ev[1], c.st));
     HC(hipEventSynchronize(tm.ev[1]));
     float ms = 0.f;
     HC(hipEventElapsedTime(&ms, tm.ev[0], tm.ev[1]));
     t_precond += ms * 1e-3;
-    for (int64_t b = 0; b < B; ++b) P[b].resketches++;
+    for (int64_t b = 0; b < B; ++b) {
+      P[b].resketches++;
+      P[b].sketch_rounds = sketch_rounds;
+    }
     return 0;
   };
   if (!ml) {
@@ -1014,7 +1097,10 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     I.cg_iters = q.cg_total;
     I.phase_switch_iter = q.switch_iter;
     I.resketches = q.resketches;
-    I.precond_rank = 0;
+    I.precond_rank = q.precond_rank;
+    I.sketch_err = q.sketch_err;
+    I.kappa_bound = q.kappa_bound;
+    I.sketch_rounds = q.sketch_rounds;
     I.rho = q.rho;
     I.r_p = q.rp;
     I.r_d = std::sqrt(hs[b].red[kRedRd2]);

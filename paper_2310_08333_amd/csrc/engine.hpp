@@ -66,6 +66,7 @@ struct Layout {
   void* gaps = nullptr;       // [batch][m] r or sigmoid(w)
   double* gpart = nullptr;    // [batch][kGapSlots][kGapPStride]
   GapState* gstate = nullptr; // [batch]
+  double* pm_est = nullptr;   // [batch] power-method estimate of ||H - H_hat|| (adaptive sketch)
   size_t total = 0;
 
   int setup(int op, const genios_matrix* A, const genios_opts* o, int s);

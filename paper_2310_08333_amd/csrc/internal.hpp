@@ -255,6 +255,29 @@ struct GapArgs {
   GapState* state;     // [batch]
 };
 int gap_blocks(int64_t len);
+// ---- power method on E = H - U diag(lam_hat) U^T (Sec. 2.2 adaptive sketch), adaptive.hip ----
+struct PowerArgs {
+  VType vt;
+  int64_t n, batch;
+  const void* U;             // n x s_stride column-major per problem
+  int s_stride;              // also the lam_hat stride
+  const double* lamhat;
+  const int32_t* s_eff;      // retained columns per problem
+  const void* h;             // H v, n per problem
+  void* v;                   // the unit vector (updated in place by a step)
+  void* ev;                  // E v (the start vector before launch_power_start)
+  double* ut_part;           // [batch][kMaxS][pstride]
+  double* part2;             // [batch][2][pstride]
+  int pstride, nb;           // nb = power_blocks(n, pstride)
+  double* est;               // [batch] v^T E v of the last step
+};
+int power_blocks(int64_t n, int pstride);
+// Philox stream id of the power method's start vectors (key (seed, kPowerStream + problem)).
+constexpr uint64_t kPowerStream = 0x706F776572ull;
+// v = ev / ||ev|| (the start vector drawn into ev).
+hipError_t launch_power_start(const PowerArgs& a, hipStream_t st);
+// With h = H v: est = v^T E v, v <- E v / ||E v||.
+hipError_t launch_power_step(const PowerArgs& a, hipStream_t st);
 // f'(t), the folded s and the loss partials from the t partials.
 hipError_t launch_gap_elem(const GapArgs& a, hipStream_t st);
 // After A^T f'(t) is in ypart: ||.||_inf, ||v||_1, kappa, primal, dual, gap.

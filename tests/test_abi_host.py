@@ -194,3 +194,15 @@ def test_huber_entry_point_checks_its_arguments(abi):
     a = lib.genios_workspace_size(abi.OP_HUBER, C.byref(M), C.byref(q))
     b = lib.genios_workspace_size(abi.OP_LOGREG, C.byref(M), C.byref(q))
     assert a == b > 0
+
+
+def test_adaptive_sketch_options_defaults_and_checks(abi):
+    o = abi.default_opts()
+    assert o.adaptive_sketch == 0 and o.sketch_rank_init == 8 and o.sketch_kappa == 10.0
+    assert o.power_iters == 10
+    M = _mat(abi)
+    for field, bad in (("adaptive_sketch", 2), ("sketch_rank_init", 0), ("sketch_kappa", 1.0),
+                       ("sketch_kappa", float("nan")), ("power_iters", 0), ("power_iters", 1001)):
+        q = abi.default_opts()
+        setattr(q, field, bad)
+        assert _solve(abi, M, q) == abi.ERR_ARG, field

@@ -4,10 +4,13 @@ import pytest
 import torch
 
 import genios_data
+from oracle import adaptive as oadapt
 from oracle import adjoint as oadj
 from oracle import huber as ohuber
 from oracle import lasso as olasso
 from oracle import logreg as ologreg
+from oracle import nystrom as nystrom_o
+from oracle import philox
 from oracle import residuals as ores
 
 pytestmark = pytest.mark.gpu
@@ -541,3 +544,86 @@ def test_huber_with_large_delta_is_twice_the_lasso(g, cfg1):
     F = olasso.objective(A, b, P["lam"], z)
     assert _rel(F, P["sol"]["F"]) <= 1e-10, (F, P["sol"]["F"])
     assert abs(out["info"][0]["obj"] - 2.0 * F) <= 1e-10 * F
+
+
+# ---- adaptive sketch size (Sec. 2.2): doubling rule on the kappa bound ----
+
+SEED = 0x5EED2310  # the library's default opts.seed
+
+
+def _adaptive_case():
+    P = genios_data.lasso_decay(300, 1200, 30, seed=2)
+    return P["A"], P["b"], P["lam"]
+
+
+def _oracle_bound_at(H, r, nu, q, problem, u, thresh):
+    n = H.shape[0]
+    Om = philox.gaussian_matrix(n, r, SEED, problem).astype(np.float64)
+    v0 = philox.gaussian_matrix(n, 1, SEED, oadapt.POWER_STREAM + problem)[:, 0].astype(np.float64)
+    U, lam = oadapt.sketch_at(H, Om, u, thresh)
+    err = oadapt.power_norm(lambda v: H @ v - U @ (lam * (U.T @ v)), v0, q)
+    return lam.size, err, nystrom_o.kappa_bound(lam, err, nu)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adaptive_sketch_size_matches_oracle(g, prec):
+    print("adaptive sketch", prec, flush=True)
+    A, b, lam = _adaptive_case()
+    rho, q, target = 0.03, 10, 10.0
+    A64 = A.astype(np.float64)
+    H = A64.T @ A64
+    u, thresh = (2.0 ** -53, 1e-13) if prec == "f64" else (2.0 ** -24, 1e-6)
+    ref = oadapt.adaptive_sketch(H, rho + 1e-6, 4, 64, target, q, SEED, 0, u, thresh)
+    assert ref["rank"] == 32 and len(ref["history"]) == 4  # 4, 8, 16, 32
+    At, bt = (_t(A64), _t(b.astype(np.float64))) if prec == "f64" else (_t(A), _t(b))
+    out = g.lasso_solve(At, bt, lam, rho=rho, precision=prec, max_iter=1, adaptive_sketch=1,
+                        sketch_rank=64, sketch_rank_init=4, sketch_kappa=target, power_iters=q)
+    info = out["info"][0]
+    assert info["sketch_rounds"] == 4, info
+    assert info["precond_rank"] == ref["lam"].size, (info["precond_rank"], ref["lam"].size)
+    tol = 1e-9 if prec == "f64" else 2e-4
+    assert abs(info["sketch_err"] - ref["err"]) <= tol * ref["err"], (info["sketch_err"], ref["err"])
+    assert abs(info["kappa_bound"] - ref["bound"]) <= tol * ref["bound"]
+
+
+def test_adaptive_sketch_batch_grows_to_the_largest_need(g):
+    # problem 1 is a scaled copy (H / 4): it meets the target earlier, but the batch
+    # shares the size, so both report the bound at the size problem 0 needs
+    print("adaptive sketch batch", flush=True)
+    A, b, lam = _adaptive_case()
+    A2 = np.stack([A, 0.5 * A]).astype(np.float64)
+    B2 = np.stack([b, b]).astype(np.float64)
+    rho, q, target = 0.03, 10, 10.0
+    out = g.lasso_solve(_t(A2), _t(B2), lam, rho=rho, precision="f64", max_iter=1,
+                        adaptive_sketch=1, sketch_rank=64, sketch_rank_init=4,
+                        sketch_kappa=target, power_iters=q)
+    infos = out["info"]
+    own = []
+    for p in range(2):
+        H = A2[p].T @ A2[p]
+        ref = oadapt.adaptive_sketch(H, rho + 1e-6, 4, 64, target, q, SEED, p, 2.0 ** -53, 1e-13)
+        own.append(ref["rank"])
+        keep, err, bound = _oracle_bound_at(H, 32, rho + 1e-6, q, p, 2.0 ** -53, 1e-13)
+        assert infos[p]["precond_rank"] == keep
+        assert abs(infos[p]["sketch_err"] - err) <= 1e-9 * err
+        assert abs(infos[p]["kappa_bound"] - bound) <= 1e-9 * bound
+        assert infos[p]["sketch_rounds"] == 4
+    assert own[0] == 32 and own[1] < 32
+
+
+def test_adaptive_sketch_solve_reaches_the_same_optimum(g):
+    print("adaptive sketch solve", flush=True)
+    A, b, lam = _adaptive_case()
+    ref = olasso.solve(A, b, lam)
+    # rho = 0.03: the rule grows the sketch to 32 (4, 8, 16, 32) before the first iteration
+    out = g.lasso_solve(_t(A), _t(b), lam, rho=0.03, precision="f32", eps=1e-6,
+                        adaptive_sketch=1, sketch_rank=64, sketch_rank_init=4)
+    info = out["info"][0]
+    assert out["status"] == 0, info
+    assert info["sketch_rounds"] == 4 and info["kappa_bound"] <= 10.0, info
+    z = out["z"].cpu().numpy().astype(np.float64)
+    F = olasso.objective(A.astype(np.float64), b.astype(np.float64), lam, z)
+    assert _rel(F, ref["F"]) <= 1e-6, (F, ref["F"])
+    # without the rule the reported rank is the retained rank of the fixed-size sketch
+    out2 = g.lasso_solve(_t(A), _t(b), lam, precision="f32", eps=1e-6, sketch_rank=20)
+    assert 1 <= out2["info"][0]["precond_rank"] <= 20 and out2["info"][0]["sketch_rounds"] == 1
