@@ -27,8 +27,9 @@ runs only a few Nystrom builds of the workload's BF16 operator (the sketch
 products on the matrix cores), for counter passes over those kernels.
 
 After the timed steps, `next_rows` times (once warm, outside the timed region)
-the elastic net and the duality-gap termination on the same workload and
-Huber fitting at n = 16000 under the paper's stopping rule (--no-next skips them).
+the elastic net, the duality-gap termination and the adaptive sketch size on the
+same workload and Huber fitting at n = 16000 under the paper's stopping rule
+(--no-next skips them).
 """
 from __future__ import annotations
 
@@ -161,8 +162,10 @@ def _solve_record(info, target_key="t_to_target"):
 
 def next_rows(g, torch, A, b, lam, s):
     """The rows built after the headline path, each measured once warm:
-    elastic net (Sec. 4.1's lambda2 = lambda1) and duality-gap termination on the
-    headline workload, and Huber fitting at the paper's largest size (n = 16000,
+    elastic net (Sec. 4.1's lambda2 = lambda1), duality-gap termination and the
+    adaptive sketch size (Sec. 2.2; sizes 8, 16, ... up to 128, kappa bound <= 10 and
+    <= 1.2) on
+    the headline workload, and Huber fitting at the paper's largest size (n = 16000,
     N = 8000, no preconditioner) under its own stopping rule, dist(0, dF(z)) <= 1e-4."""
     import genios_data
     out = {}
@@ -170,13 +173,24 @@ def next_rows(g, torch, A, b, lam, s):
     for _ in range(2):
         en = g.lasso_solve(A, b, lam, eps=1e-4, lambda2=lam, **kw)["info"][0]
     out["elastic_net"] = dict(_solve_record(en), lambda2=lam, eps=1e-4,
-                              rel_gap=en["rel_gap"])
+                              rel_gap=en["rel_gap"], precond_s=round(en["t_precond"], 4))
     log(f"elastic net: {out['elastic_net']}")
     # (thousands of iterations here: one run, the kernels are warm from the one above)
     gp = g.lasso_solve(A, b, lam, termination=1, eps_gap=1e-4, **kw)["info"][0]
     out["gap_termination"] = dict(_solve_record(gp), eps_gap=1e-4, rel_gap=gp["rel_gap"],
                                   gap_checks=gp["gap_checks"])
     log(f"gap termination: {out['gap_termination']}")
+    for target in (10.0, 1.2):
+        for _ in range(2):
+            ad = g.lasso_solve(A, b, lam, eps=1e-4, precision="bf16_refine", profile_kernels=1,
+                               adaptive_sketch=1, sketch_rank=128, sketch_rank_init=8,
+                               sketch_kappa=target)["info"][0]
+        key = f"adaptive_sketch_kappa{target:g}"
+        out[key] = dict(_solve_record(ad), rank_cap=128, rank_init=8, kappa_target=target,
+                        chosen_rank=ad["precond_rank"], sizes_tried=ad["sketch_rounds"],
+                        kappa_bound=ad["kappa_bound"], sketch_err=ad["sketch_err"],
+                        precond_s=round(ad["t_precond"], 4))
+        log(f"{key}: {out[key]}")
     t0 = time.time()
     H = genios_data.huber_outliers(16000, seed=6)
     Ah = torch.from_numpy(H["A"]).to(A.device)
@@ -340,6 +354,7 @@ def main():
         "time_to_1e-4_s": {"bf16_refine": round(statistics.median(ttt), 4),
                            "fp32": fp32["time_to_1e-4_s"] if fp32 else None},
         "admm_iters": statistics.median(iters),
+        "precond_s": round(statistics.median(i["t_precond"] for i in infos), 4),
         "fp32": fp32,
         "roofline": roofline,
         "sketch_gemm": sketch,
