@@ -191,6 +191,21 @@ def huber_outliers(n: int = 2000, seed: int = 6, s: int = 0) -> dict:
                 name=f"huber_{m}x{n}")
 
 
+def boxls_decay(m: int = 20000, n: int = 10000, seed: int = 8, s: int = 50,
+                noise: float = 0.01) -> dict:
+    """Bounded least squares data: A = G diag(j^-1/2) / sqrt(m) with G iid N(0, 1) (a
+    dense matrix with a decaying spectrum, N = m samples and n = N/2 features in the
+    paper's runs), x0 ~ U(-0.5, 1.5)^n, b = A x0 + noise N(0, 1); bounds 0 <= x <= 1."""
+    G = _gaussian_rows(seed, _STREAM_MATRIX, m, n)
+    j = np.arange(1, n + 1, dtype=np.float64)
+    A = _scale_columns_inplace(G, j ** -0.5 / math.sqrt(m))
+    rng = np.random.default_rng([seed, _STREAM_MISC])
+    x0 = rng.uniform(-0.5, 1.5, size=n)
+    b = (matvec_f64(A, x0) + noise * rng.standard_normal(m)).astype(np.float32)
+    return dict(kind="boxls", A=A, b=b, lo=np.zeros(n), hi=np.ones(n), x0=x0, s=s, rho=1.0,
+                lam=0.0, name=f"boxls_{m}x{n}")
+
+
 def lasso_batch(batch: int = 64, m: int = 2000, n: int = 8000, k: int = 80,
                 seed0: int = 5000, s: int = 50) -> dict:
     """`batch` independent decaying-spectrum Lasso problems, problem j seeded seed0 + j."""
