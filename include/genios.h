@@ -84,7 +84,8 @@ typedef enum {
   GENIOS_OP_BACKWARD = 3,
   GENIOS_OP_MATVEC = 4,
   GENIOS_OP_HVP = 5,
-  GENIOS_OP_HUBER = 6
+  GENIOS_OP_HUBER = 6,
+  GENIOS_OP_BOXLS = 7
 } genios_op;
 
 /* Dense data matrix (or a batch of them).  m rows (samples) by n columns
@@ -276,6 +277,21 @@ int genios_logreg_solve(const genios_matrix* A, const void* y, const double* lam
  * |v| <= 2 delta (App. A).  b m per problem; other arguments as genios_lasso_solve. */
 int genios_huber_solve(const genios_matrix* A, const void* b, const double* lambda, double rho,
                        const genios_opts* o, void* x, void* z, void* u, genios_info* info);
+
+/* Box-constrained least squares (Sec. 4.5, bounded least squares, through the QP
+ * form of Sec. 3.2 with P = A^T A, q = -A^T b, M = I):
+ *   minimize (1/2)||A x - b||^2  subject to  lo <= x <= hi.
+ * The x-system is the Lasso's ((A^T A + (rho + sigma) I) x = rhs, Nystrom-preconditioned
+ * CG); the z-step projects onto the box.
+ *   lo, hi   (device) n per problem in the vector dtype, or NULL for -inf / +inf;
+ *            lo <= hi is the caller's to ensure (where lo > hi, z takes hi).
+ * opts->lambda2 must be 0.  The duality gap and the termination rules use the dual of
+ * this split (the box's support function, App. A's construction) and, for
+ * termination = 2, the distance from 0 to grad f(z) + the box's normal cone at z.
+ * z is the feasible solution; other arguments as genios_lasso_solve. */
+int genios_boxls_solve(const genios_matrix* A, const void* b, const void* lo, const void* hi,
+                       double rho, const genios_opts* o, void* x, void* z, void* u,
+                       genios_info* info);
 
 /* Randomized Nystrom approximation (Sec. 2.2) of H = A^T diag(d) A (d == NULL:
  * H = A^T A) with an n x s test matrix Omega:

@@ -100,8 +100,9 @@ def admm(A, b, lo, hi, rho=1.0, alpha=1.0, sigma=0.0, max_iter=500, eps=None,
 def support_term(w, lo, hi):
     """sum_j max(lo_j w_j, hi_j w_j) (0 * inf = 0: a zero w_j adds nothing)."""
     w = _f64(w)
-    a = np.where(w == 0, 0.0, lo * w)
-    c = np.where(w == 0, 0.0, hi * w)
+    with np.errstate(invalid="ignore"):
+        a = np.where(w == 0, 0.0, lo * w)
+        c = np.where(w == 0, 0.0, hi * w)
     return float(np.sum(np.maximum(a, c)))
 
 

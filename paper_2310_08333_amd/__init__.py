@@ -7,9 +7,9 @@ kernels; importing this package fails if the library has not been built.
 
 Functions
 ---------
-lasso_solve, logreg_solve, huber_solve
+lasso_solve, logreg_solve, huber_solve, boxls_solve
                                the solvers (Sec. 3.1 / Sec. 4.1 Lasso, Sec. 4.2 logistic,
-                               Sec. 4.3 Huber fitting)
+                               Sec. 4.3 Huber fitting, Sec. 4.5 bounded least squares)
 nystrom_build, nystrom_apply   the randomized Nystrom preconditioner (Sec. 2.2)
 lasso_backward, GeniosLasso    adjoint of the Lasso solution map (torch.autograd.Function)
 matvec, cast_bf16, gaussian_matrix, admm_update   single-kernel entry points
@@ -24,7 +24,7 @@ import torch
 from . import _abi
 from ._abi import GeniosError, Info
 
-__all__ = ["lasso_solve", "logreg_solve", "huber_solve", "nystrom_build", "nystrom_apply", "lasso_backward",
+__all__ = ["lasso_solve", "logreg_solve", "huber_solve", "boxls_solve", "nystrom_build", "nystrom_apply", "lasso_backward",
            "GeniosLasso", "lasso", "matvec", "cast_bf16", "gaussian_matrix", "admm_update",
            "workspace_size", "make_opts", "GeniosError"]
 
@@ -101,7 +101,20 @@ def _infos(arr, batch):
     return [arr[i].as_dict() for i in range(batch)]
 
 
-def _solve(kind, A, vec, lam, rho, A16, x0, z0, u0, history, **kw):
+def _bound(v, shape, dtype, dev, name):
+    """None (unbounded), a scalar, or a tensor of the solution's shape -> device tensor or None."""
+    if v is None:
+        return None
+    if isinstance(v, (int, float)):
+        return torch.full(shape, float(v), dtype=dtype, device=dev)
+    t = torch.as_tensor(v, dtype=dtype, device=dev)
+    try:
+        return torch.broadcast_to(t, shape).contiguous()
+    except RuntimeError as e:
+        raise ValueError(f"{name} must broadcast to {tuple(shape)}") from e
+
+
+def _solve(kind, A, vec, lam, rho, A16, x0, z0, u0, history, box=None, **kw):
     dev = A.device
     M = _matrix(A, A16)
     o = make_opts(A.dtype, **kw)
@@ -121,12 +134,20 @@ def _solve(kind, A, vec, lam, rho, A16, x0, z0, u0, history, **kw):
         hist = np.zeros((B, int(history), _abi.HIST_FIELDS))
         o.history = hist.ctypes.data_as(C.POINTER(C.c_double))
         o.history_cap = int(history)
-    op = {"lasso": _abi.OP_LASSO, "logreg": _abi.OP_LOGREG, "huber": _abi.OP_HUBER}[kind]
+    op = {"lasso": _abi.OP_LASSO, "logreg": _abi.OP_LOGREG, "huber": _abi.OP_HUBER,
+          "boxls": _abi.OP_BOXLS}[kind]
     ws = _attach_workspace(o, workspace_size(op, M, o), dev)
     infos = (Info * B)()
     fn = getattr(_lib, f"genios_{kind}_solve")
-    rc = fn(C.byref(M), _ptr(vec), lam_h.ctypes.data_as(C.POINTER(C.c_double)), float(rho),
-            C.byref(o), _ptr(x), _ptr(z), _ptr(u), infos)
+    if kind == "boxls":
+        lo = _bound(box[0], shape, A.dtype, dev, "lo")
+        hi = _bound(box[1], shape, A.dtype, dev, "hi")
+        rc = fn(C.byref(M), _ptr(vec), _ptr(lo) if lo is not None else None,
+                _ptr(hi) if hi is not None else None, float(rho), C.byref(o), _ptr(x), _ptr(z),
+                _ptr(u), infos)
+    else:
+        rc = fn(C.byref(M), _ptr(vec), lam_h.ctypes.data_as(C.POINTER(C.c_double)), float(rho),
+                C.byref(o), _ptr(x), _ptr(z), _ptr(u), infos)
     del ws
     if rc < 0:
         raise GeniosError(rc, f"genios_{kind}_solve")
@@ -156,6 +177,13 @@ def huber_solve(A, b, lam, rho=1.0, A16=None, x0=None, z0=None, u0=None, history
     """l1-regularised Huber fitting sum l(a_i^T x - b_i) + lam ||x||_1, l(r) = r^2 for
     |r| <= huber_delta (default 1), 2 delta |r| - delta^2 beyond (Sec. 4.3)."""
     return _solve("huber", A, b, lam, rho, A16, x0, z0, u0, history, **kw)
+
+
+def boxls_solve(A, b, lo=0.0, hi=1.0, rho=1.0, A16=None, x0=None, z0=None, u0=None, history=0,
+                **kw):
+    """Box-constrained least squares (1/2)||Ax - b||^2, lo <= x <= hi (Sec. 4.5 through the
+    QP form of Sec. 3.2).  lo/hi: None (unbounded), a scalar or a tensor of x's shape."""
+    return _solve("boxls", A, b, 0.0, rho, A16, x0, z0, u0, history, box=(lo, hi), **kw)
 
 
 def nystrom_build(A, s, d=None, omega=None, A16=None, **kw):

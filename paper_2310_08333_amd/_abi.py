@@ -24,7 +24,7 @@ ERR_UNSUPPORTED = -7
 
 DT_F32, DT_BF16, DT_F64 = 0, 1, 2
 PREC_F64, PREC_F32, PREC_BF16_REFINE, PREC_BF16_ONLY = 0, 1, 2, 3
-OP_LASSO, OP_LOGREG, OP_NYSTROM, OP_BACKWARD, OP_MATVEC, OP_HVP, OP_HUBER = 0, 1, 2, 3, 4, 5, 6
+OP_LASSO, OP_LOGREG, OP_NYSTROM, OP_BACKWARD, OP_MATVEC, OP_HVP, OP_HUBER, OP_BOXLS = range(8)
 
 HIST_FIELDS = 10
 HIST_NAMES = ("k", "r_p", "r_d", "r_kkt", "rho", "cg", "rtol", "phase", "time", "xnorm")
@@ -92,7 +92,7 @@ class Info(C.Structure):
 
 EXPORTED = (
     "genios_default_opts", "genios_workspace_size", "genios_lasso_solve", "genios_logreg_solve",
-    "genios_huber_solve",
+    "genios_huber_solve", "genios_boxls_solve",
     "genios_nystrom_build", "genios_nystrom_apply", "genios_lasso_backward", "genios_matvec",
     "genios_hvp",
     "genios_cast_bf16", "genios_stream_read", "genios_gaussian_matrix", "genios_admm_update", "genios_status_string",
@@ -122,6 +122,8 @@ def load(path: str | None = None):
         f = getattr(lib, name)
         f.argtypes = [P(Matrix), vp, P(dbl), dbl, P(Opts), vp, vp, vp, P(Info)]
         f.restype = C.c_int
+    lib.genios_boxls_solve.argtypes = [P(Matrix), vp, vp, vp, dbl, P(Opts), vp, vp, vp, P(Info)]
+    lib.genios_boxls_solve.restype = C.c_int
     lib.genios_nystrom_build.argtypes = [P(Matrix), vp, i32, vp, P(Opts), vp, vp, P(Info)]
     lib.genios_nystrom_build.restype = C.c_int
     lib.genios_nystrom_apply.argtypes = [i64, i32, i64, i32, vp, vp, dbl, vp, vp, P(Opts)]

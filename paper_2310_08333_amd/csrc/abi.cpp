@@ -171,6 +171,7 @@ size_t genios_workspace_size(int op, const genios_matrix* A, const genios_opts* 
     case GENIOS_OP_LASSO:
     case GENIOS_OP_LOGREG:
     case GENIOS_OP_HUBER:
+    case GENIOS_OP_BOXLS:
     case GENIOS_OP_BACKWARD:
       s = o->precondition ? effective_rank(o, A->n, A->m) : 0;
       break;
@@ -225,6 +226,25 @@ int genios_huber_solve(const genios_matrix* A, const void* b, const double* lamb
   if (!(rho > 0.0) || !std::isfinite(rho)) FAIL(GENIOS_ERR_ARG, "rho must be finite and > 0");
   if ((rc = check_ws(GENIOS_OP_HUBER, A, o))) return rc;
   return run_admm(A, b, lambda, rho, o, x, z, u, info, kLossHuber);
+}
+
+int genios_boxls_solve(const genios_matrix* A, const void* b, const void* lo, const void* hi,
+                       double rho, const genios_opts* o, void* x, void* z, void* u,
+                       genios_info* info) {
+  int rc;
+  if ((rc = check_matrix(A)) || (rc = check_opts(o)) || (rc = check_precision_vs_dtype(A, o)))
+    return rc;
+  if (b == nullptr || x == nullptr || z == nullptr || u == nullptr || info == nullptr)
+    FAIL(GENIOS_ERR_ARG, "b, x, z, u and info must be non-NULL");
+  if (o->lambda2 != 0.0) FAIL(GENIOS_ERR_UNSUPPORTED, "the box path takes no l2 term (lambda2 = 0)");
+  if (!(rho > 0.0) || !std::isfinite(rho)) FAIL(GENIOS_ERR_ARG, "rho must be finite and > 0");
+  if ((rc = check_ws(GENIOS_OP_BOXLS, A, o))) return rc;
+  std::vector<double> zero((size_t)A->batch, 0.0);
+  ProxSpec box;
+  box.kind = kProxBox;
+  box.lo = lo;
+  box.hi = hi;
+  return run_admm(A, b, zero.data(), rho, o, x, z, u, info, kLossSquare, box);
 }
 
 int genios_nystrom_build(const genios_matrix* A, const void* d, int32_t s, const void* omega,

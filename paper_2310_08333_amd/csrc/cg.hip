@@ -500,6 +500,9 @@ __global__ __launch_bounds__(256) void k_admm_end(VecArgs a) {
   VT* u = static_cast<VT*>(a.u) + off;
   const VT* h = static_cast<const VT*>(a.h) + off;
   const VT* c = P.use_c ? static_cast<const VT*>(a.c) + off : nullptr;
+  const bool box = P.prox == kProxBox;
+  const VT* lo = box && a.lo ? static_cast<const VT*>(a.lo) + off : nullptr;
+  const VT* hi_b = box && a.hi ? static_cast<const VT*>(a.hi) + off : nullptr;
   __shared__ double red[7 * 4];
   const VT al = VT(P.alpha), one_m = VT(1.0 - P.alpha), kap = VT(P.kappa), rho = VT(P.rho);
   double s_rp = 0, s_x = 0, s_z = 0, s_u = 0, s_rd = 0, s_z1 = 0, s_nnz = 0;
@@ -507,7 +510,14 @@ __global__ __launch_bounds__(256) void k_admm_end(VecArgs a) {
     const VT xi = x[i], zi = z[i], ui = u[i];
     const VT hi = c ? h[i] : VT(0), ci = c ? c[i] : VT(0);
     const VT xh = al * xi + one_m * zi;
-    const VT zn = soft_threshold<VT>(xh + ui, kap);
+    VT zn;
+    if (box) {  // projection onto the box (Sec. 3.2)
+      zn = xh + ui;
+      if (lo) zn = zn < lo[i] ? lo[i] : zn;
+      if (hi_b) zn = zn > hi_b[i] ? hi_b[i] : zn;
+    } else {
+      zn = soft_threshold<VT>(xh + ui, kap);
+    }
     const VT un = ui + xh - zn;
     z[i] = zn;
     u[i] = un;

@@ -153,10 +153,11 @@ int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_)
   vt = A->hi_dtype == GENIOS_DT_F64 ? VT_F64 : VT_F32;
   ml = op == GENIOS_OP_LOGREG || op == GENIOS_OP_HUBER;
   backward = op == GENIOS_OP_BACKWARD;
-  gap = op == GENIOS_OP_LASSO || ml;
+  gap = op == GENIOS_OP_LASSO || op == GENIOS_OP_BOXLS || ml;
   s = s_;
   const int prec = o->precision;
-  const bool uses_lo = (op == GENIOS_OP_LASSO || ml || op == GENIOS_OP_NYSTROM ||
+  const bool uses_lo = (op == GENIOS_OP_LASSO || op == GENIOS_OP_BOXLS || ml ||
+                        op == GENIOS_OP_NYSTROM ||
                         op == GENIOS_OP_MATVEC || op == GENIOS_OP_HVP) &&
                        (prec == GENIOS_PREC_BF16_REFINE || prec == GENIOS_PREC_BF16_ONLY);
   need_a16 = uses_lo && A->A_bf16 == nullptr;
@@ -168,7 +169,7 @@ int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_)
   nrhs = ml ? 2 : 1;
   ksplit = std::max(gemv_t_splits(probe, batch), uses_lo ? gemv_t_splits(probe_lo, batch) : 1);
   // partial slots of A^T products: gemv_t's row splits or the fused H p's blocks
-  const bool cg_op = op == GENIOS_OP_LASSO || ml ||
+  const bool cg_op = op == GENIOS_OP_LASSO || op == GENIOS_OP_BOXLS || ml ||
                      op == GENIOS_OP_BACKWARD || op == GENIOS_OP_HVP;
   yslots = std::max<int64_t>((int64_t)ksplit * (ml ? 2 : 1),
                              cg_op ? std::max<int64_t>(1, kHvpMaxBlocks / batch) : 1);
@@ -288,6 +289,8 @@ struct Ctx {
   int32_t* gate_done = nullptr;  // &state[0].admm_done
   int32_t* gate_run = nullptr;   // &params[0].run
   int gs_state = sizeof(ProbState) / 4, gs_params = sizeof(ProbParams) / 4;
+  const void* box_lo = nullptr;  // box bounds of a kProxBox solve (n per problem)
+  const void* box_hi = nullptr;
   KernelProf prof;
   int64_t n_mv[4] = {0, 0, 0, 0};
   // bytes of A v / A^T w (the matrix) and of the fused H p on the BF16 / master copy
@@ -340,6 +343,8 @@ struct Ctx {
     a.ypart_ks_stride = (int64_t)L.nrhs * L.npad;
     a.ypart_prob_stride = L.yprob();
     a.mask = mask;
+    a.lo = box_lo;
+    a.hi = box_hi;
     return a;
   }
 
@@ -514,7 +519,8 @@ int cg_iteration(Ctx& c, const MatArg& op, const VecArgs& va, const void* dscale
 }  // namespace
 
 int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, double rho0,
-             const genios_opts* o, void* x, void* z, void* u, genios_info* info, int loss) {
+             const genios_opts* o, void* x, void* z, void* u, genios_info* info, int loss,
+             const ProxSpec& prox) {
   // ml: the loss has curvature D = f''(A x - b) that changes with x (Sec. 3.3)
   const bool ml = loss != kLossSquare;
   const double delta = o->huber_delta;
@@ -530,8 +536,12 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
   c.ve = c.vt == VT_F32 ? 4 : 8;
   const int s = o->precondition ? effective_rank(o, A->n, A->m) : 0;
   c.L.setup(loss == kLossLogistic ? GENIOS_OP_LOGREG
-                                  : (loss == kLossHuber ? GENIOS_OP_HUBER : GENIOS_OP_LASSO),
+            : loss == kLossHuber    ? GENIOS_OP_HUBER
+            : prox.kind == kProxBox ? GENIOS_OP_BOXLS
+                                    : GENIOS_OP_LASSO,
             A, o, s);
+  c.box_lo = prox.kind == kProxBox ? prox.lo : nullptr;
+  c.box_hi = prox.kind == kProxBox ? prox.hi : nullptr;
   int rc = c.L.bind(o->workspace, o->workspace_bytes);
   if (rc) return rc;
   c.prof.on = o->profile_kernels != 0;
@@ -604,6 +614,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
       q.max_cg = o->max_cg_iter;
       q.rhs_rel = o->rhs_relative;
       q.use_c = ml ? 0 : 1;
+      q.prox = prox.kind;
     }
   };
 
@@ -678,6 +689,8 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     ga.yprob = c.L.yprob();
     ga.v = v;
     ga.params = c.L.ctrl.params;
+    ga.lo = c.box_lo;
+    ga.hi = c.box_hi;
     ga.part = c.L.gpart;
     ga.state = c.L.gstate;
     HC(launch_gap_elem(ga, c.st));

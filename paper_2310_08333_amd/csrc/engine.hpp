@@ -75,8 +75,16 @@ struct Layout {
 };
 
 int effective_rank(const genios_opts* o, int64_t n, int64_t m);
+// z-step of the solve: soft-threshold (l1) or projection onto [lo, hi] (device
+// n-vectors per problem, nullable for an unbounded side).
+struct ProxSpec {
+  int kind = kProxL1;
+  const void* lo = nullptr;
+  const void* hi = nullptr;
+};
 int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, double rho0,
-             const genios_opts* o, void* x, void* z, void* u, genios_info* info, int loss);
+             const genios_opts* o, void* x, void* z, void* u, genios_info* info, int loss,
+             const ProxSpec& prox = ProxSpec{});
 int run_nystrom_build(const genios_matrix* A, const void* d, int s, const void* omega,
                       const genios_opts* o, void* U, double* lamhat, genios_info* info);
 int run_matvec(const genios_matrix* A, int trans, int use_bf16, const void* v, void* out,

@@ -16,6 +16,9 @@
 // with the l2 term (lambda2 > 0) the dual is finite for every nu: kappa = 1
 // and g gains -(1 / (2 lambda2)) ||(|A^T nu| - lam)_+||^2, while l(x) gains
 // (lambda2 / 2) ||x||^2,
+// with a box instead of the l1 term (box-constrained least squares, the QP of
+// Sec. 3.2 with M = I), nu = t - b unscaled and g(nu) = -||nu||^2 / 2 - b^T nu -
+// sum_j max(lo_j w_j, hi_j w_j), w = -A^T nu (the box's support function),
 // so l(x) - g(nu) >= l(x) - l(x*) and the relative gap is
 // (l(x) - g(nu)) / min(l(x), |g(nu)|) (Sec. 3.3).
 //
@@ -134,14 +137,19 @@ __global__ __launch_bounds__(kGapThreads) void k_gap_elem(
 // partials, ||v||_1, ||v||^2, and the squared distance from 0 to
 // grad f(v) + lambda d||v||_1 (grad f = A^T f'(t) + lambda2 v): per entry
 // grad_j + lambda sign(v_j) where v_j != 0, (|grad_j| - lambda)_+ where v_j = 0.
+// Box: the support-function terms instead of the excess, and the distance from 0
+// to grad f(v) + the box's normal cone at v.
 template <typename VT>
 __global__ __launch_bounds__(kGapThreads) void k_gap_inf(
     int64_t n, const VT* __restrict__ ypart, int ks, int64_t ks_stride, int64_t prob_stride,
-    const VT* __restrict__ v, const ProbParams* __restrict__ params, double* __restrict__ part,
-    int pstride) {
+    const VT* __restrict__ v, const ProbParams* __restrict__ params, const VT* __restrict__ lo_all,
+    const VT* __restrict__ hi_all, double* __restrict__ part, int pstride) {
   __shared__ double sm[4];
   const int b = blockIdx.y;
   const double lam = params[b].lambda, lam2 = params[b].lambda2;
+  const bool box = params[b].prox == kProxBox;
+  const VT* lo = box && lo_all ? lo_all + (int64_t)b * n : nullptr;
+  const VT* hi = box && hi_all ? hi_all + (int64_t)b * n : nullptr;
   const VT* yp = ypart + (int64_t)b * prob_stride;
   const VT* vb = v + (int64_t)b * n;
   double gmax = 0.0, l1 = 0.0, x2 = 0.0, ex2 = 0.0, sd2 = 0.0;
@@ -150,14 +158,26 @@ __global__ __launch_bounds__(kGapThreads) void k_gap_inf(
     double g = 0.0;
     for (int k = 0; k < ks; ++k) g += (double)yp[(int64_t)k * ks_stride + j];
     gmax = fmax(gmax, fabs(g));
-    const double e = fmax(fabs(g) - lam, 0.0);
-    ex2 += e * e;
     const double vj = (double)vb[j];
     l1 += fabs(vj);
     x2 += vj * vj;
     const double gf = g + lam2 * vj;
-    const double sd = vj != 0.0 ? gf + copysign(lam, vj) : fmax(fabs(gf) - lam, 0.0);
-    sd2 += sd * sd;
+    if (box) {
+      // support function of the box at w = -g, and the normal-cone distance at v
+      const double w = -g;
+      const double lj = lo ? (double)lo[j] : -INFINITY, hj = hi ? (double)hi[j] : INFINITY;
+      if (w > 0.0) ex2 += hj * w;
+      else if (w < 0.0) ex2 += lj * w;
+      const bool at_lo = lo && vj <= lj, at_hi = hi && vj >= hj;
+      const double sd = (at_lo && at_hi) ? 0.0
+                        : at_lo ? fmax(-gf, 0.0) : (at_hi ? fmax(gf, 0.0) : fabs(gf));
+      sd2 += sd * sd;
+    } else {
+      const double e = fmax(fabs(g) - lam, 0.0);
+      ex2 += e * e;
+      const double sd = vj != 0.0 ? gf + copysign(lam, vj) : fmax(fabs(gf) - lam, 0.0);
+      sd2 += sd * sd;
+    }
   }
   gmax = block_max1(gmax, sm);
   l1 = block_sum1(l1, sm);
@@ -196,9 +216,11 @@ __global__ __launch_bounds__(64) void k_gap_kappa(const double* __restrict__ par
     G.x2 = x2;
     G.excess2 = ex2;
     G.subgrad = sqrt(sd2);
-    // lambda2 > 0: g is finite for every nu, nu = f'(t) unscaled (App. A)
-    G.kappa = lam2 > 0.0 ? 1.0 : (ginf > lam ? lam / ginf : 1.0);
-    G.reg = lam2 > 0.0 ? -ex2 / (2.0 * lam2) : 0.0;
+    // lambda2 > 0: g is finite for every nu, nu = f'(t) unscaled (App. A); box: the
+    // dual of the split is finite wherever the support function is, nu = f'(t)
+    const bool box = params[b].prox == kProxBox;
+    G.kappa = (lam2 > 0.0 || box) ? 1.0 : (ginf > lam ? lam / ginf : 1.0);
+    G.reg = box ? -ex2 : (lam2 > 0.0 ? -ex2 / (2.0 * lam2) : 0.0);
     G.primal = loss + lam * l1 + 0.5 * lam2 * x2;
   }
 }
@@ -253,7 +275,8 @@ hipError_t gap_after_t_vt(const GapArgs& a, hipStream_t st) {
   const int nbm = gap_blocks(a.m), nbn = gap_blocks(a.n);
   hipLaunchKernelGGL((k_gap_inf<VT>), dim3(nbn, (unsigned)a.batch), dim3(kGapThreads), 0, st,
                      a.n, static_cast<const VT*>(a.ypart), a.ks, a.ks_stride, a.yprob,
-                     static_cast<const VT*>(a.v), a.params, a.part, kGapPStride);
+                     static_cast<const VT*>(a.v), a.params, static_cast<const VT*>(a.lo),
+                     static_cast<const VT*>(a.hi), a.part, kGapPStride);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gap_kappa, dim3((unsigned)a.batch), dim3(64), 0, st, a.part, kGapPStride,

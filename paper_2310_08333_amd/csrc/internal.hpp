@@ -48,7 +48,9 @@ struct alignas(128) ProbParams {
   int32_t max_cg;
   int32_t rhs_rel;   // 1: tolerance relative to ||rhs||, 0: relative to ||r_0||
   int32_t use_c;     // 1: gradient is h - c (Lasso); 0: gradient vector given
+  int32_t prox;      // z-step: kProxL1 (soft-threshold at kappa) or kProxBox (clamp to [lo, hi])
 };
+enum : int32_t { kProxL1 = 0, kProxBox = 1 };
 
 // Device-written state of one problem (read back by the host after each sync).
 struct alignas(128) ProbState {
@@ -185,6 +187,7 @@ struct VecArgs {
   int ksplit;
   int64_t ypart_ks_stride, ypart_prob_stride;
   const uint8_t* mask;    // masked operator (adjoint): 1 = in the active set
+  const void *lo, *hi;    // box bounds of kProxBox, n per problem (nullable: unbounded side)
 };
 // One x-solve: admm_begin; precond_coef, precond_step(init), p_update(init); then
 // per CG iteration t = 0, 1, ...: cg_alpha, cg_update(t), precond_coef,
@@ -224,7 +227,8 @@ struct GapState {
   double grad_inf;  // ||A^T f'(t)||_inf
   double l1;        // ||v||_1
   double x2;        // ||v||^2
-  double excess2;   // ||(|A^T f'(t)| - lambda)_+||^2
+  double excess2;   // ||(|A^T f'(t)| - lambda)_+||^2; box: the support function sum
+                    // sum_j max(lo_j w_j, hi_j w_j), w = -A^T f'(t)
   double kappa;     // lambda2 = 0: min(1, lambda / grad_inf); lambda2 > 0: 1
   double reg;       // lambda2 > 0: -excess2 / (2 lambda2), the dual's l2 part; else 0
   double primal;    // l(v) = loss + lambda ||v||_1 + (lambda2 / 2) ||v||^2
@@ -232,6 +236,7 @@ struct GapState {
   double gap;       // primal - dual
   double rel_gap;   // gap / min(primal, |dual|)
   double subgrad;   // ||.||_2 of the least-norm element of grad f(v) + lambda d||v||_1
+                    // (box: of grad f(v) + the normal cone of the box at v)
 };
 constexpr int kGapPStride = 256;  // block partials per reduction and problem
 constexpr int kGapSlots = 7;      // loss, inf, l1, conjugate sum, x2, excess2, subgrad^2
@@ -250,7 +255,8 @@ struct GapArgs {
   int ks;
   int64_t ks_stride, yprob;
   const void* v;       // the point, n per problem
-  const ProbParams* params;  // lambda
+  const ProbParams* params;  // lambda, lambda2, prox
+  const void *lo, *hi; // box bounds (prox = kProxBox), n per problem, nullable
   double* part;        // [batch][kGapSlots][kGapPStride]
   GapState* state;     // [batch]
 };

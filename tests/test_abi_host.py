@@ -206,3 +206,19 @@ def test_adaptive_sketch_options_defaults_and_checks(abi):
         q = abi.default_opts()
         setattr(q, field, bad)
         assert _solve(abi, M, q) == abi.ERR_ARG, field
+
+
+def test_boxls_entry_point_checks_its_arguments(abi):
+    lib = abi.load()
+    M = _mat(abi)
+    info = (abi.Info * 1)()
+    p = C.c_void_p(0x20000000)  # never dereferenced: the argument checks come first
+    q = abi.default_opts()
+    assert lib.genios_boxls_solve(C.byref(M), None, None, None, 1.0, C.byref(q), p, p, p, info) == abi.ERR_ARG
+    assert lib.genios_boxls_solve(C.byref(M), p, None, None, 0.0, C.byref(q), p, p, p, info) == abi.ERR_ARG
+    q.lambda2 = 0.5
+    assert lib.genios_boxls_solve(C.byref(M), p, None, None, 1.0, C.byref(q), p, p, p, info) == abi.ERR_UNSUPPORTED
+    q = abi.default_opts()
+    assert lib.genios_boxls_solve(C.byref(M), p, p, p, 1.0, C.byref(q), p, p, p, info) == abi.ERR_WORKSPACE
+    a = lib.genios_workspace_size(abi.OP_BOXLS, C.byref(M), C.byref(q))
+    assert a == lib.genios_workspace_size(abi.OP_LASSO, C.byref(M), C.byref(q)) > 0
