@@ -192,13 +192,14 @@ def huber_outliers(n: int = 2000, seed: int = 6, s: int = 0) -> dict:
 
 
 def boxls_decay(m: int = 20000, n: int = 10000, seed: int = 8, s: int = 50,
-                noise: float = 0.01) -> dict:
-    """Bounded least squares data: A = G diag(j^-1/2) / sqrt(m) with G iid N(0, 1) (a
-    dense matrix with a decaying spectrum, N = m samples and n = N/2 features in the
-    paper's runs), x0 ~ U(-0.5, 1.5)^n, b = A x0 + noise N(0, 1); bounds 0 <= x <= 1."""
+                noise: float = 0.01, scale: float = 10.0) -> dict:
+    """Bounded least squares data: A = scale G diag(j^-1/2) / sqrt(m) with G iid N(0, 1)
+    (a dense matrix with a decaying spectrum, top eigenvalue of A^T A ~ scale^2, N = m
+    samples and n = N/2 features in the paper's runs), x0 ~ U(-0.5, 1.5)^n,
+    b = A x0 + noise N(0, 1); bounds 0 <= x <= 1."""
     G = _gaussian_rows(seed, _STREAM_MATRIX, m, n)
     j = np.arange(1, n + 1, dtype=np.float64)
-    A = _scale_columns_inplace(G, j ** -0.5 / math.sqrt(m))
+    A = _scale_columns_inplace(G, scale * j ** -0.5 / math.sqrt(m))
     rng = np.random.default_rng([seed, _STREAM_MISC])
     x0 = rng.uniform(-0.5, 1.5, size=n)
     b = (matvec_f64(A, x0) + noise * rng.standard_normal(m)).astype(np.float32)
