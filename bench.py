@@ -28,8 +28,8 @@ products on the matrix cores), for counter passes over those kernels.
 
 After the timed steps, `next_rows` times (once warm, outside the timed region)
 the elastic net, the duality-gap termination and the adaptive sketch size on the
-same workload and Huber fitting at n = 16000 under the paper's stopping rule
-(--no-next skips them).
+same workload, Huber fitting at n = 16000 under the paper's stopping rule and
+the bounded least squares ablation at 32000 x 16000 (--no-next skips them).
 """
 from __future__ import annotations
 
@@ -165,8 +165,10 @@ def next_rows(g, torch, A, b, lam, s):
     elastic net (Sec. 4.1's lambda2 = lambda1), duality-gap termination and the
     adaptive sketch size (Sec. 2.2; sizes 8, 16, ... up to 128, kappa bound <= 10 and
     <= 1.2) on
-    the headline workload, and Huber fitting at the paper's largest size (n = 16000,
-    N = 8000, no preconditioner) under its own stopping rule, dist(0, dF(z)) <= 1e-4."""
+    the headline workload, Huber fitting at the paper's largest size (n = 16000,
+    N = 8000, no preconditioner) under its own stopping rule, dist(0, dF(z)) <= 1e-4,
+    and bounded least squares at the size of its ablation (N = 32000, n = 16000,
+    eps 1e-5) with and without the preconditioner and inexact solves."""
     import genios_data
     out = {}
     kw = dict(precision="bf16_refine", sketch_rank=s, profile_kernels=1)
@@ -204,6 +206,24 @@ def next_rows(g, torch, A, b, lam, s):
                                     subgrad_dist=hu["subgrad_dist"], obj=hu["obj"])
         log(f"huber {prec}: {out[f'huber_{prec}']}")
     del Ah, bh
+    # bounded least squares at the size of the paper's ablation (N = 32000, n = 16000),
+    # eps 1e-5, with and without the preconditioner and inexact solves
+    t0 = time.time()
+    Q = genios_data.boxls_decay(32000, 16000, seed=8, s=50)
+    Aq = torch.from_numpy(Q["A"]).to(A.device)
+    bq = torch.from_numpy(Q["b"]).to(A.device)
+    log(f"generated {Q['name']} in {time.time() - t0:.1f}s")
+    variants = [("bf16_refine", 1, 1), ("f32", 1, 1), ("f32", 0, 1), ("f32", 1, 0), ("f32", 0, 0)]
+    for prec, pc, inexact in variants:
+        for _ in range(2 if (pc and inexact) else 1):
+            bx = g.boxls_solve(Aq, bq, 0.0, 1.0, precision=prec, eps=1e-5, sketch_rank=Q["s"],
+                               precondition=pc, inexact=inexact, profile_kernels=1,
+                               max_iter=5000)["info"][0]
+        key = f"boxls_{prec}" + ("" if pc else "_nopc") + ("" if inexact else "_exact")
+        out[key] = dict(_solve_record(bx), workload=Q["name"], eps=1e-5,
+                        precond_s=round(bx["t_precond"], 4), obj=bx["obj"])
+        log(f"{key}: {out[key]}")
+    del Aq, bq
     return out
 
 
