@@ -385,36 +385,50 @@ __global__ __launch_bounds__(256) void k_cg_alpha(VecArgs a) {
   const ProbState* S = a.ctrl.state + b;
   if (!P.run || !S->cg_active) return;
   const int64_t n = a.n;
-  const Chunk ch = my_chunk(n, a.chunk);
+  const Chunk ch = my_chunk(n, a.chunkf);
   const int64_t off = (int64_t)b * n;
   const VT* p = static_cast<const VT*>(a.p) + off;
   VT* hp = static_cast<VT*>(a.hp) + off;
   const VT* yp = static_cast<const VT*>(a.ypart) + (int64_t)b * a.ypart_prob_stride;
   const uint8_t* mask = a.mask ? a.mask + off : nullptr;
   __shared__ double red[16];
+  __shared__ VT sums[4][64];
   const VT nu = VT(P.nu);
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t kst = a.ypart_ks_stride;
   double pq = 0.0;
-  for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) {
+  // 64 elements per step; wave grp sums the partial slots grp, grp + 4, ... (8 loads
+  // in flight), then wave 0 adds the four sums in a fixed order
+  for (int64_t base = ch.lo; base < ch.hi; base += 64) {
+    const int64_t i = base + lane;
+    const bool ok = i < ch.hi;
+    const int64_t ic = ok ? i : ch.hi - 1;
     VT s = VT(0);
-    int k = 0;
-    for (; k + 8 <= a.ksplit; k += 8) {  // 8 independent loads, then the adds in order
+    int k = grp;
+    for (; k + 28 < a.ksplit; k += 32) {
       VT tq[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) tq[q] = yp[(int64_t)(k + q) * a.ypart_ks_stride + i];
+      for (int q = 0; q < 8; ++q) tq[q] = yp[(int64_t)(k + 4 * q) * kst + ic];
 #pragma unroll
       for (int q = 0; q < 8; ++q) s += tq[q];
     }
-    for (; k < a.ksplit; ++k) s += yp[(int64_t)k * a.ypart_ks_stride + i];
-    const VT pi = p[i];
-    VT q;
-    if (mask && !mask[i]) {
-      s = VT(0);
-      q = pi;
-    } else {
-      q = s + nu * pi;
+    for (; k < a.ksplit; k += 4) s += yp[(int64_t)k * kst + ic];
+    sums[grp][lane] = s;
+    __syncthreads();
+    if (grp == 0 && ok) {
+      VT t = ((sums[0][lane] + sums[1][lane]) + sums[2][lane]) + sums[3][lane];
+      const VT pi = p[i];
+      VT q;
+      if (mask && !mask[i]) {
+        t = VT(0);
+        q = pi;
+      } else {
+        q = t + nu * pi;
+      }
+      hp[i] = t;
+      pq += double(pi) * double(q);
     }
-    hp[i] = s;
-    pq += double(pi) * double(q);
+    __syncthreads();
   }
   double v[1] = {pq};
   block_sum<1>(v, red);
@@ -432,7 +446,7 @@ __global__ __launch_bounds__(256) void k_cg_update(VecArgs a, int t) {
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   const int sl[1] = {kSlPq};
   double tv[1];
-  reduce_slots<1>(a.ctrl, b, a.nb, sl, tv);
+  reduce_slots<1>(a.ctrl, b, a.nbf, sl, tv);  // written by k_cg_alpha's finer grid
   const double pq = tv[0];
   if (!(pq > 0.0) || !(pq <= 1.0e300)) {  // not positive definite along p, or non-finite
     if (lead) {
@@ -588,43 +602,6 @@ __global__ __launch_bounds__(256) void k_dual_finish(Ctrl ctrl, int nb) {
   double tv[1];
   reduce_slots<1>(ctrl, b, nb, sl, tv);
   if (threadIdx.x == 0) ctrl.state[b].red[kRedRd2] = tv[0];
-}
-
-// Objective over the m samples from partials of t = A z.
-template <typename VT>
-__global__ __launch_bounds__(256) void k_objective_m(int64_t m, const VT* __restrict__ tparts,
-                                                     int nsplit, int64_t split_stride,
-                                                     int64_t prob_stride,
-                                                     const VT* __restrict__ bvec, int loss,
-                                                     double delta, Ctrl ctrl, int nb) {
-  const int b = blockIdx.y;
-  const int64_t chunk = (m + nb - 1) / nb;
-  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(m, lo + chunk);
-  __shared__ double red[4];
-  double s = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    double t = 0.0;
-    for (int k = 0; k < nsplit; ++k)
-      t += double(tparts[(int64_t)b * prob_stride + (int64_t)k * split_stride + i]);
-    const double bi = double(bvec[(int64_t)b * m + i]);
-    if (loss == kLossLogistic) {
-      const double w = -bi * t;  // log(1 + e^w), computed stably
-      s += (w > 0.0 ? w + log1p(exp(-w)) : log1p(exp(w)));
-    } else if (loss == kLossHuber) {
-      const double r = t - bi, a = fabs(r);
-      s += a <= delta ? r * r : 2.0 * delta * a - delta * delta;
-    } else {
-      s += 0.5 * (t - bi) * (t - bi);
-    }
-  }
-  double v[1] = {s};
-  block_sum<1>(v, red);
-  double* pb = ctrl.part + (int64_t)b * ctrl.part_stride;
-  if (threadIdx.x == 0) pb[(int64_t)blockIdx.x * kPartW + kMaxS + 13] = v[0];
-  if (!last_block_arrive(ctrl.counters + (int64_t)b * kNumCounters + kCntObj, nb)) return;
-  double tv[1];
-  sum_slots<1>(pb, nb, 13, tv, red);
-  if (threadIdx.x == 0) ctrl.state[b].red[kRedAux] = tv[0];
 }
 
 // Elementwise terms of the ML x-system: d = f''(t), col0 = d o t (for H x),
@@ -802,7 +779,8 @@ __global__ __launch_bounds__(256) void k_masked_dot(int64_t n, const VT* __restr
 static bool vec_geometry_ok(const VecArgs& a) {
   // every vector kernel writes one partial per block into pstride-sized slots
   return a.nb >= 1 && a.nb <= a.ctrl.pstride && a.chunk >= 1 && a.chunk <= 4 * kVecChunk &&
-         (int64_t)a.nb * a.chunk >= a.n;
+         (int64_t)a.nb * a.chunk >= a.n && a.nbf >= 1 && a.nbf <= a.ctrl.pstride &&
+         a.chunkf >= 1 && a.chunkf <= 4 * kVecChunk && (int64_t)a.nbf * a.chunkf >= a.n;
 }
 
 #define GENIOS_VEC_CHECK() \
@@ -827,7 +805,12 @@ hipError_t launch_precond_step(const VecArgs& a, int t, int init, hipStream_t st
 }
 hipError_t launch_cg_alpha(const VecArgs& a, hipStream_t st) {
   GENIOS_VEC_CHECK();
-  GENIOS_VEC_LAUNCH(k_cg_alpha);
+  dim3 grid((unsigned)a.nbf, (unsigned)a.batch);  // the finer grid
+  if (a.vt == VT_F32)
+    hipLaunchKernelGGL(k_cg_alpha<float>, grid, dim3(kVecBlock), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_cg_alpha<double>, grid, dim3(kVecBlock), 0, st, a);
+  return hipGetLastError();
 }
 hipError_t launch_cg_update(const VecArgs& a, int t, hipStream_t st) {
   GENIOS_VEC_CHECK();
@@ -859,22 +842,6 @@ hipError_t launch_dual_residual(const VecArgs& a, hipStream_t st) {
 
 static int m_blocks(int64_t m) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((m + kVecChunk - 1) / kVecChunk, kMaxVecBlocks));
-}
-
-hipError_t launch_objective_m(VType vt, int64_t m, int64_t batch, const void* tparts, int nsplit,
-                              int64_t split_stride, int64_t prob_stride, const void* bvec,
-                              int loss, double delta, Ctrl ctrl, hipStream_t st) {
-  const int nb = m_blocks(m);
-  dim3 grid((unsigned)nb, (unsigned)batch);
-  if (vt == VT_F32)
-    hipLaunchKernelGGL(k_objective_m<float>, grid, dim3(256), 0, st, m,
-                       static_cast<const float*>(tparts), nsplit, split_stride, prob_stride,
-                       static_cast<const float*>(bvec), loss, delta, ctrl, nb);
-  else
-    hipLaunchKernelGGL(k_objective_m<double>, grid, dim3(256), 0, st, m,
-                       static_cast<const double*>(tparts), nsplit, split_stride, prob_stride,
-                       static_cast<const double*>(bvec), loss, delta, ctrl, nb);
-  return hipGetLastError();
 }
 
 template <typename VT, int LOSS>

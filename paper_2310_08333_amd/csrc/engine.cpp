@@ -176,7 +176,8 @@ int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_)
   npad = (n + 7) / 8 * 8;
   chunk = vec_chunk(n);
   nb = (int)((n + chunk - 1) / chunk);
-  part_blocks = std::max<int>(nb, std::max<int>(kMaxVecBlocks, (int)((n + kVecChunk - 1) / kVecChunk)));
+  part_blocks = std::max<int>(std::max<int>(nb, (int)vec_blocks_max(n)),
+                              std::max<int>(kMaxVecBlocks, (int)((n + kVecChunk - 1) / kVecChunk)));
   n_vecs = (op == GENIOS_OP_MATVEC || op == GENIOS_OP_NYSTROM || op == GENIOS_OP_HVP) ? 0 : kNumNVec;
   // columns of the gathered A_S: |S| <= min(m, n) without the l2 term (else A_S^T A_S
   // is singular and the call fails), up to n with it
@@ -343,6 +344,8 @@ struct Ctx {
     a.ypart_ks_stride = (int64_t)L.nrhs * L.npad;
     a.ypart_prob_stride = L.yprob();
     a.mask = mask;
+    a.chunkf = vec_chunk_fine(n);
+    a.nbf = (int)((n + a.chunkf - 1) / a.chunkf);
     a.lo = box_lo;
     a.hi = box_hi;
     return a;
@@ -459,6 +462,7 @@ struct HostProb {
   int switch_iter = -1, resketches = 0;
   int gap_checks = 0;
   int precond_rank = 0, sketch_rounds = 0;
+  bool rd_exact = false;  // rd is r_d at the final x with the master copy
   double sketch_err = 0.0, kappa_bound = 0.0;
   std::vector<double> rk_hist;
 };
@@ -1012,6 +1016,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
         q.rkkt = kkt_from(q.rp, q.rd, q.xn, q.zn, rhou, n);
         if (paper_test(q.rp, q.rd, q.xn, q.zn, rhou, n, eps_abs, eps_rel)) {
           q.done = 1;
+          q.rd_exact = !ml && op == &c.op_hi;
           q.t_target = now_s() - t0;
           q.status = GENIOS_OK;
           // undo a penalty change decided in this iteration (u was not rescaled yet)
@@ -1072,27 +1077,29 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
   }
 
   // ---- final report with the master-copy operator ----
+  // r_d at the returned x: already exact where the problem was certified with the
+  // master copy at that x (the certification's explicit H x); else recomputed here.
+  bool all_exact = true;
+  for (int64_t b = 0; b < B; ++b)
+    if (!P[b].rd_exact) all_exact = false;
   set_params(k, true);
   HC(upload_params(c, hp));
-  if (ml) {
-    rc = gradient_pass(c.op_hi, nullptr, 0);
-    if (rc) return rc;
-  } else {
-    rc = hvp_explicit(c, c.op_hi, x, h, nullptr, nullptr, 0);
-    if (rc) return rc;
-  }
-  {
+  if (!all_exact) {
+    if (ml) {
+      rc = gradient_pass(c.op_hi, nullptr, 0);
+      if (rc) return rc;
+    } else {
+      rc = hvp_explicit(c, c.op_hi, x, h, nullptr, nullptr, 0);
+      if (rc) return rc;
+    }
     VecArgs vr = c.vargs(x, z, u, h, g, c_hi, nullptr);
     HC(launch_dual_residual(vr, c.st));
+    rc = sync_state(c, hs);
+    if (rc) return rc;
+    for (int64_t b = 0; b < B; ++b) P[b].rd = std::sqrt(hs[b].red[kRedRd2]);
   }
-  // objective at z
-  rc = c.gemv_n(c.op_hi, z, nullptr, 0);
-  if (rc) return rc;
-  HC(launch_objective_m(c.vt, m, B, c.L.tparts, c.nsplit_for(c.op_hi, 0), m,
-                        (int64_t)c.L.nsplit_n * m, bvec, loss, delta, c.L.ctrl, c.st));
-  rc = sync_state(c, hs);
-  if (rc) return rc;
-  // relative duality gap at the returned z with the master copy
+  // objective (the gap pass's primal value) and relative duality gap at the returned z
+  // with the master copy
   rc = eval_gap(c.op_hi, z, nullptr, 0);
   if (rc) return rc;
   rc = read_gap();
@@ -1116,9 +1123,9 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     I.sketch_rounds = q.sketch_rounds;
     I.rho = q.rho;
     I.r_p = q.rp;
-    I.r_d = std::sqrt(hs[b].red[kRedRd2]);
+    I.r_d = q.rd;
     I.r_kkt = kkt_from(I.r_p, I.r_d, q.xn, q.zn, q.rho * q.un, n);
-    I.obj = hs[b].red[kRedAux] + q.lambda * hs[b].red[kRedZ1] + 0.5 * o->lambda2 * hs[b].red[kRedZ2];
+    I.obj = hg[b].primal;
     I.rel_gap = hg[b].rel_gap;
     I.gap_primal = hg[b].primal;
     I.gap_dual = hg[b].dual;
@@ -1392,6 +1399,8 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
   va.n = ldS;
   va.chunk = vec_chunk(ldS);
   va.nb = (int)((ldS + va.chunk - 1) / va.chunk);
+  va.chunkf = vec_chunk_fine(ldS);
+  va.nbf = (int)((ldS + va.chunkf - 1) / va.chunkf);
   va.U = s > 0 ? c.L.U : nullptr;
   va.s_stride = std::max(1, s);
   const int nsS = std::min(gemv_n_splits(opS, B), c.L.nsplit_n);

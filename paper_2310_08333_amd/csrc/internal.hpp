@@ -31,6 +31,22 @@ inline int64_t vec_chunk(int64_t n) {
   const int64_t c = (int64_t)kVecBlock * q;
   return c < 4 * kVecChunk ? c : 4 * kVecChunk;
 }
+// The finer grid of k_cg_alpha (sum of the H p block partials): 64 elements per
+// block (the four waves split the partial slots) until a problem has 1024 blocks,
+// then wider chunks in steps of 64, at most 4 kVecChunk.
+inline int64_t vec_chunk_fine(int64_t n) {
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t c = per <= 64 ? 64 : (per + 63) / 64 * 64;
+  return c < 4 * kVecChunk ? c : 4 * kVecChunk;
+}
+// Largest block count either grid gives for any length up to n (partial-slot capacity).
+inline int64_t vec_blocks_max(int64_t n) {
+  const int64_t cf = vec_chunk_fine(n), cc = vec_chunk(n);
+  const int64_t nf = (n + cf - 1) / cf, nc = (n + cc - 1) / cc;
+  const int64_t small = (n + 63) / 64 < 1024 ? (n + 63) / 64 : 1024;
+  const int64_t m1 = nf > nc ? nf : nc;
+  return m1 > small ? m1 : small;
+}
 
 // Host-written parameters of one problem, uploaded before each ADMM iteration.
 struct alignas(128) ProbParams {
@@ -77,7 +93,7 @@ enum {
   kRedRd2 = 4,   // ||grad + rho u||^2 (Lasso: grad = h - c)
   kRedZ1 = 5,    // ||z||_1
   kRedNnz = 6,   // nonzeros of z
-  kRedAux = 7
+  kRedAux = 7    // unused
 };
 
 // Slots of the block-partial array (slot-major: spart[b][slot][block]).  A kernel
@@ -97,7 +113,7 @@ enum {
 // Counter slots for the last-block reductions.
 enum {
   kCntBegin = 0, kCntPrecond, kCntAlpha, kCntUpdate, kCntEnd, kCntAux0, kCntAux1, kCntAux2,
-  kCntObj, kCntMasked
+  kCntObj /* unused */, kCntMasked
 };
 
 // Pointers to the per-problem control arrays in the workspace.
@@ -178,6 +194,8 @@ struct VecArgs {
   int64_t n, batch;
   int nb;                 // blocks per problem
   int64_t chunk;          // elements per block
+  int nbf;                // k_cg_alpha's blocks per problem (finer grid)
+  int64_t chunkf;         // and its elements per block
   Ctrl ctrl;
   // n-vectors (per problem stride n)
   void *x, *z, *u, *h, *g, *c, *r, *p, *hp, *w;  // w: preconditioned residual
@@ -208,10 +226,6 @@ hipError_t launch_dual_residual(const VecArgs& a, hipStream_t st);
 //   logistic  log(1 + exp(-y t)) (Sec. 4.2),
 //   Huber     l(t - b), l(r) = r^2 (|r| <= delta), 2 delta |r| - delta^2 (Sec. 4.3).
 enum LossKind : int { kLossSquare = 0, kLossLogistic = 1, kLossHuber = 2 };
-// Objective pieces sum_i f(t_i) at t = A z (FP64 sum) into red[kRedAux].
-hipError_t launch_objective_m(VType vt, int64_t m, int64_t batch, const void* tparts, int nsplit,
-                              int64_t split_stride, int64_t prob_stride, const void* bvec,
-                              int loss, double delta, Ctrl ctrl, hipStream_t st);
 // Elementwise terms of the ML x-system from the t = A x partials: the curvature
 // d = f''(t) and the two right-hand columns col0 = d o t (for H x) and
 // col1 = f'(t) (for grad f).  Logistic: d = s (1 - s), f' = -y s with s = sigmoid(-y t);
