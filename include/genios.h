@@ -335,7 +335,10 @@ int genios_nystrom_apply(int64_t n, int32_t s, int64_t batch, int32_t dtype, con
  * into an m x |S| block in the workspace (padded to a multiple of 8 with
  * identity columns), and the system is solved there by Nystrom-preconditioned
  * CG (sketch of A_S^T A_S) to relative residual opts->cg_tol_floor (default 1e-7
- * here as well); info->iters reports |S|, info->cg_iters the CG iterations.
+ * here as well); info->iters reports |S|, info->cg_iters the CG iterations.  The
+ * sketch size is the solver's s capped at a quarter of the compact system's size,
+ * max(8, ceil(|S| / 4) rounded up to 8) with |S| the largest support of the batch:
+ * past that the s x s core costs more than the CG iterations it saves.
  *   z_star, grad_z  n per problem.  lambda (host) is accepted for symmetry with
  *   the forward call and checked to be >= 0. */
 int genios_lasso_backward(const genios_matrix* A, const void* z_star, const void* grad_z,

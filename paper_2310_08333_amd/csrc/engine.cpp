@@ -1361,8 +1361,10 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
   HC(launch_fill(zero_z, B * ldS * c.ve, c.st));
   HC(launch_fill(zero_u, B * ldS * c.ve, c.st));
   HC(launch_fill(h, B * ldS * c.ve, c.st));
-  // sketch of the compact operator (padding rows of Omega and Y masked)
-  const int s = std::min(s_req, ldS);
+  // sketch of the compact operator (padding rows of Omega and Y masked), at most a
+  // quarter of the compact system's size (rounded up to 8, at least 8)
+  const int s_cap = std::max(8, ((cmax + 3) / 4 + 7) / 8 * 8);
+  const int s = std::min(std::min(s_req, ldS), s_cap);
   if (s > 0) {
     SketchWs skc = c.L.sk;
     int kw = 1, ky = 1, ng = 1;

@@ -186,6 +186,9 @@ def test_lasso_backward_fp32_matches_dense_adjoint_at_its_solution(g):
     got = grad_b.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(got - db) <= 1e-4 * np.linalg.norm(db), info
     assert abs(float(grad_lam[0]) - dl) <= 1e-4 * abs(dl)
+    # the compact system's sketch is capped at a quarter of its size (rounded up to 8)
+    k = int(np.count_nonzero(zn))
+    assert 1 <= info[0]["precond_rank"] <= min(16, max(8, (-(-k // 4) + 7) // 8 * 8)), (k, info)
 
 
 def test_lasso_backward_fp64_end_to_end_vs_oracle_and_fd(g):
