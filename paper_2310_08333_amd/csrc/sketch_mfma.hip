@@ -25,7 +25,11 @@
 // * Y = A^T (d o W): A's rows are contiguous in j, but the instruction needs 8
 //   consecutive k = r per lane, so each 32-row x 128-column A tile is written
 //   to LDS transposed ([j][r]) and read back as 16-byte fragments; the hi/lo
-//   tiles of d o W are staged in LDS beside it.
+//   tiles of d o W are staged in LDS beside it.  A wavefront loads 16 rows x 4
+//   column chunks, and row j of the transposed tile keeps its 32 entries at
+//   positions rotated by 16 ((j / 8) mod 4) in a 72-wide row, so the 2-byte
+//   stores of one instruction spread over all 32 banks and the fragment reads
+//   still take the minimum two passes.
 // Results are per-K-split partials, summed in a fixed order by the consumers.
 #include <algorithm>
 
@@ -42,6 +46,7 @@ constexpr int kMK = 32;        // K step of one instruction
 constexpr int kPitch = 40;     // LDS row pitch in 16-bit elements (32 + 8: 80 bytes)
 constexpr int kWRows = 128;    // rows of A per block in W = A Omega
 constexpr int kYCols = 128;    // columns of A per block in Y = A^T W
+constexpr int kPitchT = 72;    // LDS row pitch of the transposed A tile (16-bit elements)
 
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
   uint32_t u = __float_as_uint(f);
@@ -214,7 +219,7 @@ __global__ __launch_bounds__(256) void k_sketch_y_mfma(const uint16_t* __restric
                                                        int rchunk, int64_t ks_stride,
                                                        int64_t prob_stride) {
   constexpr int NT = SP / 16;
-  __shared__ __align__(16) uint16_t at[kYCols * kPitch];       // A tile transposed: [j][r]
+  __shared__ __align__(16) uint16_t at[kYCols * kPitchT];      // A tile transposed: [j][r]
   // hi, lo tiles [c][r], plus one spare row that threads past the tile write into
   // (never read), so every staging store is unconditional
   __shared__ __align__(16) uint16_t ws[2][(SP + 1) * kPitch];
@@ -232,17 +237,21 @@ __global__ __launch_bounds__(256) void k_sketch_y_mfma(const uint16_t* __restric
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-  // A tile: 32 rows x 128 columns = 512 chunks of 8 columns, 2 per thread.
-  // Thread -> (row tr, chunk tc): rows past m are clamped (their W rows are 0),
-  // chunks past n read column 0 (their results are not stored).
+  // A tile: 32 rows x 128 columns = 512 chunks of 8 columns, 2 per thread:
+  // thread -> rows tr = (lane mod 16) + 16 h (h = 0, 1), chunk tc = 4 wave + lane / 16.
+  // Rows past m are clamped (their W rows are 0), chunks past n read column 0
+  // (their results are not stored).
+  const int tc = 4 * wave + (lane >> 4);
+  // position of entry r of transposed row j (rotation by 16 ((j / 8) mod 4) in a 64 ring)
+  auto tpos = [](int j, int r) { return j * kPitchT + ((r + 16 * ((j >> 3) & 3)) & 63); };
   for (int rr = r0; rr < r1; rr += kMK) {
-    auto load_chunk = [&](int ch) {
-      const int tr = ch >> 4, tc = ch & 15;
+    auto load_chunk = [&](int h) {
+      const int tr = (lane & 15) + 16 * h;
       const int row = min(rr + tr, m - 1);
       const int j = j0 + 8 * tc;
       return *reinterpret_cast<const uint4*>(Ab + (int64_t)row * lda + (j < n ? j : 0));
     };
-    const uint4 av0 = load_chunk(tid), av1 = load_chunk(tid + 256);
+    const uint4 av0 = load_chunk(0), av1 = load_chunk(1);
     // hi / lo tiles: SP columns x 32 r each = WCH chunks of 16 bytes, at most two
     // per thread (named registers; chunk indices past the tile re-read chunk 0)
     constexpr int WCH = SP * 4;
@@ -259,20 +268,21 @@ __global__ __launch_bounds__(256) void k_sketch_y_mfma(const uint16_t* __restric
       wl1 = wload(Lb, tid + 256);
     }
     __syncthreads();  // previous step's reads of the LDS tiles are done
-    auto store_transposed = [&](int ch, const uint4& v) {
-      const int tr = ch >> 4, tc = ch & 15;
-      uint16_t* dst = &at[(8 * tc) * kPitch + tr];
-      dst[0 * kPitch] = (uint16_t)(v.x & 0xffffu);
-      dst[1 * kPitch] = (uint16_t)(v.x >> 16);
-      dst[2 * kPitch] = (uint16_t)(v.y & 0xffffu);
-      dst[3 * kPitch] = (uint16_t)(v.y >> 16);
-      dst[4 * kPitch] = (uint16_t)(v.z & 0xffffu);
-      dst[5 * kPitch] = (uint16_t)(v.z >> 16);
-      dst[6 * kPitch] = (uint16_t)(v.w & 0xffffu);
-      dst[7 * kPitch] = (uint16_t)(v.w >> 16);
+    auto store_transposed = [&](int h, const uint4& v) {
+      const int tr = (lane & 15) + 16 * h;
+      // the 8 rows j = 8 tc .. 8 tc + 7 share (j / 8) mod 4 = tc mod 4
+      uint16_t* dst = &at[(8 * tc) * kPitchT + ((tr + 16 * (tc & 3)) & 63)];
+      dst[0 * kPitchT] = (uint16_t)(v.x & 0xffffu);
+      dst[1 * kPitchT] = (uint16_t)(v.x >> 16);
+      dst[2 * kPitchT] = (uint16_t)(v.y & 0xffffu);
+      dst[3 * kPitchT] = (uint16_t)(v.y >> 16);
+      dst[4 * kPitchT] = (uint16_t)(v.z & 0xffffu);
+      dst[5 * kPitchT] = (uint16_t)(v.z >> 16);
+      dst[6 * kPitchT] = (uint16_t)(v.w & 0xffffu);
+      dst[7 * kPitchT] = (uint16_t)(v.w >> 16);
     };
-    store_transposed(tid, av0);
-    store_transposed(tid + 256, av1);
+    store_transposed(0, av0);
+    store_transposed(1, av1);
     auto wstore = [&](int ch, const uint4& h, const uint4& l) {
       const int o = ch < WCH ? (ch >> 2) * kPitch + 8 * (ch & 3) : SP * kPitch;
       *reinterpret_cast<uint4*>(&ws[0][o]) = h;
@@ -284,7 +294,7 @@ __global__ __launch_bounds__(256) void k_sketch_y_mfma(const uint16_t* __restric
     uint4 fa[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
-      fa[t] = *reinterpret_cast<const uint4*>(&at[(32 * wave + 16 * t + (lane & 15)) * kPitch + kl]);
+      fa[t] = *reinterpret_cast<const uint4*>(&at[tpos(32 * wave + 16 * t + (lane & 15), kl)]);
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
       const uint4 fh = *reinterpret_cast<const uint4*>(&ws[0][(16 * c + (lane & 15)) * kPitch + kl]);
