@@ -432,14 +432,14 @@ struct Ctx {
   int64_t cur_ks_stride = 0;
 };
 
+// h = H x outside CG (warm start, precision switch, certification): the fused
+// one-pass product where A qualifies, else A x then A^T (d o t).
 int hvp_explicit(Ctx& c, const MatArg& op, const void* x, void* h, const void* d,
                  const int32_t* gate, int gstride) {
-  int rc = c.gemv_n(op, x, gate, gstride);
+  int rc = c.hvp(op, x, d, gate, gstride);
   if (rc) return rc;
-  rc = c.gemv_t_from_t(op, d, gate, gstride, c.nsplit_for(op, 0));
-  if (rc) return rc;
-  HC(launch_sum_splits(c.vt, c.B, c.n, c.L.ypart, c.cur_ks, (int64_t)c.L.nrhs * c.L.npad,
-                       c.L.yprob(), h, c.n, c.st, gate, gstride));
+  HC(launch_sum_splits(c.vt, c.B, c.n, c.L.ypart, c.cur_ks, c.cur_ks_stride, c.L.yprob(), h, c.n,
+                       c.st, gate, gstride));
   return 0;
 }
 
