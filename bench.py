@@ -1,6 +1,6 @@
 """Benchmark of the GeNIOS hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+    python bench.py [--gpus 1] [--steps K (5)] [--warmup W (1)] [--workload NAME]
 
 A step is one pass of the whole hot path over the workload: a cold-start Lasso
 solve in BF16-A + FP32-refinement precision (BF16 rounding of A, A^T b, the
@@ -230,7 +230,7 @@ def next_rows(g, torch, A, b, lam, s):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="lasso_20000x40000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -345,6 +345,31 @@ def main():
                   "avg_ms": round(1e3 * t_sk / n_sk, 3),
                   "hbm_GBps": round(n_sk * 2.0 * m * n * 2 / t_sk / 1e9, 1)}
 
+    # per-phase iteration rates from one solve with the iteration history (outside
+    # the timed steps): the BF16-A phase from the end of set-up to its last
+    # iteration, the FP32 phase from there to the last iteration
+    hs = g.lasso_solve(A, b, lam, precision="bf16_refine", history=400, **opts)
+    hist, hinf = hs["history"][0], hs["info"][0]
+    k_tot = hinf["iters"]
+    rows = hist[:k_tot]
+    ph0 = rows[rows[:, 7] == 0]
+    ph1 = rows[rows[:, 7] == 1]
+    t0_end = ph0[-1, 8] if len(ph0) else hinf["t_setup"]
+    phases = {
+        "setup_s": round(hinf["t_setup"], 4),
+        "bf16_A": {"iters": int(len(ph0)),
+                   "iters_per_s": round(float(len(ph0) / max(t0_end - hinf["t_setup"], 1e-9)), 1)},
+        "fp32_A": {"iters": int(len(ph1)),
+                   "iters_per_s": round(float(len(ph1) / max(ph1[-1, 8] - t0_end, 1e-9)), 1)
+                   if len(ph1) else None},
+    }
+    # the plain matrix-vector kernels of the step (set-up A^T b, duality gap, adjoint)
+    t_n, b_n, n_n = tot("t_matvec_n"), tot("bytes_matvec_n"), tot("n_matvec_n")
+    t_t, b_t, n_t = tot("t_matvec_t"), tot("bytes_matvec_t"), tot("n_matvec_t")
+    matvecs = {"A_v": {"launches": n_n, "GBps": round(b_n / t_n / 1e9, 1) if t_n > 0 else None},
+               "At_w": {"launches": n_t, "GBps": round(b_t / t_t / 1e9, 1) if t_t > 0 else None}}
+    log(f"phases: {phases} matvecs: {matvecs}")
+
     fp32 = None
     if not args.no_fp32:
         o32 = g.lasso_solve(A, b, lam, precision="f32", **opts)["info"][0]
@@ -374,6 +399,9 @@ def main():
         "time_to_1e-4_s": {"bf16_refine": round(statistics.median(ttt), 4),
                            "fp32": fp32["time_to_1e-4_s"] if fp32 else None},
         "admm_iters": statistics.median(iters),
+        "time_to_1e-4_min_s": round(min(ttt), 4),
+        "phases": phases,
+        "matvecs": matvecs,
         "precond_s": round(statistics.median(i["t_precond"] for i in infos), 4),
         "fp32": fp32,
         "roofline": roofline,
