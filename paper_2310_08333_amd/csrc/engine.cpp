@@ -563,13 +563,29 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
 
   // ---- setup ----
   HC(launch_fill(c.L.ctrl.params, c.L.ctrl_bytes_end - 0, c.st));
-  if (use_lo && A->A_bf16 == nullptr) {
-    HC(launch_cast_bf16(static_cast<const float*>(A->A_hi), c.L.A16, c.L.a16_elems, c.st));
-  }
   void* h = c.L.nv[kVH];
   void* g = c.L.nv[kVG];
   void* c_hi = c.L.nv[kVCH];
   void* c_lo = c.L.nv[kVCL];
+  // The BF16 copy, and for the squared loss c = A^T b of both operators, in one pass
+  // over the FP32 master where the layout allows it (one matrix per problem).
+  bool setup_fused = false;
+  if (use_lo && A->A_bf16 == nullptr && !ml && c.vt == VT_F32 && (A->stride_A != 0 || B == 1)) {
+    const int ksc = cast_atb_splits(m, n, B, (int)(c.L.yslots / 2));
+    if (2 * (int64_t)ksc <= c.L.yslots &&
+        cast_atb_eligible(A->A_hi, A->lda, A->stride_A, n, c.L.A16, c.L.ypart, c.L.npad)) {
+      HC(launch_cast_atb(static_cast<const float*>(A->A_hi), A->lda, A->stride_A, c.L.A16, m, n,
+                         B, static_cast<const float*>(bvec), static_cast<float*>(c.L.ypart), ksc,
+                         c.L.npad, (int64_t)ksc * c.L.npad, c.L.yprob(), c.st));
+      HC(launch_sum_splits(c.vt, B, n, c.L.ypart, ksc, c.L.npad, c.L.yprob(), c_hi, n, c.st));
+      HC(launch_sum_splits(c.vt, B, n, static_cast<float*>(c.L.ypart) + (int64_t)ksc * c.L.npad,
+                           ksc, c.L.npad, c.L.yprob(), c_lo, n, c.st));
+      setup_fused = true;
+    }
+  }
+  if (use_lo && A->A_bf16 == nullptr && !setup_fused) {
+    HC(launch_cast_bf16(static_cast<const float*>(A->A_hi), c.L.A16, c.L.a16_elems, c.st));
+  }
   if (!o->warm_start) {
     HC(launch_fill(x, B * n * c.ve, c.st));
     HC(launch_fill(z, B * n * c.ve, c.st));
@@ -623,7 +639,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
   };
 
   // Right-hand sides c = A^T b for the Lasso (per operator in use).
-  if (!ml) {
+  if (!ml && !setup_fused) {
     if (use_lo) {
       HC(launch_gemv_t(c.op_lo, B, c.vt, bvec, 1, 0, m, 0, 1, nullptr, 0, c.L.ypart,
                        c.nsplit_for(c.op_lo, 1), (int64_t)c.L.nrhs * c.L.npad, c.L.npad,

@@ -275,6 +275,17 @@ struct GapArgs {
   GapState* state;     // [batch]
 };
 int gap_blocks(int64_t len);
+// ---- set-up pass of a BF16-A solve, setup.hip ----
+// Row splits of the fused pass (at most max_splits).
+int cast_atb_splits(int64_t m, int64_t n, int64_t batch, int max_splits);
+bool cast_atb_eligible(const void* A, int64_t lda, int64_t strideA, int64_t n, const void* A16,
+                       const void* ypart, int64_t ks_stride);
+// A16 = bf16(A) and the per-split partials of A^T b (slots [0, ksplit)) and
+// bf16(A)^T b (slots lo_offset / ks_stride + [0, ksplit)), FP32 b.
+hipError_t launch_cast_atb(const float* A, int64_t lda, int64_t strideA, uint16_t* A16,
+                           int64_t m, int64_t n, int64_t batch, const float* b, float* ypart,
+                           int ksplit, int64_t ks_stride, int64_t lo_offset,
+                           int64_t prob_stride, hipStream_t st);
 // ---- power method on E = H - U diag(lam_hat) U^T (Sec. 2.2 adaptive sketch), adaptive.hip ----
 struct PowerArgs {
   VType vt;

@@ -740,3 +740,22 @@ def test_boxls_gap_and_normal_cone_termination(g, boxsmall, term, eps):
     else:
         sd = oboxls.normal_cone_distance(oboxls.grad_f(A, b, z), z, np.zeros(300), np.ones(300))
         assert info["subgrad_dist"] <= eps and sd <= eps * 1.001, (info["subgrad_dist"], sd)
+
+
+@pytest.mark.parametrize("batch", [1, 3])
+def test_fused_setup_pass_matches_caller_supplied_bf16_copy(g, batch):
+    # the set-up pass that rounds A to BF16 while forming A^T b (both operators) must
+    # give the iterates of a solve handed the separately rounded copy
+    print("fused setup", batch, flush=True)
+    Ps = [genios_data.lasso_decay(301, 1204, 12, seed=40 + j, s=16) for j in range(batch)]
+    A = np.stack([P["A"] for P in Ps]) if batch > 1 else Ps[0]["A"]
+    b = np.stack([P["b"] for P in Ps]) if batch > 1 else Ps[0]["b"]
+    lam = [P["lam"] for P in Ps]
+    At, bt = _t(A), _t(b)
+    A16 = g.cast_bf16(At)
+    kw = dict(precision="bf16_only", max_iter=8, eps=1e-30, sketch_rank=16)
+    o1 = g.lasso_solve(At, bt, lam, **kw)
+    o2 = g.lasso_solve(At, bt, lam, A16=A16, **kw)
+    for k in ("x", "z", "u"):
+        d = (o1[k] - o2[k]).abs().max().item()
+        assert d <= 1e-5 * max(1.0, o2[k].abs().max().item()), (k, d)
