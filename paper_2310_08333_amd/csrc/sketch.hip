@@ -617,8 +617,8 @@ __global__ __launch_bounds__(kCoreThreads) void k_nystrom_core_lds(
     int32_t* __restrict__ s_eff_out, int32_t* __restrict__ status_out,
     double* __restrict__ shift_out) {
   extern __shared__ double lds[];
-  __shared__ double cs_c[kCoreLdsMaxS / 2 + 1], cs_s[kCoreLdsMaxS / 2 + 1];
-  __shared__ int16_t pr_p[kCoreLdsMaxS / 2 + 1], pr_q[kCoreLdsMaxS / 2 + 1];
+  __shared__ double2 pr_cs[kCoreLdsMaxS / 2 + 1];  // (c, s) of pair i
+  __shared__ int2 pr_pq[kCoreLdsMaxS / 2 + 1];     // (p, q) of pair i
   __shared__ int16_t perm[kCoreLdsMaxS];
   __shared__ double evals[kCoreLdsMaxS];
   __shared__ double s_red[4];
@@ -796,72 +796,77 @@ __global__ __launch_bounds__(kCoreThreads) void k_nystrom_core_lds(
             s_rot[sweep & 1] = 1;
           }
         }
-        pr_p[tid] = (int16_t)p;
-        pr_q[tid] = (int16_t)q;
-        cs_c[tid] = c;
-        cs_s[tid] = sn;
+        pr_pq[tid] = make_int2(p, q);
+        pr_cs[tid] = make_double2(c, sn);
       }
       __syncthreads();
       if (round == 0 && tid == 0) s_rot[(sweep + 1) & 1] = 0;
       {
-        constexpr int BPT = (kCoreLdsMaxS / 2) * (kCoreLdsMaxS / 2) / kCoreThreads + 1;
-        constexpr int VPT = kCoreLdsMaxS * (kCoreLdsMaxS / 2) / kCoreThreads + 1;
-        const int nblk = npairs * npairs;
-        const int nv = npairs * s;
-        double g[BPT][4], v[VPT][2];
-        // loads
+        // G: thread t takes column pair J = t mod npairs and the row pairs
+        // I = t / npairs, + T, + 2 T, ... (T = threads per column pair); the 2 x 2
+        // blocks partition G, so no two threads touch one entry.  Loads first.
+        constexpr int kMaxBlk = 3;  // npairs <= 50 and T >= 20
+        static_assert(kMaxBlk * (kCoreThreads / (kCoreLdsMaxS / 2)) >= kCoreLdsMaxS / 2,
+                      "every row pair is covered");
+        const int T = nt / npairs;
+        if (tid < T * npairs) {
+          const int J = tid % npairs, I0 = tid / npairs;
+          const int2 qj = pr_pq[J];
+          const double2 rj = pr_cs[J];
+          const int pJ = qj.x, qJ = qj.y;
+          double g[kMaxBlk][4];
+          int2 qi[kMaxBlk];
+          double2 ri[kMaxBlk];
+          bool act[kMaxBlk];
 #pragma unroll
-        for (int t = 0; t < BPT; ++t) {
-          const int bi = tid + t * kCoreThreads;
-          const int I = bi < nblk ? bi / npairs : 0, J = bi < nblk ? bi - I * npairs : 0;
-          const int pI = pr_p[I], qI = pr_q[I], pJ = pr_p[J], qJ = pr_q[J];
-          g[t][0] = R2[pI * LG + pJ];
-          g[t][1] = R2[pI * LG + qJ];
-          g[t][2] = R2[qI * LG + pJ];
-          g[t][3] = R2[qI * LG + qJ];
-        }
-        // rotate and store
-#pragma unroll
-        for (int t = 0; t < BPT; ++t) {
-          const int bi = tid + t * kCoreThreads;
-          if (bi >= nblk) continue;
-          const int I = bi / npairs, J = bi - I * npairs;
-          const double cI = cs_c[I], sI = cs_s[I], cJ = cs_c[J], sJ = cs_s[J];
-          if (sI == 0.0 && sJ == 0.0) continue;
-          const int pI = pr_p[I], qI = pr_q[I], pJ = pr_p[J], qJ = pr_q[J];
-          // rows: R_I = [[c, -s], [s, c]]
-          const double r00 = cI * g[t][0] - sI * g[t][2], r01 = cI * g[t][1] - sI * g[t][3];
-          const double r10 = sI * g[t][0] + cI * g[t][2], r11 = sI * g[t][1] + cI * g[t][3];
-          // columns: times R_J^T = [[c, s], [-s, c]]
-          double o00 = cJ * r00 - sJ * r01, o01 = sJ * r00 + cJ * r01;
-          double o10 = cJ * r10 - sJ * r11, o11 = sJ * r10 + cJ * r11;
-          if (I == J) {  // the rotated pair's off-diagonal entries are zero
-            o01 = 0.0;
-            o10 = 0.0;
+          for (int u = 0; u < kMaxBlk; ++u) {
+            const int I = I0 + u * T;
+            act[u] = false;
+            if (I < npairs) {
+              ri[u] = pr_cs[I];
+              act[u] = ri[u].y != 0.0 || rj.y != 0.0;
+            }
+            if (act[u]) {
+              qi[u] = pr_pq[I];
+              g[u][0] = R2[qi[u].x * LG + pJ];
+              g[u][1] = R2[qi[u].x * LG + qJ];
+              g[u][2] = R2[qi[u].y * LG + pJ];
+              g[u][3] = R2[qi[u].y * LG + qJ];
+            }
           }
-          // an idle player has qI == pI (or qJ == pJ): the identity writes the
-          // same value twice from this thread
-          R2[qI * LG + qJ] = o11;
-          R2[qI * LG + pJ] = o10;
-          R2[pI * LG + qJ] = o01;
-          R2[pI * LG + pJ] = o00;
-        }
 #pragma unroll
-        for (int t = 0; t < VPT; ++t) {
-          const int vi = tid + t * kCoreThreads;
-          const int J = vi < nv ? vi / s : 0, k = vi < nv ? vi - J * s : 0;
-          v[t][0] = R1[pr_p[J] * s + k];
-          v[t][1] = R1[pr_q[J] * s + k];
+          for (int u = 0; u < kMaxBlk; ++u) {
+            if (!act[u]) continue;
+            const int I = I0 + u * T;
+            const double cI = ri[u].x, sI = ri[u].y, cJ = rj.x, sJ = rj.y;
+            const int pI = qi[u].x, qI = qi[u].y;
+            // rows: R_I = [[c, -s], [s, c]]
+            const double r00 = cI * g[u][0] - sI * g[u][2], r01 = cI * g[u][1] - sI * g[u][3];
+            const double r10 = sI * g[u][0] + cI * g[u][2], r11 = sI * g[u][1] + cI * g[u][3];
+            // columns: times R_J^T = [[c, s], [-s, c]]
+            double o00 = cJ * r00 - sJ * r01, o01 = sJ * r00 + cJ * r01;
+            double o10 = cJ * r10 - sJ * r11, o11 = sJ * r10 + cJ * r11;
+            if (I == J) {  // the rotated pair's off-diagonal entries are zero
+              o01 = 0.0;
+              o10 = 0.0;
+            }
+            // an idle player has qI == pI (or qJ == pJ): the identity writes the
+            // same value twice from this thread
+            R2[qI * LG + qJ] = o11;
+            R2[qI * LG + pJ] = o10;
+            R2[pI * LG + qJ] = o01;
+            R2[pI * LG + pJ] = o00;
+          }
         }
-#pragma unroll
-        for (int t = 0; t < VPT; ++t) {
-          const int vi = tid + t * kCoreThreads;
-          if (vi >= nv) continue;
+        // V: entry pairs V[k, (p_J, q_J)], consecutive k on consecutive threads
+        for (int vi = tid; vi < npairs * s; vi += nt) {
           const int J = vi / s, k = vi - J * s;
-          const double cJ = cs_c[J], sJ = cs_s[J];
-          if (sJ == 0.0) continue;
-          R1[pr_p[J] * s + k] = cJ * v[t][0] - sJ * v[t][1];
-          R1[pr_q[J] * s + k] = sJ * v[t][0] + cJ * v[t][1];
+          const double2 rj = pr_cs[J];
+          if (rj.y == 0.0) continue;
+          const int2 qj = pr_pq[J];
+          const double v0 = R1[qj.x * s + k], v1 = R1[qj.y * s + k];
+          R1[qj.x * s + k] = rj.x * v0 - rj.y * v1;
+          R1[qj.y * s + k] = rj.y * v0 + rj.x * v1;
         }
       }
       __syncthreads();
