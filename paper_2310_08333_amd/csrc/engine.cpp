@@ -562,7 +562,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
   HC(tm.init());
 
   // ---- setup ----
-  HC(launch_fill(c.L.ctrl.params, c.L.ctrl_bytes_end - 0, c.st));
+  HC(launch_fill(c.L.ctrl.params, c.L.ctrl_bytes_end, c.st));
   void* h = c.L.nv[kVH];
   void* g = c.L.nv[kVG];
   void* c_hi = c.L.nv[kVCH];
@@ -648,14 +648,12 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
                            (int64_t)c.L.nrhs * c.L.npad, c.L.yprob(),
                            c_lo, n, c.st));
     }
-    if (prec != GENIOS_PREC_BF16_ONLY || true) {
-      HC(launch_gemv_t(c.op_hi, B, c.vt, bvec, 1, 0, m, 0, 1, nullptr, 0, c.L.ypart,
-                       c.nsplit_for(c.op_hi, 1), (int64_t)c.L.nrhs * c.L.npad, c.L.npad,
-                       c.L.yprob(), nullptr, 0, c.st));
-      HC(launch_sum_splits(c.vt, B, n, c.L.ypart, c.nsplit_for(c.op_hi, 1),
-                           (int64_t)c.L.nrhs * c.L.npad, c.L.yprob(),
-                           c_hi, n, c.st));
-    }
+    // with the master copy in every precision: the final report's r_d uses it
+    HC(launch_gemv_t(c.op_hi, B, c.vt, bvec, 1, 0, m, 0, 1, nullptr, 0, c.L.ypart,
+                     c.nsplit_for(c.op_hi, 1), (int64_t)c.L.nrhs * c.L.npad, c.L.npad,
+                     c.L.yprob(), nullptr, 0, c.st));
+    HC(launch_sum_splits(c.vt, B, n, c.L.ypart, c.nsplit_for(c.op_hi, 1),
+                         (int64_t)c.L.nrhs * c.L.npad, c.L.yprob(), c_hi, n, c.st));
   }
   // Every problem runs during setup passes.
   set_params(1, true);
