@@ -51,7 +51,7 @@ template <typename VT>
 __device__ __forceinline__ void ut_r_partial(const VT* __restrict__ Ub, int64_t ldu, int s_eff,
                                              const Chunk& ch, const VT* rs, double* part_out,
                                              int64_t ostride = 1) {
-  constexpr int G = sizeof(VT) == 4 ? 8 : 4;
+  constexpr int G = sizeof(VT) == 4 ? 16 : 8;  // columns in flight per lane
   constexpr int T = 4;  // row loads per lane per column (one 256-row slab)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int len = (int)(ch.hi - ch.lo);
