@@ -29,7 +29,8 @@ products on the matrix cores), for counter passes over those kernels.
 After the timed steps, `next_rows` times (once warm, outside the timed region)
 the elastic net, the duality-gap termination and the adaptive sketch size on the
 same workload, Huber fitting at n = 16000 under the paper's stopping rule and
-the bounded least squares ablation at 32000 x 16000 (--no-next skips them).
+the bounded least squares ablation at 32000 x 16000, the logistic workload and the
+batch of 64 Lasso problems (--no-next skips them).
 """
 from __future__ import annotations
 
@@ -167,8 +168,10 @@ def next_rows(g, torch, A, b, lam, s):
     <= 1.2) on
     the headline workload, Huber fitting at the paper's largest size (n = 16000,
     N = 8000, no preconditioner) under its own stopping rule, dist(0, dF(z)) <= 1e-4,
-    and bounded least squares at the size of its ablation (N = 32000, n = 16000,
-    eps 1e-5) with and without the preconditioner and inexact solves."""
+    bounded least squares at the size of its ablation (N = 32000, n = 16000,
+    eps 1e-5) with and without the preconditioner and inexact solves, the
+    l1-logistic workload (20000 x 5000, 300 iterations) and the batch of 64 Lasso
+    problems with their adjoints."""
     import genios_data
     out = {}
     kw = dict(precision="bf16_refine", sketch_rank=s, profile_kernels=1)
@@ -206,6 +209,53 @@ def next_rows(g, torch, A, b, lam, s):
                                     subgrad_dist=hu["subgrad_dist"], obj=hu["obj"])
         log(f"huber {prec}: {out[f'huber_{prec}']}")
     del Ah, bh
+    # l1-logistic regression at the paper's settings (re-sketch every 20): a fixed 300
+    # iterations (this workload converges slowly, oracle and GPU alike)
+    Lg = genios_data.config("logreg_20000x5000")
+    Al = torch.from_numpy(Lg["A"]).to(A.device)
+    yl = torch.from_numpy(Lg["y"]).to(A.device)
+    for _ in range(2):
+        lo = g.logreg_solve(Al, yl, Lg["lam"], precision="bf16_refine", eps=1e-4,
+                            sketch_rank=Lg["s"], resketch_every=20, max_iter=300,
+                            profile_kernels=1)["info"][0]
+    gbs, frac = _hvp_rate(lo)
+    out["logreg_20000x5000"] = {
+        "iters": lo["iters"], "cg_iters": lo["cg_iters"], "resketches": lo["resketches"],
+        "iters_per_s": round(lo["iters"] / lo["t_solve"], 1), "t_solve_s": round(lo["t_solve"], 4),
+        "precond_s": round(lo["t_precond"], 4), "r_kkt": lo["r_kkt"],
+        "hvp_GBps": gbs, "hvp_frac_of_peak": frac}
+    log(f"logreg: {out['logreg_20000x5000']}")
+    del Al, yl
+    # the batch of 64 Lasso problems (2000 x 8000 each) and their adjoints
+    t0 = time.time()
+    Pb = genios_data.config("lasso_batch_64x2000x8000")
+    Ab = torch.from_numpy(Pb["A"]).to(A.device)
+    bb = torch.from_numpy(Pb["b"]).to(A.device)
+    x0b = torch.from_numpy(Pb["x0"]).to(A.device, torch.float32)
+    log(f"generated {Pb['name']} in {time.time() - t0:.1f}s")
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ob = g.lasso_solve(Ab, bb, Pb["lam"], precision="bf16_refine", eps=1e-4,
+                           sketch_rank=Pb["s"], profile_kernels=1)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        gzb = (2.0 * (ob["z"] - x0b)).contiguous()
+        _, _, binf = g.lasso_backward(Ab, ob["z"], gzb, Pb["lam"], sketch_rank=Pb["s"])
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+    its = [i["iters"] for i in ob["info"]]
+    gbs, frac = _hvp_rate(ob["info"][0])
+    out["lasso_batch_64x2000x8000"] = {
+        "problems": len(its), "all_ok": all(i["status"] == 0 for i in ob["info"]) and
+        all(i["status"] == 0 for i in binf),
+        "solve_s": round(t2 - t1, 4), "adjoint_s": round(t3 - t2, 4),
+        "admm_iters_total": int(sum(its)), "admm_iters_max": int(max(its)),
+        "admm_iters_per_s": round(sum(its) / (t2 - t1), 1),
+        "problems_per_s": round(len(its) / (t3 - t1), 1),
+        "hvp_GBps": gbs, "hvp_frac_of_peak": frac}
+    log(f"batch: {out['lasso_batch_64x2000x8000']}")
+    del Ab, bb, x0b
     # bounded least squares at the size of the paper's ablation (N = 32000, n = 16000),
     # eps 1e-5, with and without the preconditioner and inexact solves
     t0 = time.time()
