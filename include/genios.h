@@ -120,7 +120,8 @@ typedef struct {
   double cg_tol_floor;         /* lower bound on the CG relative tolerance, default 1e-7
                                   (1e-13 for FP64); also the tolerance of exact solves */
   int32_t sketch_rank;         /* Nystrom rank s (<= 128); 0 = min(50, floor(n/20)) */
-  int32_t resketch_every;      /* logistic: re-sketch period in ADMM iterations, default 20 */
+  int32_t resketch_every;      /* logistic and Huber (D changes with x): re-sketch period in
+                                  ADMM iterations, default 20 */
   int32_t precondition;        /* 1 = Nystrom preconditioner, 0 = plain CG; default 1 */
   int32_t inexact;             /* 1 = tolerance schedule of Sec. 2.1, 0 = exact (cg_tol_floor) */
   double switch_tol;           /* BF16 -> FP32 switch when the BF16 problem's r_kkt <= switch_tol;
@@ -147,8 +148,9 @@ typedef struct {
                                   BF16_ONLY: with the BF16 copy) every gap_every iterations;
                                   2: the same pass's distance from 0 to the subdifferential
                                   of the objective at z, ||grad f(z) + lambda v||_2 for the
-                                  best v in d||z||_1, <= eps_gap (the criterion of the
-                                  Huber comparison in Sec. 4.3) */
+                                  best v in d||z||_1 (genios_boxls_solve: in the box's normal
+                                  cone at z), <= eps_gap (the criterion of the Huber
+                                  comparison in Sec. 4.3) */
   int32_t gap_every;           /* iterations between gap evaluations, default 1 */
   double eps_gap;              /* tolerance of termination 1 (relative) or 2 (absolute),
                                   default 1e-4 */
@@ -193,7 +195,8 @@ typedef struct {
   int32_t phase_switch_iter; /* first FP32-operator iteration (BF16_REFINE), else -1 */
   int32_t resketches;        /* Nystrom builds performed */
   int32_t precond_rank;      /* retained sketch rank of the last build (eigenpairs kept) */
-  double obj;                /* objective at z with the master-copy data (FP64 reduction) */
+  double obj;                /* objective at z with the master-copy data (FP64 reduction; the
+                                duality-gap pass's primal value, gap_primal) */
   double r_p, r_d, r_kkt;    /* final residuals (r_d with the master-copy operator) */
   double rho;                /* final penalty */
   double t_setup;            /* seconds: casting, A^T b, first sketch */
@@ -226,11 +229,13 @@ typedef struct {
   double rel_gap;            /* relative duality gap (Sec. 3.3, App. A) at the returned z with the
                                 master copy: (l(z) - g(nu)) / min(l(z), |g(nu)|) */
   double gap_primal;         /* l(z) */
-  double gap_dual;           /* g(nu), nu = min(1, lambda / ||A^T f'(A z - b)||_inf) f'(A z - b) */
+  double gap_dual;           /* g(nu), nu = min(1, lambda / ||A^T f'(A z - b)||_inf) f'(A z - b)
+                                (lambda2 > 0 or the box: nu = f'(A z - b); the box dual is
+                                -inf where an infinite bound meets a wrong sign of A^T nu) */
   int32_t gap_checks;        /* gap evaluations during the solve (termination = 1 or 2) */
   int32_t reserved2;
   double subgrad_dist;       /* at the returned z with the master copy: the distance from 0 to
-                                grad f(z) + lambda d||z||_1 (l2 norm) */
+                                grad f(z) + lambda d||z||_1 (box: + the normal cone; l2 norm) */
   double sketch_err;         /* adaptive_sketch: power-method estimate of ||H - H_hat|| for the
                                 last Nystrom build, else 0 */
   double kappa_bound;        /* adaptive_sketch: 1 + (lam_hat_rr + sketch_err) / nu of that build */
