@@ -170,7 +170,12 @@ typedef struct {
   int32_t sketch_rank_init;    /* first size of the doubling rule, default 8, >= 1 */
   double sketch_kappa;         /* target of the condition-number bound, default 10, > 1 */
   int32_t power_iters;         /* power-method steps per size, default 10, >= 1 */
-  int32_t reserved3;
+  int32_t batch_mfma;          /* a batch sharing one matrix (stride_A = 0) with the squared loss
+                                  (Lasso, elastic net, box) forms the BF16 H p of all problems
+                                  at once on the matrix cores: T = A [p_1 .. p_B], then A^T T,
+                                  two streams of A instead of B (p and T carried as BF16
+                                  hi + lo parts, ~16 bits); 0 = off, 1 (default) = for batches
+                                  of 5 to 128 problems, 2 = for 2 to 128 */
 } genios_opts;
 
 /* Per-iteration history row layout (doubles); problem p, iteration k (1-based)
@@ -240,7 +245,9 @@ typedef struct {
                                 last Nystrom build, else 0 */
   double kappa_bound;        /* adaptive_sketch: 1 + (lam_hat_rr + sketch_err) / nu of that build */
   int32_t sketch_rounds;     /* sizes tried in the last build (1 without adaptive_sketch) */
-  int32_t reserved4;
+  int32_t n_hvp_mrhs;        /* batch_mfma: H p launches that served the whole batch */
+  double t_hvp_mrhs;         /* with profile_kernels: their summed duration */
+  int64_t bytes_hvp_mrhs;    /* bytes they must move: A twice, every problem's p in and H p out */
 } genios_info;
 
 /* Fill *o with the defaults listed above.  Returns GENIOS_OK. */

@@ -304,11 +304,14 @@ def matvec(A, v, trans=False, A16=None):
     return out
 
 
-def hvp(A, p, d=None, A16=None):
-    """A^T diag(d) A p (d None: A^T A p) with the CG loop's product kernels."""
+def hvp(A, p, d=None, A16=None, batch_mfma=1):
+    """A^T diag(d) A p (d None: A^T A p) with the CG loop's product kernels.  A batch
+    sharing one matrix (A.expand(B, m, n)) with BF16 A16 uses the matrix-core products
+    for all problems at once unless batch_mfma = 0 (see genios_opts.batch_mfma)."""
     dev = A.device
     M = _matrix(A, A16)
     o = _abi.default_opts()
+    o.batch_mfma = int(batch_mfma)
     o.precision = _abi.PREC_BF16_ONLY if A16 is not None else (
         _abi.PREC_F64 if A.dtype == torch.float64 else _abi.PREC_F32)
     B, m, n = M.batch, M.m, M.n

@@ -60,7 +60,7 @@ class Opts(C.Structure):
                 ("eps_gap", C.c_double), ("lambda2", C.c_double),
                 ("huber_delta", C.c_double), ("adaptive_sketch", C.c_int32),
                 ("sketch_rank_init", C.c_int32), ("sketch_kappa", C.c_double),
-                ("power_iters", C.c_int32), ("reserved3", C.c_int32)]
+                ("power_iters", C.c_int32), ("batch_mfma", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -84,7 +84,8 @@ class Info(C.Structure):
                 ("gap_checks", C.c_int32), ("reserved2", C.c_int32),
                 ("subgrad_dist", C.c_double), ("sketch_err", C.c_double),
                 ("kappa_bound", C.c_double), ("sketch_rounds", C.c_int32),
-                ("reserved4", C.c_int32)]
+                ("n_hvp_mrhs", C.c_int32), ("t_hvp_mrhs", C.c_double),
+                ("bytes_hvp_mrhs", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -60,6 +60,7 @@ int check_opts(const genios_opts* o) {
     FAIL(GENIOS_ERR_ARG, "sketch_kappa must be finite and > 1");
   if (o->power_iters < 1 || o->power_iters > 1000)
     FAIL(GENIOS_ERR_ARG, "power_iters must lie in [1, 1000]");
+  if (o->batch_mfma < 0 || o->batch_mfma > 2) FAIL(GENIOS_ERR_ARG, "batch_mfma must be 0, 1 or 2");
   return GENIOS_OK;
 }
 
@@ -155,6 +156,7 @@ int genios_default_opts(genios_opts* o) {
   o->sketch_rank_init = 8;
   o->sketch_kappa = 10.0;
   o->power_iters = 10;
+  o->batch_mfma = 1;
   return GENIOS_OK;
 }
 

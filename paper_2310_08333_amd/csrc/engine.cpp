@@ -124,6 +124,12 @@ void Layout::carve(Arena& ar) {
     AS = ar.take((size_t)B * m * ldS_max * ve);
     maskS = static_cast<uint8_t*>(ar.take((size_t)B * ldS_max));
   }
+  if (mr.sp > 0) {
+    const int64_t kpn = (n + 31) / 32 * 32, kpm = (m + 31) / 32 * 32;
+    mr.p16 = static_cast<uint16_t*>(ar.take((size_t)2 * mr.sp * kpn * sizeof(uint16_t)));
+    mr.w16 = static_cast<uint16_t*>(ar.take((size_t)2 * mr.sp * kpm * sizeof(uint16_t)));
+    mr.wpart = static_cast<float*>(ar.take((size_t)mr.ksW * mr.sp * m * sizeof(float)));
+  }
   if (s > 0) {
     pm_est = static_cast<double*>(ar.take((size_t)B * sizeof(double)));
     U = vec(n * (int64_t)s);
@@ -183,6 +189,21 @@ int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_)
   // is singular and the call fails), up to n with it
   ldS_max = backward ? (int)(((o->lambda2 > 0.0 ? n : std::min(m, n)) + 7) / 8 * 8) : 0;
   if (s > 0) sketch_ws_bytes(m, n, s, batch, vt, &sk.ksW, &sk.ksY, &sk.nbG);
+  // H p of a batch sharing A on the matrix cores (squared loss, BF16 operand)
+  mr = MrhsWs{};
+  const bool shared = A->stride_A == 0 && batch >= 2 && batch <= 128;
+  const bool sq_op = op == GENIOS_OP_LASSO || op == GENIOS_OP_BOXLS || op == GENIOS_OP_HVP;
+  const int64_t min_batch = o->batch_mfma == 2 ? 2 : 5;
+  if (o->batch_mfma != 0 && shared && batch >= min_batch && sq_op && uses_lo && vt == VT_F32 &&
+      n % 8 == 0 && A->lda % 8 == 0) {
+    mr.sp = mrhs_pad((int)batch);
+    const int64_t rb = (m + 127) / 128, cb = (n + 127) / 128;
+    mr.ksW = (int)std::max<int64_t>(1, std::min<int64_t>((1024 + rb - 1) / rb, std::max<int64_t>(1, n / 256)));
+    int64_t ky = std::max<int64_t>(1, std::min<int64_t>((1024 + cb - 1) / cb, std::max<int64_t>(1, m / 256)));
+    ky = std::min<int64_t>(ky, batch * yslots / mr.sp);  // ypart holds ksY x sp columns
+    mr.ksY = (int)std::max<int64_t>(1, ky);
+    if (batch * yslots < mr.sp) mr.sp = 0;  // cannot happen: yslots >= 512 / batch
+  }
   Arena ar{nullptr, 0, 0, true};
   carve(ar);
   return 0;
@@ -224,10 +245,11 @@ struct KernelProf {
   bool on = false;
   std::vector<hipEvent_t> evs;
   // 0 = A v, 1 = A^T w, 2 / 3 = fused H p on the BF16 / master copy,
-  // 4 / 5 = sketch products on the matrix cores / vector units
+  // 4 / 5 = sketch products on the matrix cores / vector units,
+  // 6 = H p of a batch sharing A on the matrix cores
   std::vector<int> kind;
   size_t used = 0;
-  double t[6] = {0, 0, 0, 0, 0, 0};
+  double t[7] = {0, 0, 0, 0, 0, 0, 0};
   ~KernelProf() {
     for (auto e : evs) (void)hipEventDestroy(e);
   }
@@ -294,6 +316,7 @@ struct Ctx {
   const void* box_hi = nullptr;
   KernelProf prof;
   int64_t n_mv[4] = {0, 0, 0, 0};
+  int64_t n_mrhs = 0, bytes_mrhs = 0;  // H p launches of a batch sharing A (all problems at once)
   // bytes of A v / A^T w (the matrix) and of the fused H p on the BF16 / master copy
   // (the matrix once, p read, H p written)
   int64_t bytes_kind[4] = {0, 0, 0, 0};
@@ -400,12 +423,37 @@ struct Ctx {
     HC(prof.end(st));
     cur_ks = ks;
     cur_ks_stride = (int64_t)L.nrhs * L.npad;
+    cur_prob_stride = L.yprob();
     account(op, 1);
     return 0;
   }
   // ypart = H p = A^T (d o (A p)) (gated): one pass over A when it qualifies for
   // the fused kernel, else gemv_n then gemv_t.
+  int64_t mrhs_bytes(const MatArg& op) const {
+    return 2 * op.m * op.n * elem_size(op.mt) + (int64_t)B * op.n * 2 * (int64_t)ve;
+  }
+  void unaccount_mrhs(int64_t launches) {
+    if (launches <= 0 || last_hvp_kind != 6) return;
+    n_mrhs -= launches;
+    bytes_mrhs -= launches * mrhs_bytes(last_hvp_op);
+  }
   int hvp(const MatArg& op, const void* p, const void* d, const int32_t* gate, int gstride) {
+    // a batch sharing A: both passes over A serve every problem (matrix cores)
+    if (d == nullptr && L.mr.sp > 0 && mrhs_eligible(op, vt, B, L.mr)) {
+      HC(prof.begin(st, 6));
+      HC(launch_mrhs_hvp(op, (int)B, static_cast<const float*>(p), n, L.mr,
+                         static_cast<float*>(L.ypart), L.npad, gate, gstride, st));
+      HC(prof.end(st));
+      cur_ks = L.mr.ksY;
+      cur_ks_stride = (int64_t)L.mr.sp * L.npad;
+      cur_prob_stride = L.npad;
+      n_mrhs += 1;
+      bytes_mrhs += mrhs_bytes(op);
+      last_hvp_kind = 6;
+      last_hvp_op = op;
+      return 0;
+    }
+    cur_prob_stride = L.yprob();
     if (vt == VT_F32) {
       const HvpGeom g = hvp_geometry(op, B, true);
       if (g.threads > 0 && g.blocks <= L.yslots && hvp_p_aligned(p, n, B)) {
@@ -430,6 +478,7 @@ struct Ctx {
   }
   int cur_ks = 1;
   int64_t cur_ks_stride = 0;
+  int64_t cur_prob_stride = 0;  // per-problem stride of the last product's partials
 };
 
 // h = H x outside CG (warm start, precision switch, certification): the fused
@@ -438,8 +487,8 @@ int hvp_explicit(Ctx& c, const MatArg& op, const void* x, void* h, const void* d
                  const int32_t* gate, int gstride) {
   int rc = c.hvp(op, x, d, gate, gstride);
   if (rc) return rc;
-  HC(launch_sum_splits(c.vt, c.B, c.n, c.L.ypart, c.cur_ks, c.cur_ks_stride, c.L.yprob(), h, c.n,
-                       c.st, gate, gstride));
+  HC(launch_sum_splits(c.vt, c.B, c.n, c.L.ypart, c.cur_ks, c.cur_ks_stride, c.cur_prob_stride,
+                       h, c.n, c.st, gate, gstride));
   return 0;
 }
 
@@ -517,6 +566,7 @@ int cg_iteration(Ctx& c, const MatArg& op, const VecArgs& va, const void* dscale
   VecArgs a = va;
   a.ksplit = c.cur_ks;
   a.ypart_ks_stride = c.cur_ks_stride;
+  a.ypart_prob_stride = c.cur_prob_stride;
   return cg_vector_step(c, a, t);
 }
 
@@ -904,10 +954,15 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
         if (hp[b].run && !hs[b].admm_done) more = true;
       if (!more) {
         // products enqueued for problems whose CG had stopped ran as no-ops
-        int64_t gated = 0;
-        for (int64_t b = 0; b < B; ++b)
+        int64_t gated = 0, longest = 0;
+        for (int64_t b = 0; b < B; ++b) {
           gated += hp[b].run ? std::max<int64_t>(0, enq - hs[b].cg_iters) : enq;
-        c.unaccount_gated(gated);
+          if (hp[b].run) longest = std::max<int64_t>(longest, hs[b].cg_iters);
+        }
+        if (c.last_hvp_kind == 6)
+          c.unaccount_mrhs(enq - longest);  // launches after every problem's CG had stopped
+        else
+          c.unaccount_gated(gated);
         break;
       }
       chunk = std::max(1, std::min(2, o->max_cg_iter - enq));
@@ -1135,6 +1190,9 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     I.sketch_err = q.sketch_err;
     I.kappa_bound = q.kappa_bound;
     I.sketch_rounds = q.sketch_rounds;
+    I.t_hvp_mrhs = c.prof.t[6];
+    I.n_hvp_mrhs = (int32_t)c.n_mrhs;
+    I.bytes_hvp_mrhs = c.bytes_mrhs;
     I.rho = q.rho;
     I.r_p = q.rp;
     I.r_d = q.rd;
@@ -1289,7 +1347,7 @@ int run_hvp(const genios_matrix* A, int use_bf16, const void* d, const void* p, 
                                 A->stride_A};
   rc = c.hvp(op, p, d, nullptr, 0);
   if (rc) return rc;
-  HC(launch_sum_splits(c.vt, c.B, c.n, c.L.ypart, c.cur_ks, c.cur_ks_stride, c.L.yprob(), out,
+  HC(launch_sum_splits(c.vt, c.B, c.n, c.L.ypart, c.cur_ks, c.cur_ks_stride, c.cur_prob_stride, out,
                        c.n, c.st));
   HC(hipStreamSynchronize(c.st));
   return 0;

@@ -67,6 +67,7 @@ struct Layout {
   double* gpart = nullptr;    // [batch][kGapSlots][kGapPStride]
   GapState* gstate = nullptr; // [batch]
   double* pm_est = nullptr;   // [batch] power-method estimate of ||H - H_hat|| (adaptive sketch)
+  MrhsWs mr{};                // H p of a batch sharing A on the matrix cores (sp = 0: off)
   size_t total = 0;
 
   int setup(int op, const genios_matrix* A, const genios_opts* o, int s);

@@ -353,6 +353,20 @@ bool sketch_mfma_eligible(const MatArg& A, VType vt, const SketchWs& ws);
 hipError_t launch_sketch_mfma(const MatArg& A, int64_t batch, int sp, const float* d,
                               int64_t d_stride, const SketchWs& ws, hipStream_t st);
 int sketch_pad(int s);
+// ---- H p of a batch sharing A on the matrix cores (sketch_mfma.hip) ----
+struct MrhsWs {
+  uint16_t* p16 = nullptr;  // BF16 hi then lo parts of the p block [c][kpad(n)]
+  uint16_t* w16 = nullptr;  // BF16 hi then lo parts of T = A P [c][kpad(m)]
+  float* wpart = nullptr;   // ksW x SP x m partials of T
+  int sp = 0, ksW = 1, ksY = 1;
+};
+int mrhs_pad(int B);
+bool mrhs_eligible(const MatArg& A, VType vt, int64_t B, const MrhsWs& ws);
+// ypart[ks][c][j] (column stride ldy, split stride sp ldy) for ks < ws.ksY; every kernel
+// exits at once when no problem's flag (gate, gstride) is set.
+hipError_t launch_mrhs_hvp(const MatArg& A, int B, const float* P, int64_t pstride,
+                           const MrhsWs& ws, float* ypart, int64_t ldy, const int32_t* gate,
+                           int gstride, hipStream_t st);
 size_t sketch_ws_bytes(int64_t m, int64_t n, int s, int64_t batch, VType vt, int* ksW, int* ksY,
                        int* nbG);
 // Y = H Omega (H = A^T diag(d) A) then the stabilised s x s core and U.

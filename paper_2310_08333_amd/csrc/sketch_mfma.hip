@@ -85,23 +85,43 @@ __global__ __launch_bounds__(256) void k_omega_bf16(int64_t n, int sp, int64_t k
   }
 }
 
-// Wpart[b][ks][c][r] = sum_{k in split ks} A[r][k] Omega[k][c]
-template <int SP>
+// True if any of the `count` flags (stride `gstride` ints) is set, or gate is NULL.
+__device__ __forceinline__ bool any_flag(const int32_t* gate, int gstride, int count) {
+  if (gate == nullptr) return true;
+  __shared__ int s_any;
+  if (threadIdx.x == 0) s_any = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < count; i += blockDim.x)
+    if (gate[(int64_t)i * gstride] != 0) s_any = 1;
+  __syncthreads();
+  return s_any != 0;
+}
+
+// Wpart[b][ks][c][r] = sum_{k in split ks} A[r][k] Omega[k][c]; with LO the operand is
+// the sum of two BF16 parts (hi + lo of an FP32 block), both staged per step.
+template <int SP, bool LO>
 __global__ __launch_bounds__(256) void k_sketch_w_mfma(const uint16_t* __restrict__ A,
                                                        int64_t lda, int64_t strideA, int m, int n,
                                                        const uint16_t* __restrict__ o16,
+                                                       const uint16_t* __restrict__ o16lo,
                                                        int64_t kpad, float* __restrict__ wpart,
                                                        int kchunk, int64_t ks_stride,
-                                                       int64_t prob_stride) {
+                                                       int64_t prob_stride,
+                                                       const int32_t* __restrict__ gate,
+                                                       int gstride, int gcount) {
   constexpr int NT = SP / 16;  // column tiles
-  __shared__ __align__(16) uint16_t os[2][SP * kPitch];
+  constexpr int NO = LO ? 2 : 1;  // operand parts
+  __shared__ __align__(16) uint16_t os[NO][2][SP * kPitch];
+  if (!any_flag(gate, gstride, gcount)) return;
   const int b = blockIdx.z, ks = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int row0 = blockIdx.x * kWRows + wave * 32;
   const int k0 = ks * kchunk;
   const int k1 = min(n, k0 + kchunk);
   const uint16_t* Ab = A + (int64_t)b * strideA;
-  const uint16_t* Ob = o16 + (int64_t)b * SP * kpad;
+  const uint16_t* Obp[NO];
+  Obp[0] = o16 + (int64_t)b * SP * kpad;
+  if constexpr (LO) Obp[NO - 1] = o16lo + (int64_t)b * SP * kpad;
   // this lane's A rows (clamped: rows past m are computed but not stored)
   const uint16_t* arow[2];
 #pragma unroll
@@ -116,23 +136,28 @@ __global__ __launch_bounds__(256) void k_sketch_w_mfma(const uint16_t* __restric
   constexpr int OCH = SP * 4;
   // (loads are unconditional -- chunk indices past the tile re-read chunk 0 -- so
   // the staging registers stay registers; only the LDS stores are guarded)
-  auto load_omega = [&](int kk, uint4 (&reg)[(OCH + 255) / 256]) {
+  constexpr int OQ = (OCH + 255) / 256;
+  auto load_omega = [&](int kk, uint4 (&reg)[NO][OQ]) {
 #pragma unroll
-    for (int q = 0; q < (OCH + 255) / 256; ++q) {
-      const int ch = tid + 256 * q < OCH ? tid + 256 * q : 0;
-      const int c = ch >> 2, part = ch & 3;
-      reg[q] = *reinterpret_cast<const uint4*>(Ob + (int64_t)c * kpad + kk + 8 * part);
-    }
-  };
-  auto store_omega = [&](int buf, const uint4 (&reg)[(OCH + 255) / 256]) {
+    for (int o = 0; o < NO; ++o)
 #pragma unroll
-    for (int q = 0; q < (OCH + 255) / 256; ++q) {
-      const int ch = tid + 256 * q;
-      if (ch < OCH) {
+      for (int q = 0; q < OQ; ++q) {
+        const int ch = tid + 256 * q < OCH ? tid + 256 * q : 0;
         const int c = ch >> 2, part = ch & 3;
-        *reinterpret_cast<uint4*>(&os[buf][c * kPitch + 8 * part]) = reg[q];
+        reg[o][q] = *reinterpret_cast<const uint4*>(Obp[o] + (int64_t)c * kpad + kk + 8 * part);
       }
-    }
+  };
+  auto store_omega = [&](int buf, const uint4 (&reg)[NO][OQ]) {
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+      for (int q = 0; q < OQ; ++q) {
+        const int ch = tid + 256 * q;
+        if (ch < OCH) {
+          const int c = ch >> 2, part = ch & 3;
+          *reinterpret_cast<uint4*>(&os[o][buf][c * kPitch + 8 * part]) = reg[o][q];
+        }
+      }
   };
   // A fragments of a step: columns past n read column 0 (their Omega rows are 0)
   auto load_a = [&](int kk, uint4 (&fa)[2]) {
@@ -141,7 +166,7 @@ __global__ __launch_bounds__(256) void k_sketch_w_mfma(const uint16_t* __restric
 #pragma unroll
     for (int t = 0; t < 2; ++t) fa[t] = *reinterpret_cast<const uint4*>(arow[t] + kc);
   };
-  uint4 oreg[(OCH + 255) / 256];
+  uint4 oreg[NO][OQ];
   uint4 fa[2], fn[2];
   if (k0 < k1) {
     load_omega(k0, oreg);
@@ -157,9 +182,13 @@ __global__ __launch_bounds__(256) void k_sketch_w_mfma(const uint16_t* __restric
     load_a(kn, fn);
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
-      const uint4 fb = *reinterpret_cast<const uint4*>(&os[buf][(16 * c + (lane & 15)) * kPitch + kl]);
 #pragma unroll
-      for (int t = 0; t < 2; ++t) acc[t][c] = mfma(fa[t], fb, acc[t][c]);
+      for (int o = 0; o < NO; ++o) {
+        const uint4 fb =
+            *reinterpret_cast<const uint4*>(&os[o][buf][(16 * c + (lane & 15)) * kPitch + kl]);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[t][c] = mfma(fa[t], fb, acc[t][c]);
+      }
     }
     if (more) store_omega(buf ^ 1, oreg);
     __syncthreads();
@@ -185,7 +214,10 @@ __global__ __launch_bounds__(256) void k_w_split(int64_t m, int sp, int ksW,
                                                  int64_t ks_stride, int64_t prob_stride,
                                                  const float* __restrict__ d, int64_t d_stride,
                                                  int64_t kpad, uint16_t* __restrict__ hi,
-                                                 uint16_t* __restrict__ lo) {
+                                                 uint16_t* __restrict__ lo,
+                                                 const int32_t* __restrict__ gate, int gstride,
+                                                 int gcount) {
+  if (!any_flag(gate, gstride, gcount)) return;
   const int b = blockIdx.y;
   const float* Wp = wpart + (int64_t)b * prob_stride;
   const float* db = d ? d + (int64_t)b * d_stride : nullptr;
@@ -217,12 +249,15 @@ __global__ __launch_bounds__(256) void k_sketch_y_mfma(const uint16_t* __restric
                                                        const uint16_t* __restrict__ wlo,
                                                        int64_t kpad, float* __restrict__ ypart,
                                                        int rchunk, int64_t ks_stride,
-                                                       int64_t prob_stride) {
+                                                       int64_t prob_stride, int64_t ldy,
+                                                       const int32_t* __restrict__ gate,
+                                                       int gstride, int gcount) {
   constexpr int NT = SP / 16;
   __shared__ __align__(16) uint16_t at[kYCols * kPitchT];      // A tile transposed: [j][r]
   // hi, lo tiles [c][r], plus one spare row that threads past the tile write into
   // (never read), so every staging store is unconditional
   __shared__ __align__(16) uint16_t ws[2][(SP + 1) * kPitch];
+  if (!any_flag(gate, gstride, gcount)) return;
   const int b = blockIdx.z, ks = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int j0 = blockIdx.x * kYCols;
@@ -314,7 +349,7 @@ __global__ __launch_bounds__(256) void k_sketch_y_mfma(const uint16_t* __restric
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int j = j0 + 32 * wave + 16 * t + 4 * (lane >> 4) + i;
-        if (j < n) Yb[(int64_t)(16 * c + (lane & 15)) * n + j] = acc[t][c][i];
+        if (j < n) Yb[(int64_t)(16 * c + (lane & 15)) * ldy + j] = acc[t][c][i];
       }
 }
 
@@ -335,9 +370,10 @@ hipError_t sketch_mfma_sp(const MatArg& A, int64_t batch, const float* d, int64_
     int kchunk = (int)((A.n + ws.ksW - 1) / ws.ksW);
     kchunk = (kchunk + kMK - 1) / kMK * kMK;
     dim3 grid((unsigned)((m + kWRows - 1) / kWRows), (unsigned)ws.ksW, (unsigned)batch);
-    hipLaunchKernelGGL(k_sketch_w_mfma<SP>, grid, dim3(256), 0, st, Ap, A.lda, A.strideA, m, n,
-                       ws.o16, kpn, static_cast<float*>(ws.Wpart), kchunk, (int64_t)m * SP,
-                       (int64_t)ws.ksW * m * SP);
+    hipLaunchKernelGGL((k_sketch_w_mfma<SP, false>), grid, dim3(256), 0, st, Ap, A.lda,
+                       A.strideA, m, n, ws.o16, (const uint16_t*)nullptr, kpn,
+                       static_cast<float*>(ws.Wpart), kchunk, (int64_t)m * SP,
+                       (int64_t)ws.ksW * m * SP, (const int32_t*)nullptr, 0, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -346,7 +382,7 @@ hipError_t sketch_mfma_sp(const MatArg& A, int64_t batch, const float* d, int64_
     hipLaunchKernelGGL(k_w_split, dim3(nb, (unsigned)batch), dim3(256), 0, st, A.m, SP, ws.ksW,
                        static_cast<const float*>(ws.Wpart), (int64_t)m * SP,
                        (int64_t)ws.ksW * m * SP, d, d_stride, kpm, ws.w16,
-                       ws.w16 + (size_t)batch * SP * kpm);
+                       ws.w16 + (size_t)batch * SP * kpm, (const int32_t*)nullptr, 0, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -357,12 +393,100 @@ hipError_t sketch_mfma_sp(const MatArg& A, int64_t batch, const float* d, int64_
     hipLaunchKernelGGL(k_sketch_y_mfma<SP>, grid, dim3(256), 0, st, Ap, A.lda, A.strideA, m, n,
                        ws.w16, ws.w16 + (size_t)batch * SP * kpm, kpm,
                        static_cast<float*>(ws.Ypart), rchunk, (int64_t)n * SP,
-                       (int64_t)ws.ksY * n * SP);
+                       (int64_t)ws.ksY * n * SP, (int64_t)n, (const int32_t*)nullptr, 0, 0);
     return hipGetLastError();
   }
 }
 
+// P (n x B FP32, column c at P + c pstride) -> BF16 hi and lo parts [c][kpad], zero
+// past n and for the padding columns c >= B.
+__global__ __launch_bounds__(256) void k_cols_split(int64_t n, int B, int sp,
+                                                    const float* __restrict__ P, int64_t pstride,
+                                                    int64_t kpad, uint16_t* __restrict__ hi,
+                                                    uint16_t* __restrict__ lo,
+                                                    const int32_t* __restrict__ gate, int gstride,
+                                                    int gcount) {
+  if (!any_flag(gate, gstride, gcount)) return;
+  const int64_t total = (int64_t)sp * kpad;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / kpad);
+    const int64_t k = e - (int64_t)c * kpad;
+    const float v = (c < B && k < n) ? P[(int64_t)c * pstride + k] : 0.f;
+    const uint16_t h = f32_to_bf16_rne(v);
+    hi[e] = h;
+    lo[e] = f32_to_bf16_rne(v - __uint_as_float((uint32_t)h << 16));
+  }
+}
+
+// H p for B problems sharing A (BF16): T = A [p_1 .. p_B] (P in BF16 hi + lo parts, one
+// pass over A), then A^T (T in BF16 hi + lo parts, one pass): two streams of A for
+// all B right-hand sides.  Output: ypart[ks][c][j] with column stride ldy.
+template <int SP>
+hipError_t mrhs_sp(const MatArg& A, int B, const float* P, int64_t pstride, const MrhsWs& ws,
+                   float* ypart, int64_t ldy, const int32_t* gate, int gstride, hipStream_t st) {
+  const int m = (int)A.m, n = (int)A.n;
+  const uint16_t* Ap = static_cast<const uint16_t*>(A.ptr);
+  const int64_t kpn = (A.n + kMK - 1) / kMK * kMK, kpm = (A.m + kMK - 1) / kMK * kMK;
+  uint16_t* ph = ws.p16;
+  uint16_t* pl = ws.p16 + (size_t)SP * kpn;
+  uint16_t* th = ws.w16;
+  uint16_t* tl = ws.w16 + (size_t)SP * kpm;
+  {
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((SP * kpn + 255) / 256, 2048));
+    hipLaunchKernelGGL(k_cols_split, dim3(nb), dim3(256), 0, st, A.n, B, SP, P, pstride, kpn, ph,
+                       pl, gate, gstride, B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    int kchunk = (int)((A.n + ws.ksW - 1) / ws.ksW);
+    kchunk = (kchunk + kMK - 1) / kMK * kMK;
+    dim3 grid((unsigned)((m + kWRows - 1) / kWRows), (unsigned)ws.ksW, 1u);
+    hipLaunchKernelGGL((k_sketch_w_mfma<SP, true>), grid, dim3(256), 0, st, Ap, A.lda, (int64_t)0,
+                       m, n, ph, pl, kpn, ws.wpart, kchunk, (int64_t)m * SP,
+                       (int64_t)ws.ksW * m * SP, gate, gstride, B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((SP * kpm + 255) / 256, 2048));
+    hipLaunchKernelGGL(k_w_split, dim3(nb, 1u), dim3(256), 0, st, A.m, SP, ws.ksW, ws.wpart,
+                       (int64_t)m * SP, (int64_t)ws.ksW * m * SP, (const float*)nullptr,
+                       (int64_t)0, kpm, th, tl, gate, gstride, B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  int rchunk = (int)((A.m + ws.ksY - 1) / ws.ksY);
+  rchunk = (rchunk + kMK - 1) / kMK * kMK;
+  dim3 grid((unsigned)((n + kYCols - 1) / kYCols), (unsigned)ws.ksY, 1u);
+  hipLaunchKernelGGL(k_sketch_y_mfma<SP>, grid, dim3(256), 0, st, Ap, A.lda, (int64_t)0, m, n, th,
+                     tl, kpm, ypart, rchunk, (int64_t)SP * ldy, (int64_t)0, ldy, gate, gstride,
+                     B);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+int mrhs_pad(int B) { return B <= 16 ? 16 : B <= 32 ? 32 : B <= 64 ? 64 : 128; }
+
+bool mrhs_eligible(const MatArg& A, VType vt, int64_t B, const MrhsWs& ws) {
+  return vt == VT_F32 && A.mt == MT_BF16 && A.strideA == 0 && B >= 2 && B <= 128 &&
+         ws.p16 != nullptr && ws.sp == mrhs_pad((int)B) && A.n % 8 == 0 && A.lda % 8 == 0 &&
+         reinterpret_cast<uintptr_t>(A.ptr) % 16 == 0;
+}
+
+hipError_t launch_mrhs_hvp(const MatArg& A, int B, const float* P, int64_t pstride,
+                           const MrhsWs& ws, float* ypart, int64_t ldy, const int32_t* gate,
+                           int gstride, hipStream_t st) {
+  switch (ws.sp) {
+    case 16: return mrhs_sp<16>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
+    case 32: return mrhs_sp<32>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
+    case 64: return mrhs_sp<64>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
+    case 128: return mrhs_sp<128>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 bool sketch_mfma_eligible(const MatArg& A, VType vt, const SketchWs& ws) {
   return vt == VT_F32 && A.mt == MT_BF16 && ws.o16 != nullptr && ws.w16 != nullptr &&

@@ -352,3 +352,26 @@ def test_stream_read_reads_every_word(g):
     got = np.bitwise_xor.reduce(scratch.cpu().numpy().view(np.uint32))
     assert got == np.bitwise_xor.reduce(words.view(np.uint32))
     assert g.stream_read_seconds(t, reps=2) > 0
+
+
+@pytest.mark.parametrize("B", [8, 20])
+def test_hvp_shared_matrix_batch_on_the_matrix_cores(g, B):
+    # B problems sharing one BF16 matrix: T = A P and A^T T on the matrix cores (P and T
+    # as BF16 hi + lo parts) against FP64 products with the same BF16 values, and
+    # against the per-problem fused kernel
+    print("hvp shared batch", B, flush=True)
+    m, n = 301, 1208
+    rng = np.random.default_rng(B)
+    A = torch.from_numpy(rng.standard_normal((m, n)).astype(np.float32)).to(DEV)
+    A16 = g.cast_bf16(A)
+    P = torch.from_numpy(rng.standard_normal((B, n)).astype(np.float32)).to(DEV)
+    Ab, A16b = A.expand(B, m, n), A16.expand(B, m, n)
+    got = g.hvp(Ab, P, A16=A16b, batch_mfma=1).cpu().numpy().astype(np.float64)
+    per = g.hvp(Ab, P, A16=A16b, batch_mfma=0).cpu().numpy().astype(np.float64)
+    Af = A16.float().cpu().numpy().astype(np.float64)
+    Pn = P.cpu().numpy().astype(np.float64)
+    for b in range(B):
+        ref = Af.T @ (Af @ Pn[b])
+        scale = np.linalg.norm(ref)
+        assert np.linalg.norm(got[b] - ref) <= 1e-4 * scale, (b, np.linalg.norm(got[b] - ref) / scale)
+        assert np.linalg.norm(per[b] - ref) <= 1e-5 * scale
