@@ -170,8 +170,9 @@ def next_rows(g, torch, A, b, lam, s):
     N = 8000, no preconditioner) under its own stopping rule, dist(0, dF(z)) <= 1e-4,
     bounded least squares at the size of its ablation (N = 32000, n = 16000,
     eps 1e-5) with and without the preconditioner and inexact solves, the
-    l1-logistic workload (20000 x 5000, 300 iterations) and the batch of 64 Lasso
-    problems with their adjoints."""
+    l1-logistic workload (20000 x 5000, 300 iterations), the batch of 64 Lasso
+    problems with their adjoints, and 32 problems sharing the headline matrix (their
+    H p on the matrix cores, and a lambda path)."""
     import genios_data
     out = {}
     kw = dict(precision="bf16_refine", sketch_rank=s, profile_kernels=1)
@@ -209,6 +210,47 @@ def next_rows(g, torch, A, b, lam, s):
                                     subgrad_dist=hu["subgrad_dist"], obj=hu["obj"])
         log(f"huber {prec}: {out[f'huber_{prec}']}")
     del Ah, bh
+    # a batch sharing the headline matrix: the H p of 32 problems at once on the matrix
+    # cores against one fused product per problem, and a 32-value lambda path
+    Bsh = 32
+    m = A.shape[0]
+    Ash, A16sh = A.expand(Bsh, m, A.shape[1]), g.cast_bf16(A).expand(Bsh, m, A.shape[1])
+    Psh = torch.randn(Bsh, A.shape[1], device=A.device, dtype=torch.float32)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_sh = {}
+    for mf in (1, 0):
+        g.hvp(Ash, Psh, A16=A16sh, batch_mfma=mf)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(3):
+            g.hvp(Ash, Psh, A16=A16sh, batch_mfma=mf)
+        ev1.record()
+        torch.cuda.synchronize()
+        t_sh[mf] = ev0.elapsed_time(ev1) / 3 / 1e3
+    a_bytes = m * A.shape[1] * 2
+    out["shared_matrix_hvp_32"] = {
+        "matrix_cores_ms": round(1e3 * t_sh[1], 3), "per_problem_fused_ms": round(1e3 * t_sh[0], 3),
+        "speedup": round(t_sh[0] / t_sh[1], 2),
+        "matrix_cores_GBps": round((2 * a_bytes + Bsh * A.shape[1] * 8) / t_sh[1] / 1e9, 1),
+        "per_problem_equivalent_GBps": round(Bsh * a_bytes / t_sh[1] / 1e9, 1)}
+    log(f"shared hvp: {out['shared_matrix_hvp_32']}")
+    lams = [float(lam) * 2.0 ** ((j - 16) / 8.0) for j in range(Bsh)]
+    bsh = b.expand(Bsh, m).contiguous()
+    for mf in (1, 0):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        op = g.lasso_solve(Ash, bsh, lams, A16=A16sh, precision="bf16_refine", eps=1e-4, sketch_rank=s,
+                           batch_mfma=mf, profile_kernels=1)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        its = [i["iters"] for i in op["info"]]
+        out[f"lasso_path_32_batch_mfma{mf}"] = {
+            "all_ok": all(i["status"] == 0 for i in op["info"]), "solve_s": round(t2 - t1, 4),
+            "admm_iters_total": int(sum(its)), "admm_iters_max": int(max(its)),
+            "hvp_launches_matrix_cores": op["info"][0]["n_hvp_mrhs"],
+            "phase_switch_iter": op["info"][0]["phase_switch_iter"]}
+        log(f"lasso path 32 batch_mfma={mf}: {out[f'lasso_path_32_batch_mfma{mf}']}")
+    del Ash, A16sh, Psh, bsh
     # l1-logistic regression at the paper's settings (re-sketch every 20): a fixed 300
     # iterations (this workload converges slowly, oracle and GPU alike)
     Lg = genios_data.config("logreg_20000x5000")

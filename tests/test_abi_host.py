@@ -48,6 +48,8 @@ def test_default_opts_are_the_papers(abi):
     assert o.resketch_every == 20 and o.sketch_rank == 0 and o.rho_update_every == 25
     # Sec. 2.1's relative CG tolerance is taken against the warm-started initial residual
     assert o.rhs_relative == 0
+    # a batch sharing one matrix uses the matrix-core products from 5 problems on
+    assert o.batch_mfma == 1
 
 
 def _mat(abi, m=100, n=200, lda=None, batch=1, dt=None):
@@ -96,7 +98,8 @@ def test_matrix_validation(abi, field, value, code):
 @pytest.mark.parametrize("field,value", [
     ("alpha", 2.5), ("alpha", 0.0), ("sigma", -1.0), ("gamma", 0.0), ("tau", 1.0), ("mu", 0.5),
     ("max_iter", 0), ("max_cg_iter", 0), ("cg_tol_floor", 0.0), ("sketch_rank", 129),
-    ("resketch_every", 0), ("precision", 9), ("struct_size", 8)])
+    ("resketch_every", 0), ("precision", 9), ("struct_size", 8), ("batch_mfma", 3),
+    ("batch_mfma", -1)])
 def test_option_validation(abi, field, value):
     o = abi.default_opts()
     setattr(o, field, value)
