@@ -217,23 +217,25 @@ def next_rows(g, torch, A, b, lam, s):
     Ash, A16sh = A.expand(Bsh, m, A.shape[1]), g.cast_bf16(A).expand(Bsh, m, A.shape[1])
     Psh = torch.randn(Bsh, A.shape[1], device=A.device, dtype=torch.float32)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t_sh = {}
-    for mf in (1, 0):
-        g.hvp(Ash, Psh, A16=A16sh, batch_mfma=mf)
-        torch.cuda.synchronize()
-        ev0.record()
-        for _ in range(3):
-            g.hvp(Ash, Psh, A16=A16sh, batch_mfma=mf)
-        ev1.record()
-        torch.cuda.synchronize()
-        t_sh[mf] = ev0.elapsed_time(ev1) / 3 / 1e3
-    a_bytes = m * A.shape[1] * 2
-    out["shared_matrix_hvp_32"] = {
-        "matrix_cores_ms": round(1e3 * t_sh[1], 3), "per_problem_fused_ms": round(1e3 * t_sh[0], 3),
-        "speedup": round(t_sh[0] / t_sh[1], 2),
-        "matrix_cores_GBps": round((2 * a_bytes + Bsh * A.shape[1] * 8) / t_sh[1] / 1e9, 1),
-        "per_problem_equivalent_GBps": round(Bsh * a_bytes / t_sh[1] / 1e9, 1)}
-    log(f"shared hvp: {out['shared_matrix_hvp_32']}")
+    for name, a16, e_a in (("bf16", A16sh, 2), ("fp32", None, 4)):
+        t_sh = {}
+        for mf in (1, 0):
+            g.hvp(Ash, Psh, A16=a16, batch_mfma=mf)
+            torch.cuda.synchronize()
+            ev0.record()
+            for _ in range(3):
+                g.hvp(Ash, Psh, A16=a16, batch_mfma=mf)
+            ev1.record()
+            torch.cuda.synchronize()
+            t_sh[mf] = ev0.elapsed_time(ev1) / 3 / 1e3
+        a_bytes = m * A.shape[1] * e_a
+        out[f"shared_matrix_hvp_32_{name}"] = {
+            "matrix_cores_ms": round(1e3 * t_sh[1], 3),
+            "per_problem_fused_ms": round(1e3 * t_sh[0], 3), "speedup": round(t_sh[0] / t_sh[1], 2),
+            "matrix_cores_GBps": round((2 * a_bytes + Bsh * A.shape[1] * 8) / t_sh[1] / 1e9, 1),
+            "matrix_cores_TFLOPs": round(4 * m * A.shape[1] * Bsh / t_sh[1] / 1e12, 1),
+            "per_problem_equivalent_GBps": round(Bsh * a_bytes / t_sh[1] / 1e9, 1)}
+        log(f"shared hvp {name}: {out[f'shared_matrix_hvp_32_{name}']}")
     lams = [float(lam) * 2.0 ** ((j - 16) / 8.0) for j in range(Bsh)]
     bsh = b.expand(Bsh, m).contiguous()
     for mf in (1, 0):

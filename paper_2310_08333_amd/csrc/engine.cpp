@@ -194,14 +194,16 @@ int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_)
   const bool shared = A->stride_A == 0 && batch >= 2 && batch <= 128;
   const bool sq_op = op == GENIOS_OP_LASSO || op == GENIOS_OP_BOXLS || op == GENIOS_OP_HVP;
   const int64_t min_batch = o->batch_mfma == 2 ? 2 : 5;
-  if (o->batch_mfma != 0 && shared && batch >= min_batch && sq_op && uses_lo && vt == VT_F32 &&
+  if (o->batch_mfma != 0 && shared && batch >= min_batch && sq_op && vt == VT_F32 &&
       n % 8 == 0 && A->lda % 8 == 0) {
     mr.sp = mrhs_pad((int)batch);
-    const int64_t rb = (m + 127) / 128, cb = (n + 127) / 128;
+    const int64_t rb = (m + 127) / 128, cb = (n + 127) / 128, cbf = (n + 255) / 256;
     mr.ksW = (int)std::max<int64_t>(1, std::min<int64_t>((1024 + rb - 1) / rb, std::max<int64_t>(1, n / 256)));
     int64_t ky = std::max<int64_t>(1, std::min<int64_t>((1024 + cb - 1) / cb, std::max<int64_t>(1, m / 256)));
     ky = std::min<int64_t>(ky, batch * yslots / mr.sp);  // ypart holds ksY x sp columns
     mr.ksY = (int)std::max<int64_t>(1, ky);
+    ky = std::max<int64_t>(1, std::min<int64_t>((1024 + cbf - 1) / cbf, std::max<int64_t>(1, m / 256)));
+    mr.ksYf = (int)std::max<int64_t>(1, std::min<int64_t>(ky, batch * yslots / mr.sp));
     if (batch * yslots < mr.sp) mr.sp = 0;  // cannot happen: yslots >= 512 / batch
   }
   Arena ar{nullptr, 0, 0, true};
@@ -444,7 +446,7 @@ struct Ctx {
       HC(launch_mrhs_hvp(op, (int)B, static_cast<const float*>(p), n, L.mr,
                          static_cast<float*>(L.ypart), L.npad, gate, gstride, st));
       HC(prof.end(st));
-      cur_ks = L.mr.ksY;
+      cur_ks = op.mt == MT_F32 ? L.mr.ksYf : L.mr.ksY;
       cur_ks_stride = (int64_t)L.mr.sp * L.npad;
       cur_prob_stride = L.npad;
       n_mrhs += 1;

@@ -355,10 +355,12 @@ hipError_t launch_sketch_mfma(const MatArg& A, int64_t batch, int sp, const floa
 int sketch_pad(int s);
 // ---- H p of a batch sharing A on the matrix cores (sketch_mfma.hip) ----
 struct MrhsWs {
-  uint16_t* p16 = nullptr;  // BF16 hi then lo parts of the p block [c][kpad(n)]
-  uint16_t* w16 = nullptr;  // BF16 hi then lo parts of T = A P [c][kpad(m)]
+  uint16_t* p16 = nullptr;  // BF16 hi then lo parts of the p block [c][kpad(n)] (FP32
+                            // operand: the p block in FP32, same bytes)
+  uint16_t* w16 = nullptr;  // BF16 hi then lo parts of T = A P [c][kpad(m)] (FP32: T)
   float* wpart = nullptr;   // ksW x SP x m partials of T
-  int sp = 0, ksW = 1, ksY = 1;
+  int sp = 0, ksW = 1, ksY = 1;  // ksY: row splits of A^T T with the BF16 operand
+  int ksYf = 1;                  // ... and with the FP32 operand (256 columns per block)
 };
 int mrhs_pad(int B);
 bool mrhs_eligible(const MatArg& A, VType vt, int64_t B, const MrhsWs& ws);

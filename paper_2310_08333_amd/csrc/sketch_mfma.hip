@@ -419,6 +419,286 @@ __global__ __launch_bounds__(256) void k_cols_split(int64_t n, int B, int sp,
   }
 }
 
+// ---- the same products with the FP32 operand (v_mfma_f32_16x16x4_f32) ----------
+// A lane's 16-byte fragment of A holds 4 consecutive k; instruction i of a 16-wide
+// K step takes component i, so lane group g = l / 16 covers k = 4 g + i and the
+// other operand is read with the same k order.  P and T stay FP32: the products are
+// FP32 products with FP32 accumulation, in another summation order than the fused
+// kernel's.
+constexpr int kFK = 16;       // K step (4 instructions)
+constexpr int kFPitch = 20;   // LDS row pitch in floats (16 + 4: 80 bytes)
+constexpr int kFYCols = 256;  // columns of A per block in A^T T (64 per wavefront)
+
+__device__ __forceinline__ floatx4 mfma_f32(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float comp(const float4& v, int i) {
+  return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+
+// P (n x B FP32, column c at P + c pstride) -> [c][kpad] FP32, zero past n and for the
+// padding columns c >= B.
+__global__ __launch_bounds__(256) void k_cols_f32(int64_t n, int B, int sp,
+                                                  const float* __restrict__ P, int64_t pstride,
+                                                  int64_t kpad, float* __restrict__ out,
+                                                  const int32_t* __restrict__ gate, int gstride,
+                                                  int gcount) {
+  if (!any_flag(gate, gstride, gcount)) return;
+  const int64_t total = (int64_t)sp * kpad;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / kpad);
+    const int64_t k = e - (int64_t)c * kpad;
+    out[e] = (c < B && k < n) ? P[(int64_t)c * pstride + k] : 0.f;
+  }
+}
+
+// Tpart[ks][c][r] = sum_{k in split ks} A[r][k] P[c][k]: a block owns 128 rows (a
+// wavefront 32: two row tiles) and all SP columns for a K range; the P tile of each
+// step is staged in LDS (double-buffered) and shared by the four wavefronts.
+template <int SP>
+__global__ __launch_bounds__(256) void k_mrhs_w_f32(const float* __restrict__ A, int64_t lda,
+                                                    int m, int n, const float* __restrict__ pc,
+                                                    int64_t kpad, float* __restrict__ tpart,
+                                                    int kchunk, int64_t ks_stride,
+                                                    const int32_t* __restrict__ gate, int gstride,
+                                                    int gcount) {
+  constexpr int NT = SP / 16;
+  __shared__ __align__(16) float os[2][SP * kFPitch];
+  if (!any_flag(gate, gstride, gcount)) return;
+  const int ks = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int row0 = blockIdx.x * kWRows + wave * 32;
+  const int k0 = ks * kchunk;
+  const int k1 = min(n, k0 + kchunk);
+  const float* arow[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) arow[t] = A + (int64_t)min(row0 + 16 * t + (lane & 15), m - 1) * lda;
+  const int kl = 4 * (lane >> 4);
+  floatx4 acc[2][NT];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // P tile: SP columns x 16 k = SP * 4 chunks of 16 bytes (loads unconditional, chunk
+  // indices past the tile re-read chunk 0; only the LDS stores are guarded)
+  constexpr int OCH = SP * 4;
+  constexpr int OQ = (OCH + 255) / 256;
+  auto load_p = [&](int kk, float4 (&reg)[OQ]) {
+#pragma unroll
+    for (int q = 0; q < OQ; ++q) {
+      const int ch = tid + 256 * q < OCH ? tid + 256 * q : 0;
+      reg[q] = *reinterpret_cast<const float4*>(pc + (int64_t)(ch >> 2) * kpad + kk + 4 * (ch & 3));
+    }
+  };
+  auto store_p = [&](int buf, const float4 (&reg)[OQ]) {
+#pragma unroll
+    for (int q = 0; q < OQ; ++q) {
+      const int ch = tid + 256 * q;
+      if (ch < OCH) *reinterpret_cast<float4*>(&os[buf][(ch >> 2) * kFPitch + 4 * (ch & 3)]) = reg[q];
+    }
+  };
+  // columns past n read column 0 (their P rows are 0); n % 4 == 0 keeps a fragment whole
+  auto load_a = [&](int kk, float4 (&fa)[2]) {
+    const int k = kk + kl;
+    const int kc = k < n ? k : 0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) fa[t] = *reinterpret_cast<const float4*>(arow[t] + kc);
+  };
+  float4 preg[OQ];
+  float4 fa[2], fn[2];
+  if (k0 < k1) {
+    load_p(k0, preg);
+    store_p(0, preg);
+    load_a(k0, fa);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int kk = k0; kk < k1; kk += kFK) {
+    const bool more = kk + kFK < k1;
+    const int kn = more ? kk + kFK : kk;
+    load_p(kn, preg);
+    load_a(kn, fn);
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+      const float4 fb = *reinterpret_cast<const float4*>(&os[buf][(16 * c + (lane & 15)) * kFPitch + kl]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[t][c] = mfma_f32(comp(fa[t], i), comp(fb, i), acc[t][c]);
+    }
+    if (more) store_p(buf ^ 1, preg);
+    __syncthreads();
+    buf ^= 1;
+    fa[0] = fn[0];
+    fa[1] = fn[1];
+  }
+  float* Tb = tpart + (int64_t)ks * ks_stride;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = row0 + 16 * t + 4 * (lane >> 4) + i;
+        if (r < m) Tb[(int64_t)(16 * c + (lane & 15)) * m + r] = acc[t][c][i];
+      }
+}
+
+// sum_ks Tpart -> T [c][kpad] FP32, zero past m.
+__global__ __launch_bounds__(256) void k_t_sum_f32(int64_t m, int sp, int ksW,
+                                                   const float* __restrict__ tpart,
+                                                   int64_t ks_stride, int64_t kpad,
+                                                   float* __restrict__ T,
+                                                   const int32_t* __restrict__ gate, int gstride,
+                                                   int gcount) {
+  if (!any_flag(gate, gstride, gcount)) return;
+  const int64_t total = (int64_t)sp * kpad;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / kpad);
+    const int64_t r = e - (int64_t)c * kpad;
+    float w = 0.f;
+    if (r < m)
+      for (int k = 0; k < ksW; ++k) w += tpart[(int64_t)k * ks_stride + (int64_t)c * m + r];
+    T[e] = w;
+  }
+}
+
+// Ypart[ks][c][j] = sum_{r in split ks} T[c][r] A[r][j], formed as (T^T A)^T so that
+// A's rows feed the second operand unchanged: lane group g loads rows 4 g + s
+// (s = 0..3) of a 16-row step, 4 consecutive columns per lane, and instruction
+// (s, q) pairs component s of the T fragment with component q of row s's A
+// fragment; result column l % 16 of sub-tile q is j = 4 (l % 16) + q.  The T tile
+// of each step is staged in LDS (double-buffered); the next step's A fragments are
+// loaded before this step's instructions.
+template <int SP>
+__global__ __launch_bounds__(256) void k_mrhs_y_f32(const float* __restrict__ A, int64_t lda,
+                                                    int m, int n, const float* __restrict__ T,
+                                                    int64_t kpad, float* __restrict__ ypart,
+                                                    int rchunk, int64_t ks_stride, int64_t ldy,
+                                                    const int32_t* __restrict__ gate, int gstride,
+                                                    int gcount) {
+  constexpr int NT = SP / 16;
+  __shared__ __align__(16) float ts[2][SP * kFPitch];
+  if (!any_flag(gate, gstride, gcount)) return;
+  const int ks = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int jl = blockIdx.x * kFYCols + 64 * wave + 4 * (lane & 15);  // this lane's 4 columns
+  const int jc = jl < n ? jl : 0;  // columns past n read column 0 (not stored)
+  const int r0 = ks * rchunk;
+  const int r1 = min(m, r0 + rchunk);
+  const int g4 = 4 * (lane >> 4);
+  floatx4 acc[NT][4];
+#pragma unroll
+  for (int c = 0; c < NT; ++c)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[c][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+  constexpr int OCH = SP * 4;
+  constexpr int OQ = (OCH + 255) / 256;
+  auto load_t = [&](int rr, float4 (&reg)[OQ]) {
+#pragma unroll
+    for (int q = 0; q < OQ; ++q) {
+      const int ch = tid + 256 * q < OCH ? tid + 256 * q : 0;
+      reg[q] = *reinterpret_cast<const float4*>(T + (int64_t)(ch >> 2) * kpad + rr + 4 * (ch & 3));
+    }
+  };
+  auto store_t = [&](int buf, const float4 (&reg)[OQ]) {
+#pragma unroll
+    for (int q = 0; q < OQ; ++q) {
+      const int ch = tid + 256 * q;
+      if (ch < OCH) *reinterpret_cast<float4*>(&ts[buf][(ch >> 2) * kFPitch + 4 * (ch & 3)]) = reg[q];
+    }
+  };
+  // rows past m are clamped (their T entries are 0)
+  auto load_a = [&](int rr, float4 (&fa)[4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      fa[s] = *reinterpret_cast<const float4*>(A + (int64_t)min(rr + g4 + s, m - 1) * lda + jc);
+  };
+  float4 treg[OQ];
+  float4 fa[4], fn[4];
+  if (r0 < r1) {
+    load_t(r0, treg);
+    store_t(0, treg);
+    load_a(r0, fa);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int rr = r0; rr < r1; rr += kFK) {
+    const bool more = rr + kFK < r1;
+    const int rn = more ? rr + kFK : rr;
+    load_t(rn, treg);
+    load_a(rn, fn);
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+      const float4 ft = *reinterpret_cast<const float4*>(&ts[buf][(16 * c + (lane & 15)) * kFPitch + g4]);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[c][q] = mfma_f32(comp(ft, s), comp(fa[s], q), acc[c][q]);
+    }
+    if (more) store_t(buf ^ 1, treg);
+    __syncthreads();
+    buf ^= 1;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) fa[s] = fn[s];
+  }
+  if (jl >= n) return;
+  float* Yb = ypart + (int64_t)ks * ks_stride;
+#pragma unroll
+  for (int c = 0; c < NT; ++c)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int col = 16 * c + g4 + i;
+      *reinterpret_cast<float4*>(Yb + (int64_t)col * ldy + jl) =
+          make_float4(acc[c][0][i], acc[c][1][i], acc[c][2][i], acc[c][3][i]);
+    }
+}
+
+// H p for B problems sharing A (FP32): T = A P, then (T^T A)^T, both on the matrix
+// cores in FP32; P and T [c][kpad] FP32 in the space of the BF16 hi + lo parts.
+template <int SP>
+hipError_t mrhs_f32_sp(const MatArg& A, int B, const float* P, int64_t pstride, const MrhsWs& ws,
+                       float* ypart, int64_t ldy, const int32_t* gate, int gstride,
+                       hipStream_t st) {
+  const int m = (int)A.m, n = (int)A.n;
+  const float* Ap = static_cast<const float*>(A.ptr);
+  const int64_t kpn = (A.n + kMK - 1) / kMK * kMK, kpm = (A.m + kMK - 1) / kMK * kMK;
+  float* pc = reinterpret_cast<float*>(ws.p16);
+  float* tc = reinterpret_cast<float*>(ws.w16);
+  {
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((SP * kpn + 255) / 256, 2048));
+    hipLaunchKernelGGL(k_cols_f32, dim3(nb), dim3(256), 0, st, A.n, B, SP, P, pstride, kpn, pc,
+                       gate, gstride, B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    int kchunk = (int)((A.n + ws.ksW - 1) / ws.ksW);
+    kchunk = (kchunk + kMK - 1) / kMK * kMK;
+    dim3 grid((unsigned)((m + kWRows - 1) / kWRows), (unsigned)ws.ksW, 1u);
+    hipLaunchKernelGGL(k_mrhs_w_f32<SP>, grid, dim3(256), 0, st, Ap, A.lda, m, n, pc, kpn,
+                       ws.wpart, kchunk, (int64_t)m * SP, gate, gstride, B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((SP * kpm + 255) / 256, 2048));
+    hipLaunchKernelGGL(k_t_sum_f32, dim3(nb), dim3(256), 0, st, A.m, SP, ws.ksW, ws.wpart,
+                       (int64_t)m * SP, kpm, tc, gate, gstride, B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  int rchunk = (int)((A.m + ws.ksYf - 1) / ws.ksYf);
+  rchunk = (rchunk + kMK - 1) / kMK * kMK;
+  dim3 grid((unsigned)((n + kFYCols - 1) / kFYCols), (unsigned)ws.ksYf, 1u);
+  hipLaunchKernelGGL(k_mrhs_y_f32<SP>, grid, dim3(256), 0, st, Ap, A.lda, m, n, tc, kpm, ypart,
+                     rchunk, (int64_t)SP * ldy, ldy, gate, gstride, B);
+  return hipGetLastError();
+}
+
 // H p for B problems sharing A (BF16): T = A [p_1 .. p_B] (P in BF16 hi + lo parts, one
 // pass over A), then A^T (T in BF16 hi + lo parts, one pass): two streams of A for
 // all B right-hand sides.  Output: ypart[ks][c][j] with column stride ldy.
@@ -471,14 +751,23 @@ hipError_t mrhs_sp(const MatArg& A, int B, const float* P, int64_t pstride, cons
 int mrhs_pad(int B) { return B <= 16 ? 16 : B <= 32 ? 32 : B <= 64 ? 64 : 128; }
 
 bool mrhs_eligible(const MatArg& A, VType vt, int64_t B, const MrhsWs& ws) {
-  return vt == VT_F32 && A.mt == MT_BF16 && A.strideA == 0 && B >= 2 && B <= 128 &&
-         ws.p16 != nullptr && ws.sp == mrhs_pad((int)B) && A.n % 8 == 0 && A.lda % 8 == 0 &&
-         reinterpret_cast<uintptr_t>(A.ptr) % 16 == 0;
+  return vt == VT_F32 && (A.mt == MT_BF16 || A.mt == MT_F32) && A.strideA == 0 && B >= 2 &&
+         B <= 128 && ws.p16 != nullptr && ws.sp == mrhs_pad((int)B) && A.n % 8 == 0 &&
+         A.lda % 8 == 0 && reinterpret_cast<uintptr_t>(A.ptr) % 16 == 0;
 }
 
 hipError_t launch_mrhs_hvp(const MatArg& A, int B, const float* P, int64_t pstride,
                            const MrhsWs& ws, float* ypart, int64_t ldy, const int32_t* gate,
                            int gstride, hipStream_t st) {
+  if (A.mt == MT_F32) {
+    switch (ws.sp) {
+      case 16: return mrhs_f32_sp<16>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
+      case 32: return mrhs_f32_sp<32>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
+      case 64: return mrhs_f32_sp<64>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
+      case 128: return mrhs_f32_sp<128>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (ws.sp) {
     case 16: return mrhs_sp<16>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
     case 32: return mrhs_sp<32>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);

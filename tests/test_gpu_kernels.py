@@ -354,6 +354,28 @@ def test_stream_read_reads_every_word(g):
     assert g.stream_read_seconds(t, reps=2) > 0
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("B", [8, 20, 100])
+def test_hvp_shared_matrix_batch_fp32_on_the_matrix_cores(g, B):
+    # B problems sharing one FP32 matrix: T = A P and (T^T A)^T on the FP32 matrix
+    # instructions (FP32 products, FP32 accumulation) against FP64 products and the
+    # per-problem fused kernel; 301 x 1208 leaves ragged row, column and K tails
+    print("hvp shared batch fp32", B, flush=True)
+    m, n = 301, 1208
+    rng = np.random.default_rng(100 + B)
+    A = torch.from_numpy(rng.standard_normal((m, n)).astype(np.float32)).to(DEV)
+    P = torch.from_numpy(rng.standard_normal((B, n)).astype(np.float32)).to(DEV)
+    Ab = A.expand(B, m, n)
+    got = g.hvp(Ab, P, batch_mfma=1).cpu().numpy().astype(np.float64)
+    per = g.hvp(Ab, P, batch_mfma=0).cpu().numpy().astype(np.float64)
+    An = A.cpu().numpy().astype(np.float64)
+    Pn = P.cpu().numpy().astype(np.float64)
+    for b in range(B):
+        ref = An.T @ (An @ Pn[b])
+        scale = np.linalg.norm(ref)
+        assert np.linalg.norm(got[b] - ref) <= 1e-5 * scale, (b, np.linalg.norm(got[b] - ref) / scale)
+        assert np.linalg.norm(per[b] - ref) <= 1e-5 * scale
+
 @pytest.mark.parametrize("B", [8, 20])
 def test_hvp_shared_matrix_batch_on_the_matrix_cores(g, B):
     # B problems sharing one BF16 matrix: T = A P and A^T T on the matrix cores (P and T

@@ -844,18 +844,19 @@ def _shared_batch(B, m=240, n=1000, seed=50):
     return A, np.stack(bs), lams
 
 
-def test_lasso_shared_matrix_batch_matches_oracle(g):
-    print("lasso shared batch", flush=True)
+@pytest.mark.parametrize("precision", ["bf16_refine", "f32"])
+def test_lasso_shared_matrix_batch_matches_oracle(g, precision):
+    print("lasso shared batch", precision, flush=True)
     B = 8
     A, bs, lams = _shared_batch(B)
     m, n = A.shape
     At = _t(A).expand(B, m, n)
     # (one of these problems needs ~5100 iterations for 1e-6, with either product)
-    out = g.lasso_solve(At, _t(bs), lams, precision="bf16_refine", eps=1e-6, sketch_rank=16,
+    out = g.lasso_solve(At, _t(bs), lams, precision=precision, eps=1e-6, sketch_rank=16,
                         profile_kernels=1, max_iter=20000)
     assert out["status"] == 0, [i["status"] for i in out["info"]]
     assert out["info"][0]["n_hvp_mrhs"] > 0
-    ref = g.lasso_solve(At, _t(bs), lams, precision="bf16_refine", eps=1e-6, sketch_rank=16,
+    ref = g.lasso_solve(At, _t(bs), lams, precision=precision, eps=1e-6, sketch_rank=16,
                         batch_mfma=0, max_iter=20000)
     assert ref["info"][0]["n_hvp_mrhs"] == 0
     Z = out["z"].cpu().numpy().astype(np.float64)
@@ -864,9 +865,10 @@ def test_lasso_shared_matrix_batch_matches_oracle(g):
         sol = olasso.solve(A, bs[j], lams[j])
         F = olasso.objective(A, bs[j], lams[j], Z[j])
         Fr = olasso.objective(A, bs[j], lams[j], Zr[j])
-        # both products stop at the same point: the r_kkt test at 1e-6 leaves F within
-        # 3e-4 of F* on these small-scale problems (F* ~ 1e-2), the paths within 1e-7
-        assert abs(F - Fr) <= 1e-7 * sol["F"], (j, F, Fr)
+        # both products stop at nearly the same point: the r_kkt test at 1e-6 leaves F
+        # within 3e-4 of F* on these small-scale problems (F* ~ 1e-2); the two FP32
+        # summation orders move the iterates by rounding only (2e-7 of F* measured)
+        assert abs(F - Fr) <= 1e-6 * sol["F"], (j, F, Fr)
         assert 0.0 <= (F - sol["F"]) / sol["F"] <= 5e-4, (j, F, sol["F"])
         assert out["info"][j]["iters"] == pytest.approx(ref["info"][j]["iters"], abs=3)
 
