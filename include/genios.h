@@ -170,10 +170,10 @@ typedef struct {
   int32_t sketch_rank_init;    /* first size of the doubling rule, default 8, >= 1 */
   double sketch_kappa;         /* target of the condition-number bound, default 10, > 1 */
   int32_t power_iters;         /* power-method steps per size, default 10, >= 1 */
-  int32_t batch_mfma;          /* a batch sharing one matrix (stride_A = 0) with the squared loss
-                                  (Lasso, elastic net, box) forms the H p of all problems at
-                                  once on the matrix cores: T = A [p_1 .. p_B], then A^T T, two
-                                  streams of A instead of B.  BF16 operand: p and T carried as
+  int32_t batch_mfma;          /* a batch sharing one matrix (stride_A = 0) forms the H p of
+                                  all problems at once on the matrix cores: T = A [p_1 .. p_B],
+                                  each column weighted by its problem's curvature D (logistic,
+                                  Huber), then A^T T: two streams of A instead of B.  BF16 operand: p and T carried as
                                   BF16 hi + lo parts (~16 bits); FP32 operand: FP32 products
                                   and accumulation throughout.  0 = off, 1 (default) = for
                                   batches of 5 to 128 problems, 2 = for 2 to 128 */

@@ -189,10 +189,10 @@ int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_)
   // is singular and the call fails), up to n with it
   ldS_max = backward ? (int)(((o->lambda2 > 0.0 ? n : std::min(m, n)) + 7) / 8 * 8) : 0;
   if (s > 0) sketch_ws_bytes(m, n, s, batch, vt, &sk.ksW, &sk.ksY, &sk.nbG);
-  // H p of a batch sharing A on the matrix cores (squared loss, BF16 operand)
+  // H p of a batch sharing A on the matrix cores (every loss; BF16 or FP32 operand)
   mr = MrhsWs{};
   const bool shared = A->stride_A == 0 && batch >= 2 && batch <= 128;
-  const bool sq_op = op == GENIOS_OP_LASSO || op == GENIOS_OP_BOXLS || op == GENIOS_OP_HVP;
+  const bool sq_op = op == GENIOS_OP_LASSO || op == GENIOS_OP_BOXLS || op == GENIOS_OP_HVP || ml;
   const int64_t min_batch = o->batch_mfma == 2 ? 2 : 5;
   if (o->batch_mfma != 0 && shared && batch >= min_batch && sq_op && vt == VT_F32 &&
       n % 8 == 0 && A->lda % 8 == 0) {
@@ -441,9 +441,10 @@ struct Ctx {
   }
   int hvp(const MatArg& op, const void* p, const void* d, const int32_t* gate, int gstride) {
     // a batch sharing A: both passes over A serve every problem (matrix cores)
-    if (d == nullptr && L.mr.sp > 0 && mrhs_eligible(op, vt, B, L.mr)) {
+    if (L.mr.sp > 0 && mrhs_eligible(op, vt, B, L.mr)) {
       HC(prof.begin(st, 6));
-      HC(launch_mrhs_hvp(op, (int)B, static_cast<const float*>(p), n, L.mr,
+      HC(launch_mrhs_hvp(op, (int)B, static_cast<const float*>(p), n,
+                         static_cast<const float*>(d), m, L.mr,
                          static_cast<float*>(L.ypart), L.npad, gate, gstride, st));
       HC(prof.end(st));
       cur_ks = op.mt == MT_F32 ? L.mr.ksYf : L.mr.ksY;

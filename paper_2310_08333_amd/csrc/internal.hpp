@@ -366,9 +366,10 @@ int mrhs_pad(int B);
 bool mrhs_eligible(const MatArg& A, VType vt, int64_t B, const MrhsWs& ws);
 // ypart[ks][c][j] (column stride ldy, split stride sp ldy) for ks < ws.ksY; every kernel
 // exits at once when no problem's flag (gate, gstride) is set.
+// With d, problem c's product is A^T diag(d + c d_stride) A p_c.
 hipError_t launch_mrhs_hvp(const MatArg& A, int B, const float* P, int64_t pstride,
-                           const MrhsWs& ws, float* ypart, int64_t ldy, const int32_t* gate,
-                           int gstride, hipStream_t st);
+                           const float* d, int64_t d_stride, const MrhsWs& ws, float* ypart,
+                           int64_t ldy, const int32_t* gate, int gstride, hipStream_t st);
 size_t sketch_ws_bytes(int64_t m, int64_t n, int s, int64_t batch, VType vt, int* ksW, int* ksY,
                        int* nbG);
 // Y = H Omega (H = A^T diag(d) A) then the stabilised s x s core and U.

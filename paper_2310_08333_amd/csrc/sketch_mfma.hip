@@ -208,11 +208,13 @@ __global__ __launch_bounds__(256) void k_sketch_w_mfma(const uint16_t* __restric
       }
 }
 
-// (d o sum_ks Wpart) -> BF16 hi and lo parts [c][kpad], zero past m.
+// (d o sum_ks Wpart) -> BF16 hi and lo parts [c][kpad], zero past m.  Column c < dcols
+// is weighted by d + c d_cstride (d_cstride = 0: one d for every column).
 __global__ __launch_bounds__(256) void k_w_split(int64_t m, int sp, int ksW,
                                                  const float* __restrict__ wpart,
                                                  int64_t ks_stride, int64_t prob_stride,
                                                  const float* __restrict__ d, int64_t d_stride,
+                                                 int64_t d_cstride, int dcols,
                                                  int64_t kpad, uint16_t* __restrict__ hi,
                                                  uint16_t* __restrict__ lo,
                                                  const int32_t* __restrict__ gate, int gstride,
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(256) void k_w_split(int64_t m, int sp, int ksW,
     if (r < m) {
       float w = 0.f;
       for (int k = 0; k < ksW; ++k) w += Wp[(int64_t)k * ks_stride + (int64_t)c * m + r];
-      if (db) w *= db[r];
+      if (db && c < dcols) w *= db[(int64_t)c * d_cstride + r];
       h = f32_to_bf16_rne(w);
       l = f32_to_bf16_rne(w - __uint_as_float((uint32_t)h << 16));
     }
@@ -381,7 +383,7 @@ hipError_t sketch_mfma_sp(const MatArg& A, int64_t batch, const float* d, int64_
     const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((SP * kpm + 255) / 256, 2048));
     hipLaunchKernelGGL(k_w_split, dim3(nb, (unsigned)batch), dim3(256), 0, st, A.m, SP, ws.ksW,
                        static_cast<const float*>(ws.Wpart), (int64_t)m * SP,
-                       (int64_t)ws.ksW * m * SP, d, d_stride, kpm, ws.w16,
+                       (int64_t)ws.ksW * m * SP, d, d_stride, (int64_t)0, SP, kpm, ws.w16,
                        ws.w16 + (size_t)batch * SP * kpm, (const int32_t*)nullptr, 0, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -546,10 +548,12 @@ __global__ __launch_bounds__(256) void k_mrhs_w_f32(const float* __restrict__ A,
       }
 }
 
-// sum_ks Tpart -> T [c][kpad] FP32, zero past m.
+// d_c o sum_ks Tpart -> T [c][kpad] FP32, zero past m (column c < B weighted by
+// d + c d_stride when d is given).
 __global__ __launch_bounds__(256) void k_t_sum_f32(int64_t m, int sp, int ksW,
                                                    const float* __restrict__ tpart,
-                                                   int64_t ks_stride, int64_t kpad,
+                                                   int64_t ks_stride, const float* __restrict__ d,
+                                                   int64_t d_stride, int B, int64_t kpad,
                                                    float* __restrict__ T,
                                                    const int32_t* __restrict__ gate, int gstride,
                                                    int gcount) {
@@ -560,8 +564,10 @@ __global__ __launch_bounds__(256) void k_t_sum_f32(int64_t m, int sp, int ksW,
     const int c = (int)(e / kpad);
     const int64_t r = e - (int64_t)c * kpad;
     float w = 0.f;
-    if (r < m)
+    if (r < m) {
       for (int k = 0; k < ksW; ++k) w += tpart[(int64_t)k * ks_stride + (int64_t)c * m + r];
+      if (d && c < B) w *= d[(int64_t)c * d_stride + r];
+    }
     T[e] = w;
   }
 }
@@ -660,9 +666,9 @@ __global__ __launch_bounds__(256) void k_mrhs_y_f32(const float* __restrict__ A,
 // H p for B problems sharing A (FP32): T = A P, then (T^T A)^T, both on the matrix
 // cores in FP32; P and T [c][kpad] FP32 in the space of the BF16 hi + lo parts.
 template <int SP>
-hipError_t mrhs_f32_sp(const MatArg& A, int B, const float* P, int64_t pstride, const MrhsWs& ws,
-                       float* ypart, int64_t ldy, const int32_t* gate, int gstride,
-                       hipStream_t st) {
+hipError_t mrhs_f32_sp(const MatArg& A, int B, const float* P, int64_t pstride, const float* d,
+                       int64_t d_stride, const MrhsWs& ws, float* ypart, int64_t ldy,
+                       const int32_t* gate, int gstride, hipStream_t st) {
   const int m = (int)A.m, n = (int)A.n;
   const float* Ap = static_cast<const float*>(A.ptr);
   const int64_t kpn = (A.n + kMK - 1) / kMK * kMK, kpm = (A.m + kMK - 1) / kMK * kMK;
@@ -687,7 +693,7 @@ hipError_t mrhs_f32_sp(const MatArg& A, int B, const float* P, int64_t pstride, 
   {
     const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((SP * kpm + 255) / 256, 2048));
     hipLaunchKernelGGL(k_t_sum_f32, dim3(nb), dim3(256), 0, st, A.m, SP, ws.ksW, ws.wpart,
-                       (int64_t)m * SP, kpm, tc, gate, gstride, B);
+                       (int64_t)m * SP, d, d_stride, B, kpm, tc, gate, gstride, B);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -699,12 +705,14 @@ hipError_t mrhs_f32_sp(const MatArg& A, int B, const float* P, int64_t pstride, 
   return hipGetLastError();
 }
 
-// H p for B problems sharing A (BF16): T = A [p_1 .. p_B] (P in BF16 hi + lo parts, one
+// H p for B problems sharing A (BF16), H = A^T diag(d_c) A for problem c when d is given
+// (d_c at d + c d_stride): T = A [p_1 .. p_B] (P in BF16 hi + lo parts, one
 // pass over A), then A^T (T in BF16 hi + lo parts, one pass): two streams of A for
 // all B right-hand sides.  Output: ypart[ks][c][j] with column stride ldy.
 template <int SP>
-hipError_t mrhs_sp(const MatArg& A, int B, const float* P, int64_t pstride, const MrhsWs& ws,
-                   float* ypart, int64_t ldy, const int32_t* gate, int gstride, hipStream_t st) {
+hipError_t mrhs_sp(const MatArg& A, int B, const float* P, int64_t pstride, const float* d,
+                   int64_t d_stride, const MrhsWs& ws, float* ypart, int64_t ldy,
+                   const int32_t* gate, int gstride, hipStream_t st) {
   const int m = (int)A.m, n = (int)A.n;
   const uint16_t* Ap = static_cast<const uint16_t*>(A.ptr);
   const int64_t kpn = (A.n + kMK - 1) / kMK * kMK, kpm = (A.m + kMK - 1) / kMK * kMK;
@@ -732,8 +740,8 @@ hipError_t mrhs_sp(const MatArg& A, int B, const float* P, int64_t pstride, cons
   {
     const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((SP * kpm + 255) / 256, 2048));
     hipLaunchKernelGGL(k_w_split, dim3(nb, 1u), dim3(256), 0, st, A.m, SP, ws.ksW, ws.wpart,
-                       (int64_t)m * SP, (int64_t)ws.ksW * m * SP, (const float*)nullptr,
-                       (int64_t)0, kpm, th, tl, gate, gstride, B);
+                       (int64_t)m * SP, (int64_t)ws.ksW * m * SP, d, (int64_t)0, d_stride,
+                       B, kpm, th, tl, gate, gstride, B);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -757,22 +765,22 @@ bool mrhs_eligible(const MatArg& A, VType vt, int64_t B, const MrhsWs& ws) {
 }
 
 hipError_t launch_mrhs_hvp(const MatArg& A, int B, const float* P, int64_t pstride,
-                           const MrhsWs& ws, float* ypart, int64_t ldy, const int32_t* gate,
-                           int gstride, hipStream_t st) {
+                           const float* d, int64_t d_stride, const MrhsWs& ws, float* ypart,
+                           int64_t ldy, const int32_t* gate, int gstride, hipStream_t st) {
   if (A.mt == MT_F32) {
     switch (ws.sp) {
-      case 16: return mrhs_f32_sp<16>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
-      case 32: return mrhs_f32_sp<32>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
-      case 64: return mrhs_f32_sp<64>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
-      case 128: return mrhs_f32_sp<128>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
+      case 16: return mrhs_f32_sp<16>(A, B, P, pstride, d, d_stride, ws, ypart, ldy, gate, gstride, st);
+      case 32: return mrhs_f32_sp<32>(A, B, P, pstride, d, d_stride, ws, ypart, ldy, gate, gstride, st);
+      case 64: return mrhs_f32_sp<64>(A, B, P, pstride, d, d_stride, ws, ypart, ldy, gate, gstride, st);
+      case 128: return mrhs_f32_sp<128>(A, B, P, pstride, d, d_stride, ws, ypart, ldy, gate, gstride, st);
       default: return hipErrorInvalidValue;
     }
   }
   switch (ws.sp) {
-    case 16: return mrhs_sp<16>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
-    case 32: return mrhs_sp<32>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
-    case 64: return mrhs_sp<64>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
-    case 128: return mrhs_sp<128>(A, B, P, pstride, ws, ypart, ldy, gate, gstride, st);
+    case 16: return mrhs_sp<16>(A, B, P, pstride, d, d_stride, ws, ypart, ldy, gate, gstride, st);
+    case 32: return mrhs_sp<32>(A, B, P, pstride, d, d_stride, ws, ypart, ldy, gate, gstride, st);
+    case 64: return mrhs_sp<64>(A, B, P, pstride, d, d_stride, ws, ypart, ldy, gate, gstride, st);
+    case 128: return mrhs_sp<128>(A, B, P, pstride, d, d_stride, ws, ypart, ldy, gate, gstride, st);
     default: return hipErrorInvalidValue;
   }
 }

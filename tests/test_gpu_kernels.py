@@ -355,6 +355,31 @@ def test_stream_read_reads_every_word(g):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("dt", ["bf16", "f32"])
+def test_hvp_shared_matrix_batch_weighted(g, dt):
+    # the logistic/Huber form: H_c = A^T diag(d_c) A with one d per problem on one matrix
+    print("hvp shared batch weighted", dt, flush=True)
+    B, m, n = 12, 277, 1096
+    rng = np.random.default_rng(77)
+    A = torch.from_numpy(rng.standard_normal((m, n)).astype(np.float32)).to(DEV)
+    A16 = g.cast_bf16(A) if dt == "bf16" else None
+    P = torch.from_numpy(rng.standard_normal((B, n)).astype(np.float32)).to(DEV)
+    D = torch.from_numpy(rng.uniform(0.0, 0.25, (B, m)).astype(np.float32)).to(DEV)
+    Ab = A.expand(B, m, n)
+    A16b = A16.expand(B, m, n) if A16 is not None else None
+    got = g.hvp(Ab, P, d=D, A16=A16b, batch_mfma=1).cpu().numpy().astype(np.float64)
+    per = g.hvp(Ab, P, d=D, A16=A16b, batch_mfma=0).cpu().numpy().astype(np.float64)
+    An = (A16 if A16 is not None else A).float().cpu().numpy().astype(np.float64)
+    Pn, Dn = P.cpu().numpy().astype(np.float64), D.cpu().numpy().astype(np.float64)
+    tol = 1e-4 if dt == "bf16" else 1e-5
+    for b in range(B):
+        ref = An.T @ (Dn[b] * (An @ Pn[b]))
+        scale = np.linalg.norm(ref)
+        assert np.linalg.norm(got[b] - ref) <= tol * scale, (b, np.linalg.norm(got[b] - ref) / scale)
+        assert np.linalg.norm(per[b] - ref) <= 1e-5 * scale
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("B", [8, 20, 100])
 def test_hvp_shared_matrix_batch_fp32_on_the_matrix_cores(g, B):
     # B problems sharing one FP32 matrix: T = A P and (T^T A)^T on the FP32 matrix

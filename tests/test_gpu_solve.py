@@ -873,6 +873,37 @@ def test_lasso_shared_matrix_batch_matches_oracle(g, precision):
         assert out["info"][j]["iters"] == pytest.approx(ref["info"][j]["iters"], abs=3)
 
 
+@pytest.mark.parametrize("precision", ["bf16_refine", "f32"])
+def test_logreg_shared_matrix_path(g, logsmall, precision):
+    # a regularisation path of l1-logistic problems on one matrix: every problem's
+    # A^T D_c A p_c from the shared products, against the per-problem products, each
+    # point certified by the oracle's duality gap (its own solves take minutes here) and
+    # the middle one against the oracle's solution
+    print("logreg shared path", precision, flush=True)
+    P = logsmall
+    lams = [P["lam"] * f for f in (0.5, 0.7, 1.0, 1.4, 2.0, 2.8)]
+    B = len(lams)
+    m, n = P["A"].shape
+    At = _t(P["A"]).expand(B, m, n)
+    Y = _t(np.tile(P["y"], (B, 1)))
+    kw = dict(precision=precision, eps=1e-5, sketch_rank=P["s"], resketch_every=20)
+    out = g.logreg_solve(At, Y, lams, profile_kernels=1, **kw)
+    assert out["status"] == 0, [i["status"] for i in out["info"]]
+    assert out["info"][0]["n_hvp_mrhs"] > 0
+    ref = g.logreg_solve(At, Y, lams, batch_mfma=0, **kw)
+    assert ref["info"][0]["n_hvp_mrhs"] == 0
+    Z = out["z"].cpu().numpy().astype(np.float64)
+    Zr = ref["z"].cpu().numpy().astype(np.float64)
+    for j, lam in enumerate(lams):
+        F = ologreg.objective(P["A"], P["y"], lam, Z[j])
+        Fr = ologreg.objective(P["A"], P["y"], lam, Zr[j])
+        gap, _, _ = ologreg.duality_gap(P["A"], P["y"], lam, Z[j])
+        assert gap <= 1e-4 * F, (j, gap, F)
+        assert _rel(F, Fr) <= 1e-6, (j, F, Fr)
+        if lam == P["lam"]:
+            assert _rel(F, P["sol"]["F"]) <= 1e-6, (F, P["sol"]["F"])
+
+
 def test_boxls_shared_matrix_batch(g):
     print("boxls shared batch", flush=True)
     B = 6
