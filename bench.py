@@ -170,7 +170,8 @@ def next_rows(g, torch, A, b, lam, s):
     N = 8000, no preconditioner) under its own stopping rule, dist(0, dF(z)) <= 1e-4,
     bounded least squares at the size of its ablation (N = 32000, n = 16000,
     eps 1e-5) with and without the preconditioner and inexact solves, the
-    l1-logistic workload (20000 x 5000, 300 iterations), the batch of 64 Lasso
+    l1-logistic workload (20000 x 5000, 300 iterations; a 16-value lambda path of it on
+    its one matrix, 100 iterations each), the batch of 64 Lasso
     problems with their adjoints, and 32 problems sharing the headline matrix (their
     H p on the matrix cores, and a lambda path)."""
     import genios_data
@@ -269,7 +270,25 @@ def next_rows(g, torch, A, b, lam, s):
         "precond_s": round(lo["t_precond"], 4), "r_kkt": lo["r_kkt"],
         "hvp_GBps": gbs, "hvp_frac_of_peak": frac}
     log(f"logreg: {out['logreg_20000x5000']}")
-    del Al, yl
+    # a 16-value lambda path of that workload on its one matrix, 100 iterations each
+    Bl = 16
+    Alb = Al.expand(Bl, *Al.shape)
+    ylb = yl.expand(Bl, yl.shape[0]).contiguous()
+    lams_l = [float(Lg["lam"]) * 2.0 ** ((j - 8) / 4.0) for j in range(Bl)]
+    for mf in (1, 0):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ol = g.logreg_solve(Alb, ylb, lams_l, precision="bf16_refine", eps=1e-4,
+                            sketch_rank=Lg["s"], resketch_every=20, max_iter=100,
+                            batch_mfma=mf, profile_kernels=1)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out[f"logreg_path_16_batch_mfma{mf}"] = {
+            "solve_s": round(t2 - t1, 4), "admm_iters_total": int(sum(i["iters"] for i in ol["info"])),
+            "cg_iters_max": int(max(i["cg_iters"] for i in ol["info"])),
+            "hvp_launches_matrix_cores": ol["info"][0]["n_hvp_mrhs"]}
+        log(f"logreg path 16 batch_mfma={mf}: {out[f'logreg_path_16_batch_mfma{mf}']}")
+    del Al, yl, Alb, ylb
     # the batch of 64 Lasso problems (2000 x 8000 each) and their adjoints
     t0 = time.time()
     Pb = genios_data.config("lasso_batch_64x2000x8000")
