@@ -26,6 +26,12 @@ the traffic.
 runs only a few Nystrom builds of the workload's BF16 operator (the sketch
 products on the matrix cores), for counter passes over those kernels.
 
+    python bench.py --probe-shared
+
+runs only a few H p of 32 problems sharing the workload's matrix on the matrix
+cores (BF16 copy, then the FP32 matrix), for the kernel trace and counter
+passes over those kernels.
+
 After the timed steps, `next_rows` times (once warm, outside the timed region)
 the elastic net, the duality-gap termination and the adaptive sketch size on the
 same workload, Huber fitting at n = 16000 under the paper's stopping rule and
@@ -116,6 +122,26 @@ def probe_sketch(workload):
         torch.cuda.synchronize()
         log(f"sketch {i}: rank {info[0]['precond_rank']} products "
             f"{1e3 * info[0]['t_sketch_mc']:.3f} ms on the matrix cores")
+
+
+def probe_shared(workload, B=32):
+    """A few H p of B problems sharing the workload's matrix, on the matrix cores, with
+    the BF16 copy and with the FP32 matrix."""
+    import torch
+
+    import genios_data
+    import paper_2310_08333_amd as g
+    dev = torch.device("cuda:0")
+    P = genios_data.config(workload)
+    A = torch.from_numpy(P["A"]).to(dev)
+    m, n = A.shape
+    A16 = g.cast_bf16(A)
+    Pm = torch.randn(B, n, device=dev, dtype=torch.float32)
+    for name, a16 in (("bf16", A16.expand(B, m, n)), ("fp32", None)):
+        for i in range(3):
+            g.hvp(A.expand(B, m, n), Pm, A16=a16, batch_mfma=1)
+            torch.cuda.synchronize()
+        log(f"shared H p {name}: 3 products of {B} problems")
 
 
 def cpu_baseline(P, rows=8000, cols=16000, budget_iters=100):
@@ -352,6 +378,7 @@ def main():
     ap.add_argument("--no-next", action="store_true")
     ap.add_argument("--probe-traffic", action="store_true")
     ap.add_argument("--probe-sketch", action="store_true")
+    ap.add_argument("--probe-shared", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path "
@@ -363,6 +390,9 @@ def main():
         return
     if args.probe_sketch:
         probe_sketch(args.workload)
+        return
+    if args.probe_shared:
+        probe_shared(args.workload)
         return
 
     import torch
