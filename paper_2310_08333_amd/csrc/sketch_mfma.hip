@@ -457,8 +457,13 @@ __global__ __launch_bounds__(256) void k_cols_f32(int64_t n, int B, int sp,
 }
 
 // Tpart[ks][c][r] = sum_{k in split ks} A[r][k] P[c][k]: a block owns 128 rows (a
-// wavefront 32: two row tiles) and all SP columns for a K range; the P tile of each
-// step is staged in LDS (double-buffered) and shared by the four wavefronts.
+// wavefront 32: two row tiles) and all SP columns for a K range, in steps of 32 k: a
+// lane loads 8 consecutive k of its row (two 16-byte fragments, so the four lanes of a
+// row read 128 contiguous bytes), and instruction (h, i) takes k = 8 g + 4 h + i.  The
+// P tile of each step is staged in LDS (double-buffered) and shared by the four
+// wavefronts.  kchunk is a multiple of 32; P entries at or past kpad read as 0.
+constexpr int kFW = 32;       // K step of the FP32 W kernel
+constexpr int kFWPitch = 36;  // its LDS row pitch in floats (32 + 4: 144 bytes)
 template <int SP>
 __global__ __launch_bounds__(256) void k_mrhs_w_f32(const float* __restrict__ A, int64_t lda,
                                                     int m, int n, const float* __restrict__ pc,
@@ -467,7 +472,7 @@ __global__ __launch_bounds__(256) void k_mrhs_w_f32(const float* __restrict__ A,
                                                     const int32_t* __restrict__ gate, int gstride,
                                                     int gcount) {
   constexpr int NT = SP / 16;
-  __shared__ __align__(16) float os[2][SP * kFPitch];
+  __shared__ __align__(16) float os[2][SP * kFWPitch];
   if (!any_flag(gate, gstride, gcount)) return;
   const int ks = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -477,39 +482,44 @@ __global__ __launch_bounds__(256) void k_mrhs_w_f32(const float* __restrict__ A,
   const float* arow[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) arow[t] = A + (int64_t)min(row0 + 16 * t + (lane & 15), m - 1) * lda;
-  const int kl = 4 * (lane >> 4);
+  const int kl = 8 * (lane >> 4);
   floatx4 acc[2][NT];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-  // P tile: SP columns x 16 k = SP * 4 chunks of 16 bytes (loads unconditional, chunk
-  // indices past the tile re-read chunk 0; only the LDS stores are guarded)
-  constexpr int OCH = SP * 4;
+  // P tile: SP columns x 32 k = SP * 8 chunks of 16 bytes (chunk indices past the tile
+  // re-read chunk 0 and offsets at or past kpad read offset 0, then count as 0; only the
+  // LDS stores are guarded)
+  constexpr int OCH = SP * 8;
   constexpr int OQ = (OCH + 255) / 256;
   auto load_p = [&](int kk, float4 (&reg)[OQ]) {
 #pragma unroll
     for (int q = 0; q < OQ; ++q) {
       const int ch = tid + 256 * q < OCH ? tid + 256 * q : 0;
-      reg[q] = *reinterpret_cast<const float4*>(pc + (int64_t)(ch >> 2) * kpad + kk + 4 * (ch & 3));
+      const int64_t k = kk + 4 * (ch & 7);
+      const float4 v = *reinterpret_cast<const float4*>(pc + (int64_t)(ch >> 3) * kpad + (k < kpad ? k : 0));
+      reg[q] = k < kpad ? v : make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
   auto store_p = [&](int buf, const float4 (&reg)[OQ]) {
 #pragma unroll
     for (int q = 0; q < OQ; ++q) {
       const int ch = tid + 256 * q;
-      if (ch < OCH) *reinterpret_cast<float4*>(&os[buf][(ch >> 2) * kFPitch + 4 * (ch & 3)]) = reg[q];
+      if (ch < OCH) *reinterpret_cast<float4*>(&os[buf][(ch >> 3) * kFWPitch + 4 * (ch & 7)]) = reg[q];
     }
   };
-  // columns past n read column 0 (their P rows are 0); n % 4 == 0 keeps a fragment whole
-  auto load_a = [&](int kk, float4 (&fa)[2]) {
+  // columns past n read column 0 (their P rows are 0); n % 8 == 0 keeps a lane's 8 whole
+  auto load_a = [&](int kk, float4 (&fa)[2][2]) {
     const int k = kk + kl;
     const int kc = k < n ? k : 0;
 #pragma unroll
-    for (int t = 0; t < 2; ++t) fa[t] = *reinterpret_cast<const float4*>(arow[t] + kc);
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) fa[t][h] = *reinterpret_cast<const float4*>(arow[t] + kc + 4 * h);
   };
   float4 preg[OQ];
-  float4 fa[2], fn[2];
+  float4 fa[2][2], fn[2][2];
   if (k0 < k1) {
     load_p(k0, preg);
     store_p(0, preg);
@@ -517,24 +527,32 @@ __global__ __launch_bounds__(256) void k_mrhs_w_f32(const float* __restrict__ A,
   }
   __syncthreads();
   int buf = 0;
-  for (int kk = k0; kk < k1; kk += kFK) {
-    const bool more = kk + kFK < k1;
-    const int kn = more ? kk + kFK : kk;
+  for (int kk = k0; kk < k1; kk += kFW) {
+    const bool more = kk + kFW < k1;
+    const int kn = more ? kk + kFW : kk;
     load_p(kn, preg);
     load_a(kn, fn);
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
-      const float4 fb = *reinterpret_cast<const float4*>(&os[buf][(16 * c + (lane & 15)) * kFPitch + kl]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int h = 0; h < 2; ++h) {
+        const float4 fb =
+            *reinterpret_cast<const float4*>(&os[buf][(16 * c + (lane & 15)) * kFWPitch + kl + 4 * h]);
 #pragma unroll
-        for (int t = 0; t < 2; ++t) acc[t][c] = mfma_f32(comp(fa[t], i), comp(fb, i), acc[t][c]);
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int t = 0; t < 2; ++t)
+            acc[t][c] = mfma_f32(comp(fa[t][h], i), comp(fb, i), acc[t][c]);
+      }
     }
     if (more) store_p(buf ^ 1, preg);
     __syncthreads();
     buf ^= 1;
-    fa[0] = fn[0];
-    fa[1] = fn[1];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      fa[t][0] = fn[t][0];
+      fa[t][1] = fn[t][1];
+    }
   }
   float* Tb = tpart + (int64_t)ks * ks_stride;
 #pragma unroll
@@ -683,7 +701,7 @@ hipError_t mrhs_f32_sp(const MatArg& A, int B, const float* P, int64_t pstride, 
   }
   {
     int kchunk = (int)((A.n + ws.ksW - 1) / ws.ksW);
-    kchunk = (kchunk + kMK - 1) / kMK * kMK;
+    kchunk = (kchunk + kFW - 1) / kFW * kFW;
     dim3 grid((unsigned)((m + kWRows - 1) / kWRows), (unsigned)ws.ksW, 1u);
     hipLaunchKernelGGL(k_mrhs_w_f32<SP>, grid, dim3(256), 0, st, Ap, A.lda, m, n, pc, kpn,
                        ws.wpart, kchunk, (int64_t)m * SP, gate, gstride, B);
