@@ -873,6 +873,40 @@ def test_lasso_shared_matrix_batch_matches_oracle(g, precision):
         assert out["info"][j]["iters"] == pytest.approx(ref["info"][j]["iters"], abs=3)
 
 
+@pytest.mark.parametrize("B,mode,n,expect", [
+    (2, 2, 96, True), (2, 1, 96, False), (4, 1, 96, False), (5, 1, 96, True),
+    (128, 1, 96, True), (129, 1, 96, False), (12, 1, 100, False), (12, 0, 96, False)])
+def test_shared_matrix_batch_eligibility(g, B, mode, n, expect):
+    # which batches take the matrix-core products (5..128 problems, 2..128 with mode 2,
+    # n a multiple of 8) and that every batch solves the same problems either way
+    print("shared batch eligibility", B, mode, n, flush=True)
+    m = 60
+    rng = np.random.default_rng(1000 + B + n)
+    A = (rng.standard_normal((m, n)) / np.sqrt(m)).astype(np.float32)
+    X0 = np.zeros((B, n))
+    for j in range(B):
+        X0[j, rng.choice(n, 5, replace=False)] = rng.standard_normal(5)
+    bs = (X0 @ A.T.astype(np.float64) + 0.01 * rng.standard_normal((B, m))).astype(np.float32)
+    lams = [0.1 * float(np.max(np.abs(A.T.astype(np.float64) @ bs[j]))) for j in range(B)]
+    At = _t(A).expand(B, m, n)
+    kw = dict(precision="bf16_refine", eps=1e-6, sketch_rank=16, max_iter=20000)
+    out = g.lasso_solve(At, _t(bs), lams, batch_mfma=mode, **kw)
+    assert out["status"] == 0, [i["status"] for i in out["info"]]
+    assert (out["info"][0]["n_hvp_mrhs"] > 0) == expect
+    ref = g.lasso_solve(At, _t(bs), lams, batch_mfma=0, **kw)
+    assert ref["status"] == 0
+    Z = out["z"].cpu().numpy().astype(np.float64)
+    Zr = ref["z"].cpu().numpy().astype(np.float64)
+    for j in range(B):
+        F = olasso.objective(A, bs[j], lams[j], Z[j])
+        Fr = olasso.objective(A, bs[j], lams[j], Zr[j])
+        assert abs(F - Fr) <= 1e-6 * Fr, (j, F, Fr)
+    for j in (0, B - 1):
+        sol = olasso.solve(A, bs[j], lams[j])
+        rel = (olasso.objective(A, bs[j], lams[j], Z[j]) - sol["F"]) / sol["F"]
+        assert -1e-9 <= rel <= 5e-4, (j, rel)
+
+
 @pytest.mark.parametrize("precision", ["bf16_refine", "f32"])
 def test_logreg_shared_matrix_path(g, logsmall, precision):
     # a regularisation path of l1-logistic problems on one matrix: every problem's
