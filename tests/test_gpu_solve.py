@@ -88,6 +88,34 @@ def test_lasso_f64_lockstep_with_oracle(g, cfg1):
     assert np.allclose(h[:, 2], hist[:, 2], rtol=1e-6, atol=1e-10)  # ||r_d||
 
 
+def test_lasso_high_precision_linear_convergence(g, cfg1):
+    # high-precision solves (Sec. 4.1's convergence figure): with the FP64 operator and
+    # inexact solves the KKT residual falls geometrically down to 1e-10, like the
+    # oracle's ADMM with exact solves, and the objective meets the certified optimum
+    print("lasso high precision", flush=True)
+    P = cfg1
+    A64 = P["A"].astype(np.float64)
+    b64 = P["b"].astype(np.float64)
+    _, _, _, _, hist = olasso.admm(A64, b64, P["lam"], rho=1.0, alpha=1.6, sigma=1e-6,
+                                   max_iter=20000, eps=1e-10)
+    out = g.lasso_solve(_t(A64), _t(b64), P["lam"], precision="f64", eps=1e-10,
+                        sketch_rank=P["s"], history=20000, max_iter=20000)
+    info = out["info"][0]
+    assert out["status"] == 0, info
+    K = info["iters"]
+    r = out["history"][0][:K, 3]
+    assert r[-1] <= 1e-10 and K <= 2 * len(hist), (K, len(hist))
+    # log r_kkt over the second half lies on a line of negative slope (the oracle's
+    # run on this problem: slope -0.17 per iteration, R^2 0.9997)
+    k = np.arange(K // 2, K)
+    y = np.log(r[K // 2:])
+    slope, icpt = np.polyfit(k, y, 1)
+    r2 = 1.0 - np.var(y - (slope * k + icpt)) / np.var(y)
+    assert slope < -0.02 and r2 >= 0.95, (slope, r2)
+    F = olasso.objective(P["A"], P["b"], P["lam"], out["z"].cpu().numpy())
+    assert _rel(F, P["sol"]["F"]) <= 1e-9, (F, P["sol"]["F"])
+
+
 def test_lasso_cg_tolerance_schedule_replay(g, cfg1):
     # Sec. 2.1: rtol_k = min(sqrt(||r_p^{k-1}|| ||r_d^{k-1}||), 1) / k^gamma, floored
     P = cfg1
