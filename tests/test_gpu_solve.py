@@ -966,6 +966,49 @@ def test_logreg_shared_matrix_path(g, logsmall, precision):
             assert _rel(F, P["sol"]["F"]) <= 1e-6, (F, P["sol"]["F"])
 
 
+@pytest.mark.parametrize("extra", [dict(adaptive_sketch=1, sketch_kappa=2.0),
+                                   dict(termination=1, eps_gap=1e-4)])
+def test_shared_matrix_batch_with_adaptive_sketch_and_gap(g, cfg1, extra):
+    # the power method of the adaptive sketch size and the gap-terminated loop on top of
+    # the shared products: the same sizes, iterations and solutions as per problem (a
+    # lambda path on the 200 x 1000 parity matrix; the FP32 evaluation of the relative
+    # gap floors near 1e-5 at its smallest lambda, so the target is 1e-4)
+    print("shared batch with", extra, flush=True)
+    A = cfg1["A"]
+    lams = [cfg1["lam"] * f for f in (0.5, 0.7, 1.0, 1.4, 2.0, 2.8)]
+    B = len(lams)
+    bs = np.tile(cfg1["b"], (B, 1))
+    m, n = A.shape
+    At = _t(A).expand(B, m, n)
+    kw = dict(precision="f32", eps=1e-6, sketch_rank=32, max_iter=20000, **extra)
+    out = g.lasso_solve(At, _t(bs), lams, **kw)
+    ref = g.lasso_solve(At, _t(bs), lams, batch_mfma=0, **kw)
+    assert out["status"] == 0 and ref["status"] == 0, (
+        [(i["status"], i["iters"], i["rel_gap"]) for i in out["info"]],
+        [(i["status"], i["iters"], i["rel_gap"]) for i in ref["info"]])
+    assert out["info"][0]["n_hvp_mrhs"] > 0
+    Z = out["z"].cpu().numpy().astype(np.float64)
+    Zr = ref["z"].cpu().numpy().astype(np.float64)
+    for j in range(B):
+        i, ir = out["info"][j], ref["info"][j]
+        assert i["precond_rank"] == ir["precond_rank"], (j, i["precond_rank"], ir["precond_rank"])
+        assert i["iters"] == pytest.approx(ir["iters"], abs=3), (j, i["iters"], ir["iters"])
+        F = olasso.objective(A, bs[j], lams[j], Z[j])
+        Fr = olasso.objective(A, bs[j], lams[j], Zr[j])
+        assert abs(F - Fr) <= 1e-6 * Fr, (j, F, Fr)
+        if "termination" in extra:
+            # (the same FP32 evaluation allowance as the single-problem gap test)
+            assert i["rel_gap"] <= 1e-4 * 1.05, (j, i["rel_gap"])
+            assert olasso.relative_gap(A, bs[j], lams[j], Z[j]) <= 1e-4 * 1.05 + 2e-6
+    if "adaptive_sketch" in extra:
+        # the target is met or the sizes stop at the cap (here: 8, 16, 32 with the bound
+        # still above 2), with the bound the per-problem products give
+        i0, r0 = out["info"][0], ref["info"][0]
+        assert i0["sketch_rounds"] == r0["sketch_rounds"] >= 1
+        assert i0["kappa_bound"] <= 2.0 or i0["precond_rank"] == 32, i0
+        assert i0["kappa_bound"] == pytest.approx(r0["kappa_bound"], rel=1e-3)
+
+
 def test_boxls_shared_matrix_batch(g):
     print("boxls shared batch", flush=True)
     B = 6
