@@ -199,10 +199,10 @@ int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_)
     mr.sp = mrhs_pad((int)batch);
     const int64_t rb = (m + 127) / 128, cb = (n + 127) / 128, cbf = (n + 255) / 256;
     mr.ksW = (int)std::max<int64_t>(1, std::min<int64_t>((2048 + rb - 1) / rb, std::max<int64_t>(1, n / 256)));
-    int64_t ky = std::max<int64_t>(1, std::min<int64_t>((1024 + cb - 1) / cb, std::max<int64_t>(1, m / 256)));
+    int64_t ky = std::max<int64_t>(1, std::min<int64_t>((2048 + cb - 1) / cb, std::max<int64_t>(1, m / 256)));
     ky = std::min<int64_t>(ky, batch * yslots / mr.sp);  // ypart holds ksY x sp columns
     mr.ksY = (int)std::max<int64_t>(1, ky);
-    ky = std::max<int64_t>(1, std::min<int64_t>((1024 + cbf - 1) / cbf, std::max<int64_t>(1, m / 256)));
+    ky = std::max<int64_t>(1, std::min<int64_t>((2048 + cbf - 1) / cbf, std::max<int64_t>(1, m / 256)));
     mr.ksYf = (int)std::max<int64_t>(1, std::min<int64_t>(ky, batch * yslots / mr.sp));
     if (batch * yslots < mr.sp) mr.sp = 0;  // cannot happen: yslots >= 512 / batch
   }
