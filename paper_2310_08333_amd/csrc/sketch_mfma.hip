@@ -31,6 +31,12 @@
 //   stores of one instruction spread over all 32 banks and the fragment reads
 //   still take the minimum two passes.
 // Results are per-K-split partials, summed in a fixed order by the consumers.
+//
+// The same two products serve a batch of problems sharing one matrix: with
+// P = [p_1 .. p_B] in place of Omega, T = A P and A^T (D o T) give every problem's
+// H p for two streams of A (BF16: P and T as hi + lo parts; FP32 matrix: FP32
+// operands on v_mfma_f32_16x16x4_f32, the second product formed as (T^T A)^T so
+// that A's rows feed the instruction as loaded).
 #include <algorithm>
 
 #include "device.hpp"
