@@ -57,7 +57,7 @@ extern "C" {
 #define GENIOS_ERR_FACTOR (-4)      /* factorisation failure that could not be recovered */
 #define GENIOS_ERR_DEVICE (-5)      /* a HIP runtime call failed */
 #define GENIOS_ERR_WORKSPACE (-6)   /* workspace missing, misaligned or too small */
-#define GENIOS_ERR_UNSUPPORTED (-7) /* valid request this build does not implement */
+#define GENIOS_ERR_UNSUPPORTED (-7) /* valid request the library does not implement */
 
 /* Element types of the data matrix. */
 typedef enum { GENIOS_DT_F32 = 0, GENIOS_DT_BF16 = 1, GENIOS_DT_F64 = 2 } genios_dtype;
