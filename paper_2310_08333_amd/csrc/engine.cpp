@@ -179,6 +179,14 @@ int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_)
                      op == GENIOS_OP_BACKWARD || op == GENIOS_OP_HVP;
   yslots = std::max<int64_t>((int64_t)ksplit * (ml ? 2 : 1),
                              cg_op ? std::max<int64_t>(1, kHvpMaxBlocks / batch) : 1);
+  if (cg_op && batch > 1 && vt == VT_F32) {
+    // room for one problem's whole-chip grid of the fused H p, used once few problems
+    // of the batch still run (bounded: at most 2 GiB of partials over the batch)
+    int64_t g1 = hvp_geometry(probe, 1, false).blocks;
+    if (uses_lo) g1 = std::max<int64_t>(g1, hvp_geometry(probe_lo, 1, false).blocks);
+    const int64_t budget = ((int64_t)1 << 31) / (batch * ((n + 7) / 8 * 8) * (int64_t)sizeof(float));
+    yslots = std::max<int64_t>(yslots, std::min<int64_t>(g1, budget));
+  }
   npad = (n + 7) / 8 * 8;
   chunk = vec_chunk(n);
   nb = (int)((n + chunk - 1) / chunk);
@@ -319,6 +327,10 @@ struct Ctx {
   KernelProf prof;
   int64_t n_mv[4] = {0, 0, 0, 0};
   int64_t n_mrhs = 0, bytes_mrhs = 0;  // H p launches of a batch sharing A (all problems at once)
+  // problems taking part in the coming kernels (set with the parameters; -1: all)
+  std::vector<char> run_flags;
+  int64_t running = -1;
+  int batch_mode = 1;  // opts.batch_mfma
   // bytes of A v / A^T w (the matrix) and of the fused H p on the BF16 / master copy
   // (the matrix once, p read, H p written)
   int64_t bytes_kind[4] = {0, 0, 0, 0};
@@ -441,7 +453,10 @@ struct Ctx {
   }
   int hvp(const MatArg& op, const void* p, const void* d, const int32_t* gate, int gstride) {
     // a batch sharing A: both passes over A serve every problem (matrix cores)
-    if (L.mr.sp > 0 && mrhs_eligible(op, vt, B, L.mr)) {
+    // (two streams of A beat one whole-chip fused pass per running problem from 3 (FP32)
+    // or 4 (BF16) running problems on; batch_mfma = 2 keeps them down to 2)
+    const int64_t min_run = batch_mode == 2 ? 2 : (op.mt == MT_F32 ? 3 : 4);
+    if (L.mr.sp > 0 && (running < 0 || running >= min_run) && mrhs_eligible(op, vt, B, L.mr)) {
       HC(prof.begin(st, 6));
       HC(launch_mrhs_hvp(op, (int)B, static_cast<const float*>(p), n,
                          static_cast<const float*>(d), m, L.mr,
@@ -459,6 +474,31 @@ struct Ctx {
     cur_prob_stride = L.yprob();
     if (vt == VT_F32) {
       const HvpGeom g = hvp_geometry(op, B, true);
+      // a batch with few problems still running: one launch per running problem over
+      // the whole chip (the batched grid gives each problem a 1/B share of it)
+      if (B > 1 && running >= 1 && running <= 8 && g.threads > 0 && hvp_p_aligned(p, n, B)) {
+        const HvpGeom g1 = hvp_geometry(op, 1, true);
+        if (g1.threads > 0 && g1.blocks >= 2 * g.blocks && g1.blocks <= L.yslots) {
+          HC(prof.begin(st, hvp_kind(op)));
+          const size_t es = elem_size(op.mt);
+          for (int64_t b = 0; b < B; ++b) {
+            if (!run_flags[b]) continue;
+            MatArg ob = op;
+            ob.ptr = static_cast<const char*>(op.ptr) + (size_t)(b * op.strideA) * es;
+            HC(launch_hvp_fused(ob, g1, 1, static_cast<const float*>(p) + b * n, n,
+                                d ? static_cast<const float*>(d) + b * m : nullptr, m,
+                                static_cast<float*>(L.ypart) + b * L.yprob(), L.npad, L.yprob(),
+                                gate ? gate + b * gstride : nullptr, gstride, st));
+          }
+          HC(prof.end(st));
+          cur_ks = g1.blocks;
+          cur_ks_stride = L.npad;
+          account(op, hvp_kind(op));
+          last_hvp_kind = hvp_kind(op);
+          last_hvp_op = op;
+          return 0;
+        }
+      }
       if (g.threads > 0 && g.blocks <= L.yslots && hvp_p_aligned(p, n, B)) {
         HC(prof.begin(st, hvp_kind(op)));
         HC(launch_hvp_fused(op, g, B, static_cast<const float*>(p), n,
@@ -539,7 +579,16 @@ int sync_state(Ctx& c, ProbState* hs) {
   return 0;
 }
 
+// Also records which problems take part in the coming kernels (the H p launch shape
+// depends on how many do).
 hipError_t upload_params(Ctx& c, ProbParams* hp) {
+  c.run_flags.assign(c.B, 0);
+  c.running = 0;
+  for (int64_t b = 0; b < c.B; ++b)
+    if (hp[b].run) {
+      c.run_flags[b] = 1;
+      ++c.running;
+    }
   return hipMemcpyAsync(c.L.ctrl.params, hp, c.B * sizeof(ProbParams), hipMemcpyHostToDevice, c.st);
 }
 
@@ -590,6 +639,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
   c.m = A->m;
   c.n = A->n;
   c.vt = A->hi_dtype == GENIOS_DT_F64 ? VT_F64 : VT_F32;
+  c.batch_mode = o->batch_mfma;
   c.ve = c.vt == VT_F32 ? 4 : 8;
   const int s = o->precondition ? effective_rank(o, A->n, A->m) : 0;
   c.L.setup(loss == kLossLogistic ? GENIOS_OP_LOGREG
