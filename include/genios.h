@@ -176,7 +176,10 @@ typedef struct {
                                   Huber), then A^T T: two streams of A instead of B.  BF16 operand: p and T carried as
                                   BF16 hi + lo parts (~16 bits); FP32 operand: FP32 products
                                   and accumulation throughout.  0 = off, 1 (default) = for
-                                  batches of 5 to 128 problems, 2 = for 2 to 128 */
+                                  batches of 5 to 128 problems while at least 3 (FP32
+                                  operand) or 4 (BF16) of them still run (fewer: one fused
+                                  pass per running problem), 2 = for 2 to 128 while at least
+                                  2 run */
 } genios_opts;
 
 /* Per-iteration history row layout (doubles); problem p, iteration k (1-based)
