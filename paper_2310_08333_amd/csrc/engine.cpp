@@ -475,8 +475,11 @@ struct Ctx {
     if (vt == VT_F32) {
       const HvpGeom g = hvp_geometry(op, B, true);
       // a batch with few problems still running: one launch per running problem over
-      // the whole chip (the batched grid gives each problem a 1/B share of it)
-      if (B > 1 && running >= 1 && running <= 8 && g.threads > 0 && hvp_p_aligned(p, n, B)) {
+      // the whole chip (the batched grid gives each problem a 1/B share of it).  Gated
+      // products only: their gate (run or cg_active) is clear for every problem left out,
+      // while an ungated product (the power method's) is wanted for all of them.
+      if (B > 1 && gate != nullptr && running >= 1 && running <= 8 && g.threads > 0 &&
+          hvp_p_aligned(p, n, B)) {
         const HvpGeom g1 = hvp_geometry(op, 1, true);
         if (g1.threads > 0 && g1.blocks >= 2 * g.blocks && g1.blocks <= L.yslots) {
           HC(prof.begin(st, hvp_kind(op)));
