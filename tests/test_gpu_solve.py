@@ -935,6 +935,34 @@ def test_shared_matrix_batch_eligibility(g, B, mode, n, expect):
         assert -1e-9 <= rel <= 5e-4, (j, rel)
 
 
+def test_logreg_batch_adaptive_resketch_with_problems_stopping_apart(g, logsmall):
+    # a batch whose problems stop at different iterations, re-sketched every 5
+    # iterations at an adaptive size: the H p of the last running problems take one
+    # launch each, the power method's products still cover every problem; each problem
+    # is certified by the oracle's duality gap and matches its own single-problem solve
+    print("logreg batch adaptive resketch", flush=True)
+    P = logsmall
+    lams = [P["lam"] * f for f in (0.6, 1.0, 2.0, 4.0)]
+    B = len(lams)
+    m, n = P["A"].shape
+    A = np.ascontiguousarray(np.broadcast_to(P["A"], (B, m, n)))
+    Y = np.tile(P["y"], (B, 1))
+    kw = dict(precision="f32", eps=1e-5, sketch_rank=16, resketch_every=5, adaptive_sketch=1,
+              sketch_rank_init=4, sketch_kappa=5.0, max_iter=5000)
+    out = g.logreg_solve(_t(A), _t(Y), lams, **kw)
+    assert out["status"] == 0, [i["status"] for i in out["info"]]
+    its = [i["iters"] for i in out["info"]]
+    assert max(its) > min(its), its
+    Z = out["z"].cpu().numpy().astype(np.float64)
+    for j, lam in enumerate(lams):
+        F = ologreg.objective(P["A"], P["y"], lam, Z[j])
+        gap, _, _ = ologreg.duality_gap(P["A"], P["y"], lam, Z[j])
+        assert gap <= 1e-4 * F, (j, gap, F)
+        one = g.logreg_solve(_t(P["A"]), _t(P["y"]), lam, **kw)
+        F1 = ologreg.objective(P["A"], P["y"], lam, one["z"].cpu().numpy().astype(np.float64))
+        assert _rel(F, F1) <= 1e-6, (j, F, F1)
+
+
 @pytest.mark.parametrize("precision", ["bf16_refine", "f32"])
 def test_logreg_shared_matrix_path(g, logsmall, precision):
     # a regularisation path of l1-logistic problems on one matrix: every problem's
