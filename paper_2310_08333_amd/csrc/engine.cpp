@@ -502,13 +502,21 @@ struct Ctx {
           return 0;
         }
       }
-      if (g.threads > 0 && g.blocks <= L.yslots && hvp_p_aligned(p, n, B)) {
+      // more than 8 but not all running, problems of 256 MB or more: the grid over the
+      // batch sized for the running problems (the stopped ones' blocks exit at their
+      // gate; on small problems those empty blocks cost more than the wider grid gains)
+      const bool big = op.m * op.n * (int64_t)elem_size(op.mt) >= ((int64_t)256 << 20);
+      const HvpGeom gr = B > 1 && big && gate != nullptr && running >= 1 && running < B
+                             ? hvp_geometry(op, running, true)
+                             : HvpGeom{};
+      const HvpGeom& gb = gr.threads > 0 && gr.blocks <= L.yslots ? gr : g;
+      if (gb.threads > 0 && gb.blocks <= L.yslots && hvp_p_aligned(p, n, B)) {
         HC(prof.begin(st, hvp_kind(op)));
-        HC(launch_hvp_fused(op, g, B, static_cast<const float*>(p), n,
+        HC(launch_hvp_fused(op, gb, B, static_cast<const float*>(p), n,
                             static_cast<const float*>(d), m, static_cast<float*>(L.ypart), L.npad,
                             L.yprob(), gate, gstride, st));
         HC(prof.end(st));
-        cur_ks = g.blocks;
+        cur_ks = gb.blocks;
         cur_ks_stride = L.npad;
         account(op, hvp_kind(op));
         last_hvp_kind = hvp_kind(op);
