@@ -269,6 +269,63 @@ def solve(A, b, lam, rhos=(1.0, 0.1, 0.01), iters_per_rho=1500, gap_rel=1e-12,
                 polished=pol)
 
 
+def rmatvec_rows(A, r, rows=2048):
+    """A^T r in FP64 over row blocks of A (A may be FP32; each block is upcast
+    exactly), so a matrix of several GB is never copied whole."""
+    r = _f64(r)
+    out = np.zeros(A.shape[1])
+    for i in range(0, A.shape[0], rows):
+        out += _f64(A[i:i + rows]).T @ r[i:i + rows]
+    return out
+
+
+def solve_working_set(A, b, lam, gap_rel=1e-12, start=256, grow=256, max_outer=50, lam2=0.0):
+    """Certified Lasso optimum of a large problem through a working set W.
+
+    The restricted problem on the columns W is solved by ``solve`` (certified on
+    its own), x is that solution padded with zeros, and the full gradient
+    g = A^T (A x - b) + lam2 x is formed once.  On W the restricted optimality
+    conditions are the full ones; off W they ask |g_j| <= lam (App. A with
+    f'(w) = w).  If some j outside W violates that, up to ``grow`` of the worst
+    violators join W and the loop repeats; otherwise x is optimal, and the
+    duality gap of the full problem (App. A) certifies it.  W starts as the
+    ``start`` largest |A^T b|.  Returns the fields of ``solve`` plus the
+    working-set size and the number of outer rounds."""
+    b = _f64(b)
+    n = A.shape[1]
+    g0 = rmatvec_rows(A, -b)
+    W = np.sort(np.argsort(-np.abs(g0))[:min(n, start)])
+    for outer in range(1, max_outer + 1):
+        AW = _f64(A[:, W])
+        sub = solve(AW, b, lam, gap_rel=min(gap_rel, 1e-13), lam2=lam2)
+        x = np.zeros(n)
+        x[W] = sub["x"]
+        r = AW @ sub["x"] - b
+        g = rmatvec_rows(A, r) + lam2 * x
+        viol = np.abs(g) - lam * (1.0 + 1e-12)
+        viol[W] = -np.inf
+        if np.max(viol) > 0.0:
+            add = np.argsort(-viol)[:grow]
+            add = add[viol[add] > 0.0]
+            W = np.union1d(W, add)
+            continue
+        primal = 0.5 * float(r @ r) + lam * float(np.sum(np.abs(x))) + 0.5 * lam2 * float(x @ x)
+        if lam2 > 0.0:
+            excess = np.maximum(np.abs(g - lam2 * x) - lam, 0.0)
+            dual = -0.5 * float(r @ r) - float(b @ r) - float(excess @ excess) / (2.0 * lam2)
+        else:
+            ginf = float(np.max(np.abs(g)))
+            scale = 1.0 if ginf <= lam else lam / ginf
+            nu = scale * r
+            dual = -0.5 * float(nu @ nu) - float(b @ nu)
+        gap = primal - dual
+        S = np.flatnonzero(x != 0)
+        return dict(x=x, F=primal, gap=gap, support=S, signs=np.sign(x[S]),
+                    iters=sub["iters"], polished=sub["polished"], working_set=int(W.size),
+                    outer=outer, certified=bool(gap <= gap_rel * primal))
+    raise RuntimeError("working set did not settle")
+
+
 def brute_force(A, b, lam, lam2=0.0):
     """Enumerate all 3^n sign patterns; returns (x_kkt_list, x_minF, F_min).
 

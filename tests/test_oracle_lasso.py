@@ -167,3 +167,18 @@ def test_hessian_vector_with_logistic_weights_matches_gradient_differences():
     h = 1e-5
     fd = (logreg.grad_f(A, y, x + h * p) - logreg.grad_f(A, y, x - h * p)) / (2 * h)
     assert np.allclose(hv, fd, rtol=1e-7, atol=1e-8)
+
+
+def test_working_set_solve_equals_the_plain_solve():
+    import genios_data
+    P = genios_data.config("lasso_200x1000")
+    ref = lasso.solve(P["A"], P["b"], P["lam"])
+    ws = lasso.solve_working_set(P["A"], P["b"], P["lam"], start=8, grow=8)
+    assert ws["certified"] and ws["outer"] >= 2
+    assert abs(ws["F"] - ref["F"]) <= 1e-12 * ref["F"]
+    assert np.array_equal(ws["support"], ref["support"])
+    assert np.allclose(ws["x"], ref["x"], rtol=1e-9, atol=1e-12)
+    gap, F, _ = lasso.duality_gap(P["A"], P["b"], P["lam"], ws["x"])
+    assert abs(gap - ws["gap"]) <= 1e-9 * F and gap <= 1e-11 * F
+    assert np.allclose(lasso.rmatvec_rows(P["A"], P["b"], rows=7),
+                       P["A"].astype(np.float64).T @ P["b"].astype(np.float64), rtol=1e-12)

@@ -135,3 +135,67 @@ def test_l2_term_optimum_satisfies_kkt_and_matches_lbfgs():
     x = sol["x"] + 0.1 * np.random.default_rng(1).standard_normal(n)
     gap, pr, du = logreg.duality_gap(A, y, lam, x, lam2)
     assert gap >= logreg.objective(A, y, lam, x, lam2) - sol["F"] - 1e-12
+
+
+def test_newton_prox_converges_under_large_curvature():
+    # the shared factor gives curvature of 1e4 and more: the gradient norm of the
+    # prox objective bottoms out near 1e-12 in FP64, so the decrement criterion
+    # has to end the Newton loop; the result is still the prox point
+    P = genios_data.logreg_factor(1500, 120, nnz_frac=0.05, seed=11, s=8)
+    A, y = P["A"].astype(np.float64), P["y"].astype(np.float64)
+    rho = P["rho"]
+    v = np.random.default_rng(1).standard_normal(A.shape[1]) * 0.1
+    x = logreg._newton_prox(A, y, rho, v, np.zeros(A.shape[1]))
+    g = logreg.grad_f(A, y, x) + rho * (x - v)
+    g0 = logreg.grad_f(A, y, np.zeros(A.shape[1])) + rho * (0 - v)
+    assert np.linalg.norm(g) <= 1e-12 * np.linalg.norm(g0)
+
+
+def test_working_set_solve_equals_the_plain_solve():
+    P = genios_data.logreg_factor(600, 200, nnz_frac=0.05, seed=12, s=8)
+    ref = logreg.solve(P["A"], P["y"], P["lam"], rho=P["rho"])
+    ws = logreg.solve_working_set(P["A"], P["y"], P["lam"], start=16, grow=8)
+    assert ws["certified"] and ws["outer"] >= 2          # the working set had to grow
+    assert abs(ws["F"] - ref["F"]) <= 1e-12 * ref["F"]
+    assert np.max(np.abs(ws["x"] - ref["x"])) <= 1e-8 * np.max(np.abs(ref["x"]))
+    assert np.array_equal(np.flatnonzero(ws["x"]), np.flatnonzero(ref["x"]))
+    gap, F, _ = logreg.duality_gap(P["A"], P["y"], P["lam"], ws["x"])
+    assert gap <= 1e-11 * F and logreg.kkt_violation(P["A"], P["y"], P["lam"], ws["x"]) <= 1e-8
+
+
+def test_polish_on_the_right_support_is_certified_and_on_a_wrong_one_rejected():
+    P = genios_data.logreg_factor(600, 200, nnz_frac=0.05, seed=12, s=8)
+    A, y, lam = P["A"], P["y"], P["lam"]
+    ref = logreg.solve(A, y, lam, rho=P["rho"])
+    # an inexact point with the optimum's support and signs
+    z = ref["x"] * (1.0 + 0.01 * np.random.default_rng(2).standard_normal(200))
+    xp = logreg.polish(A, y, lam, z)
+    gap, F, _ = logreg.duality_gap(A, y, lam, xp)
+    assert gap <= 1e-11 * F and abs(F - ref["F"]) <= 1e-12 * ref["F"]
+    # dropping the largest coefficient leaves a support whose polished point the gap rejects
+    zw = ref["x"].copy()
+    zw[np.argmax(np.abs(zw))] = 0.0
+    xw = logreg.polish(A, y, lam, zw)
+    assert xw is None or logreg.duality_gap(A, y, lam, xw)[0] > 1e-6 * F
+
+
+def test_penalty_at_the_mean_curvature_converges_where_rho_one_stalls():
+    # The workload's reading of the initial penalty: rho = ||A||_F^2 / (4 n), the
+    # mean eigenvalue of A^T D A at x = 0.  With the shared factor the whole
+    # Hessian spectrum lies far above 1; at rho = 1 the residual-balancing rule
+    # of Sec. 2.5 never fires (the residuals stay within a factor mu of each
+    # other) and GeNIOS's ADMM creeps; at the mean curvature it converges.
+    P = genios_data.logreg_factor(2000, 500, nnz_frac=0.02, seed=4, s=20)
+    A, y, lam = P["A"].astype(np.float64), P["y"].astype(np.float64), P["lam"]
+    d0 = logreg.hess_diag(A, y, np.zeros(500))
+    ev = np.linalg.eigvalsh(A.T @ (d0[:, None] * A))
+    assert ev[0] > 50.0 and abs(P["rho"] - ev.mean()) <= 1e-9 * ev.mean()
+    kw = dict(alpha=1.6, sigma=1e-6, rho_update_every=25, eps=1e-4)
+    _, _, _, rho1, h1 = logreg.admm(A, y, lam, rho=1.0, max_iter=150, **kw)
+    assert h1[-1, 3] > 1e-3 and rho1 == 1.0                   # stalled, rule silent
+    at = h1[h1[:, 0] % 25 == 0]                                # the rule's iterations
+    assert np.all(np.maximum(at[:, 1] / at[:, 2], at[:, 2] / at[:, 1]) < 10.0)
+    _, z, _, _, h = logreg.admm(A, y, lam, rho=P["rho"], max_iter=150, **kw)
+    assert h[-1, 3] <= 1e-4 and len(h) <= 60
+    ref = logreg.solve(A, y, lam, rho=P["rho"])
+    assert abs(logreg.objective(A, y, lam, z) - ref["F"]) <= 1e-5 * ref["F"]

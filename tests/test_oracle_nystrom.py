@@ -137,3 +137,45 @@ def test_stabilised_is_the_definition_for_the_shifted_matrix(mu):
 def test_stabilising_shift_is_unit_roundoff_times_frobenius_norm():
     Y = np.array([[3.0, 0.0], [0.0, 4.0]])
     assert nystrom.stabilising_shift(Y, 2.0 ** -24) == 5.0 * 2.0 ** -24
+
+
+def _fp32_stabilised(G, Om, mu):
+    """The stabilised core with the sketch and Omega^T Y_mu formed in FP32, as a
+    single-precision device path forms them; returns lam_hat or None when the
+    Cholesky factor does not exist."""
+    Y32 = (G.T @ (G @ Om)).astype(np.float32)
+    Ymu = (Y32 + np.float32(mu) * Om).astype(np.float32)
+    M = (Om.T @ Ymu).astype(np.float32).astype(np.float64)
+    try:
+        C = np.linalg.cholesky(0.5 * (M + M.T))
+    except np.linalg.LinAlgError:
+        return None
+    B = np.linalg.solve(C, Ymu.astype(np.float64).T).T
+    sv = np.linalg.svd(B, compute_uv=False)
+    return np.maximum(sv ** 2 - mu, 0.0)
+
+
+@pytest.mark.parametrize("n,s,k", [(2000, 40, 20), (6000, 50, 20)])
+def test_stabilising_shift_scale_is_bracketed(n, s, k):
+    # The shift must be large enough that the s x s core of an exactly rank-k
+    # operator (k < s) stays positive definite under FP32 rounding of the sketch,
+    # and small enough that the recovered eigenvalues keep close to H's.  The
+    # reading's u ||Y||_F meets both on every seed; a shift n times smaller (or
+    # none) loses the factorisation, one sqrt(n) times larger (the orthonormal-
+    # Omega formula applied unscaled to a Gaussian Omega) biases the eigenvalues.
+    u = 2.0 ** -24
+    for seed in range(6):
+        rng = np.random.default_rng(seed)
+        G = (rng.standard_normal((k, n)) * np.logspace(0, -1, n)).astype(np.float32)
+        Om = rng.standard_normal((n, s)).astype(np.float32)
+        G64 = G.astype(np.float64)
+        ev = np.sort(np.linalg.eigvalsh(G64 @ G64.T))[::-1]   # the nonzero spectrum of G^T G
+        mu = nystrom.stabilising_shift((G.T @ (G @ Om)).astype(np.float32), u)
+        lam = _fp32_stabilised(G, Om, mu)
+        assert lam is not None
+        assert np.max(np.abs(lam[:k] - ev) / ev) <= 2e-3
+        assert np.max(lam[k:]) <= 1e-6 * ev[0]              # the rank is recovered
+        assert _fp32_stabilised(G, Om, 0.0) is None
+        assert _fp32_stabilised(G, Om, mu / n) is None
+        big = _fp32_stabilised(G, Om, mu * np.sqrt(n))
+        assert np.max(np.abs(big[:k] - ev) / ev) > 1e-2
