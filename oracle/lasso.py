@@ -109,15 +109,20 @@ class ShiftedGramSolve:
 
 def admm(A, b, lam, rho=1.0, alpha=1.0, sigma=0.0, max_iter=1000, eps=None,
          rho_update_every=0, rho_update_until=500, tau=2.0, mu=10.0,
-         x0=None, z0=None, u0=None, record=True, lam2=0.0):
+         x0=None, z0=None, u0=None, record=True, lam2=0.0, clock=None):
     """Scaled ADMM of Sec. 2 with exact x-steps.  Returns (x, z, u, rho, hist).
 
     hist has one row per iteration k = 1..K:
         (k, ||r_p||, ||r_d||, r_kkt, rho_used, rho_after)
     where r_p = x - z and r_d = grad f(x) + rho u are evaluated at (x^k, z^k, u^k)
     with the rho of that iteration (Sec. 2.3).  If ``eps`` is given the loop
-    stops at the first k with r_kkt <= eps.
+    stops at the first k with r_kkt <= eps.  ``clock`` (a list) receives
+    time.perf_counter() stamps: at entry, after the factorisation, after every
+    iteration (timing only; the arithmetic is the same).
     """
+    import time
+    if clock is not None:
+        clock.append(time.perf_counter())
     A = _f64(A)
     b = _f64(b)
     m, n = A.shape
@@ -125,6 +130,8 @@ def admm(A, b, lam, rho=1.0, alpha=1.0, sigma=0.0, max_iter=1000, eps=None,
     z = np.zeros(n) if z0 is None else _f64(z0).copy()
     u = np.zeros(n) if u0 is None else _f64(u0).copy()
     solver = ShiftedGramSolve(A, rho + sigma + lam2)
+    if clock is not None:
+        clock.append(time.perf_counter())
     hist = []
     for k in range(1, max_iter + 1):
         # eq. x-update-lin-sys with H = A^T A + lam2 I, M = I, c = 0
@@ -151,6 +158,8 @@ def admm(A, b, lam, rho=1.0, alpha=1.0, sigma=0.0, max_iter=1000, eps=None,
                 solver = ShiftedGramSolve(A, rho + sigma + lam2)
         if record:
             hist.append((k, rp, rd, rk, rho_used, rho))
+        if clock is not None:
+            clock.append(time.perf_counter())
         if eps is not None and rk <= eps:
             break
     return x, z, u, rho, np.array(hist)
