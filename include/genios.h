@@ -33,7 +33,8 @@
  * Determinism.  Reductions are two-stage with a fixed order and no floating
  *   point atomics: a fixed seed gives bitwise-identical results on one GPU.
  * Reentrancy.  Calls are reentrant given distinct workspaces.  The only
- *   process-wide state is a lazily created per-thread pinned host staging block.
+ *   process-wide state is a lazily created per-thread pinned host staging block
+ *   and the per-GPU static scratch buffer of genios_hvp_noalloc.
  */
 #ifndef GENIOS_H
 #define GENIOS_H
@@ -376,6 +377,26 @@ int genios_matvec(const genios_matrix* A, int32_t trans, int32_t use_bf16, const
  * given).  p, out: n per problem; d: m per problem.  Synchronises o->stream. */
 int genios_hvp(const genios_matrix* A, int32_t use_bf16, const void* d, const void* p, void* out,
                const genios_opts* o);
+
+/* For callers that cannot allocate device memory (code recorded under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): genios_hvp
+ * without a workspace.  The product's partial sums live in a library-owned
+ * static device buffer of GENIOS_HVP_NOALLOC_SCRATCH_BYTES per GPU, resolved
+ * once per device on the first call there and held until the process ends;
+ * o->workspace and o->workspace_bytes are ignored.  The call allocates nothing
+ * (no hipMalloc, hipFree, pinned host memory or allocating library routine).
+ * Errors: GENIOS_ERR_WORKSPACE, detected before any HIP call, when
+ * genios_workspace_size(GENIOS_OP_HVP, A, o) exceeds the buffer (one fused
+ * product of a 20000 x 40000 matrix needs about 80 MiB); otherwise as
+ * genios_hvp.  Every call on one GPU shares that GPU's buffer and the buffer
+ * keeps the last call's contents (the kernels write every partial they read):
+ * calls that overlap on one GPU (several streams or threads) race, so the caller
+ * serialises them.  Arguments, results and the stream synchronisation are those
+ * of genios_hvp, and the kernels and launch shapes are the same, so the output
+ * is bitwise equal to genios_hvp's. */
+#define GENIOS_HVP_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int genios_hvp_noalloc(const genios_matrix* A, int32_t use_bf16, const void* d, const void* p,
+                       void* out, const genios_opts* o);
 
 /* Round `count` FP32 values to BF16, nearest-even, NaN -> 0x7FC0 (device). */
 int genios_cast_bf16(const float* src, uint16_t* dst, int64_t count, const genios_opts* o);

@@ -26,7 +26,7 @@ from ._abi import GeniosError, Info
 
 __all__ = ["lasso_solve", "logreg_solve", "huber_solve", "boxls_solve", "nystrom_build", "nystrom_apply", "lasso_backward",
            "GeniosLasso", "lasso", "matvec", "cast_bf16", "gaussian_matrix", "admm_update",
-           "workspace_size", "make_opts", "GeniosError"]
+           "workspace_size", "make_opts", "GeniosError", "hvp_noalloc"]
 
 _lib = _abi.load()
 
@@ -325,6 +325,32 @@ def hvp(A, p, d=None, A16=None, batch_mfma=1):
     del ws
     if rc < 0:
         raise GeniosError(rc, "genios_hvp")
+    return out
+
+
+def hvp_noalloc(A, p, d=None, A16=None, out=None, batch_mfma=1):
+    """``hvp`` through genios_hvp_noalloc: no workspace is allocated (the library's
+    static per-GPU scratch holds the partial sums); ``out`` may be given so that
+    the call allocates nothing at all."""
+    dev = A.device
+    M = _matrix(A, A16)
+    o = _abi.default_opts()
+    o.batch_mfma = int(batch_mfma)
+    o.precision = _abi.PREC_BF16_ONLY if A16 is not None else (
+        _abi.PREC_F64 if A.dtype == torch.float64 else _abi.PREC_F32)
+    B, m, n = M.batch, M.m, M.n
+    _check_vec(p, "p", A.dtype, B * n, dev)
+    if d is not None:
+        _check_vec(d, "d", A.dtype, B * m, dev)
+    if out is None:
+        out = torch.empty((B, n) if A.dim() == 3 else (n,), dtype=A.dtype, device=dev)
+    else:
+        _check_vec(out, "out", A.dtype, B * n, dev)
+    o.stream = _stream(dev)
+    rc = _lib.genios_hvp_noalloc(C.byref(M), int(A16 is not None), _ptr(d), _ptr(p), _ptr(out),
+                                 C.byref(o))
+    if rc < 0:
+        raise GeniosError(rc, "genios_hvp_noalloc")
     return out
 
 

@@ -95,7 +95,7 @@ EXPORTED = (
     "genios_default_opts", "genios_workspace_size", "genios_lasso_solve", "genios_logreg_solve",
     "genios_huber_solve", "genios_boxls_solve",
     "genios_nystrom_build", "genios_nystrom_apply", "genios_lasso_backward", "genios_matvec",
-    "genios_hvp",
+    "genios_hvp", "genios_hvp_noalloc",
     "genios_cast_bf16", "genios_stream_read", "genios_gaussian_matrix", "genios_admm_update", "genios_status_string",
     "genios_last_error", "genios_abi_struct_sizes",
 )
@@ -135,6 +135,8 @@ def load(path: str | None = None):
     lib.genios_matvec.restype = C.c_int
     lib.genios_hvp.argtypes = [P(Matrix), i32, vp, vp, vp, P(Opts)]
     lib.genios_hvp.restype = C.c_int
+    lib.genios_hvp_noalloc.argtypes = [P(Matrix), i32, vp, vp, vp, P(Opts)]
+    lib.genios_hvp_noalloc.restype = C.c_int
     lib.genios_cast_bf16.argtypes = [vp, vp, i64, P(Opts)]
     lib.genios_cast_bf16.restype = C.c_int
     lib.genios_stream_read.argtypes = [vp, i64, C.c_int32, vp, P(C.c_double), P(Opts)]

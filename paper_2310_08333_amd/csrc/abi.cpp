@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -104,6 +105,34 @@ int check_lambda(const double* lambda, int64_t batch) {
   for (int64_t b = 0; b < batch; ++b)
     if (!(lambda[b] >= 0.0) || !std::isfinite(lambda[b]))
       FAIL(GENIOS_ERR_ARG, "lambda must be finite and >= 0");
+  return GENIOS_OK;
+}
+
+// Library-owned device buffer of genios_hvp_noalloc (one copy per GPU, each at its
+// own address).  The host never passes the array's name to a kernel: its device
+// address is looked up per device with hipGetSymbolAddress and kept below.
+static __device__ __align__(256) unsigned char scratch[GENIOS_HVP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch` (resolved on the first
+// call on that device, with that device current), or an error code.
+int noalloc_scratch(void** ptr) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) FAIL(GENIOS_ERR_DEVICE, std::string("HIP error: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) FAIL(GENIOS_ERR_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      FAIL(GENIOS_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
   return GENIOS_OK;
 }
 
@@ -331,6 +360,27 @@ int genios_hvp(const genios_matrix* A, int32_t use_bf16, const void* d, const vo
   if (use_bf16 && A->A_bf16 == nullptr) FAIL(GENIOS_ERR_ARG, "use_bf16 needs A_bf16");
   if ((rc = check_ws(GENIOS_OP_HVP, A, o))) return rc;
   return run_hvp(A, use_bf16, d, p, out, o);
+}
+
+int genios_hvp_noalloc(const genios_matrix* A, int32_t use_bf16, const void* d, const void* p,
+                       void* out, const genios_opts* o) {
+  int rc;
+  if ((rc = check_matrix(A)) || (rc = check_opts(o))) return rc;
+  if (p == nullptr || out == nullptr) FAIL(GENIOS_ERR_ARG, "p and out must be non-NULL");
+  if (use_bf16 && A->A_bf16 == nullptr) FAIL(GENIOS_ERR_ARG, "use_bf16 needs A_bf16");
+  const size_t need = genios_workspace_size(GENIOS_OP_HVP, A, o);
+  if (need == 0) FAIL(GENIOS_ERR_ARG, "cannot size the workspace for these arguments");
+  if (need > GENIOS_HVP_NOALLOC_SCRATCH_BYTES)
+    FAIL(GENIOS_ERR_WORKSPACE, "genios_hvp_noalloc: this product needs " + std::to_string(need) +
+                                   " bytes of scratch, more than the library's " +
+                                   std::to_string(GENIOS_HVP_NOALLOC_SCRATCH_BYTES) +
+                                   "; use genios_hvp with a workspace");
+  void* ptr = nullptr;
+  if ((rc = noalloc_scratch(&ptr))) return rc;
+  genios_opts oo = *o;
+  oo.workspace = ptr;
+  oo.workspace_bytes = GENIOS_HVP_NOALLOC_SCRATCH_BYTES;
+  return run_hvp(A, use_bf16, d, p, out, &oo);
 }
 
 int genios_cast_bf16(const float* src, uint16_t* dst, int64_t count, const genios_opts* o) {

@@ -225,3 +225,21 @@ def test_boxls_entry_point_checks_its_arguments(abi):
     assert lib.genios_boxls_solve(C.byref(M), p, p, p, 1.0, C.byref(q), p, p, p, info) == abi.ERR_WORKSPACE
     a = lib.genios_workspace_size(abi.OP_BOXLS, C.byref(M), C.byref(q))
     assert a == lib.genios_workspace_size(abi.OP_LASSO, C.byref(M), C.byref(q)) > 0
+
+
+def test_hvp_noalloc_rejects_a_product_beyond_its_scratch(abi):
+    # 20000 x 200000: the fused product's partial slots alone exceed the static
+    # scratch; the call must fail on the host, before any HIP call
+    lib = abi.load()
+    M = _mat(abi, m=20000, n=200000)
+    o = abi.default_opts()
+    o.precision = abi.PREC_F32
+    need = lib.genios_workspace_size(abi.OP_HVP, C.byref(M), C.byref(o))
+    assert need > (128 << 20)
+    rc = lib.genios_hvp_noalloc(C.byref(M), 0, None, C.c_void_p(0x20000000),
+                                C.c_void_p(0x30000000), C.byref(o))
+    assert rc == abi.ERR_WORKSPACE
+    assert b"scratch" in lib.genios_last_error()
+    # and a size within the buffer passes the same check (not called: no device here)
+    M2 = _mat(abi, m=20000, n=40000)
+    assert lib.genios_workspace_size(abi.OP_HVP, C.byref(M2), C.byref(o)) <= (128 << 20)
