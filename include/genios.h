@@ -181,6 +181,17 @@ typedef struct {
                                   operand) or 4 (BF16) of them still run (fewer: one fused
                                   pass per running problem), 2 = for 2 to 128 while at least
                                   2 run */
+  int32_t refine_cg_bf16;      /* BF16_REFINE, after the switch to the master copy: 0 = CG
+                                  products with the master copy; 1 = CG keeps the BF16 copy
+                                  (the x-system's Hessian model) while the master copy forms
+                                  grad f(x) (for the squared loss H x, one fused pass) once
+                                  per ADMM iteration, so the right-hand side, r_d and the
+                                  stopping test are the master copy's and the fixed point is
+                                  the FP32 problem's (the approximate-Hessian x-step of
+                                  Sec. 2.1).  Default 0: on the 20000 x 40000 Lasso 1 saves
+                                  1 % of the time to 1e-4, on the 1000 x 10000 one it costs
+                                  40 % (the extra pass per iteration is launch-bound there).
+                                  The logistic and Huber losses take 0 whatever the value */
 } genios_opts;
 
 /* Per-iteration history row layout (doubles); problem p, iteration k (1-based)
@@ -243,7 +254,8 @@ typedef struct {
                                 (lambda2 > 0 or the box: nu = f'(A z - b); the box dual is
                                 -inf where an infinite bound meets a wrong sign of A^T nu) */
   int32_t gap_checks;        /* gap evaluations during the solve (termination = 1 or 2) */
-  int32_t reserved2;
+  int32_t n_hvp_tail;        /* batch: fused H p launches made over the whole chip for one
+                                running problem each (at most 8 problems still running) */
   double subgrad_dist;       /* at the returned z with the master copy: the distance from 0 to
                                 grad f(z) + lambda d||z||_1 (box: + the normal cone; l2 norm) */
   double sketch_err;         /* adaptive_sketch: power-method estimate of ||H - H_hat|| for the
@@ -253,6 +265,9 @@ typedef struct {
   int32_t n_hvp_mrhs;        /* batch_mfma: H p launches that served the whole batch */
   double t_hvp_mrhs;         /* with profile_kernels: their summed duration */
   int64_t bytes_hvp_mrhs;    /* bytes they must move: A twice, every problem's p in and H p out */
+  int32_t n_hvp_resized;     /* batch of matrices of 256 MB or more: fused H p launches whose grid
+                                was sized for the running problems (more than 8, fewer than all) */
+  int32_t reserved3;
 } genios_info;
 
 /* Fill *o with the defaults listed above.  Returns GENIOS_OK. */

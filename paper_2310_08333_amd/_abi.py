@@ -60,7 +60,8 @@ class Opts(C.Structure):
                 ("eps_gap", C.c_double), ("lambda2", C.c_double),
                 ("huber_delta", C.c_double), ("adaptive_sketch", C.c_int32),
                 ("sketch_rank_init", C.c_int32), ("sketch_kappa", C.c_double),
-                ("power_iters", C.c_int32), ("batch_mfma", C.c_int32)]
+                ("power_iters", C.c_int32), ("batch_mfma", C.c_int32),
+                ("refine_cg_bf16", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -81,11 +82,12 @@ class Info(C.Structure):
                 ("n_sketch_fma", C.c_int32), ("t_sketch_fma", C.c_double),
                 ("flops_sketch_fma", C.c_int64), ("rel_gap", C.c_double),
                 ("gap_primal", C.c_double), ("gap_dual", C.c_double),
-                ("gap_checks", C.c_int32), ("reserved2", C.c_int32),
+                ("gap_checks", C.c_int32), ("n_hvp_tail", C.c_int32),
                 ("subgrad_dist", C.c_double), ("sketch_err", C.c_double),
                 ("kappa_bound", C.c_double), ("sketch_rounds", C.c_int32),
                 ("n_hvp_mrhs", C.c_int32), ("t_hvp_mrhs", C.c_double),
-                ("bytes_hvp_mrhs", C.c_int64)]
+                ("bytes_hvp_mrhs", C.c_int64), ("n_hvp_resized", C.c_int32),
+                ("reserved3", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -5,10 +5,12 @@
 //                 eq. x-update-lin-sys, (H + nu I) x = rhs with
 //                 rhs = (H + sigma I) x^k - grad f(x^k) + rho (z^k - u^k),
 //                 warm-started at x^k, so r_0 = rho (z - u - x) - grad f(x^k).
-//   precond_coef  coefficients of P^-1 (eq. preconditioner) from U^T r.
-//   precond_step  stopping decision for the current residual (CG tolerance of
-//                 the schedule, iteration limit), then w = P^-1 r.
-//   p_update      p = w + beta p.
+//   precond_coef  coefficients c_j of P^-1 = I + U diag(d) U^T (eq. preconditioner),
+//                 c = d o (U^T r), and the terms c_j (U^T r)_j of r^T P^-1 r.
+//   precond_p     stopping decision for the current residual (CG tolerance of
+//                 the schedule, iteration limit), then r^T P^-1 r = ||r||^2 +
+//                 sum_j c_j (U^T r)_j, beta, and p = P^-1 r + beta p = r + U c + beta p
+//                 in one pass (P^-1 r is never stored).
 //   cg_alpha      hp = H p (sum of gemv_t partials), q = hp + nu p.
 //   cg_update     alpha = r^T w / p^T q; x += alpha p, h += alpha hp (h tracks
 //                 H x), r -= alpha q.
@@ -47,12 +49,11 @@ __device__ __forceinline__ VT soft_threshold(VT v, VT k) {
 // pays the memory latency once per group rather than once per row.  Loads are
 // unconditional: rows past the chunk read its last row with weight 0 and
 // columns past s_eff re-read column `wave` (their sums are never stored).
-template <typename VT>
+template <typename VT, int T = 4>  // T: row loads per lane per column (a 64 T-row slab)
 __device__ __forceinline__ void ut_r_partial(const VT* __restrict__ Ub, int64_t ldu, int s_eff,
                                              const Chunk& ch, const VT* rs, double* part_out,
                                              int64_t ostride = 1) {
   constexpr int G = sizeof(VT) == 4 ? 16 : 8;  // columns in flight per lane
-  constexpr int T = 4;  // row loads per lane per column (one 256-row slab)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int len = (int)(ch.hi - ch.lo);
   const VT* base = Ub + ch.lo;
@@ -90,6 +91,33 @@ __device__ __forceinline__ void ut_r_partial(const VT* __restrict__ Ub, int64_t 
       if (g0 + jj < ncol && lane == 0) part_out[(int64_t)(wave + 4 * (g0 + jj)) * ostride] = v;
     }
   }
+}
+
+// U^T r over 64 rows [lo, lo + 64) of a chunk, accumulated into `acc`: thread t takes
+// column j = t / 2 and the 32 rows lo + 32 (t % 2) + [0, 32) (all 32 loads in flight),
+// each weighted by r from LDS (rs[0..63], zero past the chunk; rows past `hi` re-read
+// row hi - 1).  No cross-lane reduction: ut_r64_store combines the two halves.
+template <typename VT>
+__device__ __forceinline__ void ut_r64_acc(const VT* __restrict__ Ub, int64_t ldu, int s_eff,
+                                           int64_t lo, int64_t hi, const VT* rs, double& acc) {
+  const int j = threadIdx.x >> 1, half = threadIdx.x & 1;
+  if (j >= s_eff) return;
+  const VT* col = Ub + (int64_t)j * ldu;
+  VT uv[32];
+#pragma unroll
+  for (int q = 0; q < 32; ++q) {
+    const int64_t i = lo + 32 * half + q;
+    uv[q] = col[i < hi ? i : hi - 1];
+  }
+#pragma unroll
+  for (int q = 0; q < 32; ++q) acc += double(uv[q]) * double(rs[32 * half + q]);
+}
+// Partial of column j = threadIdx.x / 2: the two halves' sums added in lane order.
+__device__ __forceinline__ void ut_r64_store(int s_eff, double acc, double* part_out,
+                                             int64_t ostride) {
+  const double other = __shfl_xor(acc, 1, 64);
+  const int j = threadIdx.x >> 1;
+  if ((threadIdx.x & 1) == 0 && j < s_eff) part_out[(int64_t)j * ostride] = acc + other;
 }
 
 // Last block: w_j = sum over the nb block partials, then
@@ -186,8 +214,13 @@ template <typename VT>
 __global__ __launch_bounds__(256) void k_admm_begin(VecArgs a) {
   const int b = blockIdx.y;
   const ProbParams P = a.ctrl.params[b];
-  if (!P.run) return;
   ProbState* S = a.ctrl.state + b;
+  if (!P.run) {
+    // a problem left out of this iteration: its update flag must not open the
+    // products gated on a completed update (they would redo its last one)
+    if (blockIdx.x == 0 && threadIdx.x == 0) S->admm_done = 0;
+    return;
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     S->admm_done = 0;
     S->breakdown = 0;
@@ -195,7 +228,7 @@ __global__ __launch_bounds__(256) void k_admm_begin(VecArgs a) {
     S->cg_active = 1;
   }
   const int64_t n = a.n;
-  const Chunk ch = my_chunk(n, a.chunk);
+  const Chunk ch = my_chunk(n, a.chunkf);  // the finer grid: 64 rows per step
   const int64_t off = (int64_t)b * n;
   VT* x = static_cast<VT*>(a.x) + off;
   VT* z = static_cast<VT*>(a.z) + off;
@@ -205,37 +238,48 @@ __global__ __launch_bounds__(256) void k_admm_begin(VecArgs a) {
   const VT* c = P.use_c ? static_cast<const VT*>(a.c) + off : nullptr;
   VT* r = static_cast<VT*>(a.r) + off;
   const uint8_t* mask = a.mask ? a.mask + off : nullptr;
-  __shared__ VT rs[kVecChunk * 4];
+  const int s_eff = a.U ? a.ctrl.s_eff[b] : 0;
+  const VT* Ub = a.U ? static_cast<const VT*>(a.U) + (int64_t)b * n * a.s_stride : nullptr;
+  __shared__ VT rs[64];
   __shared__ double red[16];
   const VT rho = VT(P.rho), sig = VT(P.sigma), usc = VT(P.u_scale), l2 = VT(P.lambda2);
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  double ur = 0.0;  // this thread's share of (U^T r_0)_j, j = threadIdx.x / 2
   double rhs2 = 0.0, rr = 0.0;
-  for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) {
-    // all loads before the first store (the vectors are distinct)
-    VT ui = u[i];
-    const VT xi = x[i], zi = z[i], hi = h[i];
-    // grad f(x^k) with the l2 term; (H + sigma I) x^k with H's lambda2 I
-    const VT gi = (c ? hi - c[i] : g[i]) + l2 * xi;
-    if (P.u_scale != 1.0) {
-      ui *= usc;
-      u[i] = ui;
+  for (int64_t base = ch.lo; base < ch.hi; base += 64) {
+    const int64_t i = base + lane;
+    const bool ok = i < ch.hi;
+    if (grp == 0) {
+      VT ri = VT(0);
+      if (ok) {
+        // all loads before the first store (the vectors are distinct)
+        VT ui = u[i];
+        const VT xi = x[i], zi = z[i], hi = h[i];
+        // grad f(x^k) with the l2 term; (H + sigma I) x^k with H's lambda2 I
+        const VT gi = (c ? hi - c[i] : g[i]) + l2 * xi;
+        if (P.u_scale != 1.0) {
+          ui *= usc;
+          u[i] = ui;
+        }
+        VT rhs = hi + l2 * xi + sig * xi - gi + rho * (zi - ui);
+        ri = rho * (zi - ui - xi) - gi;
+        if (mask && !mask[i]) {
+          rhs = VT(0);
+          ri = VT(0);
+        }
+        r[i] = ri;
+        rhs2 += double(rhs) * double(rhs);
+        rr += double(ri) * double(ri);
+      }
+      rs[lane] = ri;  // zero past the chunk
     }
-    VT rhs = hi + l2 * xi + sig * xi - gi + rho * (zi - ui);
-    VT ri = rho * (zi - ui - xi) - gi;
-    if (mask && !mask[i]) {
-      rhs = VT(0);
-      ri = VT(0);
-    }
-    r[i] = ri;
-    rs[i - ch.lo] = ri;
-    rhs2 += double(rhs) * double(rhs);
-    rr += double(ri) * double(ri);
+    __syncthreads();
+    if (s_eff > 0) ut_r64_acc<VT>(Ub, n, s_eff, base, ch.hi, rs, ur);
+    __syncthreads();
   }
-  __syncthreads();
-  const int s_eff = a.U ? a.ctrl.s_eff[b] : 0;
   if (s_eff > 0)
-    ut_r_partial<VT>(static_cast<const VT*>(a.U) + (int64_t)b * n * a.s_stride, n, s_eff, ch, rs,
-                     a.ctrl.upart + (int64_t)b * kMaxS * a.ctrl.pstride + blockIdx.x,
-                     a.ctrl.pstride);
+    ut_r64_store(s_eff, ur, a.ctrl.upart + (int64_t)b * kMaxS * a.ctrl.pstride + blockIdx.x,
+                 a.ctrl.pstride);
   double v[2] = {rhs2, rr};
   block_sum<2>(v, red);
   if (threadIdx.x == 0) {
@@ -260,29 +304,37 @@ __global__ __launch_bounds__(256) void k_precond_coef(Ctrl ctrl, int nb) {
   if (threadIdx.x == 0) {
     const double* lam = ctrl.lamhat + (int64_t)b * ctrl.s_stride;
     const double lrr = lam[s_eff - 1];
-    ctrl.coef[(int64_t)b * kMaxS + j] = ((lrr + P.nu) / (lam[j] + P.nu) - 1.0) * v[0];
+    const double cj = ((lrr + P.nu) / (lam[j] + P.nu) - 1.0) * v[0];
+    ctrl.coef[(int64_t)b * 2 * kMaxS + j] = cj;
+    ctrl.coef[(int64_t)b * 2 * kMaxS + kMaxS + j] = cj * v[0];  // its share of r^T P^-1 r
   }
 }
 
-// w = P^-1 r (eq. preconditioner) and the partials of r^T w.  It first takes the
-// stopping decision of the residual it is given: init -- the x-system's set-up
+// The stopping decision for the residual it is given -- init: the x-system's set-up
 // (tolerance of the CG schedule, empty or non-finite right-hand side); else the
-// residual of CG iteration t (tolerance reached or iteration limit).
+// residual of CG iteration t (tolerance reached or iteration limit) -- then, with
+// P^-1 = I + U diag(d) U^T (eq. preconditioner) and c = d o (U^T r) from
+// precond_coef, r^T P^-1 r = ||r||^2 + sum_j c_j (U^T r)_j (every block sums the
+// same terms in the same order), beta = (r^T P^-1 r) / (the previous one) and
+// p = r + U c + beta p (init: beta = 0).  The new r^T P^-1 r goes to the parity
+// slot of the next iteration.
 template <typename VT>
-__global__ __launch_bounds__(256) void k_precond_step(VecArgs a, int t, int init) {
+__global__ __launch_bounds__(256) void k_precond_p(VecArgs a, int t, int init, int np) {
   const int b = blockIdx.y;
   const ProbParams P = a.ctrl.params[b];
   ProbState* S = a.ctrl.state + b;
   if (!block_gate_cg(P, S)) return;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   bool stop;
+  double rr;
   if (init) {
     const int sl[2] = {kSlRhs2, kSlRr};
     double tv[2];
-    reduce_slots<2>(a.ctrl, b, a.nb, sl, tv);
+    reduce_slots<2>(a.ctrl, b, np, sl, tv);
     const double trhs2 = tv[0], tr2 = tv[1];
     const bool bad = !(trhs2 <= 1.0e300) || !(tr2 <= 1.0e300);  // NaN or Inf
     stop = bad || !(tr2 > 0.0) || P.max_cg <= 0;
+    rr = tr2;
     if (lead) {
       double tol2 = P.rtol * P.rtol * (P.rhs_rel ? trhs2 : tr2);
       tol2 = fmax(tol2, P.tol_floor * P.tol_floor * trhs2);
@@ -296,8 +348,8 @@ __global__ __launch_bounds__(256) void k_precond_step(VecArgs a, int t, int init
   } else {
     const int sl[1] = {kSlRr};
     double tv[1];
-    reduce_slots<1>(a.ctrl, b, a.nb, sl, tv);
-    const double rr = tv[0];
+    reduce_slots<1>(a.ctrl, b, np, sl, tv);  // written by the CG update in use
+    rr = tv[0];
     const bool bad = !(rr <= 1.0e300);
     stop = bad || rr <= S->tol2 || t + 1 >= P.max_cg;
     if (lead) {
@@ -309,70 +361,81 @@ __global__ __launch_bounds__(256) void k_precond_step(VecArgs a, int t, int init
   }
   if (stop) return;
   const int64_t n = a.n;
-  const Chunk ch = my_chunk(n, a.chunk);
+  const Chunk ch = my_chunk(n, a.chunkf);  // the finer grid: 64 rows per step
   const int64_t off = (int64_t)b * n;
   const VT* r = static_cast<const VT*>(a.r) + off;
-  VT* w = static_cast<VT*>(a.w) + off;
-  __shared__ double cf[kMaxS];
-  __shared__ double red[16];
+  VT* p = static_cast<VT*>(a.p) + off;
+  __shared__ double cf[kMaxS];  // c_j, zero past s_eff
+  __shared__ double s_rz;
+  __shared__ double uc[4][64];
   const int s_eff = a.U ? a.ctrl.s_eff[b] : 0;
-  for (int j = threadIdx.x; j < s_eff; j += blockDim.x)
-    cf[j] = a.ctrl.coef[(int64_t)b * kMaxS + j];
-  __syncthreads();
-  const VT* Ub = a.U ? static_cast<const VT*>(a.U) + (int64_t)b * n * a.s_stride : nullptr;
-  double rz = 0.0;
-  for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) {
-    const double ri = double(r[i]);
-    double acc = ri;
-    int j = 0;
-    for (; j + 16 <= s_eff; j += 16) {  // 16 independent loads, then the adds in order
-      VT tq[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) tq[q] = Ub[(int64_t)(j + q) * n + i];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc += double(tq[q]) * cf[j + q];
-    }
-    for (; j < s_eff; ++j) acc += double(Ub[(int64_t)j * n + i]) * cf[j];
-    const VT wi = VT(acc);
-    w[i] = wi;
-    rz += ri * double(wi);
+  const double* cb = a.ctrl.coef + (int64_t)b * 2 * kMaxS;
+  __shared__ double tm[kMaxS];
+  for (int j = threadIdx.x; j < kMaxS; j += blockDim.x) {
+    cf[j] = j < s_eff ? cb[j] : 0.0;
+    tm[j] = j < s_eff ? cb[kMaxS + j] : 0.0;
   }
-  double v[1] = {rz};
-  block_sum<1>(v, red);
-  if (threadIdx.x == 0) slot_ptr(a.ctrl, b, kSlRz)[blockIdx.x] = v[0];
-}
-
-// p = w + beta p with beta = (r^T w)_new / (r^T w)_old (init: p = w).  The new
-// r^T w goes to the parity slot of the next iteration.
-template <typename VT>
-__global__ __launch_bounds__(256) void k_p_update(VecArgs a, int t, int init) {
-  const int b = blockIdx.y;
-  const ProbParams P = a.ctrl.params[b];
-  ProbState* S = a.ctrl.state + b;
-  if (!P.run || !S->cg_active) return;
-  const int sl[1] = {kSlRz};
-  double tv[1];
-  reduce_slots<1>(a.ctrl, b, a.nb, sl, tv);
-  const double rz_new = tv[0];
+  __syncthreads();
+  if (threadIdx.x < 64) {  // fixed order: lane l adds terms l and l + 64, then the wave sum
+    const double w = wave_sum(tm[threadIdx.x] + tm[threadIdx.x + 64]);
+    if (threadIdx.x == 0) s_rz = rr + w;
+  }
+  __syncthreads();
+  const double rz_new = s_rz;
   double beta = 0.0;
   if (!init) {
     const double rz_old = S->rz2[t & 1];
     beta = rz_old != 0.0 ? rz_new / rz_old : 0.0;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (lead) {
     S->rz2[init ? 0 : ((t + 1) & 1)] = rz_new;
     S->beta_cg = beta;
   }
-  const int64_t n = a.n;
-  const Chunk ch = my_chunk(n, a.chunk);
-  const int64_t off = (int64_t)b * n;
-  VT* p = static_cast<VT*>(a.p) + off;
-  const VT* w = static_cast<const VT*>(a.w) + off;
+  const VT* Ub = a.U ? static_cast<const VT*>(a.U) + (int64_t)b * n * a.s_stride : nullptr;
+  const uint8_t* mask = a.mask ? a.mask + off : nullptr;
   const VT be = VT(beta);
-  if (init) {
-    for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) p[i] = w[i];
-  } else {
-    for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += blockDim.x) p[i] = w[i] + be * p[i];
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  __shared__ double red[16];
+  double pp_on = 0.0, pp_off = 0.0;  // ||p||^2 on and off the mask (for p^T q)
+  for (int64_t base = ch.lo; base < ch.hi; base += 64) {
+    const int64_t i = base + lane;
+    const bool ok = i < ch.hi;
+    const int64_t ic = ok ? i : ch.hi - 1;
+    // (U c)_i: wave grp takes columns grp, grp + 4, ..., all its loads in flight at once
+    // (columns past s_eff re-read the last one with weight 0)
+    if (s_eff > 0) {
+      constexpr int NJ = kMaxS / 4;
+      VT uv[NJ];
+#pragma unroll
+      for (int jj = 0; jj < NJ; ++jj) {
+        const int j = min(grp + 4 * jj, s_eff - 1);
+        uv[jj] = Ub[(int64_t)j * n + ic];
+      }
+      double acc = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < NJ; ++jj) acc += double(uv[jj]) * cf[grp + 4 * jj];
+      uc[grp][lane] = acc;
+    }
+    __syncthreads();
+    if (grp == 0 && ok) {
+      double acc = double(r[i]);
+      if (s_eff > 0) acc += ((uc[0][lane] + uc[1][lane]) + uc[2][lane]) + uc[3][lane];
+      const VT wi = VT(acc);
+      const VT pi = init ? wi : wi + be * p[i];
+      p[i] = pi;
+      const double p2 = double(pi) * double(pi);
+      if (mask && !mask[i])
+        pp_off += p2;
+      else
+        pp_on += p2;
+    }
+    __syncthreads();
+  }
+  double v[2] = {pp_on, pp_off};
+  block_sum<2>(v, red);
+  if (threadIdx.x == 0) {
+    slot_ptr(a.ctrl, b, kSlPp)[blockIdx.x] = v[0];
+    slot_ptr(a.ctrl, b, kSlPpOff)[blockIdx.x] = v[1];
   }
 }
 
@@ -492,6 +555,121 @@ __global__ __launch_bounds__(256) void k_cg_update(VecArgs a, int t) {
     ut_r_partial<VT>(static_cast<const VT*>(a.U) + (int64_t)b * n * a.s_stride, n, s_eff, ch, rs,
                      a.ctrl.upart + (int64_t)b * kMaxS * a.ctrl.pstride + blockIdx.x,
                      a.ctrl.pstride);
+  double v[1] = {rr};
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) slot_ptr(a.ctrl, b, kSlRr)[blockIdx.x] = v[0];
+}
+
+// CG iteration t after the fused product (one pass over A, which also left per block
+// the sum over its rows of d_i (a_i^T p)^2): p^T q = p^T H p + nu ||p||^2 (masked
+// coordinates: q = p) from those partials and precond_p's ||p||^2 partials, every
+// block summing them in the same order; alpha = (r^T P^-1 r)_t / p^T q; then, 64
+// elements per step with the four waves splitting the product's block partials,
+// hp = H p, x += alpha p, h += alpha hp (h tracks H x), r -= alpha q, and the
+// partials of ||r||^2 and U^T r over the block's chunk.  It replaces cg_alpha and
+// cg_update (hp is never stored) on the finer grid.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_cg_step(VecArgs a, int t) {
+  const int b = blockIdx.y;
+  const ProbParams P = a.ctrl.params[b];
+  ProbState* S = a.ctrl.state + b;
+  if (!block_gate_cg(P, S)) return;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  __shared__ double red[16];
+  __shared__ double bc[3];
+  {
+    double v[3] = {0.0, 0.0, 0.0};
+    const double* hq = a.hpq + (int64_t)b * a.hpq_stride;
+    for (int k = threadIdx.x; k < a.nhpq; k += blockDim.x) v[0] += hq[k];
+    const double* s_on = slot_ptr(a.ctrl, b, kSlPp);
+    const double* s_off = slot_ptr(a.ctrl, b, kSlPpOff);
+    for (int k = threadIdx.x; k < a.nbf; k += blockDim.x) {  // written by precond_p
+      v[1] += s_on[k];
+      v[2] += s_off[k];
+    }
+    block_sum<3>(v, red);
+    if (threadIdx.x == 0) {
+      bc[0] = v[0];
+      bc[1] = v[1];
+      bc[2] = v[2];
+    }
+    __syncthreads();
+  }
+  const double pq = (bc[0] + P.nu * bc[1]) + bc[2];
+  if (!(pq > 0.0) || !(pq <= 1.0e300)) {  // not positive definite along p, or non-finite
+    if (lead) {
+      S->pq = pq;
+      S->alpha_cg = 0.0;
+      S->breakdown = 1;
+      S->cg_active = 0;
+    }
+    return;
+  }
+  const double alpha = S->rz2[t & 1] / pq;
+  if (lead) {
+    S->pq = pq;
+    S->alpha_cg = alpha;
+  }
+  const int64_t n = a.n;
+  const Chunk ch = my_chunk(n, a.chunkf);
+  const int64_t off = (int64_t)b * n;
+  VT* x = static_cast<VT*>(a.x) + off;
+  VT* h = static_cast<VT*>(a.h) + off;
+  VT* r = static_cast<VT*>(a.r) + off;
+  const VT* p = static_cast<const VT*>(a.p) + off;
+  const VT* yp = static_cast<const VT*>(a.ypart) + (int64_t)b * a.ypart_prob_stride;
+  const uint8_t* mask = a.mask ? a.mask + off : nullptr;
+  const int s_eff = a.U ? a.ctrl.s_eff[b] : 0;
+  const VT* Ub = a.U ? static_cast<const VT*>(a.U) + (int64_t)b * n * a.s_stride : nullptr;
+  __shared__ VT sums[4][64];
+  __shared__ VT rs[64];
+  const VT al = VT(alpha), nu = VT(P.nu);
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t kst = a.ypart_ks_stride;
+  constexpr int KB = 32;  // partial slots in flight per lane
+  double ur = 0.0;        // this thread's share of (U^T r)_j, j = threadIdx.x / 2
+  double rr = 0.0;
+  for (int64_t base = ch.lo; base < ch.hi; base += 64) {
+    const int64_t i = base + lane;
+    const bool ok = i < ch.hi;
+    const int64_t ic = ok ? i : ch.hi - 1;
+    // hp_i: wave grp sums the partial slots grp, grp + 4, ..., KB loads in flight
+    VT sacc = VT(0);
+    for (int k0 = grp; k0 < a.ksplit; k0 += 4 * KB) {
+      VT tq[KB];
+#pragma unroll
+      for (int q = 0; q < KB; ++q) {
+        const int k = k0 + 4 * q;
+        tq[q] = yp[(int64_t)(k < a.ksplit ? k : grp) * kst + ic];
+      }
+#pragma unroll
+      for (int q = 0; q < KB; ++q)
+        if (k0 + 4 * q < a.ksplit) sacc += tq[q];
+    }
+    sums[grp][lane] = sacc;
+    __syncthreads();
+    if (grp == 0) {
+      VT ri = VT(0);
+      if (ok) {
+        const VT hpi = ((sums[0][lane] + sums[1][lane]) + sums[2][lane]) + sums[3][lane];
+        const VT pi = p[i], xi = x[i], hi = h[i], r0 = r[i];
+        const bool on = !(mask && !mask[i]);
+        const VT q = on ? hpi + nu * pi : pi;
+        x[i] = xi + al * pi;
+        if (on) h[i] = hi + al * hpi;
+        ri = r0 - al * q;
+        r[i] = ri;
+        rr += double(ri) * double(ri);
+      }
+      rs[lane] = ri;  // zero past the chunk
+    }
+    __syncthreads();
+    if (s_eff > 0) ut_r64_acc<VT>(Ub, n, s_eff, base, ch.hi, rs, ur);
+    __syncthreads();
+  }
+  if (s_eff > 0)
+    ut_r64_store(s_eff, ur, a.ctrl.upart + (int64_t)b * kMaxS * a.ctrl.pstride + blockIdx.x,
+                 a.ctrl.pstride);
   double v[1] = {rr};
   block_sum<1>(v, red);
   if (threadIdx.x == 0) slot_ptr(a.ctrl, b, kSlRr)[blockIdx.x] = v[0];
@@ -790,18 +968,40 @@ static bool vec_geometry_ok(const VecArgs& a) {
 
 hipError_t launch_admm_begin(const VecArgs& a, hipStream_t st) {
   GENIOS_VEC_CHECK();
-  GENIOS_VEC_LAUNCH(k_admm_begin);
-}
-hipError_t launch_precond_coef(const VecArgs& a, hipStream_t st) {
-  GENIOS_VEC_CHECK();
-  if (a.U == nullptr) return hipSuccess;
-  hipLaunchKernelGGL(k_precond_coef, dim3((unsigned)kMaxS, (unsigned)a.batch), dim3(256), 0, st,
-                     a.ctrl, a.nb);
+  dim3 grid((unsigned)a.nbf, (unsigned)a.batch);  // the finer grid
+  if (a.vt == VT_F32)
+    hipLaunchKernelGGL(k_admm_begin<float>, grid, dim3(kVecBlock), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_admm_begin<double>, grid, dim3(kVecBlock), 0, st, a);
   return hipGetLastError();
 }
-hipError_t launch_precond_step(const VecArgs& a, int t, int init, hipStream_t st) {
+hipError_t launch_precond_coef(const VecArgs& a, int np, hipStream_t st) {
   GENIOS_VEC_CHECK();
-  GENIOS_VEC_LAUNCH(k_precond_step, t, init);
+  if (np < 1 || np > a.ctrl.pstride) return hipErrorInvalidValue;
+  if (a.U == nullptr) return hipSuccess;
+  hipLaunchKernelGGL(k_precond_coef, dim3((unsigned)kMaxS, (unsigned)a.batch), dim3(256), 0, st,
+                     a.ctrl, np);
+  return hipGetLastError();
+}
+hipError_t launch_precond_p(const VecArgs& a, int t, int init, int np, hipStream_t st) {
+  GENIOS_VEC_CHECK();
+  if (np < 1 || np > a.ctrl.pstride) return hipErrorInvalidValue;
+  dim3 grid((unsigned)a.nbf, (unsigned)a.batch);  // the finer grid
+  if (a.vt == VT_F32)
+    hipLaunchKernelGGL(k_precond_p<float>, grid, dim3(kVecBlock), 0, st, a, t, init, np);
+  else
+    hipLaunchKernelGGL(k_precond_p<double>, grid, dim3(kVecBlock), 0, st, a, t, init, np);
+  return hipGetLastError();
+}
+hipError_t launch_cg_step(const VecArgs& a, int t, hipStream_t st) {
+  GENIOS_VEC_CHECK();
+  if (a.hpq == nullptr || a.nhpq < 1 || a.nhpq > a.hpq_stride) return hipErrorInvalidValue;
+  dim3 grid((unsigned)a.nbf, (unsigned)a.batch);  // the finer grid
+  if (a.vt == VT_F32)
+    hipLaunchKernelGGL(k_cg_step<float>, grid, dim3(kVecBlock), 0, st, a, t);
+  else
+    hipLaunchKernelGGL(k_cg_step<double>, grid, dim3(kVecBlock), 0, st, a, t);
+  return hipGetLastError();
 }
 hipError_t launch_cg_alpha(const VecArgs& a, hipStream_t st) {
   GENIOS_VEC_CHECK();
@@ -815,10 +1015,6 @@ hipError_t launch_cg_alpha(const VecArgs& a, hipStream_t st) {
 hipError_t launch_cg_update(const VecArgs& a, int t, hipStream_t st) {
   GENIOS_VEC_CHECK();
   GENIOS_VEC_LAUNCH(k_cg_update, t);
-}
-hipError_t launch_p_update(const VecArgs& a, int t, int init, hipStream_t st) {
-  GENIOS_VEC_CHECK();
-  GENIOS_VEC_LAUNCH(k_p_update, t, init);
 }
 hipError_t launch_admm_end(const VecArgs& a, hipStream_t st) {
   GENIOS_VEC_CHECK();

@@ -89,7 +89,7 @@ void Layout::carve(Arena& ar) {
   ctrl.params = static_cast<ProbParams*>(ar.take(B * sizeof(ProbParams)));
   ctrl.state = static_cast<ProbState*>(ar.take(B * sizeof(ProbState)));
   ctrl.counters = static_cast<unsigned*>(ar.take(B * kNumCounters * sizeof(unsigned)));
-  ctrl.coef = static_cast<double*>(ar.take(B * kMaxS * sizeof(double)));
+  ctrl.coef = static_cast<double*>(ar.take(B * 2 * kMaxS * sizeof(double)));
   ctrl.s_eff = static_cast<int32_t*>(ar.take(B * sizeof(int32_t)));
   ctrl.lamhat = static_cast<double*>(ar.take(B * std::max(1, s) * sizeof(double)));
   ctrl.s_stride = std::max(1, s);
@@ -107,6 +107,7 @@ void Layout::carve(Arena& ar) {
   for (int k = 0; k < kNumNVec; ++k) nv[k] = n_vecs > k ? vec(n) : nullptr;
   tparts = ar.take((size_t)B * nsplit_n * m * ve);
   ypart = ar.take((size_t)B * yprob() * ve);
+  hpq = static_cast<double*>(ar.take((size_t)B * yslots * sizeof(double)));
   if (gap) {
     gapf = vec(m);
     gaps = vec(m);
@@ -179,9 +180,10 @@ int Layout::setup(int op_, const genios_matrix* A, const genios_opts* o, int s_)
                      op == GENIOS_OP_BACKWARD || op == GENIOS_OP_HVP;
   yslots = std::max<int64_t>((int64_t)ksplit * (ml ? 2 : 1),
                              cg_op ? std::max<int64_t>(1, kHvpMaxBlocks / batch) : 1);
-  if (cg_op && batch > 1 && vt == VT_F32) {
+  if (cg_op && op != GENIOS_OP_HVP && batch > 1 && vt == VT_F32) {
     // room for one problem's whole-chip grid of the fused H p, used once few problems
-    // of the batch still run (bounded: at most 2 GiB of partials over the batch)
+    // of the batch still run (bounded: at most 2 GiB of partials over the batch); only
+    // the gated products of a CG loop take that shape, so a lone H p reserves none
     int64_t g1 = hvp_geometry(probe, 1, false).blocks;
     if (uses_lo) g1 = std::max<int64_t>(g1, hvp_geometry(probe_lo, 1, false).blocks);
     const int64_t budget = ((int64_t)1 << 31) / (batch * ((n + 7) / 8 * 8) * (int64_t)sizeof(float));
@@ -327,6 +329,12 @@ struct Ctx {
   KernelProf prof;
   int64_t n_mv[4] = {0, 0, 0, 0};
   int64_t n_mrhs = 0, bytes_mrhs = 0;  // H p launches of a batch sharing A (all problems at once)
+  // fused H p launch shapes used once part of a batch has stopped: one whole-chip launch
+  // per running problem (counted per problem), and the batch grid sized for the running
+  // count (counted per launch)
+  int64_t n_tail = 0, n_resized = 0;
+  // the last product was the fused one, so L.hpq holds its per-block p^T H p partials
+  bool pq_rows = false;
   // problems taking part in the coming kernels (set with the parameters; -1: all)
   std::vector<char> run_flags;
   int64_t running = -1;
@@ -462,6 +470,7 @@ struct Ctx {
                          static_cast<const float*>(d), m, L.mr,
                          static_cast<float*>(L.ypart), L.npad, gate, gstride, st));
       HC(prof.end(st));
+      pq_rows = false;
       cur_ks = op.mt == MT_F32 ? L.mr.ksYf : L.mr.ksY;
       cur_ks_stride = (int64_t)L.mr.sp * L.npad;
       cur_prob_stride = L.npad;
@@ -491,9 +500,12 @@ struct Ctx {
             HC(launch_hvp_fused(ob, g1, 1, static_cast<const float*>(p) + b * n, n,
                                 d ? static_cast<const float*>(d) + b * m : nullptr, m,
                                 static_cast<float*>(L.ypart) + b * L.yprob(), L.npad, L.yprob(),
-                                gate ? gate + b * gstride : nullptr, gstride, st));
+                                gate ? gate + b * gstride : nullptr, gstride, st,
+                                L.hpq + b * L.yslots, L.yslots));
           }
           HC(prof.end(st));
+          pq_rows = true;
+          for (int64_t b = 0; b < B; ++b) n_tail += run_flags[b] ? 1 : 0;
           cur_ks = g1.blocks;
           cur_ks_stride = L.npad;
           account(op, hvp_kind(op));
@@ -514,8 +526,10 @@ struct Ctx {
         HC(prof.begin(st, hvp_kind(op)));
         HC(launch_hvp_fused(op, gb, B, static_cast<const float*>(p), n,
                             static_cast<const float*>(d), m, static_cast<float*>(L.ypart), L.npad,
-                            L.yprob(), gate, gstride, st));
+                            L.yprob(), gate, gstride, st, L.hpq, L.yslots));
         HC(prof.end(st));
+        pq_rows = true;
+        if (&gb == &gr) n_resized += 1;
         cur_ks = gb.blocks;
         cur_ks_stride = L.npad;
         account(op, hvp_kind(op));
@@ -526,6 +540,7 @@ struct Ctx {
     }
     last_hvp_kind = 0;
     last_hvp_op = op;
+    pq_rows = false;
     int rc = gemv_n(op, p, gate, gstride);
     if (rc) return rc;
     return gemv_t_from_t(op, d, gate, gstride, nsplit_for(op, 0));
@@ -606,19 +621,26 @@ hipError_t upload_params(Ctx& c, ProbParams* hp) {
 // The x-system set-up up to the first search direction (kernels gated on run).
 int cg_setup(Ctx& c, const VecArgs& va) {
   HC(launch_admm_begin(va, c.st));
-  HC(launch_precond_coef(va, c.st));
-  HC(launch_precond_step(va, 0, 1, c.st));
-  HC(launch_p_update(va, 0, 1, c.st));
+  HC(launch_precond_coef(va, va.nbf, c.st));
+  HC(launch_precond_p(va, 0, 1, va.nbf, c.st));
   return 0;
 }
 
-// The vector part of CG iteration t (kernels gated on cg_active).
-int cg_vector_step(Ctx& c, const VecArgs& a, int t) {
-  HC(launch_cg_alpha(a, c.st));
-  HC(launch_cg_update(a, t, c.st));
-  HC(launch_precond_coef(a, c.st));
-  HC(launch_precond_step(a, t, 0, c.st));
-  HC(launch_p_update(a, t, 0, c.st));
+// The vector part of CG iteration t (kernels gated on cg_active).  After the fused
+// product (pq_rows: its per-block p^T H p partials are in a.hpq) one kernel takes the
+// step; after the others hp is summed first.
+int cg_vector_step(Ctx& c, const VecArgs& a, int t, bool pq_rows) {
+  int np;
+  if (pq_rows) {
+    HC(launch_cg_step(a, t, c.st));
+    np = a.nbf;
+  } else {
+    HC(launch_cg_alpha(a, c.st));
+    HC(launch_cg_update(a, t, c.st));
+    np = a.nb;
+  }
+  HC(launch_precond_coef(a, np, c.st));
+  HC(launch_precond_p(a, t, 0, np, c.st));
   return 0;
 }
 
@@ -630,7 +652,10 @@ int cg_iteration(Ctx& c, const MatArg& op, const VecArgs& va, const void* dscale
   a.ksplit = c.cur_ks;
   a.ypart_ks_stride = c.cur_ks_stride;
   a.ypart_prob_stride = c.cur_prob_stride;
-  return cg_vector_step(c, a, t);
+  a.hpq = c.L.hpq;
+  a.hpq_stride = c.L.yslots;
+  a.nhpq = c.cur_ks;
+  return cg_vector_step(c, a, t, c.pq_rows);
 }
 
 }  // namespace
@@ -665,6 +690,10 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
   c.prof.on = o->profile_kernels != 0;
   const int prec = o->precision;
   const bool use_lo = prec == GENIOS_PREC_BF16_REFINE || prec == GENIOS_PREC_BF16_ONLY;
+  // After the switch to the master copy, CG may keep the BF16 copy as the x-system's
+  // Hessian model while the master copy forms H x (the gradient) once per iteration
+  // (squared loss only: the curvature-weighted losses keep master-copy CG).
+  const bool lo_cg = prec == GENIOS_PREC_BF16_REFINE && o->refine_cg_bf16 != 0 && !ml;
   c.op_hi = MatArg{A->A_hi, c.vt == VT_F64 ? MT_F64 : MT_F32, A->m, A->n, A->lda, A->stride_A};
   c.op_lo = MatArg{A->A_bf16 ? (const void*)A->A_bf16 : (const void*)c.L.A16, MT_BF16, A->m, A->n,
                    A->lda, A->stride_A};
@@ -994,15 +1023,25 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
       if (!P[b].done) chunk = std::max(chunk, P[b].last_cg);
     chunk = std::min(chunk, o->max_cg_iter);
     int enq = 0;
+    const MatArg* cgop = (phase == 1 && lo_cg) ? &c.op_lo : op;
     for (;;) {
       for (int it = 0; it < chunk; ++it) {
-        rc = cg_iteration(c, *op, va, ml ? c.L.dvec : nullptr, enq + it);
+        rc = cg_iteration(c, *cgop, va, ml ? c.L.dvec : nullptr, enq + it);
         if (rc) return rc;
       }
       enq += chunk;
       HC(hipEventRecord(tm.ev[1], c.st));
       HC(launch_admm_end(va, c.st));
       HC(launch_admm_finish(va, c.st));
+      if (cgop != op) {
+        // CG ran on the BF16 model: H x at the new x with the master copy (gated on
+        // the completed update), then r_d from it -- the right-hand side of the next
+        // iteration and the stopping test are the master copy's
+        rc = hvp_explicit(c, *op, x, h, nullptr, c.gate_done, c.gs_state);
+        if (rc) return rc;
+        VecArgs vr = va;
+        HC(launch_dual_residual(vr, c.st));
+      }
       if (ml) {
         // gradient pass at the new x (gated on the completed update)
         rc = gradient_pass(*op, c.gate_done, c.gs_state);
@@ -1131,7 +1170,9 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     if (any_certify) {
       for (int64_t b = 0; b < B; ++b) hp[b].run = want_cert[b];
       HC(upload_params(c, hp));
-      if (!ml) {
+      // (with BF16-model CG after the switch, h and r_d are already the master copy's)
+      const bool rd_fresh = phase == 1 && lo_cg;
+      if (!ml && !rd_fresh) {
         rc = hvp_explicit(c, *op, x, h, nullptr, c.gate_run, c.gs_params);
         if (rc) return rc;
         VecArgs vr = c.vargs(x, z, u, h, g, phase == 0 ? c_lo : c_hi, nullptr);
@@ -1257,6 +1298,8 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     I.t_hvp_mrhs = c.prof.t[6];
     I.n_hvp_mrhs = (int32_t)c.n_mrhs;
     I.bytes_hvp_mrhs = c.bytes_mrhs;
+    I.n_hvp_tail = (int32_t)c.n_tail;
+    I.n_hvp_resized = (int32_t)c.n_resized;
     I.rho = q.rho;
     I.r_p = q.rp;
     I.r_d = q.rd;
@@ -1567,10 +1610,14 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
       HC(c.prof.begin(c.st, Ctx::hvp_kind(opS)));
       HC(launch_hvp_fused(opS, gS, B, static_cast<const float*>(va.p), ldS, nullptr, 0,
                           static_cast<float*>(c.L.ypart), ldS, va.ypart_prob_stride, c.gate_cg,
-                          c.gs_state, c.st));
+                          c.gs_state, c.st, c.L.hpq, c.L.yslots));
       HC(c.prof.end(c.st));
       c.account(opS, Ctx::hvp_kind(opS));
-      return cg_vector_step(c, va, t_cg++);
+      VecArgs vq = va;
+      vq.hpq = c.L.hpq;
+      vq.hpq_stride = c.L.yslots;
+      vq.nhpq = gS.blocks;
+      return cg_vector_step(c, vq, t_cg++, true);
     }
     HC(c.prof.begin(c.st, 0));
     HC(launch_gemv_n(opS, B, c.vt, va.p, ldS, c.L.tparts, m, (int64_t)c.L.nsplit_n * m, nsS,
@@ -1582,7 +1629,7 @@ int run_backward(const genios_matrix* A, const void* zstar, const void* gz, cons
                      c.L.ypart, ksS, ldS, ldS, (int64_t)ksS * ldS, c.gate_cg, c.gs_state, c.st));
     HC(c.prof.end(c.st));
     c.account(opS, 1);
-    return cg_vector_step(c, va, t_cg++);
+    return cg_vector_step(c, va, t_cg++, false);
   };
   for (;;) {
     for (int it = 0; it < 8; ++it) {

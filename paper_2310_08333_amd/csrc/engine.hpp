@@ -50,6 +50,7 @@ struct Layout {
   void* nv[kNumNVec] = {};
   void* tparts = nullptr;
   void* ypart = nullptr;
+  double* hpq = nullptr;  // [batch][yslots] per-block p^T H p partials of the fused product
   void* dvec = nullptr;
   void* cols = nullptr;
   uint8_t* mask = nullptr;

@@ -407,7 +407,8 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
     const T* __restrict__ A, int64_t lda, int64_t strideA, int m, int n,
     const float* __restrict__ p, int64_t p_stride, const float* __restrict__ d, int64_t d_stride,
     float* __restrict__ ypart, int64_t ks_stride, int64_t prob_stride, int rows_per_block,
-    const int32_t* __restrict__ gate, int gate_stride) {
+    const int32_t* __restrict__ gate, int gate_stride, double* __restrict__ pqpart,
+    int64_t pq_stride) {
   static_assert(D >= 0 && D <= 2, "prefetch depth 0..2");
   constexpr int V = Elem<T>::V;
   constexpr int NC = EPT / V;
@@ -451,6 +452,8 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
 #pragma unroll
     for (int e = 0; e < V; ++e) y[k][e] = 0.f;
   int par = 0;
+  // p^T H p of the block's rows, sum of d_i (a_i^T p)^2 (the same value in every thread)
+  double pq = 0.0;
   // one row: dot with p, block reduction, scale, rank-one update of the owned columns
   auto process = [&](RT (&cur)[NC], int r) {
     float s = 0.f;
@@ -472,7 +475,9 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
     float t = 0.f;
 #pragma unroll
     for (int w = 0; w < W; ++w) t += red[par][w];
+    const float traw = t;
     if (db) t *= db[__builtin_amdgcn_readfirstlane(r)];  // uniform: a scalar load
+    pq = fma(double(traw), double(t), pq);
     par ^= 1;
 #pragma unroll
     for (int k = 0; k < NC; ++k)
@@ -540,6 +545,7 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
       if (r + 2 < r1) process(b2, r + 2);
     }
   }
+  if (pqpart != nullptr && tid == 0) pqpart[(int64_t)b * pq_stride + blockIdx.x] = pq;
   float* yb = ypart + (int64_t)b * prob_stride + (int64_t)blockIdx.x * ks_stride;
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
@@ -562,8 +568,17 @@ __global__ __launch_bounds__(256) void k_sum_splits(int64_t len, const VT* __res
   if (gate != nullptr && gate[(int64_t)b * gate_stride] == 0) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
        i += (int64_t)gridDim.x * blockDim.x) {
+    const VT* src = in + (int64_t)b * psi + i;
     VT s = VT(0);
-    for (int k = 0; k < nsplit; ++k) s += in[(int64_t)b * psi + (int64_t)k * split_stride + i];
+    int k = 0;
+    for (; k + 16 <= nsplit; k += 16) {  // 16 loads in flight, then the adds in order
+      VT tq[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) tq[q] = src[(int64_t)(k + q) * split_stride];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) s += tq[q];
+    }
+    for (; k < nsplit; ++k) s += src[(int64_t)k * split_stride];
     out[(int64_t)b * pso + i] = s;
   }
 }
@@ -665,7 +680,7 @@ template <typename T, int THREADS, int EPT, int D>
 hipError_t hvp_launch_one(const MatArg& A, const HvpGeom& g, int64_t batch, const float* p,
                           int64_t p_stride, const float* d, int64_t d_stride, float* ypart,
                           int64_t ks_stride, int64_t prob_stride, const int32_t* gate,
-                          int gate_stride, hipStream_t st) {
+                          int gate_stride, double* pq, int64_t pq_stride, hipStream_t st) {
   auto* fn = &k_hvp_fused<T, THREADS, EPT, D>;
   const size_t lds = (size_t)A.n * sizeof(float);
   static bool big_lds = false;  // the attribute is set once per instantiation
@@ -678,7 +693,7 @@ hipError_t hvp_launch_one(const MatArg& A, const HvpGeom& g, int64_t batch, cons
   hipLaunchKernelGGL(fn, dim3((unsigned)g.blocks, (unsigned)batch), dim3(THREADS), lds, st,
                      static_cast<const T*>(A.ptr), A.lda, A.strideA, (int)A.m, (int)A.n, p,
                      p_stride, d, d_stride, ypart, ks_stride, prob_stride, g.rows_per_block, gate,
-                     gate_stride);
+                     gate_stride, pq, pq_stride);
   return hipGetLastError();
 }
 
@@ -695,14 +710,14 @@ template <typename T, int THREADS, int... E>
 hipError_t hvp_dispatch(int ept, const MatArg& A, const HvpGeom& g, int64_t batch, const float* p,
                         int64_t p_stride, const float* d, int64_t d_stride, float* ypart,
                         int64_t ks_stride, int64_t prob_stride, const int32_t* gate,
-                        int gate_stride, hipStream_t st) {
+                        int gate_stride, double* pq, int64_t pq_stride, hipStream_t st) {
   hipError_t r = hipErrorInvalidValue;
   bool hit = false;
   ((ept == E && !hit
         ? (hit = true,
            r = hvp_launch_one<T, THREADS, E, hvp_depth<T, THREADS, E>()>(
                A, g, batch, p, p_stride, d, d_stride, ypart, ks_stride, prob_stride, gate,
-               gate_stride, st))
+               gate_stride, pq, pq_stride, st))
         : r),
    ...);
   return r;
@@ -768,7 +783,7 @@ HvpGeom hvp_geometry(const MatArg& A, int64_t batch, bool query_device) {
 hipError_t launch_hvp_fused(const MatArg& A, const HvpGeom& g, int64_t batch, const float* p,
                             int64_t p_stride, const float* d, int64_t d_stride, float* ypart,
                             int64_t ks_stride, int64_t prob_stride, const int32_t* gate,
-                            int gate_stride, hipStream_t st) {
+                            int gate_stride, hipStream_t st, double* pq, int64_t pq_stride) {
   if (g.threads == 0 || g.blocks < 1 || g.blocks > kHvpMaxBlocks ||
       (int64_t)g.blocks * g.rows_per_block < A.m ||
       (int64_t)(g.blocks - 1) * g.rows_per_block >= A.m || ks_stride < A.n ||  // no empty block
@@ -778,25 +793,25 @@ hipError_t launch_hvp_fused(const MatArg& A, const HvpGeom& g, int64_t batch, co
     if (g.threads == 256)
       return hvp_dispatch<uint16_t, 256, 8, 16, 24, 32>(g.ept, A, g, batch, p, p_stride, d,
                                                            d_stride, ypart, ks_stride, prob_stride,
-                                                           gate, gate_stride, st);
+                                                           gate, gate_stride, pq, pq_stride, st);
     if (g.threads == 1024)
       return hvp_dispatch<uint16_t, 1024, 8, 16, 24, 32>(g.ept, A, g, batch, p, p_stride, d,
                                                          d_stride, ypart, ks_stride, prob_stride,
-                                                         gate, gate_stride, st);
+                                                         gate, gate_stride, pq, pq_stride, st);
     return hvp_dispatch<uint16_t, 512, 72, 80>(g.ept, A, g, batch, p, p_stride, d, d_stride, ypart,
-                                               ks_stride, prob_stride, gate, gate_stride, st);
+                                               ks_stride, prob_stride, gate, gate_stride, pq, pq_stride, st);
   }
   if (A.mt == MT_F32) {
     if (g.threads == 256)
       return hvp_dispatch<float, 256, 4, 8, 12, 16>(g.ept, A, g, batch, p, p_stride, d,
                                                        d_stride, ypart, ks_stride, prob_stride,
-                                                       gate, gate_stride, st);
+                                                       gate, gate_stride, pq, pq_stride, st);
     if (g.threads == 1024)
       return hvp_dispatch<float, 1024, 4, 8, 12, 16, 20, 24, 28, 32, 36, 40>(
           g.ept, A, g, batch, p, p_stride, d, d_stride, ypart, ks_stride, prob_stride, gate,
-          gate_stride, st);
+          gate_stride, pq, pq_stride, st);
     return hvp_dispatch<float, 512, 76, 80>(g.ept, A, g, batch, p, p_stride, d, d_stride, ypart,
-                                        ks_stride, prob_stride, gate, gate_stride, st);
+                                        ks_stride, prob_stride, gate, gate_stride, pq, pq_stride, st);
   }
   return hipErrorInvalidValue;
 }

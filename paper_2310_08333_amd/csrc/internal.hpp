@@ -107,6 +107,8 @@ enum {
   kSlPq,         // p^T (H + nu I) p
   kSlEnd0,       // the 7 reductions of admm_end (kRedRp2 .. kRedNnz order)
   kSlDual = kSlEnd0 + 7,  // ||grad + rho u||^2
+  kSlPp,         // ||p||^2 where the operator is H + nu I (every coordinate unless masked)
+  kSlPpOff,      // ||p||^2 where it is the identity (masked-off coordinates)
   kNumSlots
 };
 
@@ -126,7 +128,8 @@ struct Ctrl {
   double* upart;        // [batch][kMaxS][pstride] U^T r block partials (column-major)
   int64_t pstride;      // blocks reserved per slot (>= blocks of any vector kernel)
   unsigned* counters;   // [batch][kNumCounters]
-  double* coef;         // [batch][kMaxS] preconditioner coefficients of the current r
+  double* coef;         // [batch][2 kMaxS] preconditioner coefficients c_j of the current r,
+                        // then their terms c_j (U^T r)_j of r^T P^-1 r
   int32_t* s_eff;       // [batch] retained sketch rank
   double* lamhat;       // [batch][s] (s = sketch stride)
   int32_t s_stride;     // lamhat stride per problem
@@ -166,10 +169,13 @@ struct HvpGeom {
 HvpGeom hvp_geometry(const MatArg& A, int64_t batch, bool query_device);
 // the fused product reads p in 16-byte pieces
 bool hvp_p_aligned(const void* p, int64_t p_stride, int64_t batch);
+// pq (nullable): per block, the sum over its rows of d_i (a_i^T p)^2 (= p^T H p of the
+// block's rows), at pq[b * pq_stride + block].
 hipError_t launch_hvp_fused(const MatArg& A, const HvpGeom& g, int64_t batch, const float* p,
                             int64_t p_stride, const float* d, int64_t d_stride, float* ypart,
                             int64_t ks_stride, int64_t prob_stride, const int32_t* gate,
-                            int gate_stride, hipStream_t st);
+                            int gate_stride, hipStream_t st, double* pq = nullptr,
+                            int64_t pq_stride = 0);
 int gemv_n_splits(const MatArg& A, int64_t batch);
 int gemv_t_splits(const MatArg& A, int64_t batch);
 int gemv_t_rows_per_split(const MatArg& A, int ksplit);
@@ -206,17 +212,24 @@ struct VecArgs {
   int64_t ypart_ks_stride, ypart_prob_stride;
   const uint8_t* mask;    // masked operator (adjoint): 1 = in the active set
   const void *lo, *hi;    // box bounds of kProxBox, n per problem (nullable: unbounded side)
+  // the fused product's per-block p^T H p partials (cg_step): hpq[b * hpq_stride + k],
+  // k < nhpq
+  const double* hpq;
+  int64_t hpq_stride;
+  int nhpq;
 };
-// One x-solve: admm_begin; precond_coef, precond_step(init), p_update(init); then
-// per CG iteration t = 0, 1, ...: cg_alpha, cg_update(t), precond_coef,
-// precond_step(t), p_update(t); then admm_end, admm_finish.  Every kernel is gated
-// on the problem's flags, so surplus iterations are no-ops.
+// One x-solve: admm_begin; precond_coef, precond_p(init); then per CG iteration
+// t = 0, 1, ...: after the fused product cg_step(t), after the others cg_alpha and
+// cg_update(t); then precond_coef, precond_p(t); then admm_end, admm_finish.  np:
+// the partial blocks of the kernel that wrote ||r||^2 and U^T r (nb: cg_update;
+// nbf: admm_begin, cg_step).  Every kernel is gated on the problem's flags, so
+// surplus iterations are no-ops.
 hipError_t launch_admm_begin(const VecArgs& a, hipStream_t st);
-hipError_t launch_precond_coef(const VecArgs& a, hipStream_t st);
-hipError_t launch_precond_step(const VecArgs& a, int t, int init, hipStream_t st);
+hipError_t launch_precond_coef(const VecArgs& a, int np, hipStream_t st);
+hipError_t launch_precond_p(const VecArgs& a, int t, int init, int np, hipStream_t st);
 hipError_t launch_cg_alpha(const VecArgs& a, hipStream_t st);
 hipError_t launch_cg_update(const VecArgs& a, int t, hipStream_t st);
-hipError_t launch_p_update(const VecArgs& a, int t, int init, hipStream_t st);
+hipError_t launch_cg_step(const VecArgs& a, int t, hipStream_t st);
 hipError_t launch_admm_end(const VecArgs& a, hipStream_t st);
 hipError_t launch_admm_finish(const VecArgs& a, hipStream_t st);
 // ||g + rho u||^2 into state.red[kRedRd2] with g = h - c or the given g (two kernels).

@@ -612,7 +612,7 @@ constexpr int kCoreLdsMaxS = 100;
 constexpr int kCoreThreads = 1024;
 
 __global__ __launch_bounds__(kCoreThreads) void k_nystrom_core_lds(
-    int s, double eps, double rel_floor, const double* __restrict__ gram, int SPg,
+    int s, double eps, double rel_floor, double jac_tol, const double* __restrict__ gram, int SPg,
     double* __restrict__ core, double* __restrict__ lamhat, int lam_stride,
     int32_t* __restrict__ s_eff_out, int32_t* __restrict__ status_out,
     double* __restrict__ shift_out) {
@@ -759,7 +759,7 @@ __global__ __launch_bounds__(kCoreThreads) void k_nystrom_core_lds(
   // for positive semidefinite matrices) and g_pq is then set to zero; an idle
   // player (odd s) is paired with itself under the identity.  The iteration
   // ends after a sweep without a rotation.
-  constexpr double tol = 1.0e-14;
+  const double tol = jac_tol;
   const int S = (s + 1) & ~1;
   const int npairs = S / 2;
   int* s_rot = s_jac_rot;
@@ -1046,6 +1046,9 @@ hipError_t run_core(const MatArg& A, int64_t batch, int s, const uint8_t* mask, 
   }
   const double eps = sizeof(VT) == 4 ? 0x1p-24 : 0x1p-53;
   const double rel_floor = sizeof(VT) == 4 ? 1.0e-6 : 1.0e-13;
+  // Jacobi stops once every |g_pq| <= tol sqrt(g_pp g_qq); the columns of U then are
+  // orthonormal to about tol, far below the FP32 rounding of U for tol = 1e-9
+  const double jac_tol = sizeof(VT) == 4 ? 1.0e-9 : 1.0e-14;
   hipError_t e = hipSuccess;
   if (s <= kCoreLdsMaxS) {
     const size_t lds = (size_t)(2 * s * s + s) * sizeof(double);
@@ -1053,7 +1056,8 @@ hipError_t run_core(const MatArg& A, int64_t batch, int s, const uint8_t* mask, 
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_nystrom_core_lds, dim3((unsigned)batch), dim3(kCoreThreads), lds, st, s,
-                       eps, rel_floor, ws.gram, SP, ws.core, lamhat, s, s_eff, status, shift);
+                       eps, rel_floor, jac_tol, ws.gram, SP, ws.core, lamhat, s, s_eff, status,
+                       shift);
   } else {
     const size_t lds = (size_t)SP * (SP + 1) * sizeof(double);
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nystrom_core<SP>),

@@ -243,3 +243,15 @@ def test_hvp_noalloc_rejects_a_product_beyond_its_scratch(abi):
     # and a size within the buffer passes the same check (not called: no device here)
     M2 = _mat(abi, m=20000, n=40000)
     assert lib.genios_workspace_size(abi.OP_HVP, C.byref(M2), C.byref(o)) <= (128 << 20)
+
+
+def test_refine_cg_option_is_validated(abi):
+    lib = abi.load()
+    o = abi.default_opts()
+    assert o.refine_cg_bf16 == 0
+    o.refine_cg_bf16 = 2
+    M = _mat(abi)
+    rc = lib.genios_lasso_solve(C.byref(M), C.c_void_p(0x1000), (C.c_double * 1)(0.1), 1.0,
+                                C.byref(o), C.c_void_p(0x2000), C.c_void_p(0x3000),
+                                C.c_void_p(0x4000), (abi.Info * 1)())
+    assert rc == abi.ERR_ARG
