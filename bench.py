@@ -144,28 +144,46 @@ def probe_shared(workload, B=32):
         log(f"shared H p {name}: 3 products of {B} problems")
 
 
-def cpu_baseline(P, rows=8000, cols=16000, budget_iters=100):
-    """The oracle's GeNIOS ADMM (exact Cholesky x-steps) on the leading rows x cols
-    block of the workload's matrix: ADMM iterations per second on the host."""
+ORACLE_TIMING_FILE = os.path.join(ROOT, "tests", "golden", "oracle_timing_lasso_20000x40000.json")
+
+
+def cpu_baseline(P, iters=3):
+    """The oracle on the benchmark workload itself (same A, b, lambda), timed on this
+    host: its GeNIOS ADMM (exact x-steps through the Cholesky factor of
+    rho I + A A^T, alpha 1.6, sigma 1e-6) for `iters` iterations after its set-up.
+    value = ADMM iterations per second after the set-up.  The whole run of the same
+    oracle to r_kkt <= 1e-4 and its certified optimum take minutes; their figures,
+    from the committed record tests/golden/oracle_timing_lasso_20000x40000.json
+    (written by tests/golden/make_golden.py), ride along as `full_run`."""
     import threadpoolctl
 
     from oracle import lasso as olasso
-    A = P["A"][:rows, :cols].astype(np.float64)
-    x0 = P["x0"][:cols]
-    rng = np.random.default_rng(12345)
-    b = A @ x0 + 0.1 * rng.standard_normal(rows)
-    lam = 0.05 * float(np.max(np.abs(A.T @ b)))
     info = threadpoolctl.threadpool_info()
     cores = max([d.get("num_threads", 1) for d in info] or [os.cpu_count() or 1])
-    t0 = time.perf_counter()
-    x, z, u, rho, hist = olasso.admm(A, b, lam, rho=1.0, alpha=1.6, sigma=1e-6,
-                                     max_iter=budget_iters, eps=1e-4, rho_update_every=25)
-    dt = time.perf_counter() - t0
-    return {"value": round(len(hist) / dt, 3), "unit": "ADMM iters/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": f"oracle Lasso ADMM (exact Cholesky x-step, Woodbury), leading "
-                      f"{rows}x{cols} block of the workload's A, {len(hist)} iterations "
-                      f"incl. factorisation, {dt:.1f} s"}
+    A64 = P["A"].astype(np.float64)
+    b64 = P["b"].astype(np.float64)
+    clock = []
+    olasso.admm(A64, b64, P["lam"], rho=1.0, alpha=1.6, sigma=1e-6, max_iter=iters,
+                rho_update_every=25, clock=clock)
+    del A64
+    setup = clock[1] - clock[0]
+    per_iter = (clock[-1] - clock[1]) / iters
+    rec = {"value": round(1.0 / per_iter, 4), "unit": "ADMM iters/s", "cores": int(cores),
+           "kind": "oracle",
+           "sample": f"oracle GeNIOS ADMM (FP64, exact x-step) on the whole "
+                     f"{P['A'].shape[0]}x{P['A'].shape[1]} workload (same A, b, lambda): "
+                     f"set-up {setup:.1f} s (Cholesky of rho I + A A^T), then {iters} "
+                     f"iterations at {per_iter:.2f} s each",
+           "setup_s": round(setup, 2), "s_per_iter": round(per_iter, 3)}
+    try:
+        with open(ORACLE_TIMING_FILE) as f:
+            full = json.load(f)
+        rec["full_run"] = {k: full[k] for k in (
+            "setup_s", "admm_iters_to_1e-4", "admm_s_per_iter", "time_to_1e-4_s",
+            "rel_obj_err_at_1e-4", "time_to_certified_optimum_s", "certified_by", "host")}
+    except (OSError, KeyError, ValueError):
+        rec["full_run"] = None
+    return rec
 
 
 def _hvp_rate(info):
@@ -192,16 +210,33 @@ def next_rows(g, torch, A, b, lam, s):
     elastic net (Sec. 4.1's lambda2 = lambda1), duality-gap termination and the
     adaptive sketch size (Sec. 2.2; sizes 8, 16, ... up to 128, kappa bound <= 10 and
     <= 1.2) on
-    the headline workload, Huber fitting at the paper's largest size (n = 16000,
+    the headline workload, FP32 against BF16-A + refinement time to 1e-4 on the
+    1000 x 10000 and the logistic workloads, Huber fitting at the paper's largest size (n = 16000,
     N = 8000, no preconditioner) under its own stopping rule, dist(0, dF(z)) <= 1e-4,
     bounded least squares at the size of its ablation (N = 32000, n = 16000,
     eps 1e-5) with and without the preconditioner and inexact solves, the
-    l1-logistic workload (20000 x 5000, 300 iterations; a 16-value lambda path of it on
+    l1-logistic workload (20000 x 5000, to 1e-4; a 16-value lambda path of it on
     its one matrix, 100 iterations each), the batch of 64 Lasso
     problems with their adjoints, and 32 problems sharing the headline matrix (their
     H p on the matrix cores, and a lambda path)."""
     import genios_data
     out = {}
+    # the 1000 x 10000 gene-expression-shaped workload: time to r_kkt <= 1e-4, FP32 A
+    # against BF16-A + FP32 refinement (median of 5 after a warm-up)
+    C2 = genios_data.config("lasso_1000x10000")
+    A2 = torch.from_numpy(C2["A"]).to(A.device)
+    b2 = torch.from_numpy(C2["b"]).to(A.device)
+    for prec in ("bf16_refine", "f32"):
+        runs = [g.lasso_solve(A2, b2, C2["lam"], precision=prec, eps=1e-4, sketch_rank=C2["s"])
+                ["info"][0] for _ in range(6)][1:]
+        r2 = sorted(runs, key=lambda i: i["t_to_target"])[len(runs) // 2]
+        out[f"lasso_1000x10000_{prec}"] = {
+            "status_ok": all(i["status"] == 0 for i in runs),
+            "time_to_1e-4_s": round(r2["t_to_target"], 5), "iters": r2["iters"],
+            "cg_iters": r2["cg_iters"], "phase_switch_iter": r2["phase_switch_iter"],
+            "iters_per_s": round(r2["iters"] / r2["t_solve"], 1)}
+        log(f"lasso 1000x10000 {prec}: {out[f'lasso_1000x10000_{prec}']}")
+    del A2, b2
     kw = dict(precision="bf16_refine", sketch_rank=s, profile_kernels=1)
     for _ in range(2):
         en = g.lasso_solve(A, b, lam, eps=1e-4, lambda2=lam, **kw)["info"][0]
@@ -280,22 +315,29 @@ def next_rows(g, torch, A, b, lam, s):
             "phase_switch_iter": op["info"][0]["phase_switch_iter"]}
         log(f"lasso path 32 batch_mfma={mf}: {out[f'lasso_path_32_batch_mfma{mf}']}")
     del Ash, A16sh, Psh, bsh
-    # l1-logistic regression at the paper's settings (re-sketch every 20): a fixed 300
-    # iterations (this workload converges slowly, oracle and GPU alike)
+    # l1-logistic regression at the paper's settings (re-sketch every 20, eps 1e-4) from
+    # the workload's initial penalty (the mean Hessian eigenvalue at x = 0): time to
+    # r_kkt <= 1e-4, FP32 against BF16-A + FP32 refinement (median of 5 after a warm-up)
     Lg = genios_data.config("logreg_20000x5000")
     Al = torch.from_numpy(Lg["A"]).to(A.device)
     yl = torch.from_numpy(Lg["y"]).to(A.device)
-    for _ in range(2):
-        lo = g.logreg_solve(Al, yl, Lg["lam"], precision="bf16_refine", eps=1e-4,
-                            sketch_rank=Lg["s"], resketch_every=20, max_iter=300,
-                            profile_kernels=1)["info"][0]
-    gbs, frac = _hvp_rate(lo)
-    out["logreg_20000x5000"] = {
-        "iters": lo["iters"], "cg_iters": lo["cg_iters"], "resketches": lo["resketches"],
-        "iters_per_s": round(lo["iters"] / lo["t_solve"], 1), "t_solve_s": round(lo["t_solve"], 4),
-        "precond_s": round(lo["t_precond"], 4), "r_kkt": lo["r_kkt"],
-        "hvp_GBps": gbs, "hvp_frac_of_peak": frac}
-    log(f"logreg: {out['logreg_20000x5000']}")
+    for prec in ("bf16_refine", "f32"):
+        runs = []
+        for _ in range(6):
+            runs.append(g.logreg_solve(Al, yl, Lg["lam"], rho=Lg["rho"], precision=prec,
+                                       eps=1e-4, sketch_rank=Lg["s"], resketch_every=20,
+                                       profile_kernels=1)["info"][0])
+        runs = runs[1:]
+        lo = sorted(runs, key=lambda i: i["t_to_target"])[len(runs) // 2]
+        gbs, frac = _hvp_rate(lo)
+        out[f"logreg_20000x5000_{prec}"] = {
+            "status_ok": all(i["status"] == 0 for i in runs), "rho0": round(Lg["rho"], 3),
+            "time_to_1e-4_s": round(lo["t_to_target"], 4), "iters": lo["iters"],
+            "cg_iters": lo["cg_iters"], "resketches": lo["resketches"],
+            "phase_switch_iter": lo["phase_switch_iter"],
+            "iters_per_s": round(lo["iters"] / lo["t_solve"], 1), "r_kkt": lo["r_kkt"],
+            "precond_s": round(lo["t_precond"], 4), "hvp_GBps": gbs, "hvp_frac_of_peak": frac}
+        log(f"logreg {prec}: {out[f'logreg_20000x5000_{prec}']}")
     # a 16-value lambda path of that workload on its one matrix, 100 iterations each
     Bl = 16
     Alb = Al.expand(Bl, *Al.shape)
@@ -304,12 +346,13 @@ def next_rows(g, torch, A, b, lam, s):
     for mf in (1, 0):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        ol = g.logreg_solve(Alb, ylb, lams_l, precision="bf16_refine", eps=1e-4,
+        ol = g.logreg_solve(Alb, ylb, lams_l, rho=Lg["rho"], precision="bf16_refine", eps=1e-4,
                             sketch_rank=Lg["s"], resketch_every=20, max_iter=100,
                             batch_mfma=mf, profile_kernels=1)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         out[f"logreg_path_16_batch_mfma{mf}"] = {
+            "all_ok": all(i["status"] == 0 for i in ol["info"]),
             "solve_s": round(t2 - t1, 4), "admm_iters_total": int(sum(i["iters"] for i in ol["info"])),
             "cg_iters_max": int(max(i["cg_iters"] for i in ol["info"])),
             "hvp_launches_matrix_cores": ol["info"][0]["n_hvp_mrhs"]}
@@ -527,6 +570,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        log("cpu baseline: the oracle's set-up and 3 ADMM iterations on the whole workload")
         cpu = cpu_baseline(P)
         log(f"cpu baseline: {cpu}")
 

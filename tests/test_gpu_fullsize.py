@@ -124,7 +124,50 @@ def test_lasso_1000x10000_at_paper_tolerance(g, cfg2, prec):
 
 @pytest.fixture(scope="module")
 def cfg3():
-    return genios_data.config("lasso_20000x40000")
+    P = genios_data.config("lasso_20000x40000")
+    with open(os.path.join(GOLDEN, "lasso_20000x40000.json")) as f:
+        P["golden"] = json.load(f)
+    assert abs(P["golden"]["lam"] - P["lam"]) <= 1e-15 * P["lam"], "generator drifted"
+    return P
+
+
+def _hvp_exact_rows(A32, p, bf16, rows=2048):
+    """H p = A^T (A p) and |A|^T (|A| |p|) in FP64 over row blocks of the operand the
+    kernel reads (the FP32 matrix, or its RNE BF16 rounding)."""
+    from oracle import bf16 as obf
+    m, n = A32.shape
+    y = np.zeros(n)
+    ya = np.zeros(n)
+    pa = np.abs(p)
+    for r0 in range(0, m, rows):
+        blk = A32[r0:r0 + rows]
+        Ab = (obf.round_to_bf16(blk) if bf16 else blk).astype(np.float64)
+        y += Ab.T @ (Ab @ p)
+        Aa = np.abs(Ab)
+        ya += Aa.T @ (Aa @ pa)
+    return y, ya
+
+
+@pytest.mark.parametrize("bf16", [True, False], ids=["bf16", "fp32"])
+def test_lasso_20000x40000_fused_hvp_elementwise(g, cfg3, bf16):
+    # The dominant kernel in the solve's own launch shape (one problem, one pass over
+    # A, block partials summed in fixed order), every element against the FP64
+    # product of the same operand within the FP32 accumulation bound
+    # (m + n + 520) u |A|^T (|A| |p|)  (u = 2^-24; the m- and n-term sums plus the
+    # block-partial tree).
+    print("fused hvp 20000x40000", "bf16" if bf16 else "fp32", flush=True)
+    P = cfg3
+    A = _t(P["A"])
+    A16 = g.cast_bf16(A) if bf16 else None
+    m, n = P["A"].shape
+    p = np.random.default_rng(41).standard_normal(n).astype(np.float32)
+    got = _np64(g.hvp(A, _t(p), A16=A16))
+    ref, refa = _hvp_exact_rows(P["A"], p.astype(np.float64), bf16)
+    bound = (m + n + 520) * 2.0 ** -24 * refa
+    ratio = np.max(np.abs(got - ref) / bound)
+    print(f"  max |err| / bound = {ratio:.3g}, max rel err "
+          f"{np.max(np.abs(got - ref)) / np.max(np.abs(ref)):.3g}", flush=True)
+    assert ratio <= 1.0
 
 
 def test_lasso_20000x40000_matvecs_on_sampled_rows_and_columns(g, cfg3):
@@ -209,41 +252,86 @@ def test_lasso_20000x40000_nystrom_vs_fp64_sketch(g, cfg3, prec):
     assert e_act <= tol
 
 
-def test_lasso_20000x40000_bench_configuration_and_fp32_reference(g, cfg3):
-    # The solve + adjoint the benchmark times (BF16-A CG, FP32 refinement, eps
-    # 1e-4), against a tight FP32 solve (eps 1e-6) whose FP64 duality gap bounds
-    # its own suboptimality.
+def test_lasso_20000x40000_tight_solve_matches_the_certified_optimum(g, cfg3):
+    # FP32 master copy at eps = 1e-6: objective within 1e-6 of the oracle's
+    # certified optimum (measured 4.2e-7), with its support and signs.
+    print("lasso 20000x40000 eps 1e-6", flush=True)
+    P, G = cfg3, cfg3["golden"]
+    for prec in ("f32", "bf16_refine"):
+        out = g.lasso_solve(_t(P["A"]), _t(P["b"]), P["lam"], precision=prec, eps=1e-6,
+                            sketch_rank=P["s"], max_iter=10000)
+        info = out["info"][0]
+        assert out["status"] == 0, info
+        z = _np64(out["z"])
+        F = olasso.objective(P["A"], P["b"], P["lam"], z)
+        print(f"  {prec}: F={F:.12g} F*={G['F']:.12g} rel {_rel(F, G['F']):.3g} iters "
+              f"{info['iters']}", flush=True)
+        assert F >= G["F"] * (1 - 1e-12)
+        assert _rel(F, G["F"]) <= 1e-6
+        S = np.flatnonzero(z)
+        assert np.array_equal(S, np.array(G["support"]))
+        assert np.array_equal(np.sign(z[S]), np.array(G["signs"]))
+
+
+def test_lasso_20000x40000_bench_configuration(g, cfg3):
+    # The solve + adjoint the benchmark times (BF16-A CG, FP32 refinement, eps 1e-4).
+    # The stop is genuine in FP64, and the objective error against the certified
+    # optimum is within the bound the solver reports with its answer: the relative
+    # duality gap of App. A at z (weak duality: F(z) - F* <= gap <= rel_gap F(z)).
+    # At this tolerance the paper's criterion leaves about 6e-4 of objective error on
+    # this workload.
     print("lasso 20000x40000 bench config", flush=True)
-    P = cfg3
+    P, G = cfg3, cfg3["golden"]
     A = _t(P["A"])
     b = _t(P["b"])
-    ref = g.lasso_solve(A, b, P["lam"], precision="f32", eps=1e-6, sketch_rank=P["s"],
-                        max_iter=5000)
-    assert ref["status"] == 0, ref["info"]
-    zr = _np64(ref["z"])
-    gap_r, F_r, _ = olasso.duality_gap(P["A"], P["b"], P["lam"], zr)
-    print(f"  f32 eps 1e-6: F={F_r:.10g} rel gap {gap_r / F_r:.3g} "
-          f"iters {ref['info'][0]['iters']}", flush=True)
-    assert gap_r <= 2e-3 * F_r
     out = g.lasso_solve(A, b, P["lam"], precision="bf16_refine", eps=1e-4, sketch_rank=P["s"])
     info = out["info"][0]
     assert out["status"] == 0, info
     assert info["phase_switch_iter"] > 1 and info["r_kkt"] <= 1e-4
     z = _np64(out["z"])
-    F = olasso.objective(P["A"], P["b"], P["lam"], z)
+    gap, F, _ = olasso.duality_gap(P["A"], P["b"], P["lam"], z)
     rk = _check_stop(P, out, 1e-4)
-    print(f"  bench config: F={F:.10g} vs ref {(F - F_r) / F_r:.3g} r_kkt(fp64) {rk:.3g} "
-          f"iters {info['iters']}", flush=True)
-    assert F >= F_r - gap_r  # weak duality through the reference's dual point
-    assert (F - F_r) / F_r <= 5e-3
+    print(f"  bench config: rel err {(F - G['F']) / G['F']:.3g} reported rel gap "
+          f"{info['rel_gap']:.3g} (oracle {gap / F:.3g}) r_kkt(fp64) {rk:.3g} iters "
+          f"{info['iters']}", flush=True)
+    assert F >= G["F"] * (1 - 1e-12)
+    assert F - G["F"] <= gap * (1 + 1e-9)
+    assert F - G["F"] <= info["rel_gap"] * F * (1 + 1e-4)
+    assert _rel(info["obj"], F) <= 1e-6
+    # large coefficients of x* keep their signs
+    S = np.array(G["support"])
+    xs = np.array(G["x_support"])
+    big = np.abs(xs) > 0.1 * np.max(np.abs(xs))
+    assert np.array_equal(np.sign(z[S[big]]), np.sign(xs[big]))
     # adjoint at the returned solution vs the dense FP64 adjoint there
     gz = (2.0 * (out["z"] - _t(P["x0"], torch.float32))).contiguous()
     grad_b, grad_lam, binfo = g.lasso_backward(A, out["z"], gz, P["lam"], sketch_rank=P["s"])
     assert binfo[0]["status"] == 0, binfo
     db, dl, _ = oadj.lasso_adjoint(P["A"], z, _np64(gz))
-    got = _np64(grad_b)
-    err = np.linalg.norm(got - db) / np.linalg.norm(db)
+    err = np.linalg.norm(_np64(grad_b) - db) / np.linalg.norm(db)
     print(f"  |S|={np.count_nonzero(z)} adjoint rel err {err:.3g}", flush=True)
+    assert err <= 1e-4
+    assert abs(float(grad_lam[0]) - dl) <= 1e-4 * abs(dl)
+
+
+def test_lasso_20000x40000_adjoint_at_the_certified_optimum(g, cfg3):
+    # The gradient of the solution map itself: the adjoint kernel at the oracle's x*
+    # (strict complementarity holds there, margin stored with the golden) against the
+    # dense FP64 formula at x*, for the loss ||x* - x0||^2.
+    print("adjoint at x* 20000x40000", flush=True)
+    P, G = cfg3, cfg3["golden"]
+    assert G["strict_complementarity_margin"] > 1e-6
+    n = P["A"].shape[1]
+    xs = np.zeros(n)
+    xs[np.array(G["support"])] = np.array(G["x_support"])
+    zst = _t(xs, torch.float32)
+    gz = (2.0 * (zst - _t(P["x0"], torch.float32))).contiguous()
+    grad_b, grad_lam, binfo = g.lasso_backward(_t(P["A"]), zst, gz, P["lam"],
+                                               sketch_rank=P["s"])
+    assert binfo[0]["status"] == 0, binfo
+    db, dl, _ = oadj.lasso_adjoint(P["A"], _np64(zst), _np64(gz))
+    err = np.linalg.norm(_np64(grad_b) - db) / np.linalg.norm(db)
+    print(f"  dL/db rel err {err:.3g}, dL/dlam {float(grad_lam[0]):.8g} vs {dl:.8g}", flush=True)
     assert err <= 1e-4
     assert abs(float(grad_lam[0]) - dl) <= 1e-4 * abs(dl)
 
@@ -253,7 +341,11 @@ def test_lasso_20000x40000_bench_configuration_and_fp32_reference(g, cfg3):
 
 @pytest.fixture(scope="module")
 def cfg4():
-    return genios_data.config("logreg_20000x5000")
+    P = genios_data.config("logreg_20000x5000")
+    with open(os.path.join(GOLDEN, "logreg_20000x5000.json")) as f:
+        P["golden"] = json.load(f)
+    assert abs(P["golden"]["lam"] - P["lam"]) <= 1e-15 * P["lam"], "generator drifted"
+    return P
 
 
 def test_logreg_20000x5000_f64_lockstep_with_oracle(g, cfg4):
@@ -264,12 +356,13 @@ def test_logreg_20000x5000_f64_lockstep_with_oracle(g, cfg4):
     K = 3
     A64 = P["A"].astype(np.float64)
     y64 = P["y"].astype(np.float64)
-    x, z, u, rho, hist = ologreg.admm(A64, y64, P["lam"], rho=1.0, alpha=1.6, sigma=1e-6,
+    x, z, u, rho, hist = ologreg.admm(A64, y64, P["lam"], rho=P["rho"], alpha=1.6, sigma=1e-6,
                                       max_iter=K, xstep="approx")
     print("  oracle done", flush=True)
-    out = g.logreg_solve(_t(A64), _t(y64), P["lam"], precision="f64", inexact=False,
-                         cg_tol_floor=1e-13, rho_update_every=0, max_iter=K, eps=1e-14,
-                         sketch_rank=P["s"], resketch_every=1, max_cg_iter=2000, history=K)
+    out = g.logreg_solve(_t(A64), _t(y64), P["lam"], rho=P["rho"], precision="f64",
+                         inexact=False, cg_tol_floor=1e-13, rho_update_every=0, max_iter=K,
+                         eps=1e-14, sketch_rank=P["s"], resketch_every=1, max_cg_iter=2000,
+                         history=K)
     assert out["status"] == 1, out["info"]  # iteration cap
     for name, ref in (("x", x), ("z", z), ("u", u)):
         got = _np64(out[name])
@@ -281,33 +374,71 @@ def test_logreg_20000x5000_f64_lockstep_with_oracle(g, cfg4):
     assert np.allclose(h[:, 2], hist[:, 2], rtol=1e-6)  # ||r_d||
 
 
+def _logreg_check(P, out, eps):
+    info = out["info"][0]
+    x, z, u = (_np64(out[k]) for k in ("x", "z", "u"))
+    gx = ologreg.grad_f(P["A"], P["y"], x)
+    rk, _, _ = ores.r_kkt(x, z, u, info["rho"], gx)
+    gap, F, _ = ologreg.duality_gap(P["A"], P["y"], P["lam"], z)
+    Fs = P["golden"]["F"]
+    S = np.flatnonzero(z)
+    print(f"  status {info['status']} iters {info['iters']} cg {info['cg_iters']} switch "
+          f"{info['phase_switch_iter']} r_kkt {info['r_kkt']:.4g} (fp64 {rk:.4g}) rel err "
+          f"{(F - Fs) / Fs:.3g} |S| {S.size} rho {info['rho']:.4g} resketches "
+          f"{info['resketches']}", flush=True)
+    assert out["status"] == 0, info
+    assert rk <= eps * (1 + 1e-3), (rk, info)          # the stop is genuine in FP64
+    assert F >= Fs * (1 - 1e-12)                          # F* is a lower bound
+    assert F - Fs <= gap * (1 + 1e-9) + 1e-12 * Fs        # weak duality at the iterate
+    return F, S, z
+
+
 @pytest.mark.parametrize("prec", ["bf16_refine", "f32"])
-def test_logreg_20000x5000_paper_settings(g, cfg4, prec):
-    # 300 iterations with the paper's defaults (re-sketch every 20).  ADMM converges
-    # slowly on this workload (large curvature of the shared factor against rho = 1,
-    # the same for the oracle's exact-step ADMM), so the checks are properties at the
-    # returned iterate, evaluated by the FP64 oracle: the reported residuals are the
-    # true ones, the objective fell below F(0) = m log 2, and the duality gap of
-    # App. A bounds the suboptimality.
-    print("logreg 20000x5000", prec, flush=True)
+def test_logreg_20000x5000_converges_to_the_certified_optimum(g, cfg4, prec):
+    # The paper's defaults (eps 1e-4, re-sketch every 20, the penalty rule of
+    # Sec. 2.5) from the workload's initial penalty (the mean Hessian eigenvalue at
+    # x = 0): the stop at eps = 1e-4 is genuine and leaves the objective within
+    # 2e-6 of the oracle's certified optimum (measured 6e-7 BF16-A + refine,
+    # 8e-7 FP32); at eps = 1e-6 it is within 1e-6 (measured 3e-8 to 5e-8), with
+    # the optimum's support and signs.
+    P, G = cfg4, cfg4["golden"]
+    for eps, tol in ((1e-4, 2e-6), (1e-6, 1e-6)):
+        print("logreg 20000x5000", prec, "eps", eps, flush=True)
+        out = g.logreg_solve(_t(P["A"]), _t(P["y"]), P["lam"], rho=P["rho"], precision=prec,
+                             eps=eps, sketch_rank=P["s"], resketch_every=20)
+        F, S, z = _logreg_check(P, out, eps)
+        assert (F - G["F"]) / G["F"] <= tol
+        assert out["info"][0]["resketches"] >= 2
+        if prec == "bf16_refine":
+            assert out["info"][0]["phase_switch_iter"] > 1
+    assert np.array_equal(S, np.array(G["support"]))
+    assert np.array_equal(np.sign(z[S]), np.array(G["signs"]))
+
+
+@pytest.mark.parametrize("prec", ["bf16_refine", "f32"])
+def test_logreg_20000x5000_at_unit_penalty(g, cfg4, prec):
+    # Extra check at rho = 1 held for 300 iterations (the paper's own setting on its
+    # unit-norm data, three orders of magnitude below this workload's curvature):
+    # the solve stays consistent -- the reported residuals are the true ones and the
+    # objective falls below F(0) = m log 2, bounded by the duality gap of App. A.
+    print("logreg 20000x5000 rho 1", prec, flush=True)
     P = cfg4
     m = P["A"].shape[0]
-    out = g.logreg_solve(_t(P["A"]), _t(P["y"]), P["lam"], precision=prec, eps=1e-4,
+    out = g.logreg_solve(_t(P["A"]), _t(P["y"]), P["lam"], rho=1.0, precision=prec, eps=1e-4,
                          sketch_rank=P["s"], resketch_every=20, max_iter=300)
     info = out["info"][0]
     x, z, u = (_np64(out[k]) for k in ("x", "z", "u"))
     gx = ologreg.grad_f(P["A"], P["y"], x)
     rk, rp, rd = ores.r_kkt(x, z, u, info["rho"], gx)
     gap, F = ologreg.duality_gap(P["A"], P["y"], P["lam"], z)[:2]
-    print(f"  status {info['status']} iters {info['iters']} cg {info['cg_iters']} r_kkt "
-          f"{info['r_kkt']:.4g} (fp64 {rk:.4g}) F {F:.8g} (F(0) {m * np.log(2):.8g}) "
-          f"rel gap {gap / F:.3g} resketches {info['resketches']}", flush=True)
+    print(f"  status {info['status']} iters {info['iters']} r_kkt {info['r_kkt']:.4g} "
+          f"(fp64 {rk:.4g}) rel gap {gap / F:.3g}", flush=True)
     assert out["status"] in (0, 1), info
     assert info["resketches"] >= 300 // 20
     assert abs(info["r_kkt"] - rk) <= 1e-3 * rk
     assert F < m * np.log(2) and 0.0 <= gap < F
+    assert F >= P["golden"]["F"] * (1 - 1e-12)
     assert _rel(info["obj"], F) <= 1e-5
-    assert rk < 0.05
 
 
 # ---------------------------------------------------------------- 64 x 2000 x 8000 batch
@@ -420,6 +551,96 @@ def test_batch_fp64_adjoint_vs_central_differences(g, cfg5):
         h /= 2
     print(f"  FD checked: b {ok_b.sum()}/{nb}, lambda {ok_l.sum()}/{nb}", flush=True)
     assert ok_b.sum() >= nb // 2 and ok_l.sum() >= nb // 2
+
+
+def test_batch_bench_adjoint_vs_finite_differences_of_the_solution_map(g, cfg5):
+    # The bench configuration's adjoint (FP32 master copy, masked Nystrom PCG) against
+    # central differences of the exact solution map on 8 of the 64 problems.  The
+    # oracle certifies x* (working-set route); on x*'s support with its signs the map
+    # (b, lam) -> x* is affine (App. A optimality conditions), so the oracle's polish
+    # at b +- h d and lam (1 +- h) is the exact perturbed minimiser whenever it is
+    # accepted, and the central difference of the quadratic L = ||x* - x0||^2 is exact.
+    # Checked: the adjoint kernel at x* against the differences (every sampled
+    # problem without a kink within h, 4 directions and lambda, within 1e-4), and the
+    # adjoint at the BF16-refine solution z wherever z has x*'s support, up to the
+    # part that is the solution error's (not the adjoint's): at the bench's eps = 1e-4
+    # none of the sampled solutions has x*'s support (small coefficients come and go),
+    # at eps = 1e-7 most do.
+    print("batch bench adjoint vs FD of the solution map", flush=True)
+    P = cfg5
+    idx = np.arange(0, 64, 8)
+    nb = len(idx)
+    A_np = [P["A"][i] for i in idx]
+    b_np = P["b"][idx]
+    lam = P["lam"][idx].astype(np.float64)
+    x0 = P["x0"][idx]
+    xs = []
+    for j in range(nb):
+        sol = olasso.solve_working_set(A_np[j], b_np[j], lam[j])
+        assert sol["certified"]
+        xs.append(sol["x"])
+    XS = np.stack(xs)
+    A = _t(np.stack(A_np))
+    zst = _t(XS, torch.float32)
+    gz = (2.0 * (zst - _t(x0, torch.float32))).contiguous()
+    grad_b, grad_lam, binfo = g.lasso_backward(A, zst, gz, list(lam), sketch_rank=P["s"])
+    assert all(i["status"] == 0 for i in binfo), binfo
+    GB, GL = _np64(grad_b), grad_lam.numpy()
+    sols = {}
+    for eps in (1e-4, 1e-7):
+        out = g.lasso_solve(A, _t(b_np), list(lam), precision="bf16_refine", eps=eps,
+                            sketch_rank=P["s"], max_iter=100000)
+        assert out["status"] == 0
+        Z = out["z"]
+        gzz = (2.0 * (Z - _t(x0, torch.float32))).contiguous()
+        gbz, glz, _ = g.lasso_backward(A, Z, gzz, list(lam), sketch_rank=P["s"])
+        sols[eps] = (_np64(gbz), glz.numpy(), _np64(Z))
+    rng = np.random.default_rng(5)
+    L = lambda x, j: float(np.sum((x - x0[j]) ** 2))
+    n_same = {1e-4: 0, 1e-7: 0}
+    n_checked = 0
+    for j in range(nb):
+        S = np.flatnonzero(XS[j])
+        polish = lambda bb, ll: olasso.polish(A_np[j], bb, ll, XS[j])
+        dirs = [rng.standard_normal(b_np.shape[1]) for _ in range(4)]
+        dirs = [d / np.linalg.norm(d) for d in dirs]
+        fds, fdl = None, None
+        h = 1e-3
+        for _ in range(4):  # halve h while the support moves (a kink nearby)
+            pb = [(polish(b_np[j] + h * d, lam[j]), polish(b_np[j] - h * d, lam[j])) for d in dirs]
+            lp, lm = polish(b_np[j], lam[j] * (1 + h)), polish(b_np[j], lam[j] * (1 - h))
+            if all(a is not None and c is not None for a, c in pb) and lp is not None and \
+                    lm is not None:
+                fds = [((L(a, j) - L(c, j)) / (2 * h), d) for (a, c), d in zip(pb, dirs)]
+                fdl = (L(lp, j) - L(lm, j)) / (2 * h * lam[j])
+                break
+            h /= 2
+        if fds is None:
+            print(f"  problem {idx[j]}: kink (support moves within h), skipped", flush=True)
+            continue
+        n_checked += 1
+        for fd, d in fds:
+            assert abs(GB[j] @ d - fd) <= 1e-4 * max(1.0, abs(fd)), (idx[j], GB[j] @ d, fd)
+        assert abs(GL[j] - fdl) <= 1e-4 * max(1.0, abs(fdl)), (idx[j], GL[j], fdl)
+        # at a returned z with x*'s support the kernel gives the gradient of L at z: it
+        # differs from the map's gradient at x* exactly by the dense adjoint of the
+        # solution error, A_S G^-1 2 (z - x*)_S (the oracle's formula at z minus at x*)
+        db_s, dl_s, _ = oadj.lasso_adjoint(A_np[j], XS[j], 2.0 * (XS[j] - x0[j]))
+        for eps, (GBZ, GLZ, ZN) in sols.items():
+            if not np.array_equal(np.flatnonzero(ZN[j]), S):
+                continue
+            n_same[eps] += 1
+            db_z, dl_z, _ = oadj.lasso_adjoint(A_np[j], ZN[j], 2.0 * (ZN[j] - x0[j]))
+            for fd, d in fds:
+                slack = abs((db_z - db_s) @ d)
+                assert abs(GBZ[j] @ d - fd) <= 1e-4 * max(1.0, abs(fd)) + 1.01 * slack, \
+                    (idx[j], eps, GBZ[j] @ d, fd, slack)
+            assert abs(GLZ[j] - fdl) <= 1e-4 * max(1.0, abs(fdl)) + 1.01 * abs(dl_z - dl_s), \
+                (idx[j], eps, GLZ[j], fdl)
+    assert n_checked >= nb - 2
+    assert n_same[1e-7] >= n_checked // 2
+    print(f"  FD of the solution map: {n_checked} of {nb} problems at x*; x*'s support at "
+          f"eps 1e-4 on {n_same[1e-4]}, at eps 1e-7 on {n_same[1e-7]} of them", flush=True)
 
 
 # ------------------------------------------- rows after the headline path, full size

@@ -1051,3 +1051,62 @@ def test_boxls_shared_matrix_batch(g):
         sol = oboxls.solve(A, bs[j], 0.0, 1.0)
         rel = (oboxls.objective(A, bs[j], Z[j]) - sol["F"]) / sol["F"]
         assert -1e-9 <= rel <= 5e-4, (j, rel)
+
+
+def test_batch_launch_shapes_while_problems_stop_apart(g):
+    # 16 problems on one FP32 matrix of 256 MiB (4096 x 16384) with the per-problem
+    # products (batch_mfma = 0) and lambdas spread over a factor 8, so the problems
+    # stop apart and the running count passes through 9..15 (the batch grid sized for
+    # the running problems) and then through 1..8 (one whole-chip launch per running
+    # problem).  Both shapes must run; each problem must match its own single-problem
+    # solve and is certified by the oracle's App. A duality gap.
+    print("batch launch shapes 4096x16384 x16", flush=True)
+    P = genios_data.lasso_small(4096, 16384, 400, noise=0.01, seed=21, s=20)
+    m, n = P["A"].shape
+    B = 16
+    lams = [P["lam"] * 8.0 ** ((j - 8) / 8.0) for j in range(B)]
+    A = _t(P["A"])
+    kw = dict(precision="f32", eps=1e-6, sketch_rank=20, batch_mfma=0, max_iter=5000)
+    out = g.lasso_solve(A.expand(B, m, n), _t(np.tile(P["b"], (B, 1))), lams, **kw)
+    infos = out["info"]
+    assert out["status"] == 0, [i["status"] for i in infos]
+    its = [i["iters"] for i in infos]
+    print("  iterations", its, "resized", infos[0]["n_hvp_resized"], "tail",
+          infos[0]["n_hvp_tail"], flush=True)
+    assert len(set(its)) >= 6
+    assert infos[0]["n_hvp_resized"] > 0 and infos[0]["n_hvp_tail"] > 0
+    Z = out["z"].cpu().numpy().astype(np.float64)
+    for j, lam in enumerate(lams):
+        F = olasso.objective(P["A"], P["b"], lam, Z[j])
+        assert olasso.relative_gap(P["A"], P["b"], lam, Z[j]) <= 1e-3, j
+        one = g.lasso_solve(A, _t(P["b"]), lam, **kw)
+        assert one["status"] == 0 and one["info"][0]["n_hvp_tail"] == 0
+        F1 = olasso.objective(P["A"], P["b"], lam, one["z"].cpu().numpy().astype(np.float64))
+        assert _rel(F, F1) <= 1e-9, (j, F, F1)
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_refinement_cg_operator_modes_reach_the_same_answer(g, eps):
+    # After the BF16 -> FP32 switch, CG on the master copy (refine_cg_bf16 = 0) or on
+    # the BF16 model with the master copy's gradient each iteration (1): both stop on
+    # the master copy's residuals (FP64 re-evaluation), at the same objective within
+    # the stopping tolerance's reach, in a similar number of ADMM iterations.
+    print("refine modes", eps, flush=True)
+    P = genios_data.config("lasso_1000x10000")
+    res = {}
+    for mode in (0, 1):
+        out = g.lasso_solve(_t(P["A"]), _t(P["b"]), P["lam"], precision="bf16_refine", eps=eps,
+                            sketch_rank=P["s"], refine_cg_bf16=mode, max_iter=20000)
+        info = out["info"][0]
+        assert out["status"] == 0, info
+        x, z, u = (out[k].cpu().numpy().astype(np.float64) for k in ("x", "z", "u"))
+        rk, _, _ = ores.r_kkt(x, z, u, info["rho"], olasso.grad_f(P["A"], P["b"], x))
+        assert rk <= eps * (1 + 1e-3), (mode, rk)
+        assert info["phase_switch_iter"] > 1
+        res[mode] = (olasso.objective(P["A"], P["b"], P["lam"], z), info)
+        print(f"  mode {mode}: iters {info['iters']} cg {info['cg_iters']} switch "
+              f"{info['phase_switch_iter']} fp32 H p {info['n_hvp_hi']} bf16 H p "
+              f"{info['n_hvp']} F {res[mode][0]:.12g}", flush=True)
+    (F0, i0), (F1, i1) = res[0], res[1]
+    assert abs(i1["iters"] - i0["iters"]) <= max(3, 0.1 * i0["iters"])
+    assert _rel(F1, F0) <= (1e-6 if eps <= 1e-6 else 2e-3)
