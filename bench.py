@@ -216,7 +216,7 @@ def next_rows(g, torch, A, b, lam, s):
     bounded least squares at the size of its ablation (N = 32000, n = 16000,
     eps 1e-5) with and without the preconditioner and inexact solves, the
     l1-logistic workload (20000 x 5000, to 1e-4; a 16-value lambda path of it on
-    its one matrix, 100 iterations each), the batch of 64 Lasso
+    its one matrix, each point to 1e-4), the batch of 64 Lasso
     problems with their adjoints, and 32 problems sharing the headline matrix (their
     H p on the matrix cores, and a lambda path)."""
     import genios_data
@@ -338,7 +338,7 @@ def next_rows(g, torch, A, b, lam, s):
             "iters_per_s": round(lo["iters"] / lo["t_solve"], 1), "r_kkt": lo["r_kkt"],
             "precond_s": round(lo["t_precond"], 4), "hvp_GBps": gbs, "hvp_frac_of_peak": frac}
         log(f"logreg {prec}: {out[f'logreg_20000x5000_{prec}']}")
-    # a 16-value lambda path of that workload on its one matrix, 100 iterations each
+    # a 16-value lambda path of that workload on its one matrix, each point to 1e-4
     Bl = 16
     Alb = Al.expand(Bl, *Al.shape)
     ylb = yl.expand(Bl, yl.shape[0]).contiguous()
@@ -347,7 +347,7 @@ def next_rows(g, torch, A, b, lam, s):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         ol = g.logreg_solve(Alb, ylb, lams_l, rho=Lg["rho"], precision="bf16_refine", eps=1e-4,
-                            sketch_rank=Lg["s"], resketch_every=20, max_iter=100,
+                            sketch_rank=Lg["s"], resketch_every=20, max_iter=1000,
                             batch_mfma=mf, profile_kernels=1)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
