@@ -22,7 +22,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libgenios.so")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 
-SOURCES = ["gemv.hip", "cg.hip", "sketch.hip", "sketch_mfma.hip", "gap.hip", "stream.hip", "adaptive.hip", "setup.hip",
+SOURCES = ["gemv.hip", "cg.hip", "sketch.hip", "sketch_mfma.hip", "core.hip", "gap.hip", "stream.hip", "adaptive.hip", "setup.hip",
            "engine.cpp", "abi.cpp"]
 ARCH = os.environ.get("GENIOS_OFFLOAD_ARCH", "gfx950")
 

@@ -366,6 +366,13 @@ bool sketch_mfma_eligible(const MatArg& A, VType vt, const SketchWs& ws);
 hipError_t launch_sketch_mfma(const MatArg& A, int64_t batch, int sp, const float* d,
                               int64_t d_stride, const SketchWs& ws, hipStream_t st);
 int sketch_pad(int s);
+// The s x s core for s <= kCoreLdsMaxS (core.hip): one workgroup per problem for the
+// Cholesky, the triangular solves and block Jacobi, then the eigenvector columns T.
+constexpr int kCoreLdsMaxS = 100;
+hipError_t launch_nystrom_core_lds(int64_t batch, int s, int SPg, double eps, double rel_floor,
+                                   double jac_tol, const double* gram, double* core,
+                                   double* lamhat, int32_t* s_eff, int32_t* status, double* shift,
+                                   hipStream_t st);
 // ---- H p of a batch sharing A on the matrix cores (sketch_mfma.hip) ----
 struct MrhsWs {
   uint16_t* p16 = nullptr;  // BF16 hi then lo parts of the p block [c][kpad(n)] (FP32

@@ -10,7 +10,8 @@
 //      orthonormal test matrix; a Gaussian Omega with the same range has
 //      columns of norm ~sqrt(n), and the equivalent shift is eps ||Y||_F),
 //        M = Omega^T Y_mu = C C^T (Cholesky; shift x10 on failure, <= 3 times),
-//        G = C^-1 (Y_mu^T Y_mu) C^-T = V Sigma^2 V^T (cyclic Jacobi),
+//        G = C^-1 (Y_mu^T Y_mu) C^-T = V Sigma^2 V^T (block Jacobi in core.hip for
+//        s <= 100, cyclic Jacobi below for larger s),
 //        lambda_hat = max(Sigma^2 - mu, 0), T = C^-T V Sigma^-1,
 //      so that B = Y_mu C^-T = U Sigma V^T and H_hat = Y_mu M^-1 Y_mu^T = B B^T.
 //   6. U = Y_mu T             (n x s)   orthonormal columns.
@@ -601,339 +602,6 @@ __global__ __launch_bounds__(256) void k_nystrom_core(int s, int64_t n, double e
   }
 }
 
-// The same s x s core with every matrix in LDS (s <= kCoreLdsMaxS): two
-// regions, R1 (s*s) and R2 (s*(s+1)), hold in turn
-//   R2: M -> C (Cholesky)          R1: Q -> X = C^-1 Q -> G = X C^-T
-//   R2: G (Jacobi, rows/columns)   R1: V (column-major, rotations)
-//   R2: C (reloaded)               R1: T' = C^-T V (back substitution)
-// and the eigenvalues, permutation and rotation parameters are small arrays.
-// One 1024-thread workgroup per problem; all loops are barrier-separated.
-constexpr int kCoreLdsMaxS = 100;
-constexpr int kCoreThreads = 1024;
-
-__global__ __launch_bounds__(kCoreThreads) void k_nystrom_core_lds(
-    int s, double eps, double rel_floor, double jac_tol, const double* __restrict__ gram, int SPg,
-    double* __restrict__ core, double* __restrict__ lamhat, int lam_stride,
-    int32_t* __restrict__ s_eff_out, int32_t* __restrict__ status_out,
-    double* __restrict__ shift_out) {
-  extern __shared__ double lds[];
-  __shared__ double2 pr_cs[kCoreLdsMaxS / 2 + 1];  // (c, s) of pair i
-  __shared__ int2 pr_pq[kCoreLdsMaxS / 2 + 1];     // (p, q) of pair i
-  __shared__ int16_t perm[kCoreLdsMaxS];
-  __shared__ double evals[kCoreLdsMaxS];
-  __shared__ double s_red[4];
-  __shared__ double s_shift;
-  __shared__ int s_flag;
-  __shared__ int s_jac_rot[2];  // a rotation happened in the sweep of this parity
-  const int b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-  const int LG = s + 1;
-  double* R1 = lds;          // s * s
-  double* R2 = lds + s * s;  // s * LG
-  const int sp2 = SPg * SPg;
-  const double* G1 = gram + ((int64_t)b * 3 + 0) * sp2;
-  const double* G2 = gram + ((int64_t)b * 3 + 1) * sp2;
-  const double* G3 = gram + ((int64_t)b * 3 + 2) * sp2;
-  double* Cg = core + (int64_t)b * 5 * sp2;
-  double* Tg = Cg + 4 * sp2;
-  double* lam_b = lamhat + (int64_t)b * lam_stride;
-
-  if (tid == 0) {
-    double tr = 0.0;
-    for (int k = 0; k < s; ++k) tr += G3[k * SPg + k];
-    s_red[0] = tr;
-  }
-  __syncthreads();
-  const double trace3 = s_red[0];
-  if (!(trace3 > 0.0) || !(trace3 < 1.0e300)) {
-    for (int j = tid; j < s; j += nt) lam_b[j] = 0.0;
-    if (tid == 0) {
-      s_eff_out[b] = 0;
-      status_out[b] = (trace3 == 0.0) ? 0 : GENIOS_WARN_PRECOND;
-      shift_out[b] = 0.0;
-    }
-    return;
-  }
-  if (tid == 0) s_shift = eps * sqrt(trace3);
-  __syncthreads();
-
-  // ---- Cholesky of M = sym(Omega^T Y) + mu Omega^T Omega in R2 (retry with 10 mu) ----
-  bool ok = false;
-  for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
-    const double mu = s_shift;
-    for (int e = tid; e < s * s; e += nt) {
-      const int i = e / s, j = e % s;
-      R2[i * LG + j] = 0.5 * (G1[i * SPg + j] + G1[j * SPg + i]) + mu * G2[i * SPg + j];
-    }
-    if (tid == 0) s_flag = 0;
-    __syncthreads();
-    for (int k = 0; k < s; ++k) {
-      if (tid == 0) {
-        const double dkk = R2[k * LG + k];
-        if (!(dkk > 0.0) || !(dkk < 1.0e300))
-          s_flag = 1;
-        else
-          R2[k * LG + k] = sqrt(dkk);
-      }
-      __syncthreads();
-      if (s_flag) break;
-      const double piv = R2[k * LG + k];
-      for (int i = k + 1 + tid; i < s; i += nt) R2[i * LG + k] /= piv;
-      __syncthreads();
-      const int rem = s - k - 1;
-      for (int e = tid; e < rem * rem; e += nt) {
-        const int i = k + 1 + e / rem, j = k + 1 + e % rem;
-        if (j <= i) R2[i * LG + j] -= R2[i * LG + k] * R2[j * LG + k];
-      }
-      __syncthreads();
-    }
-    if (!s_flag) {
-      ok = true;
-    } else {
-      if (tid == 0) s_shift = 10.0 * s_shift;
-      __syncthreads();
-    }
-  }
-  if (!ok) {
-    for (int j = tid; j < s; j += nt) lam_b[j] = 0.0;
-    if (tid == 0) {
-      s_eff_out[b] = 0;
-      status_out[b] = GENIOS_WARN_PRECOND;
-      shift_out[b] = s_shift;
-    }
-    return;
-  }
-  const double mu = s_shift;
-  // save C (lower) to global; Q = Y_mu^T Y_mu into R1 (row-major, ld s)
-  for (int e = tid; e < s * s; e += nt) {
-    const int i = e / s, j = e % s;
-    Cg[i * SPg + j] = (j <= i) ? R2[i * LG + j] : 0.0;
-    R1[i * s + j] =
-        G3[i * SPg + j] + mu * (G1[i * SPg + j] + G1[j * SPg + i]) + mu * mu * G2[i * SPg + j];
-  }
-  __syncthreads();
-  // X = C^-1 Q (right-looking forward substitution, in place in R1)
-  for (int l = 0; l < s; ++l) {
-    const double inv = 1.0 / R2[l * LG + l];
-    for (int j = tid; j < s; j += nt) R1[l * s + j] *= inv;
-    __syncthreads();
-    const int rem = s - l - 1;
-    for (int e = tid; e < rem * s; e += nt) {
-      const int i = l + 1 + e / s, j = e % s;
-      R1[i * s + j] -= R2[i * LG + l] * R1[l * s + j];
-    }
-    __syncthreads();
-  }
-  // G = X C^-T: solve G C^T = X column by column (right-looking), in place in R1
-  for (int l = 0; l < s; ++l) {
-    const double inv = 1.0 / R2[l * LG + l];
-    for (int i = tid; i < s; i += nt) R1[i * s + l] *= inv;
-    __syncthreads();
-    const int rem = s - l - 1;
-    for (int e = tid; e < s * rem; e += nt) {
-      const int i = e / rem, k = l + 1 + e % rem;
-      R1[i * s + k] -= R1[i * s + l] * R2[k * LG + l];
-    }
-    __syncthreads();
-  }
-  // G (symmetrised) into R2 with ld s+1; V = I into R1 (column-major)
-  for (int e = tid; e < s * s; e += nt) {
-    const int i = e / s, j = e % s;
-    R2[i * LG + j] = 0.5 * (R1[i * s + j] + R1[j * s + i]);
-  }
-  __syncthreads();
-  for (int e = tid; e < s * s; e += nt) {
-    const int p = e / s, k = e % s;
-    R1[p * s + k] = (p == k) ? 1.0 : 0.0;
-  }
-  if (tid == 0) s_jac_rot[0] = 0;
-  __syncthreads();
-
-  // ---- cyclic Jacobi, round-robin pairs ----
-  // A round rotates the disjoint pairs (p_i, q_i) of the round-robin schedule
-  // at once: G <- R G R^T, V <- V R^T with R the direct sum of the 2 x 2
-  // rotations.  Phase 1: thread i computes the rotation of pair i.  Phase 2:
-  // every 2 x 2 block G[I, J] (rows of pair I, columns of pair J) becomes
-  // R_I G[I, J] R_J^T, and every pair of V entries V[k, (p_J, q_J)] becomes
-  // V[k, .] R_J^T; the blocks partition G, so phase 2 needs no ordering.  A
-  // pair is rotated only while |g_pq| > tol sqrt(g_pp g_qq) (the threshold form
-  // for positive semidefinite matrices) and g_pq is then set to zero; an idle
-  // player (odd s) is paired with itself under the identity.  The iteration
-  // ends after a sweep without a rotation.
-  const double tol = jac_tol;
-  const int S = (s + 1) & ~1;
-  const int npairs = S / 2;
-  int* s_rot = s_jac_rot;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    for (int round = 0; round < S - 1; ++round) {
-      if (tid < npairs) {
-        const int a0 = tid, a1 = S - 1 - tid;
-        int t0 = a0 - 1 + round, t1 = a1 - 1 + round;
-        if (t0 >= S - 1) t0 -= S - 1;
-        if (t1 >= S - 1) t1 -= S - 1;
-        int p = a0 == 0 ? 0 : 1 + t0;
-        int q = a1 == 0 ? 0 : 1 + t1;
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        double c = 1.0, sn = 0.0;
-        if (q >= s) {
-          q = p;  // idle player
-        } else {
-          const double apq = R2[p * LG + q];
-          const double app = R2[p * LG + p], aqq = R2[q * LG + q];
-          if (fabs(apq) > tol * sqrt(fabs(app * aqq))) {
-            // tan of the angle: t = sign(h) g / (|h| + r), h = g_qq - g_pp,
-            // g = 2 g_pq, r = sqrt(h^2 + g^2); with d = |h| + r,
-            // c = d / sqrt(2 r d) and s = sign(h) g / sqrt(2 r d).
-            const double h = aqq - app, g2 = 2.0 * apq;
-            const double r = sqrt(h * h + g2 * g2);
-            const double d = fabs(h) + r;
-            const double inv = 1.0 / sqrt(2.0 * r * d);
-            c = d * inv;
-            sn = (h >= 0.0 ? g2 : -g2) * inv;
-            s_rot[sweep & 1] = 1;
-          }
-        }
-        pr_pq[tid] = make_int2(p, q);
-        pr_cs[tid] = make_double2(c, sn);
-      }
-      __syncthreads();
-      if (round == 0 && tid == 0) s_rot[(sweep + 1) & 1] = 0;
-      {
-        // G: thread t takes column pair J = t mod npairs and the row pairs
-        // I = t / npairs, + T, + 2 T, ... (T = threads per column pair); the 2 x 2
-        // blocks partition G, so no two threads touch one entry.  Loads first.
-        constexpr int kMaxBlk = 3;  // npairs <= 50 and T >= 20
-        static_assert(kMaxBlk * (kCoreThreads / (kCoreLdsMaxS / 2)) >= kCoreLdsMaxS / 2,
-                      "every row pair is covered");
-        const int T = nt / npairs;
-        if (tid < T * npairs) {
-          const int J = tid % npairs, I0 = tid / npairs;
-          const int2 qj = pr_pq[J];
-          const double2 rj = pr_cs[J];
-          const int pJ = qj.x, qJ = qj.y;
-          double g[kMaxBlk][4];
-          int2 qi[kMaxBlk];
-          double2 ri[kMaxBlk];
-          bool act[kMaxBlk];
-#pragma unroll
-          for (int u = 0; u < kMaxBlk; ++u) {
-            const int I = I0 + u * T;
-            act[u] = false;
-            if (I < npairs) {
-              ri[u] = pr_cs[I];
-              act[u] = ri[u].y != 0.0 || rj.y != 0.0;
-            }
-            if (act[u]) {
-              qi[u] = pr_pq[I];
-              g[u][0] = R2[qi[u].x * LG + pJ];
-              g[u][1] = R2[qi[u].x * LG + qJ];
-              g[u][2] = R2[qi[u].y * LG + pJ];
-              g[u][3] = R2[qi[u].y * LG + qJ];
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < kMaxBlk; ++u) {
-            if (!act[u]) continue;
-            const int I = I0 + u * T;
-            const double cI = ri[u].x, sI = ri[u].y, cJ = rj.x, sJ = rj.y;
-            const int pI = qi[u].x, qI = qi[u].y;
-            // rows: R_I = [[c, -s], [s, c]]
-            const double r00 = cI * g[u][0] - sI * g[u][2], r01 = cI * g[u][1] - sI * g[u][3];
-            const double r10 = sI * g[u][0] + cI * g[u][2], r11 = sI * g[u][1] + cI * g[u][3];
-            // columns: times R_J^T = [[c, s], [-s, c]]
-            double o00 = cJ * r00 - sJ * r01, o01 = sJ * r00 + cJ * r01;
-            double o10 = cJ * r10 - sJ * r11, o11 = sJ * r10 + cJ * r11;
-            if (I == J) {  // the rotated pair's off-diagonal entries are zero
-              o01 = 0.0;
-              o10 = 0.0;
-            }
-            // an idle player has qI == pI (or qJ == pJ): the identity writes the
-            // same value twice from this thread
-            R2[qI * LG + qJ] = o11;
-            R2[qI * LG + pJ] = o10;
-            R2[pI * LG + qJ] = o01;
-            R2[pI * LG + pJ] = o00;
-          }
-        }
-        // V: entry pairs V[k, (p_J, q_J)], consecutive k on consecutive threads
-        for (int vi = tid; vi < npairs * s; vi += nt) {
-          const int J = vi / s, k = vi - J * s;
-          const double2 rj = pr_cs[J];
-          if (rj.y == 0.0) continue;
-          const int2 qj = pr_pq[J];
-          const double v0 = R1[qj.x * s + k], v1 = R1[qj.y * s + k];
-          R1[qj.x * s + k] = rj.x * v0 - rj.y * v1;
-          R1[qj.y * s + k] = rj.y * v0 + rj.x * v1;
-        }
-      }
-      __syncthreads();
-    }
-    if (s_rot[sweep & 1] == 0) break;
-  }
-  // eigenvalues (diagonal of G) sorted descending: thread j finds the rank of
-  // g_jj under the order (value descending, index ascending) with NaN taken as
-  // -inf, a total order, so perm is a permutation of 0..s-1
-  for (int j = tid; j < s; j += nt) {
-    const double vj = R2[j * LG + j];
-    const double kj = vj == vj ? vj : -INFINITY;
-    int rank = 0;
-    for (int i = 0; i < s; ++i) {
-      const double vi = R2[i * LG + i];
-      const double ki = vi == vi ? vi : -INFINITY;
-      rank += (ki > kj || (ki == kj && i < j)) ? 1 : 0;
-    }
-    perm[rank] = (int16_t)j;
-    evals[rank] = vj;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    const double top = evals[0] - mu;
-    int keep = 0;
-    for (int j = 0; j < s; ++j) {
-      if (top > 0.0 && evals[j] - mu > rel_floor * top)
-        keep = j + 1;
-      else
-        break;
-    }
-    s_flag = keep;
-  }
-  __syncthreads();
-  const int keep = s_flag;
-  for (int j = tid; j < s; j += nt) lam_b[j] = (j < keep) ? fmax(evals[j] - mu, 0.0) : 0.0;
-  // reload C into R2
-  for (int e = tid; e < s * s; e += nt) {
-    const int i = e / s, j = e % s;
-    R2[i * LG + j] = Cg[i * SPg + j];
-  }
-  __syncthreads();
-  // T' = C^-T V in place in R1 (column p of V stored at R1[p * s + .])
-  for (int i = s - 1; i >= 0; --i) {
-    const double inv = 1.0 / R2[i * LG + i];
-    for (int p = tid; p < s; p += nt) R1[p * s + i] *= inv;
-    __syncthreads();
-    for (int e = tid; e < s * i; e += nt) {
-      const int p = e / i, l = e % i;
-      R1[p * s + l] -= R2[i * LG + l] * R1[p * s + i];
-    }
-    __syncthreads();
-  }
-  // T(:, j) = T'(:, perm[j]) / sigma_j for the kept columns, zero elsewhere
-  for (int e = tid; e < SPg * SPg; e += nt) {
-    const int j = e / SPg, i = e % SPg;
-    double v = 0.0;
-    if (j < keep && i < s) v = R1[(int)perm[j] * s + i] / sqrt(evals[j]);
-    Tg[(int64_t)j * SPg + i] = v;
-  }
-  if (tid == 0) {
-    s_eff_out[b] = keep;
-    status_out[b] = 0;
-    shift_out[b] = mu;
-  }
-}
-
 // U[b] (n x s, col-major, ld n) = (Y + mu Omega) T  for the first s_eff columns, 0 after.
 template <typename VT, int SP>
 __global__ __launch_bounds__(256) void k_form_u(int64_t n, int s, const VT* __restrict__ Y,
@@ -1051,13 +719,9 @@ hipError_t run_core(const MatArg& A, int64_t batch, int s, const uint8_t* mask, 
   const double jac_tol = sizeof(VT) == 4 ? 1.0e-9 : 1.0e-14;
   hipError_t e = hipSuccess;
   if (s <= kCoreLdsMaxS) {
-    const size_t lds = (size_t)(2 * s * s + s) * sizeof(double);
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nystrom_core_lds),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    e = launch_nystrom_core_lds(batch, s, SP, eps, rel_floor, jac_tol, ws.gram, ws.core, lamhat,
+                                s_eff, status, shift, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_nystrom_core_lds, dim3((unsigned)batch), dim3(kCoreThreads), lds, st, s,
-                       eps, rel_floor, jac_tol, ws.gram, SP, ws.core, lamhat, s, s_eff, status,
-                       shift);
   } else {
     const size_t lds = (size_t)SP * (SP + 1) * sizeof(double);
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nystrom_core<SP>),

@@ -225,8 +225,8 @@ def _compare_nystrom(U, lamhat, Href, Om, s_eff_expect=None, tol=2e-4, u=2.0 ** 
                                          (200, 300, 99, "f64"), (150, 400, 120, "f32"),
                                          (150, 400, 113, "f64")])
 def test_nystrom_build_given_omega(g, m, n, s, prec):
-    # odd s leaves one idle player per Jacobi round; s = 1 has no rotation;
-    # s > 100 takes the core whose matrices live in global memory
+    # s not a multiple of 16 leaves zero padding in the last Jacobi block; s = 1 has
+    # no rotation; s > 100 takes the core whose matrices live in global memory
     print("nystrom_build", m, n, s, prec, flush=True)
     A = _nys_case(m, n, s, seed=m + n)
     if prec == "f64":
