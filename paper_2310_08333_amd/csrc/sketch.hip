@@ -602,41 +602,85 @@ __global__ __launch_bounds__(256) void k_nystrom_core(int s, int64_t n, double e
   }
 }
 
-// U[b] (n x s, col-major, ld n) = (Y + mu Omega) T  for the first s_eff columns, 0 after.
+// U[b] (n x s, col-major, ld n) = (Y + mu Omega) T  for the first s_eff columns, 0 after
+// (T is zero there).  FP64 products on the matrix cores (v_mfma_f64_16x16x4: A[i][k] from
+// lane 16 k + i, B[k][j] from lane 16 k + j, D[4 v + L / 16][L % 16] in register v).  A
+// block of kFuRows rows stages T (s x sc, sc = s rounded up to 16) in LDS once;
+// wavefront w owns rows 16 w .. 16 w + 15 and holds their A operands (Y + mu Omega in
+// FP64) for every K step; each 16-column tile of U is staged in LDS and written a
+// column at a time.
+constexpr int kFuWaves = 8, kFuRows = 16 * kFuWaves;
 template <typename VT, int SP>
-__global__ __launch_bounds__(256) void k_form_u(int64_t n, int s, const VT* __restrict__ Y,
-                                                const VT* __restrict__ omega,
-                                                const double* __restrict__ core,
-                                                const double* __restrict__ shift,
-                                                const int32_t* __restrict__ s_eff_arr,
-                                                VT* __restrict__ U) {
-  constexpr int RB = 64;
-  __shared__ double Yt[RB][SP + 1];
-  const int b = blockIdx.y;
-  const int keep = s_eff_arr[b];
+__global__ __launch_bounds__(64 * kFuWaves) void k_form_u(int64_t n, int s,
+                                                          const VT* __restrict__ Y,
+                                                          const VT* __restrict__ omega,
+                                                          const double* __restrict__ core,
+                                                          const double* __restrict__ shift,
+                                                          VT* __restrict__ U) {
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  constexpr int KS = SP / 4;
+  extern __shared__ double Tl[];  // s rows (k) x (sc + 1), T[k][j]
+  __shared__ VT Ut[16][kFuRows + 4];
+  const int b = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
   const double mu = shift[b];
-  const int64_t row0 = (int64_t)blockIdx.x * RB;
+  const int64_t row0 = (int64_t)blockIdx.x * kFuRows;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
   const VT* Yb = Y + (int64_t)b * n * SP;
   const VT* Ob = omega + (int64_t)b * n * SP;
   const double* Tg = core + (int64_t)b * 5 * SP * SP + 4 * SP * SP;
-  for (int e = threadIdx.x; e < RB * SP; e += blockDim.x) {
-    const int k = e / RB, r = e % RB;
-    const int64_t i = row0 + r;
-    double v = 0.0;
-    if (i < n && k < s) v = double(Yb[(int64_t)k * n + i]) + mu * double(Ob[(int64_t)k * n + i]);
-    Yt[r][k] = v;
+  VT* Ub = U + (int64_t)b * n * s;
+  const int sc = (s + 15) / 16 * 16, lt = sc + 1;
+  // T into LDS (eight loads in flight per thread)
+  for (int e0 = tid; e0 < s * sc; e0 += 8 * nt) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * nt;
+      v[u] = e < s * sc ? Tg[(int64_t)(e / s) * SP + e % s] : 0.0;  // column e / s, row e % s
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * nt;
+      if (e < s * sc) Tl[(e % s) * lt + e / s] = v[u];
+    }
+  }
+  const int nks = (s + 3) / 4;
+  const int64_t r = row0 + 16 * wave + li;
+  const int64_t rc = r < n ? r : n - 1;  // clamped: every load is issued unconditionally
+  VT ya[KS], oa[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int kc = min(4 * ks + lk, s - 1);
+    ya[ks] = Yb[(int64_t)kc * n + rc];
+    oa[ks] = Ob[(int64_t)kc * n + rc];
   }
   __syncthreads();
-  const int r = threadIdx.x % RB, grp = threadIdx.x / RB;
-  const int64_t i = row0 + r;
-  VT* Ub = U + (int64_t)b * n * s;
-  for (int j = grp; j < s; j += blockDim.x / RB) {
-    double acc = 0.0;
-    if (j < keep) {
-      const double* tcol = Tg + (int64_t)j * SP;
-      for (int k = 0; k < s; ++k) acc += Yt[r][k] * tcol[k];
+  double a[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const bool ok = r < n && 4 * ks + lk < s;
+    a[ks] = ok ? double(ya[ks]) + mu * double(oa[ks]) : 0.0;
+  }
+  for (int j0 = 0; j0 < s; j0 += 16) {
+    v4d d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + lk;
+      if (ks < nks) d = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], k < s ? Tl[k * lt + j0 + li] : 0.0,
+                                                             d, 0, 0, 0);
     }
-    if (i < n) Ub[(int64_t)j * n + i] = VT(acc);
+    // D[4 v + lk][li]: row 16 wave + 4 v + lk of the block, column j0 + li
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Ut[li][16 * wave + 4 * v + lk] = VT(d[v]);
+    __syncthreads();
+    for (int e = tid; e < 16 * kFuRows; e += nt) {
+      const int c = e / kFuRows, q = e - c * kFuRows;
+      const int j = j0 + c;
+      const int64_t i = row0 + q;
+      if (j < s && i < n) Ub[(int64_t)j * n + i] = Ut[c][q];
+    }
+    __syncthreads();
   }
 }
 
@@ -732,10 +776,17 @@ hipError_t run_core(const MatArg& A, int64_t batch, int s, const uint8_t* mask, 
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  dim3 g3((unsigned)((n + 63) / 64), (unsigned)batch);
-  hipLaunchKernelGGL((k_form_u<VT, SP>), g3, dim3(256), 0, st, n, s,
-                     static_cast<const VT*>(ws.Y), static_cast<const VT*>(ws.omega), ws.core,
-                     shift, s_eff, static_cast<VT*>(U));
+  {
+    const int sc = (s + 15) / 16 * 16;
+    const size_t lds = (size_t)s * (sc + 1) * sizeof(double);
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_form_u<VT, SP>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    dim3 g3((unsigned)((n + kFuRows - 1) / kFuRows), (unsigned)batch);
+    hipLaunchKernelGGL((k_form_u<VT, SP>), g3, dim3(64 * kFuWaves), lds, st, n, s,
+                       static_cast<const VT*>(ws.Y), static_cast<const VT*>(ws.omega), ws.core,
+                       shift, static_cast<VT*>(U));
+  }
   return hipGetLastError();
 }
 
