@@ -268,6 +268,15 @@ typedef struct {
   int32_t n_hvp_resized;     /* batch of matrices of 256 MB or more: fused H p launches whose grid
                                 was sized for the running problems (more than 8, fewer than all) */
   int32_t reserved3;
+  double bf16_bound;         /* GENIOS_PREC_BF16_ONLY: a-posteriori bound on F(z) - F* from the
+                                rounding of A to BF16 alone (no FP32 pass): with E = A - A~,
+                                |E| <= u |A~|, u = 2^-8 / (1 - 2^-8), twice the perturbation
+                                bound at z, u ||A~ z - b|| || |A~| |z| || + u^2 || |A~| |z| ||^2 / 2
+                                (square loss), u sum_i |y_i| (|A~| |z|)_i (logistic),
+                                2 delta u sum_i (|A~| |z|)_i (Huber); the bound's second term
+                                evaluates the perturbation at z in place of the unknown
+                                optimum.  rel_gap (FP32 master) certifies F(z) - F* itself.
+                                0 for the other precisions */
 } genios_info;
 
 /* Fill *o with the defaults listed above.  Returns GENIOS_OK. */

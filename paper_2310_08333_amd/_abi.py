@@ -87,7 +87,7 @@ class Info(C.Structure):
                 ("kappa_bound", C.c_double), ("sketch_rounds", C.c_int32),
                 ("n_hvp_mrhs", C.c_int32), ("t_hvp_mrhs", C.c_double),
                 ("bytes_hvp_mrhs", C.c_int64), ("n_hvp_resized", C.c_int32),
-                ("reserved3", C.c_int32)]
+                ("reserved3", C.c_int32), ("bf16_bound", C.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -1278,6 +1278,39 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
   if (rc) return rc;
   rc = read_gap();
   if (rc) return rc;
+  // BF16-only: the a-posteriori bound on F(z) - F* from the rounding of A alone.  With
+  // E = A - A~ and |E| <= u |A~| (round to nearest, u = 2^-8 / (1 - 2^-8)), the objective
+  // perturbation at x is |D(x)| <= ||A~ x - b|| u || |A~| |x| || + u^2 || |A~| |x| ||^2 / 2
+  // for the square loss and <= L u sum_i w_i (|A~| |x|)_i for a loss of slope at most
+  // L w_i on sample i (logistic: w_i = |y_i|, Huber: L = 2 delta); the bound is
+  // |D(z)| + |D(x*)| with x* replaced by z, i.e. 2 |D(z)|.
+  std::vector<double> bf16_bound(B, 0.0);
+  if (prec == GENIOS_PREC_BF16_ONLY) {
+    const int ns = c.nsplit_for(c.op_lo, 0);
+    const int64_t ps = (int64_t)c.L.nsplit_n * m;
+    HC(launch_gemv_n_abs(c.op_lo, B, c.vt, z, n, c.L.tparts, m, ps, ns, c.st));
+    HC(launch_bound_terms(c.vt, m, B, c.L.tparts, ns, m, ps, bvec, m, 0, c.L.gpart, c.st));
+    if (loss == kLossSquare) {
+      HC(launch_gemv_n(c.op_lo, B, c.vt, z, n, c.L.tparts, m, ps, ns, nullptr, 0, c.st));
+      HC(launch_bound_terms(c.vt, m, B, c.L.tparts, ns, m, ps, bvec, m, 1, c.L.gpart, c.st));
+    }
+    std::vector<double> hb(4 * (size_t)B, 0.0);
+    HC(hipMemcpyAsync(hb.data(), c.L.gpart, hb.size() * sizeof(double), hipMemcpyDeviceToHost,
+                      c.st));
+    HC(hipStreamSynchronize(c.st));
+    const double ur = 0x1p-8 / (1.0 - 0x1p-8);
+    for (int64_t b = 0; b < B; ++b) {
+      const double sy2 = hb[4 * b], sy = hb[4 * b + 1], sr2 = hb[4 * b + 2], swy = hb[4 * b + 3];
+      double d = 0.0;
+      if (loss == kLossSquare)
+        d = ur * std::sqrt(sr2) * std::sqrt(sy2) + 0.5 * ur * ur * sy2;
+      else if (loss == kLossLogistic)
+        d = ur * swy;
+      else
+        d = 2.0 * delta * ur * sy;
+      bf16_bound[b] = 2.0 * d;
+    }
+  }
   const double t_total = now_s() - t0;
   int worst = GENIOS_OK;
   for (int64_t b = 0; b < B; ++b) {
@@ -1306,6 +1339,7 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     I.r_kkt = kkt_from(I.r_p, I.r_d, q.xn, q.zn, q.rho * q.un, n);
     I.obj = hg[b].primal;
     I.rel_gap = hg[b].rel_gap;
+    I.bf16_bound = bf16_bound[b];
     I.gap_primal = hg[b].primal;
     I.gap_dual = hg[b].dual;
     I.gap_checks = q.gap_checks;

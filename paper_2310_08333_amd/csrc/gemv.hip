@@ -32,7 +32,7 @@ constexpr int gemv_n_rows() {
   return sizeof(T) == 2 ? 8 : 4;
 }
 
-template <typename T, typename VT, int ROWS, bool VEC>
+template <typename T, typename VT, int ROWS, bool VEC, bool ABS = false>
 __global__ __launch_bounds__(256) void k_gemv_n(const T* __restrict__ A, int64_t lda,
                                                 int64_t strideA, int m, int n,
                                                 const VT* __restrict__ v, int64_t v_stride,
@@ -66,21 +66,35 @@ __global__ __launch_bounds__(256) void k_gemv_n(const T* __restrict__ A, int64_t
       for (int r = 0; r < ROWS; ++r) Elem<T>::load(rowp[r] + c, av[r]);
       Acc vv[V];
       load_vec<VT, Acc, V>(vb + c, vv);
+      if constexpr (ABS) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) vv[j] = fabs(vv[j]);
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+          for (int j = 0; j < V; ++j) av[r][j] = fabs(av[r][j]);
+      }
 #pragma unroll
       for (int r = 0; r < ROWS; ++r)
 #pragma unroll
         for (int j = 0; j < V; ++j) acc[r] += av[r][j] * vv[j];
     }
     for (int cc = c; cc < c1 && cc < c + V; ++cc) {
-      const Acc vv = Acc(vb[cc]);
+      const Acc vv = ABS ? fabs(Acc(vb[cc])) : Acc(vb[cc]);
 #pragma unroll
-      for (int r = 0; r < ROWS; ++r) acc[r] += Elem<T>::cvt(rowp[r][cc]) * vv;
+      for (int r = 0; r < ROWS; ++r) {
+        const Acc a = Elem<T>::cvt(rowp[r][cc]);
+        acc[r] += (ABS ? fabs(a) : a) * vv;
+      }
     }
   } else {
     for (int cc = c0 + lane; cc < c1; cc += 64) {
-      const Acc vv = Acc(vb[cc]);
+      const Acc vv = ABS ? fabs(Acc(vb[cc])) : Acc(vb[cc]);
 #pragma unroll
-      for (int r = 0; r < ROWS; ++r) acc[r] += Elem<T>::cvt(rowp[r][cc]) * vv;
+      for (int r = 0; r < ROWS; ++r) {
+        const Acc a = Elem<T>::cvt(rowp[r][cc]);
+        acc[r] += (ABS ? fabs(a) : a) * vv;
+      }
     }
   }
 #pragma unroll
@@ -234,7 +248,7 @@ int gemv_t_rows_per_split(const MatArg& A, int ksplit) {
   return (int)((A.m + ksplit - 1) / ksplit);
 }
 
-template <typename T, typename VT>
+template <typename T, typename VT, bool ABS = false>
 static hipError_t gemv_n_t(const MatArg& A, int64_t batch, const VT* v, int64_t v_stride, VT* out,
                            int64_t oss, int64_t ops, int nsplit, const int32_t* gate, int gs,
                            hipStream_t st) {
@@ -247,11 +261,11 @@ static hipError_t gemv_n_t(const MatArg& A, int64_t batch, const VT* v, int64_t 
   const bool vec = vec_ok(A) && (reinterpret_cast<uintptr_t>(v) % 16 == 0) && (v_stride % V == 0);
   const T* Ap = static_cast<const T*>(A.ptr);
   if (vec)
-    hipLaunchKernelGGL((k_gemv_n<T, VT, R, true>), grid, dim3(256), 0, st, Ap, A.lda, A.strideA,
-                       (int)A.m, (int)A.n, v, v_stride, out, oss, ops, cps, gate, gs);
+    hipLaunchKernelGGL((k_gemv_n<T, VT, R, true, ABS>), grid, dim3(256), 0, st, Ap, A.lda,
+                       A.strideA, (int)A.m, (int)A.n, v, v_stride, out, oss, ops, cps, gate, gs);
   else
-    hipLaunchKernelGGL((k_gemv_n<T, VT, R, false>), grid, dim3(256), 0, st, Ap, A.lda, A.strideA,
-                       (int)A.m, (int)A.n, v, v_stride, out, oss, ops, cps, gate, gs);
+    hipLaunchKernelGGL((k_gemv_n<T, VT, R, false, ABS>), grid, dim3(256), 0, st, Ap, A.lda,
+                       A.strideA, (int)A.m, (int)A.n, v, v_stride, out, oss, ops, cps, gate, gs);
   return hipGetLastError();
 }
 
@@ -270,6 +284,91 @@ hipError_t launch_gemv_n(const MatArg& A, int64_t batch, VType vt, const void* v
   if (A.mt != MT_F64) return hipErrorInvalidValue;
   return gemv_n_t<double, double>(A, batch, static_cast<const double*>(v), v_stride,
                                   static_cast<double*>(out), oss, ops, nsplit, gate, gs, st);
+}
+
+// |A| |v| (elementwise absolute values of both), the same split partials as launch_gemv_n.
+hipError_t launch_gemv_n_abs(const MatArg& A, int64_t batch, VType vt, const void* v,
+                             int64_t v_stride, void* out, int64_t oss, int64_t ops, int nsplit,
+                             hipStream_t st) {
+  if (vt == VT_F32) {
+    const float* vv = static_cast<const float*>(v);
+    float* o = static_cast<float*>(out);
+    if (A.mt == MT_BF16)
+      return gemv_n_t<uint16_t, float, true>(A, batch, vv, v_stride, o, oss, ops, nsplit, nullptr,
+                                             0, st);
+    if (A.mt == MT_F32)
+      return gemv_n_t<float, float, true>(A, batch, vv, v_stride, o, oss, ops, nsplit, nullptr, 0,
+                                          st);
+    return hipErrorInvalidValue;
+  }
+  if (A.mt != MT_F64) return hipErrorInvalidValue;
+  return gemv_n_t<double, double, true>(A, batch, static_cast<const double*>(v), v_stride,
+                                        static_cast<double*>(out), oss, ops, nsplit, nullptr, 0,
+                                        st);
+}
+
+namespace {
+// One block per problem: y_i = sum over the nsplit partials (fixed order) of row i, then
+// out[4 b + 0] = sum y_i^2, out[4 b + 1] = sum |y_i| and out[4 b + 3] = sum |c_i| |y_i|
+// (mode 0), or out[4 b + 2] = sum (y_i - c_i)^2 (mode 1, c the right-hand side).
+// Fixed-order sums.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_bound_terms(int64_t m, const VT* __restrict__ parts,
+                                                     int nsplit, int64_t split_stride,
+                                                     int64_t prob_stride,
+                                                     const VT* __restrict__ c, int64_t c_stride,
+                                                     int mode, double* __restrict__ out) {
+  __shared__ double red[3][256];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const VT* pb = parts + (int64_t)b * prob_stride;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int64_t i = tid; i < m; i += 256) {
+    double y = 0.0;
+    for (int k = 0; k < nsplit; ++k) y += double(pb[(int64_t)k * split_stride + i]);
+    const double ci = double(c[(int64_t)b * c_stride + i]);
+    if (mode == 0) {
+      s0 += y * y;
+      s1 += fabs(y);
+      s2 += fabs(ci) * fabs(y);
+    } else {
+      s0 += (y - ci) * (y - ci);
+    }
+  }
+  red[0][tid] = s0;
+  red[1][tid] = s1;
+  red[2][tid] = s2;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) red[q][tid] += red[q][tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (mode == 0) {
+      out[4 * b + 0] = red[0][0];
+      out[4 * b + 1] = red[1][0];
+      out[4 * b + 3] = red[2][0];
+    } else {
+      out[4 * b + 2] = red[0][0];
+    }
+  }
+}
+}  // namespace
+
+hipError_t launch_bound_terms(VType vt, int64_t m, int64_t batch, const void* parts, int nsplit,
+                              int64_t split_stride, int64_t prob_stride, const void* c,
+                              int64_t c_stride, int mode, double* out, hipStream_t st) {
+  if (vt == VT_F32)
+    hipLaunchKernelGGL(k_bound_terms<float>, dim3((unsigned)batch), dim3(256), 0, st, m,
+                       static_cast<const float*>(parts), nsplit, split_stride, prob_stride,
+                       static_cast<const float*>(c), c_stride, mode, out);
+  else
+    hipLaunchKernelGGL(k_bound_terms<double>, dim3((unsigned)batch), dim3(256), 0, st, m,
+                       static_cast<const double*>(parts), nsplit, split_stride, prob_stride,
+                       static_cast<const double*>(c), c_stride, mode, out);
+  return hipGetLastError();
 }
 
 template <typename T, typename VT, int NR>

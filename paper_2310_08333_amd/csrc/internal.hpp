@@ -149,6 +149,15 @@ struct MatArg {
 hipError_t launch_gemv_n(const MatArg& A, int64_t batch, VType vt, const void* v, int64_t v_stride,
                          void* out, int64_t out_split_stride, int64_t out_prob_stride, int nsplit,
                          const int32_t* gate, int gate_stride_ints, hipStream_t st);
+// |A| |v| with elementwise absolute values (same partial layout as launch_gemv_n).
+hipError_t launch_gemv_n_abs(const MatArg& A, int64_t batch, VType vt, const void* v,
+                             int64_t v_stride, void* out, int64_t oss, int64_t ops, int nsplit,
+                             hipStream_t st);
+// Per problem (4 doubles each) of the split-summed rows y: mode 0 writes sum y^2 at [0],
+// sum |y| at [1] and sum |c| |y| at [3]; mode 1 writes sum (y - c)^2 at [2].
+hipError_t launch_bound_terms(VType vt, int64_t m, int64_t batch, const void* parts, int nsplit,
+                              int64_t split_stride, int64_t prob_stride, const void* c,
+                              int64_t c_stride, int mode, double* out, hipStream_t st);
 // Partials of y = A^T (d o sum_s tin_s) over `ksplit` row splits, for nrhs columns:
 // ypart[b][ks][k][npad].  tin[k] column at tin + k * tin_col_stride.
 hipError_t launch_gemv_t(const MatArg& A, int64_t batch, VType vt, const void* tin, int nsplit_in,

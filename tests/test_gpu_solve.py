@@ -6,6 +6,7 @@ import torch
 import genios_data
 from oracle import adaptive as oadapt
 from oracle import adjoint as oadj
+from oracle import bf16 as obf16
 from oracle import boxls as oboxls
 from oracle import huber as ohuber
 from oracle import lasso as olasso
@@ -1110,3 +1111,47 @@ def test_refinement_cg_operator_modes_reach_the_same_answer(g, eps):
     (F0, i0), (F1, i1) = res[0], res[1]
     assert abs(i1["iters"] - i0["iters"]) <= max(3, 0.1 * i0["iters"])
     assert _rel(F1, F0) <= (1e-6 if eps <= 1e-6 else 2e-3)
+
+
+def _bf16_bound_host(A, b, z, loss, delta=1.0):
+    # reading of the BF16-only bound, evaluated on the host at the returned z with the
+    # BF16-rounded matrix: u = 2^-8 / (1 - 2^-8), y = |A~| |z|
+    u = 2.0 ** -8 / (1.0 - 2.0 ** -8)
+    Ab = obf16.round_to_bf16(A).astype(np.float64)
+    y = np.abs(Ab) @ np.abs(z)
+    if loss == "square":
+        r = Ab @ z - b.astype(np.float64)
+        d = u * np.linalg.norm(r) * np.linalg.norm(y) + 0.5 * u * u * float(y @ y)
+    elif loss == "logistic":
+        d = u * float(np.abs(b.astype(np.float64)) @ y)
+    else:
+        d = 2.0 * delta * u * float(np.sum(y))
+    return 2.0 * d
+
+
+@pytest.mark.parametrize("loss", ["square", "logistic", "huber"])
+def test_bf16_only_reports_its_rounding_bound(g, cfg1, logsmall, hubsmall, loss):
+    # The BF16-only bound on F(z) - F*: matches its formula evaluated on the host at the
+    # returned z, bounds the true objective error against the certified optimum, and is
+    # zero for the other precisions.
+    print("bf16-only bound", loss, flush=True)
+    if loss == "square":
+        P, b, run, obj = cfg1, cfg1["b"], g.lasso_solve, olasso.objective
+        kw = dict(sketch_rank=cfg1["s"])
+    elif loss == "logistic":
+        P, b, run, obj = logsmall, logsmall["y"], g.logreg_solve, ologreg.objective
+        kw = dict(sketch_rank=logsmall["s"], resketch_every=20)
+    else:
+        P, b, run, obj = hubsmall, hubsmall["b"], g.huber_solve, ohuber.objective
+        kw = dict(sketch_rank=10, resketch_every=20)
+    out = run(_t(P["A"]), _t(b), P["lam"], precision="bf16_only", eps=1e-6, max_iter=20000, **kw)
+    info = out["info"][0]
+    assert out["status"] == 0, info
+    z = out["z"].cpu().numpy().astype(np.float64)
+    bnd = info["bf16_bound"]
+    ref = _bf16_bound_host(P["A"], b, z, loss)
+    assert bnd > 0.0 and abs(bnd - ref) <= 1e-4 * ref, (bnd, ref)
+    F = obj(P["A"].astype(np.float64), b.astype(np.float64), P["lam"], z)
+    assert F - P["sol"]["F"] <= bnd, (F, P["sol"]["F"], bnd)
+    out32 = run(_t(P["A"]), _t(b), P["lam"], precision="f32", eps=1e-5, **kw)
+    assert out32["info"][0]["bf16_bound"] == 0.0
