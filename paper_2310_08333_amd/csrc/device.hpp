@@ -13,6 +13,26 @@ __device__ __forceinline__ float bf16_bits_to_float(uint16_t h) {
   return __uint_as_float(static_cast<uint32_t>(h) << 16);
 }
 
+// 16-byte loads of the matrix, which every product streams once: non-temporal,
+// so that A passes through the caches at the eviction end and leaves the
+// vectors, partials and U resident (measured: a plain read of a 1.6 GB buffer
+// runs at 6.2 TB/s, the same read non-temporal at 7.0 TB/s).
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+template <typename VEC>
+__device__ __forceinline__ VEC load_stream(const void* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const VEC*>(p));
+}
+__device__ __forceinline__ uint4 load_stream_u4(const void* p) {
+  const u32x4_t q = load_stream<u32x4_t>(p);
+  return make_uint4(q.x, q.y, q.z, q.w);
+}
+__device__ __forceinline__ float4 load_stream_f4(const void* p) {
+  const f32x4_t q = load_stream<f32x4_t>(p);
+  return make_float4(q.x, q.y, q.z, q.w);
+}
+
 template <typename T>
 struct Elem;
 template <>
@@ -21,7 +41,7 @@ struct Elem<uint16_t> {
   static constexpr int V = 8;  // elements per 16-byte load
   __device__ static __forceinline__ float cvt(uint16_t x) { return bf16_bits_to_float(x); }
   __device__ static __forceinline__ void load(const uint16_t* p, float (&o)[8]) {
-    const uint4 q = *reinterpret_cast<const uint4*>(p);
+    const u32x4_t q = load_stream<u32x4_t>(p);
     o[0] = __uint_as_float(q.x << 16);
     o[1] = __uint_as_float(q.x & 0xffff0000u);
     o[2] = __uint_as_float(q.y << 16);
@@ -38,7 +58,7 @@ struct Elem<float> {
   static constexpr int V = 4;
   __device__ static __forceinline__ float cvt(float x) { return x; }
   __device__ static __forceinline__ void load(const float* p, float (&o)[4]) {
-    const float4 q = *reinterpret_cast<const float4*>(p);
+    const f32x4_t q = load_stream<f32x4_t>(p);
     o[0] = q.x;
     o[1] = q.y;
     o[2] = q.z;
@@ -51,7 +71,7 @@ struct Elem<double> {
   static constexpr int V = 2;
   __device__ static __forceinline__ double cvt(double x) { return x; }
   __device__ static __forceinline__ void load(const double* p, double (&o)[2]) {
-    const double2 q = *reinterpret_cast<const double2*>(p);
+    const f64x2_t q = load_stream<f64x2_t>(p);
     o[0] = q.x;
     o[1] = q.y;
   }

@@ -444,7 +444,9 @@ hipError_t launch_gemv_t(const MatArg& A, int64_t batch, VType vt, const void* t
 
 // ---- fused Hessian-vector product ---------------------------------------------
 // hp = A^T (d o (A p)) in one pass over A (Sec. 3.1 HVP example, Sec. 3.3 ML
-// Hessian with D = diag(d)).  A block owns a contiguous row range.  p sits in
+// Hessian with D = diag(d)).  Of the G blocks of a problem, block g owns the
+// rows g, g + G, g + 2G, ..., so the grid reads A as one band moving down the
+// matrix (measured faster than G separate row ranges), with non-temporal loads.  p sits in
 // LDS (FP32); thread t owns the 16-byte column chunks c = V (t + THREADS k) and
 // keeps their share of the result in registers.  Each row's chunks are loaded
 // once (packed; the next row's loads are in flight while a row is processed),
@@ -459,25 +461,25 @@ template <typename T>
 struct Raw;
 template <>
 struct Raw<uint16_t> {
-  using type = uint4;  // 8 BF16
-  __device__ static __forceinline__ float get(const uint4& q, int e) {
+  using type = u32x4_t;  // 8 BF16
+  __device__ static __forceinline__ float get(const u32x4_t& q, int e) {
     const uint32_t w = e < 2 ? q.x : (e < 4 ? q.y : (e < 6 ? q.z : q.w));
     return __uint_as_float((e & 1) ? (w & 0xffff0000u) : (w << 16));
   }
   // The same value through a byte permute: a second, differently written unpack,
   // so the compiler recomputes it instead of keeping the first one's results live.
-  __device__ static __forceinline__ float get2(const uint4& q, int e) {
+  __device__ static __forceinline__ float get2(const u32x4_t& q, int e) {
     const uint32_t w = e < 2 ? q.x : (e < 4 ? q.y : (e < 6 ? q.z : q.w));
     return __uint_as_float(__builtin_amdgcn_perm(w, w, (e & 1) ? 0x07060c0cu : 0x05040c0cu));
   }
 };
 template <>
 struct Raw<float> {
-  using type = float4;
-  __device__ static __forceinline__ float get(const float4& q, int e) {
+  using type = f32x4_t;
+  __device__ static __forceinline__ float get(const f32x4_t& q, int e) {
     return e == 0 ? q.x : (e == 1 ? q.y : (e == 2 ? q.z : q.w));
   }
-  __device__ static __forceinline__ float get2(const float4& q, int e) { return get(q, e); }
+  __device__ static __forceinline__ float get2(const f32x4_t& q, int e) { return get(q, e); }
 };
 
 // Fixed-order wavefront sum without LDS traffic: DPP butterflies inside each
@@ -505,7 +507,7 @@ template <typename T, int THREADS, int EPT, int D>
 __global__ __launch_bounds__(THREADS) void k_hvp_fused(
     const T* __restrict__ A, int64_t lda, int64_t strideA, int m, int n,
     const float* __restrict__ p, int64_t p_stride, const float* __restrict__ d, int64_t d_stride,
-    float* __restrict__ ypart, int64_t ks_stride, int64_t prob_stride, int rows_per_block,
+    float* __restrict__ ypart, int64_t ks_stride, int64_t prob_stride,
     const int32_t* __restrict__ gate, int gate_stride, double* __restrict__ pqpart,
     int64_t pq_stride) {
   static_assert(D >= 0 && D <= 2, "prefetch depth 0..2");
@@ -518,8 +520,9 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
   const int b = blockIdx.y;
   if (gate != nullptr && gate[(int64_t)b * gate_stride] == 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r0 = blockIdx.x * rows_per_block;
-  const int r1 = min(m, r0 + rows_per_block);
+  // the block's rows by local index i in [r0, r1): row blockIdx.x + i * gridDim.x
+  const int G = (int)gridDim.x;
+  const int r0 = 0, r1 = (m - (int)blockIdx.x + G - 1) / G;
   // p in LDS, owner-major: the first NC - 1 chunks of thread t at t (NC - 1) V,
   // the (possibly partial) last chunk row after them, so a thread reads its
   // values from one base with small immediate offsets.  Exactly n floats.
@@ -537,12 +540,23 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
   const float lmask = last_ok ? 1.f : 0.f;  // the last chunk's p, zeroed past n (no branch)
   // A row's loads stay together and in chunk order (the scheduler may not move
   // other work across them), so a buffer's first chunk is the first to arrive
-  // and the wait before each use covers only the loads issued before it.
-  auto load_row = [&](int row, RT (&dst)[NC]) {
+  // and the wait before each use covers only the loads issued before it.  The
+  // row's d_i goes out first, as a buffer load: a vector load, retired in order
+  // with the row's chunks.  (A scalar load, issued as late as its use, would
+  // put its latency on every row: consecutive rows of a block are G apart in d.)
+  // Raw buffer over the problem's m values of d (word 3: 32-bit data format).
+  // The load is unconditional (a load under a branch gets a full wait at the
+  // join): without d the buffer has no records, so the load at offset 0 is out
+  // of range, touches no memory and returns 0 (its value is not used).
+  const __amdgpu_buffer_rsrc_t drs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(db ? db : p), 0, db ? m * 4 : 0, 0x00020000);
+  auto load_row = [&](int i, RT (&dst)[NC], float& dv) {
+    const int row = (int)blockIdx.x + i * G;
     const T* rp = Ab + (int64_t)row * lda;
     __builtin_amdgcn_sched_barrier(0);
+    dv = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(drs, db ? row * 4 : 0, 0, 0));
 #pragma unroll
-    for (int k = 0; k < NC; ++k) dst[k] = *reinterpret_cast<const RT*>(rp + col(k));
+    for (int k = 0; k < NC; ++k) dst[k] = load_stream<RT>(rp + col(k));
     __builtin_amdgcn_sched_barrier(0);
   };
   float y[NC][V];
@@ -554,7 +568,7 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
   // p^T H p of the block's rows, sum of d_i (a_i^T p)^2 (the same value in every thread)
   double pq = 0.0;
   // one row: dot with p, block reduction, scale, rank-one update of the owned columns
-  auto process = [&](RT (&cur)[NC], int r) {
+  auto process = [&](RT (&cur)[NC], float dv) {
     float s = 0.f;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
@@ -575,7 +589,7 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
 #pragma unroll
     for (int w = 0; w < W; ++w) t += red[par][w];
     const float traw = t;
-    if (db) t *= db[__builtin_amdgcn_readfirstlane(r)];  // uniform: a scalar load
+    if (db) t *= dv;
     pq = fma(double(traw), double(t), pq);
     par ^= 1;
 #pragma unroll
@@ -593,6 +607,7 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
   // (Every block owns at least one row: r0 < r1.)
   auto clampr = [&](int r) { return r < r1 ? r : r1 - 1; };
   RT b0[NC], b1[NC], b2[NC];
+  float d0 = 1.f, d1 = 1.f, d2 = 1.f;
   // Prologue: each thread loads the p values of the chunks it owns (16-byte
   // loads, all independent), then the first row's loads go out, then p is
   // written to LDS.  Loads retire in issue order, so the wait for p leaves
@@ -605,7 +620,7 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
 #pragma unroll
       for (int e4 = 0; e4 < V / 4; ++e4)
         pv[k][e4] = *reinterpret_cast<const float4*>(pb + col(k) + 4 * e4);
-    load_row(r0, b0);
+    load_row(r0, b0, d0);
 #pragma unroll
     for (int k = 0; k < NC - 1; ++k)
 #pragma unroll
@@ -619,29 +634,29 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
   }
   if constexpr (D >= 2) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    load_row(clampr(r0 + 1), b1);
+    load_row(clampr(r0 + 1), b1, d1);
   }
   __syncthreads();  // p in LDS
   if constexpr (D == 0) {
     for (int r = r0; r < r1; ++r) {
-      process(b0, r);
-      load_row(clampr(r + 1), b0);
+      process(b0, d0);
+      load_row(clampr(r + 1), b0, d0);
     }
   } else if constexpr (D == 1) {
     for (int r = r0; r < r1; r += 2) {
-      load_row(clampr(r + 1), b1);
-      process(b0, r);
-      load_row(clampr(r + 2), b0);
-      if (r + 1 < r1) process(b1, r + 1);
+      load_row(clampr(r + 1), b1, d1);
+      process(b0, d0);
+      load_row(clampr(r + 2), b0, d0);
+      if (r + 1 < r1) process(b1, d1);
     }
   } else {
     for (int r = r0; r < r1; r += 3) {
-      load_row(clampr(r + 2), b2);
-      process(b0, r);
-      load_row(clampr(r + 3), b0);
-      if (r + 1 < r1) process(b1, r + 1);
-      load_row(clampr(r + 4), b1);
-      if (r + 2 < r1) process(b2, r + 2);
+      load_row(clampr(r + 2), b2, d2);
+      process(b0, d0);
+      load_row(clampr(r + 3), b0, d0);
+      if (r + 1 < r1) process(b1, d1);
+      load_row(clampr(r + 4), b1, d1);
+      if (r + 2 < r1) process(b2, d2);
     }
   }
   if (pqpart != nullptr && tid == 0) pqpart[(int64_t)b * pq_stride + blockIdx.x] = pq;
@@ -791,18 +806,26 @@ hipError_t hvp_launch_one(const MatArg& A, const HvpGeom& g, int64_t batch, cons
   }
   hipLaunchKernelGGL(fn, dim3((unsigned)g.blocks, (unsigned)batch), dim3(THREADS), lds, st,
                      static_cast<const T*>(A.ptr), A.lda, A.strideA, (int)A.m, (int)A.n, p,
-                     p_stride, d, d_stride, ypart, ks_stride, prob_stride, g.rows_per_block, gate,
-                     gate_stride, pq, pq_stride);
+                     p_stride, d, d_stride, ypart, ks_stride, prob_stride, gate, gate_stride, pq,
+                     pq_stride);
   return hipGetLastError();
 }
 
-// Prefetch depth (rows in flight while one is processed) that fits the register
-// budget of the block size: D + 1 packed row buffers plus the EPT owned results.
+// Prefetch depth (rows in flight while one is processed): one row when every
+// row the shape serves (n > THREADS (EPT - V)) is at least 24 KB, else two
+// (measured, non-temporal loads: 20000 x 40000 BF16 6.17 against 5.96 TB/s with
+// two rows ahead, 32000 x 16000 BF16 6.85 against 6.67; 20000 x 5000 FP32 with
+// 1024 threads 6.38 with two), within the register budget of the block size:
+// D + 1 packed row buffers plus the EPT owned results.
 template <typename T, int THREADS, int EPT>
 constexpr int hvp_depth() {
   constexpr int row_regs = EPT * (int)sizeof(T) / 4;
   constexpr int budget = THREADS >= 1024 ? 80 : 210;
-  return (3 * row_regs + EPT <= budget) ? 2 : ((2 * row_regs + EPT <= budget) ? 1 : 0);
+  constexpr int min_row = THREADS * (EPT - Elem<T>::V) * (int)sizeof(T);
+  constexpr int max_depth = min_row >= 24576 ? 1 : 2;
+  return (max_depth >= 2 && 3 * row_regs + EPT <= budget)
+             ? 2
+             : ((2 * row_regs + EPT <= budget) ? 1 : 0);
 }
 
 template <typename T, int THREADS, int... E>
@@ -848,13 +871,18 @@ HvpGeom hvp_geometry(const MatArg& A, int64_t batch, bool query_device) {
   if (A.n % V || A.lda % V || (batch > 1 && A.strideA % V)) return g;
   if (reinterpret_cast<uintptr_t>(A.ptr) % 16) return g;
   if (A.n * (int64_t)sizeof(float) > kHvpLdsBytes) return g;
-  // 256 threads for short rows; 1024 while 32 (BF16) / 40 (FP32) owned columns per
-  // thread suffice; beyond, 512 threads with up to 80 owned columns (2 waves per
-  // SIMD leave room for deeper row prefetch).
-  const int e_small = A.mt == MT_BF16 ? 32 : 16, e_mid = A.mt == MT_BF16 ? 32 : 40;
+  // 256 threads (up to two blocks per CU) for short rows; 1024 threads while 8
+  // owned columns per thread suffice (FP32 only: BF16 rows that short take the
+  // 256-thread shape); beyond, one block of 512 threads per CU with up to 80 owned
+  // columns.  Measured with non-temporal loads: 512 threads against 1024 at
+  // 20000 x 40000 FP32 6.72 / 6.54 TB/s, at 32000 x 16000 BF16 6.85 / 6.77 and
+  // FP32 6.75 / 6.67; at 20000 x 5000 BF16 two 256-thread blocks per CU 5.77
+  // against four 4.82 (the block partials of H p grow with the grid), FP32 one
+  // 1024-thread block 6.38 against four 256-thread blocks 5.50.
+  const int e_small = A.mt == MT_BF16 ? 32 : 16;
   if (A.n <= 256 * e_small)
     g.threads = 256;
-  else if (A.n <= 1024 * e_mid)
+  else if (A.n <= 1024 * 8)
     g.threads = 1024;
   else
     g.threads = 512;
@@ -866,16 +894,15 @@ HvpGeom hvp_geometry(const MatArg& A, int64_t batch, bool query_device) {
   g.rows = 1;
   int per_cu = 1;
   if (g.threads == 256)
-    per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(4, (160 * 1024) / (A.n * 4 + 1024)));
+    per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(2, (160 * 1024) / (A.n * 4 + 1024)));
   const int cus = query_device ? num_cus() : 256;
   const int64_t cap = std::max<int64_t>(1, kHvpMaxBlocks / batch);
   const int64_t groups = (A.m + g.rows - 1) / g.rows;
   int64_t G = std::max<int64_t>(1, (int64_t)per_cu * cus / batch);
   G = std::min<int64_t>(G, std::min<int64_t>(cap, groups));
-  int64_t rpb = (A.m + G - 1) / G;
-  rpb = (rpb + g.rows - 1) / g.rows * g.rows;
-  g.rows_per_block = (int)rpb;
-  g.blocks = (int)((A.m + rpb - 1) / rpb);
+  // block g owns rows g, g + G, ... (G <= m: none is empty); the most any owns:
+  g.rows_per_block = (int)((A.m + G - 1) / G);
+  g.blocks = (int)G;
   return g;
 }
 
@@ -884,8 +911,7 @@ hipError_t launch_hvp_fused(const MatArg& A, const HvpGeom& g, int64_t batch, co
                             int64_t ks_stride, int64_t prob_stride, const int32_t* gate,
                             int gate_stride, hipStream_t st, double* pq, int64_t pq_stride) {
   if (g.threads == 0 || g.blocks < 1 || g.blocks > kHvpMaxBlocks ||
-      (int64_t)g.blocks * g.rows_per_block < A.m ||
-      (int64_t)(g.blocks - 1) * g.rows_per_block >= A.m || ks_stride < A.n ||  // no empty block
+      g.blocks > A.m || ks_stride < A.n ||  // every block owns a row
       !hvp_p_aligned(p, p_stride, batch))
     return hipErrorInvalidValue;
   if (A.mt == MT_BF16) {
@@ -893,12 +919,11 @@ hipError_t launch_hvp_fused(const MatArg& A, const HvpGeom& g, int64_t batch, co
       return hvp_dispatch<uint16_t, 256, 8, 16, 24, 32>(g.ept, A, g, batch, p, p_stride, d,
                                                            d_stride, ypart, ks_stride, prob_stride,
                                                            gate, gate_stride, pq, pq_stride, st);
-    if (g.threads == 1024)
-      return hvp_dispatch<uint16_t, 1024, 8, 16, 24, 32>(g.ept, A, g, batch, p, p_stride, d,
-                                                         d_stride, ypart, ks_stride, prob_stride,
-                                                         gate, gate_stride, pq, pq_stride, st);
-    return hvp_dispatch<uint16_t, 512, 72, 80>(g.ept, A, g, batch, p, p_stride, d, d_stride, ypart,
-                                               ks_stride, prob_stride, gate, gate_stride, pq, pq_stride, st);
+    if (g.threads == 512)
+      return hvp_dispatch<uint16_t, 512, 24, 32, 40, 48, 56, 64, 72, 80>(
+          g.ept, A, g, batch, p, p_stride, d, d_stride, ypart, ks_stride, prob_stride, gate,
+          gate_stride, pq, pq_stride, st);
+    return hipErrorInvalidValue;
   }
   if (A.mt == MT_F32) {
     if (g.threads == 256)
@@ -906,11 +931,12 @@ hipError_t launch_hvp_fused(const MatArg& A, const HvpGeom& g, int64_t batch, co
                                                        d_stride, ypart, ks_stride, prob_stride,
                                                        gate, gate_stride, pq, pq_stride, st);
     if (g.threads == 1024)
-      return hvp_dispatch<float, 1024, 4, 8, 12, 16, 20, 24, 28, 32, 36, 40>(
-          g.ept, A, g, batch, p, p_stride, d, d_stride, ypart, ks_stride, prob_stride, gate,
-          gate_stride, pq, pq_stride, st);
-    return hvp_dispatch<float, 512, 76, 80>(g.ept, A, g, batch, p, p_stride, d, d_stride, ypart,
-                                        ks_stride, prob_stride, gate, gate_stride, pq, pq_stride, st);
+      return hvp_dispatch<float, 1024, 8>(g.ept, A, g, batch, p, p_stride, d, d_stride, ypart,
+                                          ks_stride, prob_stride, gate, gate_stride, pq, pq_stride,
+                                          st);
+    return hvp_dispatch<float, 512, 20, 24, 28, 32, 36, 40, 44, 48, 52, 56, 60, 64, 68, 72, 76, 80>(
+        g.ept, A, g, batch, p, p_stride, d, d_stride, ypart, ks_stride, prob_stride, gate,
+        gate_stride, pq, pq_stride, st);
   }
   return hipErrorInvalidValue;
 }

@@ -172,8 +172,8 @@ struct HvpGeom {
   int threads = 0;         // 0: A does not qualify (use gemv_n + gemv_t)
   int ept = 0;             // owned columns per thread
   int rows = 0;            // rows per group
-  int blocks = 0;          // blocks (partials) per problem
-  int rows_per_block = 0;
+  int blocks = 0;          // blocks (partials) per problem; block g owns rows g, g + blocks, ...
+  int rows_per_block = 0;  // the most rows a block owns
 };
 HvpGeom hvp_geometry(const MatArg& A, int64_t batch, bool query_device);
 // the fused product reads p in 16-byte pieces

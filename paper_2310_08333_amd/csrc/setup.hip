@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void k_cast_atb(const float* __restrict__ A, i
 #pragma unroll
     for (int u = 0; u < kCastUnroll; ++u) {  // clamped rows are read, not used
       const int rr = min(r + u, r1 - 1);
-      a[u] = *reinterpret_cast<const float4*>(Ab + (int64_t)rr * lda + jc);
+      a[u] = load_stream_f4(Ab + (int64_t)rr * lda + jc);
       br[u] = bb[rr];
     }
 #pragma unroll

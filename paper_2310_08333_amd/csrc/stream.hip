@@ -1,8 +1,9 @@
 // Streaming read: the measurement reference for the HBM-bound kernels (not part
 // of the method).  A block reads contiguous tiles of 256 threads x 8 16-byte
-// words (32 KB), all eight loads of a thread in flight before any is used, and
-// steps through the buffer by the grid's tile stride; the XOR of the words a
-// block read goes to out[block], so no load is dead.
+// words (32 KB) with non-temporal loads (as the products read A), all eight
+// loads of a thread in flight before any is used, and steps through the buffer
+// by the grid's tile stride; the XOR of the words a block read goes to
+// out[block], so no load is dead.
 #include "device.hpp"
 
 namespace genios {
@@ -21,14 +22,14 @@ __global__ __launch_bounds__(kStreamThreads) void k_stream_read(const uint4* __r
     if (base + tile <= words) {
       uint4 v[kStreamUnroll];
 #pragma unroll
-      for (int k = 0; k < kStreamUnroll; ++k) v[k] = p[base + k * kStreamThreads + threadIdx.x];
+      for (int k = 0; k < kStreamUnroll; ++k) v[k] = load_stream_u4(p + base + k * kStreamThreads + threadIdx.x);
 #pragma unroll
       for (int k = 0; k < kStreamUnroll; ++k) acc ^= (v[k].x ^ v[k].y) ^ (v[k].z ^ v[k].w);
     } else {
       for (int k = 0; k < kStreamUnroll; ++k) {
         const int64_t i = base + k * kStreamThreads + threadIdx.x;
         if (i < words) {
-          const uint4 a = p[i];
+          const uint4 a = load_stream_u4(p + i);
           acc ^= (a.x ^ a.y) ^ (a.z ^ a.w);
         }
       }
