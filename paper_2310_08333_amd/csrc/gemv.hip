@@ -503,6 +503,8 @@ __device__ __forceinline__ float wave_sum_dpp(float v) {
   return ((r0 + r1) + r2) + r3;
 }
 
+constexpr int kCpolNT = 2;  // cache-policy operand of a buffer load: non-temporal
+
 template <typename T, int THREADS, int EPT, int D>
 __global__ __launch_bounds__(THREADS) void k_hvp_fused(
     const T* __restrict__ A, int64_t lda, int64_t strideA, int m, int n,
@@ -548,15 +550,26 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
   // The load is unconditional (a load under a branch gets a full wait at the
   // join): without d the buffer has no records, so the load at offset 0 is out
   // of range, touches no memory and returns 0 (its value is not used).
+  // The row itself is read through a raw buffer over its n e_A bytes, with
+  // non-temporal loads (A is streamed once per product).  The loads are
+  // unconditional for the same reason; what must not be read is kept out by
+  // the buffer's range check, which returns 0 without touching memory: a ring
+  // slot past the block's last row (never processed) gets a buffer with no
+  // records, and a last chunk past n (its p is zero and its result is never
+  // stored) lies past the row's records.
   const __amdgpu_buffer_rsrc_t drs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(db ? db : p), 0, db ? m * 4 : 0, 0x00020000);
   auto load_row = [&](int i, RT (&dst)[NC], float& dv) {
-    const int row = (int)blockIdx.x + i * G;
-    const T* rp = Ab + (int64_t)row * lda;
+    const bool live = i < r1;
+    const int row = live ? (int)blockIdx.x + i * G : 0;
+    const __amdgpu_buffer_rsrc_t ars = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<T*>(Ab + (int64_t)row * lda), 0, live ? n * (int)sizeof(T) : 0, 0x00020000);
     __builtin_amdgcn_sched_barrier(0);
     dv = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(drs, db ? row * 4 : 0, 0, 0));
 #pragma unroll
-    for (int k = 0; k < NC; ++k) dst[k] = load_stream<RT>(rp + col(k));
+    for (int k = 0; k < NC; ++k)
+      dst[k] = __builtin_bit_cast(
+          RT, __builtin_amdgcn_raw_buffer_load_b128(ars, 16 * (tid + THREADS * k), 0, kCpolNT));
     __builtin_amdgcn_sched_barrier(0);
   };
   float y[NC][V];
@@ -601,11 +614,10 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
   // ahead into the free buffer, then processes the oldest one, so rows r + 1 ..
   // r + D are in flight while row r is processed and the wait before a buffer's
   // use covers only it (the newer D rows stay in flight).  Loads are
-  // unconditional -- past the block's last row they re-read it -- so every path
-  // reaches the loop head with the same loads outstanding.  The prologue's rows
-  // are kept apart by a wavefront-scope fence (a compiler barrier only).
+  // unconditional -- past the block's last row they read p (above) -- so every
+  // path reaches the loop head with the same loads outstanding.  The prologue's
+  // rows are kept apart by a wavefront-scope fence (a compiler barrier only).
   // (Every block owns at least one row: r0 < r1.)
-  auto clampr = [&](int r) { return r < r1 ? r : r1 - 1; };
   RT b0[NC], b1[NC], b2[NC];
   float d0 = 1.f, d1 = 1.f, d2 = 1.f;
   // Prologue: each thread loads the p values of the chunks it owns (16-byte
@@ -634,28 +646,28 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
   }
   if constexpr (D >= 2) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    load_row(clampr(r0 + 1), b1, d1);
+    load_row(r0 + 1, b1, d1);
   }
   __syncthreads();  // p in LDS
   if constexpr (D == 0) {
     for (int r = r0; r < r1; ++r) {
       process(b0, d0);
-      load_row(clampr(r + 1), b0, d0);
+      load_row(r + 1, b0, d0);
     }
   } else if constexpr (D == 1) {
     for (int r = r0; r < r1; r += 2) {
-      load_row(clampr(r + 1), b1, d1);
+      load_row(r + 1, b1, d1);
       process(b0, d0);
-      load_row(clampr(r + 2), b0, d0);
+      load_row(r + 2, b0, d0);
       if (r + 1 < r1) process(b1, d1);
     }
   } else {
     for (int r = r0; r < r1; r += 3) {
-      load_row(clampr(r + 2), b2, d2);
+      load_row(r + 2, b2, d2);
       process(b0, d0);
-      load_row(clampr(r + 3), b0, d0);
+      load_row(r + 3, b0, d0);
       if (r + 1 < r1) process(b1, d1);
-      load_row(clampr(r + 4), b1, d1);
+      load_row(r + 4, b1, d1);
       if (r + 2 < r1) process(b2, d2);
     }
   }
