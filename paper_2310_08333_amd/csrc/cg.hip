@@ -155,6 +155,29 @@ __device__ __forceinline__ void finish_coef(const double* part_b, int nb, int s_
   }
 }
 
+// v[q] += load(q, k) for k = threadIdx.x, threadIdx.x + blockDim.x, ... < nb, in
+// increasing k (the order of a plain strided loop), with four loads per list in
+// flight: indices past nb re-read index k0 and are not added.  One memory round
+// trip per 4 blockDim.x partials instead of one per blockDim.x.
+template <int NV, typename L>
+__device__ __forceinline__ void strided_sum4(int nb, const L& load, double (&v)[NV]) {
+  const int bd = (int)blockDim.x;
+  for (int k0 = threadIdx.x; k0 < nb; k0 += 4 * bd) {
+    double e[NV][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + q * bd;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) e[i][q] = load(i, k < nb ? k : k0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (k0 + q * bd < nb)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] += e[i][q];
+  }
+}
+
 // Fixed-order parallel sum of NV scalar slots over the nb block partials of one
 // problem.  Called by every thread of the last block; the result is valid in
 // thread 0.
@@ -181,9 +204,7 @@ __device__ __forceinline__ void reduce_slots(const Ctrl& ctrl, int b, int nb, co
   double v[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) v[q] = 0.0;
-  for (int k = threadIdx.x; k < nb; k += blockDim.x)
-#pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] += sp[(int64_t)slot[q] * ctrl.pstride + k];
+  strided_sum4<NV>(nb, [&](int q, int k) { return sp[(int64_t)slot[q] * ctrl.pstride + k]; }, v);
   block_sum<NV>(v, sm);
   if (threadIdx.x == 0)
 #pragma unroll
@@ -299,7 +320,7 @@ __global__ __launch_bounds__(256) void k_precond_coef(Ctrl ctrl, int nb) {
   __shared__ double sm[4];
   const double* up = ctrl.upart + ((int64_t)b * kMaxS + j) * ctrl.pstride;
   double v[1] = {0.0};
-  for (int k = threadIdx.x; k < nb; k += blockDim.x) v[0] += up[k];
+  strided_sum4<1>(nb, [&](int, int k) { return up[k]; }, v);
   block_sum<1>(v, sm);
   if (threadIdx.x == 0) {
     const double* lam = ctrl.lamhat + (int64_t)b * ctrl.s_stride;
@@ -580,13 +601,15 @@ __global__ __launch_bounds__(256) void k_cg_step(VecArgs a, int t) {
   {
     double v[3] = {0.0, 0.0, 0.0};
     const double* hq = a.hpq + (int64_t)b * a.hpq_stride;
-    for (int k = threadIdx.x; k < a.nhpq; k += blockDim.x) v[0] += hq[k];
-    const double* s_on = slot_ptr(a.ctrl, b, kSlPp);
+    double vh[1] = {0.0};
+    strided_sum4<1>(a.nhpq, [&](int, int k) { return hq[k]; }, vh);
+    v[0] = vh[0];
+    const double* s_on = slot_ptr(a.ctrl, b, kSlPp);  // written by precond_p
     const double* s_off = slot_ptr(a.ctrl, b, kSlPpOff);
-    for (int k = threadIdx.x; k < a.nbf; k += blockDim.x) {  // written by precond_p
-      v[1] += s_on[k];
-      v[2] += s_off[k];
-    }
+    double vp[2] = {0.0, 0.0};
+    strided_sum4<2>(a.nbf, [&](int q, int k) { return q == 0 ? s_on[k] : s_off[k]; }, vp);
+    v[1] = vp[0];
+    v[2] = vp[1];
     block_sum<3>(v, red);
     if (threadIdx.x == 0) {
       bc[0] = v[0];

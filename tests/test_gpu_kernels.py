@@ -99,6 +99,7 @@ def _hvp_bound(Aref, p, d, m, n):
     (257, 1003, "f32", False),                              # n % 4 != 0: gemv_n + gemv_t
     (3000, 520, "bf16", True), (3000, 520, "f32", False),   # 256-thread blocks
     (33, 40704, "bf16", False), (33, 40704, "f32", True),   # largest n, ragged last chunk
+    (40, 40712, "bf16", True), (21, 65536, "f32", False),   # past the fused limit: two passes
     (50, 9000, "f32", False), (5, 24, "bf16", True), (1, 8, "f32", False)])
 def test_hvp_parity(g, m, n, kind, weighted):
     print("hvp", m, n, kind, weighted, flush=True)
