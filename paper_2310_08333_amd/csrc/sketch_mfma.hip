@@ -105,8 +105,15 @@ __device__ __forceinline__ bool any_flag(const int32_t* gate, int gstride, int c
 
 // Wpart[b][ks][c][r] = sum_{k in split ks} A[r][k] Omega[k][c]; with LO the operand is
 // the sum of two BF16 parts (hi + lo of an FP32 block), both staged per step.
-template <int SP, bool LO>
-__global__ __launch_bounds__(256) void k_sketch_w_mfma(const uint16_t* __restrict__ A,
+// A step covers KS = KC x 32 values of k: while the KC instructions per column tile
+// of the current step run, the A fragments and the Omega tile [SP][KS] of the next
+// step are in flight, so a block waits for memory once per KC instructions.  The
+// Omega tile sits in dynamic LDS, row pitch KS + 8 (conflict-free 16-byte staging
+// stores and fragment reads); tile chunks past kpad are stored as zeros.  Measured
+// at 20000 x 40000, s = 128: 572 us with KS = 64 (four blocks per CU), 593 with 32,
+// 645 with 128 (two blocks per CU: the 628 blocks take 1.23 rounds).
+template <int SP, bool LO, int KS>
+__global__ __launch_bounds__(256, 3) void k_sketch_w_mfma(const uint16_t* __restrict__ A,
                                                        int64_t lda, int64_t strideA, int m, int n,
                                                        const uint16_t* __restrict__ o16,
                                                        const uint16_t* __restrict__ o16lo,
@@ -115,9 +122,13 @@ __global__ __launch_bounds__(256) void k_sketch_w_mfma(const uint16_t* __restric
                                                        int64_t prob_stride,
                                                        const int32_t* __restrict__ gate,
                                                        int gstride, int gcount) {
-  constexpr int NT = SP / 16;  // column tiles
+  constexpr int NT = SP / 16;     // column tiles
   constexpr int NO = LO ? 2 : 1;  // operand parts
-  __shared__ __align__(16) uint16_t os[NO][2][SP * kPitch];
+  constexpr int KC = KS / kMK;    // instructions per column tile per step
+  constexpr int PITCH = KS + 8;   // LDS row pitch, 16-bit elements
+  constexpr int TILE = SP * PITCH;
+  extern __shared__ __align__(16) uint16_t os_dyn[];  // [NO][2][SP][PITCH]
+  auto os = [&](int o, int buf) { return os_dyn + (o * 2 + buf) * TILE; };
   if (!any_flag(gate, gstride, gcount)) return;
   const int b = blockIdx.z, ks = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -132,75 +143,88 @@ __global__ __launch_bounds__(256) void k_sketch_w_mfma(const uint16_t* __restric
   const uint16_t* arow[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) arow[t] = Ab + (int64_t)min(row0 + 16 * t + (lane & 15), m - 1) * lda;
-  const int kl = 8 * (lane >> 4);  // this lane's k offset inside a step
+  const int kl = 8 * (lane >> 4);  // this lane's k offset inside an instruction's 32
   floatx4 acc[2][NT];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-  // Omega tile loader: SP columns x 32 k = SP * 4 chunks of 16 bytes
-  constexpr int OCH = SP * 4;
-  // (loads are unconditional -- chunk indices past the tile re-read chunk 0 -- so
-  // the staging registers stay registers; only the LDS stores are guarded)
+  // Omega tile loader: SP columns x KS k = SP * KS / 8 chunks of 16 bytes; a thread's
+  // chunks share one k offset (part), since 256 is a multiple of KS / 8
+  constexpr int PARTS = KS / 8;
+  constexpr int OCH = SP * PARTS;
   constexpr int OQ = (OCH + 255) / 256;
+  static_assert(256 % PARTS == 0, "a thread's chunks share their k offset");
+  const int part = tid % PARTS;
+  // (loads are unconditional -- chunk indices past the tile re-read chunk 0, chunks
+  // past kpad read offset 0 -- so the staging registers stay registers; the LDS
+  // stores are guarded, and chunks past kpad are stored as zeros)
   auto load_omega = [&](int kk, uint4 (&reg)[NO][OQ]) {
+    const int kof = kk + 8 * part + 8 <= kpad ? kk + 8 * part : 0;
 #pragma unroll
     for (int o = 0; o < NO; ++o)
 #pragma unroll
       for (int q = 0; q < OQ; ++q) {
         const int ch = tid + 256 * q < OCH ? tid + 256 * q : 0;
-        const int c = ch >> 2, part = ch & 3;
-        reg[o][q] = *reinterpret_cast<const uint4*>(Obp[o] + (int64_t)c * kpad + kk + 8 * part);
+        reg[o][q] = *reinterpret_cast<const uint4*>(Obp[o] + (int64_t)(ch / PARTS) * kpad + kof);
       }
   };
-  auto store_omega = [&](int buf, const uint4 (&reg)[NO][OQ]) {
+  auto store_omega = [&](int kk, int buf, const uint4 (&reg)[NO][OQ]) {
+    const bool in = kk + 8 * part + 8 <= kpad;
 #pragma unroll
     for (int o = 0; o < NO; ++o)
 #pragma unroll
       for (int q = 0; q < OQ; ++q) {
         const int ch = tid + 256 * q;
-        if (ch < OCH) {
-          const int c = ch >> 2, part = ch & 3;
-          *reinterpret_cast<uint4*>(&os[o][buf][c * kPitch + 8 * part]) = reg[o][q];
-        }
+        if (ch < OCH)
+          *reinterpret_cast<uint4*>(&os(o, buf)[(ch / PARTS) * PITCH + 8 * part]) =
+              in ? reg[o][q] : make_uint4(0u, 0u, 0u, 0u);
       }
   };
   // A fragments of a step: columns past n read column 0 (their Omega rows are 0)
-  auto load_a = [&](int kk, uint4 (&fa)[2]) {
-    const int k = kk + kl;
-    const int kc = k < n ? k : 0;
+  auto load_a = [&](int kk, uint4 (&fa)[2][KC]) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) fa[t] = *reinterpret_cast<const uint4*>(arow[t] + kc);
+    for (int i = 0; i < KC; ++i) {
+      const int k = kk + kMK * i + kl;
+      const int kc = k < n ? k : 0;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) fa[t][i] = *reinterpret_cast<const uint4*>(arow[t] + kc);
+    }
   };
   uint4 oreg[NO][OQ];
-  uint4 fa[2], fn[2];
+  uint4 fa[2][KC], fn[2][KC];
   if (k0 < k1) {
     load_omega(k0, oreg);
-    store_omega(0, oreg);
+    store_omega(k0, 0, oreg);
     load_a(k0, fa);
   }
   __syncthreads();
   int buf = 0;
-  for (int kk = k0; kk < k1; kk += kMK) {
-    const bool more = kk + kMK < k1;
-    const int kn = more ? kk + kMK : kk;  // the last step re-reads its own tile (unused)
+  for (int kk = k0; kk < k1; kk += KS) {
+    const bool more = kk + KS < k1;
+    const int kn = more ? kk + KS : kk;  // the last step re-reads its own tile (unused)
     load_omega(kn, oreg);
     load_a(kn, fn);
 #pragma unroll
-    for (int c = 0; c < NT; ++c) {
+    for (int i = 0; i < KC; ++i)
 #pragma unroll
-      for (int o = 0; o < NO; ++o) {
-        const uint4 fb =
-            *reinterpret_cast<const uint4*>(&os[o][buf][(16 * c + (lane & 15)) * kPitch + kl]);
+      for (int c = 0; c < NT; ++c) {
 #pragma unroll
-        for (int t = 0; t < 2; ++t) acc[t][c] = mfma(fa[t], fb, acc[t][c]);
+        for (int o = 0; o < NO; ++o) {
+          const uint4 fb = *reinterpret_cast<const uint4*>(
+              &os(o, buf)[(16 * c + (lane & 15)) * PITCH + kMK * i + kl]);
+#pragma unroll
+          for (int t = 0; t < 2; ++t) acc[t][c] = mfma(fa[t][i], fb, acc[t][c]);
+        }
       }
-    }
-    if (more) store_omega(buf ^ 1, oreg);
+    if (more) store_omega(kn, buf ^ 1, oreg);
     __syncthreads();
     buf ^= 1;
-    fa[0] = fn[0];
-    fa[1] = fn[1];
+#pragma unroll
+    for (int i = 0; i < KC; ++i) {
+      fa[0][i] = fn[0][i];
+      fa[1][i] = fn[1][i];
+    }
   }
   float* Wb = wpart + (int64_t)b * prob_stride + (int64_t)ks * ks_stride;
 #pragma unroll
@@ -212,6 +236,38 @@ __global__ __launch_bounds__(256) void k_sketch_w_mfma(const uint16_t* __restric
         const int r = row0 + 16 * t + 4 * (lane >> 4) + i;
         if (r < m) Wb[(int64_t)(16 * c + (lane & 15)) * m + r] = acc[t][c][i];
       }
+}
+
+// K step of the W product (both operand forms): 64, two instructions per column
+// tile per step.
+template <bool LO>
+constexpr int w_step() {
+  return 64;
+}
+
+// Launch of k_sketch_w_mfma with its dynamic LDS; the K range per split, a multiple
+// of the step, is derived here from the split count.
+template <int SP, bool LO>
+hipError_t launch_w_mfma(dim3 grid, hipStream_t st, const uint16_t* A, int64_t lda,
+                         int64_t strideA, int m, int n, const uint16_t* o16,
+                         const uint16_t* o16lo, int64_t kpad, float* wpart, int splits,
+                         int64_t ks_stride, int64_t prob_stride, const int32_t* gate, int gstride,
+                         int gcount) {
+  constexpr int KS = w_step<LO>();
+  constexpr size_t lds = (size_t)(LO ? 2 : 1) * 2 * SP * (KS + 8) * sizeof(uint16_t);
+  auto* fn = &k_sketch_w_mfma<SP, LO, KS>;
+  static bool attr = false;  // set once per instantiation
+  if (lds > 64 * 1024 && !attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  int kchunk = (int)((n + splits - 1) / splits);
+  kchunk = (kchunk + KS - 1) / KS * KS;
+  hipLaunchKernelGGL(fn, grid, dim3(256), lds, st, A, lda, strideA, m, n, o16, o16lo, kpad, wpart,
+                     kchunk, ks_stride, prob_stride, gate, gstride, gcount);
+  return hipGetLastError();
 }
 
 // (d o sum_ks Wpart) -> BF16 hi and lo parts [c][kpad], zero past m.  Column c < dcols
@@ -375,14 +431,12 @@ hipError_t sketch_mfma_sp(const MatArg& A, int64_t batch, const float* d, int64_
     if (e != hipSuccess) return e;
   }
   {
-    int kchunk = (int)((A.n + ws.ksW - 1) / ws.ksW);
-    kchunk = (kchunk + kMK - 1) / kMK * kMK;
     dim3 grid((unsigned)((m + kWRows - 1) / kWRows), (unsigned)ws.ksW, (unsigned)batch);
-    hipLaunchKernelGGL((k_sketch_w_mfma<SP, false>), grid, dim3(256), 0, st, Ap, A.lda,
-                       A.strideA, m, n, ws.o16, (const uint16_t*)nullptr, kpn,
-                       static_cast<float*>(ws.Wpart), kchunk, (int64_t)m * SP,
-                       (int64_t)ws.ksW * m * SP, (const int32_t*)nullptr, 0, 0);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_w_mfma<SP, false>(grid, st, Ap, A.lda, A.strideA, m, n, ws.o16,
+                                            (const uint16_t*)nullptr, kpn,
+                                            static_cast<float*>(ws.Wpart), ws.ksW,
+                                            (int64_t)m * SP, (int64_t)ws.ksW * m * SP,
+                                            (const int32_t*)nullptr, 0, 0);
     if (e != hipSuccess) return e;
   }
   {
@@ -752,13 +806,10 @@ hipError_t mrhs_sp(const MatArg& A, int B, const float* P, int64_t pstride, cons
     if (e != hipSuccess) return e;
   }
   {
-    int kchunk = (int)((A.n + ws.ksW - 1) / ws.ksW);
-    kchunk = (kchunk + kMK - 1) / kMK * kMK;
     dim3 grid((unsigned)((m + kWRows - 1) / kWRows), (unsigned)ws.ksW, 1u);
-    hipLaunchKernelGGL((k_sketch_w_mfma<SP, true>), grid, dim3(256), 0, st, Ap, A.lda, (int64_t)0,
-                       m, n, ph, pl, kpn, ws.wpart, kchunk, (int64_t)m * SP,
-                       (int64_t)ws.ksW * m * SP, gate, gstride, B);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_w_mfma<SP, true>(grid, st, Ap, A.lda, (int64_t)0, m, n, ph, pl, kpn,
+                                           ws.wpart, ws.ksW, (int64_t)m * SP,
+                                           (int64_t)ws.ksW * m * SP, gate, gstride, B);
     if (e != hipSuccess) return e;
   }
   {
