@@ -188,11 +188,19 @@ typedef struct {
                                   per ADMM iteration, so the right-hand side, r_d and the
                                   stopping test are the master copy's and the fixed point is
                                   the FP32 problem's (the approximate-Hessian x-step of
-                                  Sec. 2.1).  Default 0: on the 20000 x 40000 Lasso 1 saves
-                                  1 % of the time to 1e-4, on the 1000 x 10000 one it costs
-                                  40 % (the extra pass per iteration is launch-bound there).
-                                  The logistic and Huber losses take 0 whatever the value */
+                                  Sec. 2.1); -1 (default) = 1 when one problem's master copy
+                                  holds at least GENIOS_REFINE_CG_BF16_MIN_BYTES (its
+                                  products are bandwidth-bound, and the BF16 ones take half
+                                  the time), else 0 (measured: on the 20000 x 40000 Lasso 1
+                                  saves 3 % of the time to 1e-4, on the 1000 x 10000 one it
+                                  costs 19 %: the extra pass per iteration is launch-bound
+                                  there).  The logistic and Huber losses take 0 whatever the
+                                  value */
 } genios_opts;
+
+/* Master-copy bytes of one problem (m n element size) from which refine_cg_bf16 = -1
+ * keeps the BF16 copy inside CG after the switch. */
+#define GENIOS_REFINE_CG_BF16_MIN_BYTES ((int64_t)256 << 20)
 
 /* Per-iteration history row layout (doubles); problem p, iteration k (1-based)
  * at history[(p * history_cap + k - 1) * GENIOS_HIST_FIELDS + field]. */

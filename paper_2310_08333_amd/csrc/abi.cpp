@@ -62,7 +62,8 @@ int check_opts(const genios_opts* o) {
   if (o->power_iters < 1 || o->power_iters > 1000)
     FAIL(GENIOS_ERR_ARG, "power_iters must lie in [1, 1000]");
   if (o->batch_mfma < 0 || o->batch_mfma > 2) FAIL(GENIOS_ERR_ARG, "batch_mfma must be 0, 1 or 2");
-  if (o->refine_cg_bf16 < 0 || o->refine_cg_bf16 > 1) FAIL(GENIOS_ERR_ARG, "refine_cg_bf16 must be 0 or 1");
+  if (o->refine_cg_bf16 < -1 || o->refine_cg_bf16 > 1)
+    FAIL(GENIOS_ERR_ARG, "refine_cg_bf16 must be -1, 0 or 1");
   return GENIOS_OK;
 }
 
@@ -187,7 +188,7 @@ int genios_default_opts(genios_opts* o) {
   o->sketch_kappa = 10.0;
   o->power_iters = 10;
   o->batch_mfma = 1;
-  o->refine_cg_bf16 = 0;
+  o->refine_cg_bf16 = -1;
   return GENIOS_OK;
 }
 

@@ -692,8 +692,12 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
   const bool use_lo = prec == GENIOS_PREC_BF16_REFINE || prec == GENIOS_PREC_BF16_ONLY;
   // After the switch to the master copy, CG may keep the BF16 copy as the x-system's
   // Hessian model while the master copy forms H x (the gradient) once per iteration
-  // (squared loss only: the curvature-weighted losses keep master-copy CG).
-  const bool lo_cg = prec == GENIOS_PREC_BF16_REFINE && o->refine_cg_bf16 != 0 && !ml;
+  // (squared loss only: the curvature-weighted losses keep master-copy CG); by
+  // default when the master copy's products are bandwidth-bound.
+  const int64_t hi_bytes = A->m * A->n * (int64_t)(c.vt == VT_F64 ? 8 : 4);
+  const bool lo_cg = prec == GENIOS_PREC_BF16_REFINE && !ml &&
+                     (o->refine_cg_bf16 == 1 ||
+                      (o->refine_cg_bf16 < 0 && hi_bytes >= GENIOS_REFINE_CG_BF16_MIN_BYTES));
   c.op_hi = MatArg{A->A_hi, c.vt == VT_F64 ? MT_F64 : MT_F32, A->m, A->n, A->lda, A->stride_A};
   c.op_lo = MatArg{A->A_bf16 ? (const void*)A->A_bf16 : (const void*)c.L.A16, MT_BF16, A->m, A->n,
                    A->lda, A->stride_A};

@@ -248,7 +248,7 @@ def test_hvp_noalloc_rejects_a_product_beyond_its_scratch(abi):
 def test_refine_cg_option_is_validated(abi):
     lib = abi.load()
     o = abi.default_opts()
-    assert o.refine_cg_bf16 == 0
+    assert o.refine_cg_bf16 == -1  # automatic: BF16 CG products for large master copies
     o.refine_cg_bf16 = 2
     M = _mat(abi)
     rc = lib.genios_lasso_solve(C.byref(M), C.c_void_p(0x1000), (C.c_double * 1)(0.1), 1.0,
