@@ -191,7 +191,9 @@ typedef struct {
                                   Sec. 2.1); -1 (default) = 1 when one problem's master copy
                                   holds at least GENIOS_REFINE_CG_BF16_MIN_BYTES (its
                                   products are bandwidth-bound, and the BF16 ones take half
-                                  the time), else 0 (measured: on the 20000 x 40000 Lasso 1
+                                  the time) in the iterations whose predicted CG count is 3
+                                  or more (fewer products do not pay for the extra master
+                                  pass), else 0 (measured: on the 20000 x 40000 Lasso 1
                                   saves 3 % of the time to 1e-4, on the 1000 x 10000 one it
                                   costs 19 %: the extra pass per iteration is launch-bound
                                   there).  The logistic and Huber losses take 0 whatever the

@@ -1027,7 +1027,11 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
       if (!P[b].done) chunk = std::max(chunk, P[b].last_cg);
     chunk = std::min(chunk, o->max_cg_iter);
     int enq = 0;
-    const MatArg* cgop = (phase == 1 && lo_cg) ? &c.op_lo : op;
+    // BF16-model CG pays when the iteration's CG products outweigh the extra master
+    // pass: k t32 > t32 + k t16 with t16 ~ t32 / 2 at the bandwidth bound, so k >= 3
+    // for the predicted count (always with refine_cg_bf16 = 1)
+    const bool cg_lo_it = phase == 1 && lo_cg && (o->refine_cg_bf16 == 1 || chunk >= 3);
+    const MatArg* cgop = cg_lo_it ? &c.op_lo : op;
     for (;;) {
       for (int it = 0; it < chunk; ++it) {
         rc = cg_iteration(c, *cgop, va, ml ? c.L.dvec : nullptr, enq + it);
@@ -1174,8 +1178,8 @@ int run_admm(const genios_matrix* A, const void* bvec, const double* lambda, dou
     if (any_certify) {
       for (int64_t b = 0; b < B; ++b) hp[b].run = want_cert[b];
       HC(upload_params(c, hp));
-      // (with BF16-model CG after the switch, h and r_d are already the master copy's)
-      const bool rd_fresh = phase == 1 && lo_cg;
+      // (after an iteration of BF16-model CG, h and r_d are already the master copy's)
+      const bool rd_fresh = cg_lo_it;
       if (!ml && !rd_fresh) {
         rc = hvp_explicit(c, *op, x, h, nullptr, c.gate_run, c.gs_params);
         if (rc) return rc;
