@@ -93,22 +93,27 @@ __device__ __forceinline__ void ut_r_partial(const VT* __restrict__ Ub, int64_t 
   }
 }
 
-// U^T r over 64 rows [lo, lo + 64) of a chunk, accumulated into `acc`: thread t takes
-// column j = t / 2 and the 32 rows lo + 32 (t % 2) + [0, 32) (all 32 loads in flight),
-// each weighted by r from LDS (rs[0..63], zero past the chunk; rows past `hi` re-read
-// row hi - 1).  No cross-lane reduction: ut_r64_store combines the two halves.
+// U^T r over 64 rows [lo, lo + 64) of a chunk, in two parts: ut_r64_load issues the
+// U values ahead of the step's other work (they do not depend on it) -- thread t takes
+// column j = t / 2 (column 0, never summed, past the allocated width) and the 32 rows
+// lo + 32 (t % 2) + [0, 32), all 32 loads in flight, rows past `hi` re-reading row
+// hi - 1 -- and ut_r64_use weights them by r from LDS (rs[0..63], zero past the
+// chunk) into `acc`.  No cross-lane reduction: ut_r64_store combines the two halves.
 template <typename VT>
-__device__ __forceinline__ void ut_r64_acc(const VT* __restrict__ Ub, int64_t ldu, int s_eff,
-                                           int64_t lo, int64_t hi, const VT* rs, double& acc) {
+__device__ __forceinline__ void ut_r64_load(const VT* __restrict__ Ub, int64_t ldu, int s_width,
+                                            int64_t lo, int64_t hi, VT (&uv)[32]) {
   const int j = threadIdx.x >> 1, half = threadIdx.x & 1;
-  if (j >= s_eff) return;
-  const VT* col = Ub + (int64_t)j * ldu;
-  VT uv[32];
+  const VT* col = Ub + (int64_t)(j < s_width ? j : 0) * ldu;
 #pragma unroll
   for (int q = 0; q < 32; ++q) {
     const int64_t i = lo + 32 * half + q;
     uv[q] = col[i < hi ? i : hi - 1];
   }
+}
+template <typename VT>
+__device__ __forceinline__ void ut_r64_use(int s_eff, const VT (&uv)[32], const VT* rs, double& acc) {
+  const int j = threadIdx.x >> 1, half = threadIdx.x & 1;
+  if (j >= s_eff) return;
 #pragma unroll
   for (int q = 0; q < 32; ++q) acc += double(uv[q]) * double(rs[32 * half + q]);
 }
@@ -295,7 +300,12 @@ __global__ __launch_bounds__(256) void k_admm_begin(VecArgs a) {
       rs[lane] = ri;  // zero past the chunk
     }
     __syncthreads();
-    if (s_eff > 0) ut_r64_acc<VT>(Ub, n, s_eff, base, ch.hi, rs, ur);
+    // (the U rows after r_0: issued first, they held up the first wave's vectors)
+    if ((int)(threadIdx.x >> 1) < s_eff) {
+      VT uv[32];
+      ut_r64_load<VT>(Ub, n, a.s_stride, base, ch.hi, uv);
+      ut_r64_use<VT>(s_eff, uv, rs, ur);
+    }
     __syncthreads();
   }
   if (s_eff > 0)
@@ -596,6 +606,11 @@ __global__ __launch_bounds__(256) void k_cg_step(VecArgs a, int t) {
   ProbState* S = a.ctrl.state + b;
   if (!block_gate_cg(P, S)) return;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  const int64_t n = a.n;
+  const Chunk ch = my_chunk(n, a.chunkf);
+  const VT* Ub = a.U ? static_cast<const VT*>(a.U) + (int64_t)b * a.n * a.s_stride : nullptr;
+  VT uv[32];  // the first step's U rows, in flight during the alpha and H p sums
+  if (Ub && ch.lo < ch.hi) ut_r64_load<VT>(Ub, n, a.s_stride, ch.lo, ch.hi, uv);
   __shared__ double red[16];
   __shared__ double bc[3];
   {
@@ -633,8 +648,6 @@ __global__ __launch_bounds__(256) void k_cg_step(VecArgs a, int t) {
     S->pq = pq;
     S->alpha_cg = alpha;
   }
-  const int64_t n = a.n;
-  const Chunk ch = my_chunk(n, a.chunkf);
   const int64_t off = (int64_t)b * n;
   VT* x = static_cast<VT*>(a.x) + off;
   VT* h = static_cast<VT*>(a.h) + off;
@@ -643,7 +656,6 @@ __global__ __launch_bounds__(256) void k_cg_step(VecArgs a, int t) {
   const VT* yp = static_cast<const VT*>(a.ypart) + (int64_t)b * a.ypart_prob_stride;
   const uint8_t* mask = a.mask ? a.mask + off : nullptr;
   const int s_eff = a.U ? a.ctrl.s_eff[b] : 0;
-  const VT* Ub = a.U ? static_cast<const VT*>(a.U) + (int64_t)b * n * a.s_stride : nullptr;
   __shared__ VT sums[4][64];
   __shared__ VT rs[64];
   const VT al = VT(alpha), nu = VT(P.nu);
@@ -653,6 +665,7 @@ __global__ __launch_bounds__(256) void k_cg_step(VecArgs a, int t) {
   double ur = 0.0;        // this thread's share of (U^T r)_j, j = threadIdx.x / 2
   double rr = 0.0;
   for (int64_t base = ch.lo; base < ch.hi; base += 64) {
+    if (Ub && base != ch.lo) ut_r64_load<VT>(Ub, n, a.s_stride, base, ch.hi, uv);
     const int64_t i = base + lane;
     const bool ok = i < ch.hi;
     const int64_t ic = ok ? i : ch.hi - 1;
@@ -687,7 +700,7 @@ __global__ __launch_bounds__(256) void k_cg_step(VecArgs a, int t) {
       rs[lane] = ri;  // zero past the chunk
     }
     __syncthreads();
-    if (s_eff > 0) ut_r64_acc<VT>(Ub, n, s_eff, base, ch.hi, rs, ur);
+    if (s_eff > 0) ut_r64_use<VT>(s_eff, uv, rs, ur);
     __syncthreads();
   }
   if (s_eff > 0)
