@@ -446,9 +446,9 @@ hipError_t launch_gemv_t(const MatArg& A, int64_t batch, VType vt, const void* t
 // hp = A^T (d o (A p)) in one pass over A (Sec. 3.1 HVP example, Sec. 3.3 ML
 // Hessian with D = diag(d)).  Of the G blocks of a problem, block g owns the
 // rows g, g + G, g + 2G, ..., so the grid reads A as one band moving down the
-// matrix (measured faster than G separate row ranges), with non-temporal loads.  p sits in
-// LDS (FP32); thread t owns the 16-byte column chunks c = V (t + THREADS k) and
-// keeps their share of the result in registers.  Each row's chunks are loaded
+// matrix (measured faster than G separate row ranges), with non-temporal loads.
+// p sits in LDS (FP32); thread t owns the 16-byte column chunks
+// c = V (t + THREADS k) and keeps their share of the result in registers.  Each row's chunks are loaded
 // once (packed; the next row's loads are in flight while a row is processed),
 // the row's dot product is reduced over the block (shuffles, then one LDS
 // exchange and one barrier), scaled by d, and the same registers update the
@@ -614,9 +614,10 @@ __global__ __launch_bounds__(THREADS) void k_hvp_fused(
   // ahead into the free buffer, then processes the oldest one, so rows r + 1 ..
   // r + D are in flight while row r is processed and the wait before a buffer's
   // use covers only it (the newer D rows stay in flight).  Loads are
-  // unconditional -- past the block's last row they read p (above) -- so every
-  // path reaches the loop head with the same loads outstanding.  The prologue's
-  // rows are kept apart by a wavefront-scope fence (a compiler barrier only).
+  // unconditional -- past the block's last row they are out of range and read
+  // nothing (above) -- so every path reaches the loop head with the same loads
+  // outstanding.  The prologue's rows are kept apart by a wavefront-scope fence
+  // (a compiler barrier only).
   // (Every block owns at least one row: r0 < r1.)
   RT b0[NC], b1[NC], b2[NC];
   float d0 = 1.f, d1 = 1.f, d2 = 1.f;
